@@ -1,0 +1,456 @@
+"""Pins of the FP64 CPU oracle against facts that do not come from the oracle itself.
+
+Each test names the passage of the paper (or the published definition) that fixes
+the value it checks: closed forms, invariants, the paper's propositions, special
+cases that reduce to a textbook solve, published generator outputs, brute force
+on tiny inputs.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import sgks_oracle as O
+from workloads import generators as gen
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def tiny(n=14, seed=1, mu=1e-2, sigma=1.5):
+    A = gen.blur1d_dense(n, sigma)
+    L = gen.diff1d(n)
+    rng = np.random.default_rng(seed)
+    x = gen.step_signal(n, rng)
+    b = gen.add_noise(A @ x, 0.01, rng)
+    return A, L, b, mu
+
+
+def tiny2d(N=6, seed=2, mu=5e-3):
+    A = gen.psf_blur2d(N, sigma=1.0, half=1)
+    L = gen.grad2d(N)
+    rng = np.random.default_rng(seed)
+    x = gen.random_ellipses(N, rng, count=3)
+    b = gen.add_noise(A @ x, 0.01, rng)
+    return A, L, b, mu
+
+
+# ----------------------------------------------------------------------------
+# sparse-sign embedding
+# ----------------------------------------------------------------------------
+
+def test_splitmix64_published_sequence():
+    """mix64(c * gamma) is SplitMix64 output c from state 0 (Steele, Lea & Flood 2014)."""
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "splitmix64_seed0.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for c, hx in rows:
+        with np.errstate(over="ignore"):
+            z = O.mix64(O.GAMMA * np.uint64(int(c)))
+        assert int(z) == int(hx, 16)
+
+
+def _bruteforce_column(j, s, zeta, seed, stream):
+    """Rows and signs of one column by a plain scalar loop (Python integers mod 2^64)."""
+    mask = (1 << 64) - 1
+    g = 0x9E3779B97F4A7C15
+    key = int(O.mix64(np.uint64((seed + g * (2 * j + stream + 1)) & mask)))
+    rows, signs, c = [], [], 0
+    while len(rows) < zeta:
+        z = int(O.mix64(np.uint64((key + g * (c + 1)) & mask)))
+        c += 1
+        row = ((z >> 32) * s) >> 32
+        if row in rows:
+            continue
+        rows.append(row)
+        signs.append(-1 if z & 1 else 1)
+    return rows, signs
+
+
+@pytest.mark.parametrize("s,zeta,seed,stream", [(12, 8, 0, 0), (9, 8, 3, 1), (40, 8, 11, 0), (8, 8, 5, 1)])
+def test_sparse_sign_pattern_matches_scalar_definition(s, zeta, seed, stream):
+    h = 50
+    rows, signs = O.sparse_sign_pattern(h, s, zeta, seed, stream)
+    for j in range(h):
+        r, g = _bruteforce_column(j, s, zeta, seed, stream)
+        assert list(rows[j]) == r
+        assert list(signs[j]) == g
+
+
+def test_sparse_sign_invariants():
+    h, s, zeta = 3000, 64, 8
+    S = O.sparse_sign_matrix(h, s, zeta, seed=7, stream=0)
+    assert S.shape == (s, h)
+    C = S.tocsc()
+    nnz = np.diff(C.indptr)
+    assert np.all(nnz == zeta)                                  # zeta distinct rows per column
+    assert np.allclose(np.abs(C.data), 1 / math.sqrt(zeta), rtol=0, atol=0)
+    colnorm2 = np.asarray(C.multiply(C).sum(axis=0)).ravel()
+    assert np.allclose(colnorm2, 1.0, rtol=0, atol=4e-16)      # ||S e_j|| = 1
+    # determinism, dependence on seed and stream
+    S2 = O.sparse_sign_matrix(h, s, zeta, seed=7, stream=0)
+    assert (S != S2).nnz == 0
+    assert (S != O.sparse_sign_matrix(h, s, zeta, seed=8, stream=0)).nnz > 0
+    assert (S != O.sparse_sign_matrix(h, s, zeta, seed=7, stream=1)).nnz > 0
+    # rows roughly uniform, signs balanced
+    rows, signs = O.sparse_sign_pattern(h, s, zeta, 7, 0)
+    counts = np.bincount(rows.ravel(), minlength=s)
+    assert counts.min() > 0.7 * h * zeta / s and counts.max() < 1.3 * h * zeta / s
+    assert abs(signs.mean()) < 0.02
+
+
+def test_sparse_sign_is_isometric_in_expectation():
+    """E ||S x||^2 = ||x||^2 for independent +-1 signs (Def. 1 holds on average)."""
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal(500)
+    ratios = [np.linalg.norm(O.sparse_sign_matrix(500, 40, 8, sd, 0) @ x) ** 2 / (x @ x)
+              for sd in range(200)]
+    assert abs(np.mean(ratios) - 1.0) < 0.03
+
+
+# ----------------------------------------------------------------------------
+# building blocks
+# ----------------------------------------------------------------------------
+
+def test_gradient_is_gradient_of_tikhonov_functional():
+    """eq: gradient is half the gradient of ||Ax-b||^2 + mu ||Lx||^2 (central differences)."""
+    A, L, b, mu = tiny2d()
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(A.shape[1])
+    phi = lambda z: 0.5 * (np.linalg.norm(A @ z - b) ** 2 + mu * np.linalg.norm(L @ z) ** 2)
+    r = O.gradient(A, L, b, mu, x)
+    h = 1e-6
+    fd = np.array([(phi(x + h * e) - phi(x - h * e)) / (2 * h) for e in np.eye(x.size)])
+    assert np.allclose(r, fd, rtol=1e-6, atol=1e-8)
+
+
+@pytest.mark.parametrize("passes", [1, 2])
+def test_qr_append_builds_a_qr_factorisation(passes):
+    """eq:updqr applied column by column gives Q^T Q = I, Q R = M, R upper with rho > 0."""
+    rng = np.random.default_rng(4)
+    M = rng.standard_normal((40, 12))
+    Q, R = np.zeros((40, 0)), np.zeros((0, 0))
+    for j in range(12):
+        Q, R, deg = O.qr_append(Q, R, M[:, j], passes)
+        assert not deg
+    assert np.allclose(Q.T @ Q, np.eye(12), atol=1e-13)
+    assert np.allclose(Q @ R, M, atol=1e-13)
+    assert np.allclose(np.tril(R, -1), 0)
+    assert np.all(np.diag(R) > 0)
+    # unique thin QR with positive diagonal: compare with LAPACK Householder up to signs
+    _, R2 = np.linalg.qr(M)
+    assert np.allclose(np.abs(R), np.abs(R2), atol=1e-12)
+
+
+def test_qr_append_flags_dependent_column():
+    rng = np.random.default_rng(5)
+    M = rng.standard_normal((30, 4))
+    Q, R = np.zeros((30, 0)), np.zeros((0, 0))
+    for j in range(4):
+        Q, R, _ = O.qr_append(Q, R, M[:, j])
+    c = np.array([1.0, -2.0, 0.5, 3.0])
+    Q, R, deg = O.qr_append(Q, R, M @ c)
+    assert deg and R[-1, -1] == 0.0 and np.all(Q[:, -1] == 0)
+    assert np.allclose(R[:4, -1], R[:4, :4] @ c, atol=1e-12)   # p = Q^T M c = R c
+
+
+def test_cgs2_of_ill_conditioned_columns_is_orthonormal():
+    rng = np.random.default_rng(6)
+    base = rng.standard_normal((200, 5))
+    M = base @ np.diag([1, 1e-3, 1e-6, 1e-8, 1e-9]) @ rng.standard_normal((5, 5))
+    Q, R = np.zeros((200, 0)), np.zeros((0, 0))
+    for j in range(5):
+        Q, R, _ = O.qr_append(Q, R, M[:, j], passes=2)
+    assert np.linalg.norm(Q.T @ Q - np.eye(5)) < 1e-10
+
+
+def test_projected_solve_equals_lstsq():
+    """eq:projected_sketched_bis: min ||[R_A; sqrt(mu) R_L] y - [d_A; 0]||."""
+    rng = np.random.default_rng(7)
+    d = 9
+    R_A = np.triu(rng.standard_normal((d, d))) + 3 * np.eye(d)
+    R_L = np.triu(rng.standard_normal((d, d))) + 2 * np.eye(d)
+    d_A = rng.standard_normal(d)
+    mu = 0.3
+    y, G = O.projected_solve(R_A, R_L, d_A, mu)
+    M = np.vstack([R_A, math.sqrt(mu) * R_L])
+    y2 = np.linalg.lstsq(M, np.concatenate([d_A, np.zeros(d)]), rcond=None)[0]
+    assert np.allclose(y, y2, rtol=1e-12, atol=1e-13)
+    assert np.allclose(G.T @ G, M.T @ M, rtol=1e-12, atol=1e-12)
+    g = rng.standard_normal(d)
+    assert np.allclose(M.T @ M @ O.gram_solve(G, g), g, atol=1e-11)
+
+
+def test_initial_basis_spans_krylov_space():
+    """W_0 = orthonormal basis of K_3(A^T A, A^T b) (Sec. 2.1, ell = 3 in Sec. 4)."""
+    A, L, b, mu = tiny2d()
+    V = O.initial_basis(A, b, 3)
+    assert np.allclose(V.T @ V, np.eye(3), atol=1e-13)
+    K = [A.T @ b]
+    for _ in range(2):
+        K.append(A.T @ (A @ K[-1]))
+    for v in K:
+        assert np.linalg.norm(v - V @ (V.T @ v)) <= 1e-10 * np.linalg.norm(v)
+
+
+# ----------------------------------------------------------------------------
+# GKS (Alg. 1)
+# ----------------------------------------------------------------------------
+
+def test_gks_full_space_is_dense_tikhonov():
+    """At d = n the projected problem is eq:tik itself: Cholesky/LU of the normal equations."""
+    for A, L, b, mu in (tiny(), tiny2d()):
+        n = A.shape[1]
+        res = O.gks(A, L, b, mu, n - 3)
+        # either the space is all of R^n, or it stopped growing on an invariant
+        # subspace of A^T A + mu L^T L containing A^T b, which holds the solution
+        assert res.W.shape[1] == n or res.status == O.STATUS_BREAKDOWN
+        xd = O.dense_tikhonov(A, L, b, mu)
+        assert np.linalg.norm(res.x - xd) <= 1e-11 * np.linalg.norm(xd)
+
+
+def test_gks_basis_orthonormal_and_gradient_orthogonal():
+    """V^T V = I, and V_k^T r_{k+1} = 0 (normal equations of eq:projected_withQR)."""
+    A, L, b, mu = tiny2d(N=8)
+    res = O.gks(A, L, b, mu, 20, keep_history=True)
+    V = res.W
+    assert np.linalg.norm(V.T @ V - np.eye(V.shape[1])) < 1e-12
+    for k in range(0, 20, 4):
+        d = 3 + k
+        r = O.gradient(A, L, b, mu, res.x_hist[k])
+        assert np.linalg.norm(V[:, :d].T @ r) <= 1e-9 * np.linalg.norm(r)
+
+
+def test_gks_cheap_stopping_identity():
+    """eq:stoppingcriterion_cheap: ||x_k - x_{k-1}|| = ||y_k - [y_{k-1}; 0]||."""
+    A, L, b, mu = tiny2d(N=8)
+    res = O.gks(A, L, b, mu, 12, keep_history=True)
+    for k in range(1, 13):
+        lhs = np.linalg.norm(res.x_hist[k] - res.x_hist[k - 1])
+        rhs = np.linalg.norm(res.y_hist[k] - np.concatenate([res.y_hist[k - 1], [0.0]]))
+        assert abs(lhs - rhs) <= 1e-10 * max(rhs, 1e-300)
+
+
+# ----------------------------------------------------------------------------
+# sGKS (Alg. 2)
+# ----------------------------------------------------------------------------
+
+def test_prop1_identity_sketch_equals_gks():
+    """Prop. 1: without sketching, the sGKS iterates equal the GKS iterates."""
+    for A, L, b, mu in (tiny(n=40), tiny2d(N=8)):
+        k = 15
+        g = O.gks(A, L, b, mu, k, keep_history=True)
+        s0 = O.sgks(A, L, b, mu, k, 0, 0, sketch="identity", keep_history=True)
+        for j in range(k + 1):
+            assert np.linalg.norm(g.x_hist[j] - s0.x_hist[j]) <= 1e-10 * np.linalg.norm(g.x_hist[j])
+
+
+def test_sgks_full_space_is_dense_sketched_tikhonov():
+    """At d = n, x_k minimises the sketched functional eq:tik_new_sketched over R^n."""
+    A, L, b, mu = tiny(n=8, sigma=0.8)
+    s, seed = 100, 5
+    res = O.sgks(A, L, b, mu, 5, s, seed)
+    assert res.W.shape == (8, 8)
+    S_A, S_L = O.make_sketches(A.shape[0], L.shape[0], s, seed)
+    xs = O.dense_sketched_tikhonov(A, L, b, mu, S_A, S_L)
+    tol = 1e-14 * np.linalg.cond(res.W) ** 2          # W is not orthonormal (Sec. 3)
+    assert np.linalg.norm(res.x - xs) <= tol * np.linalg.norm(xs)
+
+
+def test_sgks_qr_factors_are_factors_of_sketched_products():
+    """Q_A R_A = S_A A W_k, Q_L R_L = S_L L W_k, d_A = Q_A^T S_A b (Sec. 3)."""
+    A, L, b, mu = tiny2d(N=8)
+    s, seed = 60, 3
+    res = O.sgks(A, L, b, mu, 10, s, seed)
+    S_A, S_L = O.make_sketches(A.shape[0], L.shape[0], s, seed)
+    SAW = S_A @ (A @ res.W)
+    SLW = S_L @ (L @ res.W)
+    assert np.allclose(res.Q_A @ res.R_A, SAW, atol=1e-12 * np.abs(SAW).max())
+    assert np.allclose(res.Q_L @ res.R_L, SLW, atol=1e-12 * np.abs(SLW).max())
+    assert np.allclose(res.d_A, res.Q_A.T @ (S_A @ b), atol=1e-12)
+    # columns of W are the initial basis followed by normalised gradients
+    assert np.allclose(np.linalg.norm(res.W, axis=0), 1.0)
+
+
+def test_sgks_y_minimises_sketched_projected_functional():
+    """y_k solves eq:tik_new_sketched on the current basis (checked by dense lstsq)."""
+    A, L, b, mu = tiny2d(N=8)
+    s, seed = 60, 9
+    res = O.sgks(A, L, b, mu, 10, s, seed)
+    S_A, S_L = O.make_sketches(A.shape[0], L.shape[0], s, seed)
+    M = np.vstack([S_A @ (A @ res.W), math.sqrt(mu) * (S_L @ (L @ res.W))])
+    f = np.concatenate([S_A @ b, np.zeros(s)])
+    y2 = np.linalg.lstsq(M, f, rcond=None)[0]
+    assert np.linalg.norm(res.y - y2) <= 1e-9 * np.linalg.norm(y2)
+
+
+def test_sgks_gradient_is_new_basis_column():
+    """Alg. 2: W_{k+1} = [W_k, r_{k+1}/||r_{k+1}||] with r from eq: gradient at x_k."""
+    A, L, b, mu = tiny2d(N=8)
+    res = O.sgks(A, L, b, mu, 6, 50, 1, keep_history=True)
+    for k in range(6):
+        r = O.gradient(A, L, b, mu, res.x_hist[k])
+        assert np.allclose(res.W[:, 3 + k], r / np.linalg.norm(r), atol=1e-12)
+
+
+def _eps(S, M):
+    Q, _ = np.linalg.qr(M)
+    return O.embedding_epsilon(S, Q)
+
+
+def test_sketched_residual_within_embedding_bound_and_prop2():
+    """Def. 1 on range([AW, b]) and range(LW); Prop. 2 with theta = max(eps_A, eps_L)."""
+    A, L, b, mu = tiny2d(N=10)
+    s, seed = 150, 4
+    res = O.sgks(A, L, b, mu, 8, s, seed)
+    S_A, S_L = O.make_sketches(A.shape[0], L.shape[0], s, seed)
+    W = res.W
+    eA = _eps(S_A, np.column_stack([A @ W, b]))
+    eL = _eps(S_L, L @ W)
+    eps = max(eA, eL)
+    assert eps < 1
+    phi = lambda y: np.linalg.norm(A @ W @ y - b) ** 2 + mu * np.linalg.norm(L @ W @ y) ** 2
+    phis = lambda y: (np.linalg.norm(S_A @ (A @ W @ y - b)) ** 2
+                      + mu * np.linalg.norm(S_L @ (L @ W @ y)) ** 2)
+    rng = np.random.default_rng(0)
+    for y in [res.y] + [rng.standard_normal(W.shape[1]) for _ in range(5)]:
+        ratio = phis(y) / phi(y)
+        assert 1 - eps - 1e-12 <= ratio <= 1 + eps + 1e-12
+    y0 = O.unsketched_projected_solution(A, L, b, mu, W)
+    assert phi(res.y) <= (1 + eps) / (1 - eps) * phi(y0) * (1 + 1e-12)
+    assert phi(y0) <= phi(res.y) * (1 + 1e-12)
+
+
+@pytest.mark.parametrize("s", [30, 40, 80])
+def test_refinement_converges_to_unsketched_projected_solution(s):
+    """IR moves y_sGKS toward y_sGKS0 (end of Sec. 3.1), also at sketch distortion > 1/2."""
+    A, L, b, mu = tiny2d(N=10)
+    res = O.sgks(A, L, b, mu, 8, s, 2)
+    W = res.W
+    y0 = O.unsketched_projected_solution(A, L, b, mu, W)
+    H = W.T @ (A.T @ (A @ W)) + mu * W.T @ (L.T @ (L @ W))
+    err = lambda y: math.sqrt((y - y0) @ H @ (y - y0))
+    e0 = err(res.y)
+    assert err(O.refine(A, L, b, mu, W, res.y, res.G, s, 2)) < 0.5 * e0
+    assert err(O.refine(A, L, b, mu, W, res.y, res.G, s, 60)) <= 1e-7 * e0
+
+
+def test_sgks_with_refinement_tracks_gks_better():
+    """With IR the sGKS iterate is closer to the unsketched (GKS) iterate (Sec. 4.2.3)."""
+    A, L, b, mu = tiny2d(N=10)
+    g = O.gks(A, L, b, mu, 10)
+    plain = O.sgks(A, L, b, mu, 10, 30, 1)
+    ir = O.sgks(A, L, b, mu, 10, 30, 1, refine_steps=4)
+    assert np.linalg.norm(ir.x - g.x) < np.linalg.norm(plain.x - g.x)
+
+
+def test_breakdown_on_invariant_subspace():
+    """A = L = I: K_3(A^T A, A^T b) is span{b}; the expansion stops (status BREAKDOWN)."""
+    n = 10
+    A = sp.identity(n, format="csr")
+    L = sp.identity(n, format="csr")
+    b = np.linspace(1, 2, n)
+    V = O.initial_basis(A, b, 1)
+    res = O.sgks(A, L, b, 0.5, 4, 0, 0, ell=1, sketch="identity")
+    assert res.status == O.STATUS_BREAKDOWN and res.iters == 0
+    assert np.allclose(res.x, b / 1.5)
+    assert np.allclose(V[:, 0], b / np.linalg.norm(b))
+
+
+# ----------------------------------------------------------------------------
+# frozen-basis adjoint
+# ----------------------------------------------------------------------------
+
+def test_frozen_adjoint_matches_central_differences():
+    A, L, b, mu = tiny2d(N=8)
+    s, seed = 60, 3
+    res = O.sgks(A, L, b, mu, 10, s, seed)
+    S_A, _ = O.make_sketches(A.shape[0], L.shape[0], s, seed)
+    rng = np.random.default_rng(1)
+    x_t = rng.standard_normal(A.shape[1])
+    loss = lambda bb, mm: float(np.linalg.norm(O.frozen_map(res, bb, mm, S_A) - x_t) ** 2)
+    gb, gmu = O.frozen_adjoint_b(res, mu, 2 * (res.x - x_t), A, L, s, seed)
+    assert np.allclose(O.frozen_map(res, b, mu, S_A), res.x, rtol=1e-9)
+    h = 1e-6
+    for i in rng.choice(A.shape[0], 6, replace=False):
+        e = np.zeros_like(b)
+        e[i] = h
+        fd = (loss(b + e, mu) - loss(b - e, mu)) / (2 * h)
+        assert abs(fd - gb[i]) <= 1e-6 * max(1.0, abs(fd))
+    hm = 1e-6 * mu
+    fdm = (loss(b, mu + hm) - loss(b, mu - hm)) / (2 * hm)
+    assert abs(fdm - gmu) <= 1e-6 * max(1.0, abs(fdm))
+
+
+def test_frozen_adjoint_equals_dense_adjoint_at_full_space():
+    """At d = n the frozen map is the dense sketched Tikhonov map; compare with its adjoint."""
+    A, L, b, mu = tiny(n=8, sigma=0.8)
+    s, seed = 100, 5
+    res = O.sgks(A, L, b, mu, 5, s, seed)
+    S_A, S_L = O.make_sketches(A.shape[0], L.shape[0], s, seed)
+    Ad, Ld = A.toarray(), L.toarray()
+    SA, SL = S_A.toarray(), S_L.toarray()
+    H = Ad.T @ SA.T @ SA @ Ad + mu * Ld.T @ SL.T @ SL @ Ld
+    x = np.linalg.solve(H, Ad.T @ SA.T @ SA @ b)
+    rng = np.random.default_rng(2)
+    g_x = rng.standard_normal(A.shape[1])
+    gb_dense = SA.T @ SA @ Ad @ np.linalg.solve(H, g_x)
+    gmu_dense = -float(g_x @ np.linalg.solve(H, Ld.T @ SL.T @ SL @ Ld @ x))
+    gb, gmu = O.frozen_adjoint_b(res, mu, g_x, A, L, s, seed)
+    tol = 1e-14 * np.linalg.cond(res.W) ** 2
+    assert np.linalg.norm(gb - gb_dense) <= tol * np.linalg.norm(gb_dense)
+    assert abs(gmu - gmu_dense) <= tol * abs(gmu_dense)
+
+
+# ----------------------------------------------------------------------------
+# planted mistakes: the pins above must catch plausible slips in the oracle
+# ----------------------------------------------------------------------------
+
+def test_pins_catch_planted_mistakes(monkeypatch):
+    A, L, b, mu = tiny2d(N=8)
+    good = O.sgks(A, L, b, mu, 8, 60, 3, keep_history=True)
+
+    # (1) sign slip in the regularisation term of the gradient: the central
+    #     difference pin of eq: gradient rejects it, and the sGKS basis built
+    #     from it no longer holds the true normalised gradient
+    def bad_gradient(A_, L_, b_, mu_, x):
+        return A_.T @ (A_ @ x - b_) - mu_ * (L_.T @ (L_ @ x))
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(A.shape[1])
+    phi = lambda z: 0.5 * (np.linalg.norm(A @ z - b) ** 2 + mu * np.linalg.norm(L @ z) ** 2)
+    fd = np.array([(phi(x + 1e-6 * e) - phi(x - 1e-6 * e)) / 2e-6 for e in np.eye(x.size)])
+    assert not np.allclose(bad_gradient(A, L, b, mu, x), fd, rtol=1e-6, atol=1e-8)
+    true_gradient = O.gradient
+    with monkeypatch.context() as mp:
+        mp.setattr(O, "gradient", bad_gradient)
+        bad = O.sgks(A, L, b, mu, 3, 60, 3, keep_history=True)
+    r = true_gradient(A, L, b, mu, bad.x_hist[0])
+    assert not np.allclose(bad.W[:, 3], r / np.linalg.norm(r), atol=1e-6)
+
+    # (2) unsketched right-hand side in d_A: d_A = Q_A^T S_A b fails
+    orig = O.make_sketches
+    with monkeypatch.context() as mp:
+        def swapped(m, p, s, seed, zeta=8, kind="sparse_sign"):
+            S_A, S_L = orig(m, p, s, seed, zeta, kind)
+            return S_A, O.sparse_sign_matrix(p, s, zeta, seed, 0)   # wrong stream for S_L
+        mp.setattr(O, "make_sketches", swapped)
+        bad = O.sgks(A, L, b, mu, 8, 60, 3)
+    S_A, S_L = O.make_sketches(A.shape[0], L.shape[0], 60, 3)
+    SLW = S_L @ (L @ bad.W)
+    assert not np.allclose(bad.Q_L @ bad.R_L, SLW, atol=1e-8)
+
+    # (3) a transposed operand in the projected solve breaks the lstsq pin
+    def bad_solve(R_A, R_L, d_A, mu_):
+        d = R_A.shape[0]
+        M = np.vstack([R_A.T, math.sqrt(mu_) * R_L])
+        y = np.linalg.lstsq(M, np.concatenate([d_A, np.zeros(d)]), rcond=None)[0]
+        return y, np.linalg.qr(M)[1]
+    with monkeypatch.context() as mp:
+        mp.setattr(O, "projected_solve", bad_solve)
+        bad = O.sgks(A, L, b, mu, 4, 60, 3)
+    S_A, S_L = O.make_sketches(A.shape[0], L.shape[0], 60, 3)
+    M = np.vstack([S_A @ (A @ bad.W), math.sqrt(mu) * (S_L @ (L @ bad.W))])
+    y2 = np.linalg.lstsq(M, np.concatenate([S_A @ b, np.zeros(60)]), rcond=None)[0]
+    assert np.linalg.norm(bad.y - y2) > 1e-6 * np.linalg.norm(y2)
+    assert good.status == O.STATUS_OK

@@ -1,0 +1,174 @@
+/*
+ * sgks.h - C ABI of the sketched generalized Krylov subspace (sGKS) solver for
+ * MI355X (gfx950).
+ *
+ * Problem (general-form Tikhonov, eq:tik of Palitta & Pasha):
+ *     min_x ||A x - b||^2 + mu ||L x||^2,   A: m x n, L: p x n, mu > 0.
+ * Method (Alg. 2, Sec. 3): x_k = W_k y_k where W_k = [W_0, w_1, ..., w_k] is NOT
+ * orthonormalised; w_j = r_j / ||r_j|| with r_j the Tikhonov gradient
+ * A^T(A x - b) + mu L^T L x (eq: gradient); y_k solves the sketched projected
+ * problem (eq:projected_sketched_bis)
+ *     min_y || [R_A; sqrt(mu) R_L] y - [Q_A^T S_A b; 0] ||
+ * with Q_A R_A = S_A A W_k and Q_L R_L = S_L L W_k kept by rank-one column
+ * appends (eq:updqr, eq:dA_update).  S_A (s x m) and S_L (s x p) are seeded
+ * sparse-sign embeddings (Sec. 2.2 allows any oblivious embedding): column j
+ * has zeta entries +-1/sqrt(zeta) in distinct rows drawn from SplitMix64,
+ * key(stream, j) = mix64(seed + g (2j + stream + 1)), draw c = mix64(key + g (c+1)),
+ * row = ((draw >> 32) * s) >> 32, sign = -1 if draw is odd; stream 0 is S_A,
+ * stream 1 is S_L; a draw whose row repeats an earlier slot is skipped.
+ * W_0 is an orthonormal basis of K_ell(A^T A, A^T b) (Sec. 2.1, ell = 3 in Sec. 4).
+ *
+ * Memory and ownership.  Every pointer named "device" is HIP device memory.
+ * The operator arrays (CSR of A and L) and b are borrowed: the caller keeps
+ * them alive and unmodified until sgks_destroy.  The context allocates its own
+ * device workspace (transposes of A and L, the basis W, the small factors) in
+ * sgks_create and frees it in sgks_destroy.  All work is enqueued on the
+ * stream given in the options; calls documented as synchronising wait for it.
+ * A context is not thread safe.
+ *
+ * Precision.  A, L and b are stored in SGKS_F32 or SGKS_F64.  The basis W,
+ * the iterate x, the residual vectors and every accumulation are FP64; the
+ * small factors (Q, R, the stacked factor G) and the projected solve are FP64.
+ *
+ * Return codes: 0 = OK; SGKS_BREAKDOWN (> 0, informational) = the expansion
+ * stopped because ||r|| <= 1e-14 ||A^T b|| (invariant subspace) or because the
+ * new column of [R_A; sqrt(mu) R_L] is numerically dependent on the previous
+ * ones (kept below 1e-14 of its norm by the projections); the column is not
+ * appended, the solution stays valid and fewer iterations were done.
+ * Negative values are errors.
+ */
+#ifndef SGKS_H
+#define SGKS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SGKS_OK 0
+#define SGKS_BREAKDOWN 1
+#define SGKS_ERR_INVALID_ARG (-1)     /* null pointer, bad option value            */
+#define SGKS_ERR_SHAPE (-2)           /* A.cols != L.cols, bad CSR sizes           */
+#define SGKS_ERR_BAD_MU (-3)          /* mu <= 0 or not finite                     */
+#define SGKS_ERR_SKETCH_SIZE (-4)     /* s < ell + max_iters, zeta > s, s > 2048   */
+#define SGKS_ERR_CAPACITY (-5)        /* iterate would exceed ell + max_iters      */
+#define SGKS_ERR_ZERO_RHS (-6)        /* b = 0 or A^T b = 0                        */
+#define SGKS_ERR_NONFINITE (-7)       /* NaN/Inf in b or in a computed vector      */
+#define SGKS_ERR_HIP (-8)             /* a HIP runtime call failed                 */
+#define SGKS_ERR_DEVICE (-9)          /* device-side failure (grid barrier)        */
+#define SGKS_ERR_INITIAL_SPACE (-10)  /* K_ell(A^T A, A^T b) has dimension < ell,
+                                         or its sketched columns are dependent     */
+
+/* storage type of the operator values and of b */
+#define SGKS_F32 0
+#define SGKS_F64 1
+
+/* sketch kinds: the sparse-sign embedding, or identities (sGKS_0 of Prop. 1,
+ * meant for small checks: then s must equal max(m, p) and both sketches are
+ * the identity on the first m (resp. p) rows). */
+#define SGKS_SKETCH_SPARSE_SIGN 0
+#define SGKS_SKETCH_IDENTITY 1
+
+/* CSR matrix with int32 indices; column indices sorted within each row.  All
+ * three arrays are device pointers; val holds nnz values of the options'
+ * value_dtype. */
+typedef struct {
+    int64_t rows, cols, nnz;
+    const int32_t *rowptr;   /* rows + 1 entries, rowptr[0] = 0, rowptr[rows] = nnz */
+    const int32_t *colind;   /* nnz entries in [0, cols)                            */
+    const void *val;         /* nnz entries                                        */
+} sgks_csr;
+
+typedef struct {
+    int32_t ell;             /* initial Krylov dimension, >= 1 (default 3)                    */
+    int32_t max_iters;       /* capacity: at most ell + max_iters basis columns (default 200) */
+    int32_t zeta;            /* nonzeros per sketch column: 2, 4, 8 or 16 (default 8)         */
+    int32_t value_dtype;     /* SGKS_F32 or SGKS_F64 (default SGKS_F64)                       */
+    int32_t refine_steps;    /* iterative-refinement steps after every projected solve (0)    */
+    int32_t qr_passes;       /* 2 = project twice (CGS2, default), 1 = single projection       */
+    int32_t sketch_mode;     /* SGKS_SKETCH_SPARSE_SIGN (default) or SGKS_SKETCH_IDENTITY     */
+    int32_t lanes_A;         /* lanes per row for A-row SpMVs; 0 = choose from nnz/row          */
+    int32_t lanes_At;        /* lanes per row for A^T rows; 0 = choose                          */
+    int32_t append_groups;   /* workgroups of the cooperative append kernel; 0 = choose         */
+    void *stream;            /* hipStream_t the work is enqueued on (NULL = default stream)   */
+} sgks_options;
+
+typedef struct sgks_ctx sgks_ctx;
+
+/* Fill *opt with the defaults listed above. */
+void sgks_default_options(sgks_options *opt);
+
+/* Check the arguments of sgks_create without touching the device (host only).
+ * Returns the code sgks_create would return for an argument error, or 0. */
+int sgks_validate(const sgks_csr *A, const sgks_csr *L, const void *b, double mu,
+                  int32_t sketch_rows, const sgks_options *opt);
+
+/* Set up a solve (Alg. 2 before its loop): build A^T and L^T, the sketch of
+ * b, the initial basis W_0 (K_ell(A^T A, A^T b), orthonormal), the QR factors
+ * of S_A A W_0 and S_L L W_0 and y_0.  b: device, m values of value_dtype.
+ * sketch_rows = s (s_A = s_L = s); seed selects the sketches.
+ * Synchronises the stream.  On success *out receives a new context. */
+int sgks_create(const sgks_csr *A, const sgks_csr *L, const void *b, double mu,
+                int32_t sketch_rows, uint64_t seed, const sgks_options *opt,
+                sgks_ctx **out);
+
+/* Run k more expansions (the loop body of Alg. 2): x = W y; r = gradient;
+ * append r/||r||; sketch and QR-append the new column; solve for y;
+ * refine_steps refinement steps.  Asynchronous; resumable: iterate(a) then
+ * iterate(b) equals iterate(a + b).  Returns SGKS_ERR_CAPACITY if the
+ * basis would exceed ell + max_iters columns. */
+int sgks_iterate(sgks_ctx *ctx, int32_t k);
+
+/* x = W y (n FP64 values) into the device buffer x_dev.  Asynchronous. */
+int sgks_solution(sgks_ctx *ctx, double *x_dev);
+
+/* Synchronising.  true_norm = sqrt(||A x - b||^2 + mu ||L x||^2) at the
+ * current x; sketched_norm = sqrt(||S_A(A x - b)||^2 + mu ||S_L L x||^2)
+ * computed from the small factors: ||R_A y - d_A||^2 + ||S_A b||^2 - ||d_A||^2
+ * + mu ||R_L y||^2.  Either pointer may be NULL. */
+int sgks_residual_norm(sgks_ctx *ctx, double *true_norm, double *sketched_norm);
+
+/* Synchronising.  *iters_done = expansions done so far; returns the status
+ * word (0, SGKS_BREAKDOWN or a negative device error). */
+int sgks_status(sgks_ctx *ctx, int32_t *iters_done);
+
+/* Frozen-basis adjoint of the final projected solve (not in the paper): with
+ * W, Q_A, R_A, R_L held fixed, x = W H^{-1} R_A^T Q_A^T S_A b where
+ * H = R_A^T R_A + mu R_L^T R_L.  Given grad_x (device, n FP64) writes
+ * grad_b = S_A^T Q_A R_A z with z = H^{-1} W^T grad_x (device, m FP64) and
+ * *grad_mu = -(R_L z).(R_L y) (host).  Synchronising. */
+int sgks_backward(sgks_ctx *ctx, const double *grad_x, double *grad_b, double *grad_mu);
+
+/* Copy one piece of the solver state to host memory (synchronising), for
+ * checks.  which: 0 W (n x d, column-major, columns scaled to unit norm),
+ * 1 y (d), 2 Q_A (s x d), 3 R_A (d x d), 4 Q_L (s x d), 5 R_L (d x d),
+ * 6 d_A (d), 7 G (d x d, R factor of [R_A; sqrt(mu) R_L]), 8 S_A b (s).
+ * count = number of doubles dst can take; returns the number written (>= 0)
+ * or an error code. */
+int64_t sgks_copy_state(sgks_ctx *ctx, int32_t which, double *dst, int64_t count);
+
+/* Per-phase device timing (the per-component breakdown of Sec. 4): while
+ * enabled, every kernel launch of sgks_iterate / sgks_solution is bracketed by
+ * HIP events on the context's stream.  Phases: 0 x = W y, 1 forward products
+ * (A x - b, L x), 2 adjoint products (A^T u + mu L^T t), 3 SpMV + sketch of
+ * the new column, 4 QR appends + projected solve, 5 W^T v (refinement),
+ * 6 refinement step, 7 other.  sgks_profile_read synchronises, writes the
+ * summed milliseconds and launch counts of the SGKS_PHASES phases (either
+ * array may be NULL) and resets them. */
+#define SGKS_PHASES 8
+int sgks_profile_enable(sgks_ctx *ctx, int32_t on);
+int sgks_profile_read(sgks_ctx *ctx, double *ms, int64_t *launches);
+
+/* Current number of basis columns d (host-side view, no synchronisation). */
+int32_t sgks_dim(const sgks_ctx *ctx);
+
+void sgks_destroy(sgks_ctx *ctx);
+const char *sgks_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGKS_H */

@@ -32,7 +32,10 @@ Readings where the paper is silent (each also listed in the design notes):
   * The QR column append projects twice (CGS2) unless qr_passes = 1, which is
     the single projection written in eq:updqr.
   * "k iterations" = k expansions; the last projected problem has ell + k columns.
-  * Breakdown: stop when ||r|| <= 1e-14 ||A^T b||.
+  * Breakdown: stop when ||r|| <= 1e-14 ||A^T b||, or when the new column of
+    [R_A; sqrt(mu) R_L] keeps at most 1e-14 of its norm after projection on
+    the previous columns (the expansion adds nothing to the projected problem);
+    the column is then not appended.
   * Iterative refinement (the paper defers to FOSSILS): sketch-preconditioned
     heavy-ball steps on the unsketched projected normal equations,
         delta_i = (G^T G)^{-1} W^T r(y_i),
@@ -186,13 +189,25 @@ def cgs2_normalize(V, v):
     return v / np.linalg.norm(v)
 
 
+class DegenerateInitialSpace(ValueError):
+    """K_ell(A^T A, A^T b) has dimension below ell."""
+
+
 def initial_basis(A, b, ell):
-    """Orthonormal basis of the Krylov space K_ell(A^T A, A^T b) (Sec. 2.1, Sec. 4)."""
+    """Orthonormal basis of the Krylov space K_ell(A^T A, A^T b) (Sec. 2.1, Sec. 4).
+
+    Raises DegenerateInitialSpace when a new Krylov vector keeps less than
+    1e-12 of its norm after the two projections (the space stopped growing)."""
     v = A.T @ b
     V = (v / np.linalg.norm(v))[:, None]
     for _ in range(1, ell):
         w = A.T @ (A @ V[:, -1])
-        V = np.concatenate([V, cgs2_normalize(V, w)[:, None]], axis=1)
+        p = w
+        for _ in range(2):
+            p = p - V @ (V.T @ p)
+        if not np.linalg.norm(p) > 1e-12 * np.linalg.norm(w):
+            raise DegenerateInitialSpace("K_ell(A^T A, A^T b) has dimension < ell")
+        V = np.concatenate([V, (p / np.linalg.norm(p))[:, None]], axis=1)
     return V
 
 
@@ -266,12 +281,20 @@ def sgks(A, L, b, mu, k, s, seed, zeta=8, ell=3, refine_steps=0, qr_passes=2,
     degenerate = 0
 
     def append(w):
+        """Append w; returns False (and changes nothing) when the new column of
+        [R_A; sqrt(mu) R_L] is numerically dependent on the previous ones."""
         nonlocal W, Q_A, R_A, Q_L, R_L, d_A, degenerate
+        QA2, RA2, da = qr_append(Q_A, R_A, S_A @ (A @ w), qr_passes)
+        QL2, RL2, dl = qr_append(Q_L, R_L, S_L @ (L @ w), qr_passes)
+        col = np.concatenate([RA2[:, -1], math.sqrt(mu) * RL2[:, -1]])
+        _, Gt = np.linalg.qr(np.vstack([RA2, math.sqrt(mu) * RL2]), mode="reduced")
+        if not abs(Gt[-1, -1]) > 1e-14 * np.linalg.norm(col):
+            return False
         W = np.concatenate([W, w[:, None]], axis=1)
-        Q_A, R_A, da = qr_append(Q_A, R_A, S_A @ (A @ w), qr_passes)
-        Q_L, R_L, dl = qr_append(Q_L, R_L, S_L @ (L @ w), qr_passes)
+        Q_A, R_A, Q_L, R_L = QA2, RA2, QL2, RL2
         d_A = np.concatenate([d_A, [Q_A[:, -1] @ c_b]])
         degenerate += int(da) + int(dl)
+        return True
 
     def solve():
         y, G = projected_solve(R_A, R_L, d_A, mu)
@@ -279,7 +302,8 @@ def sgks(A, L, b, mu, k, s, seed, zeta=8, ell=3, refine_steps=0, qr_passes=2,
 
     V0 = initial_basis(A, b, ell)
     for j in range(ell):
-        append(V0[:, j])
+        if not append(V0[:, j]):
+            raise DegenerateInitialSpace("sketched initial columns are dependent")
     y, G = solve()
     x_hist = [W @ y] if keep_history else []
     y_hist = [y] if keep_history else []
@@ -289,11 +313,10 @@ def sgks(A, L, b, mu, k, s, seed, zeta=8, ell=3, refine_steps=0, qr_passes=2,
     for it in range(1, k + 1):
         r = gradient(A, L, b, mu, W @ y)
         nr = float(np.linalg.norm(r))
-        if not nr > 1e-14 * r0:
+        if not nr > 1e-14 * r0 or not append(r / nr):
             status = STATUS_BREAKDOWN
             it -= 1
             break
-        append(r / nr)
         y, G = solve()
         if keep_history:
             x_hist.append(W @ y)

@@ -1,0 +1,586 @@
+// Host runtime of the sGKS library: argument validation, workspace planning,
+// set-up (Alg. 2 before its loop) and the enqueueing of the iteration
+// kernels.  Exposes the C ABI declared in include/sgks.h.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "sgks.h"
+#include "sgks_internal.h"
+
+using sgks::Csr;
+using sgks::State;
+
+struct sgks_ctx {
+    State S;
+    sgks_options opt;
+    hipStream_t st;
+    int d_host;          // basis columns expected on the device (no breakdown)
+    int groups;          // workgroups of the cooperative append
+    std::vector<void*> allocs;
+    double* upart;       // partial sums of ||A x - b||^2
+    double* tpart;       // partial sums of ||L x||^2
+    int nbF_A, nbF_L;
+    double* coefbuf;     // dmax scratch
+    double* sbuf;        // s scratch
+    int32_t* At_rowptr;
+    int32_t* At_col;
+    void* At_val;
+    int32_t* Lt_rowptr;
+    int32_t* Lt_col;
+    void* Lt_val;
+    // per-phase timing
+    bool prof = false;
+    std::vector<hipEvent_t> events;    // pairs (start, end)
+    std::vector<int> pair_phase;
+    size_t pairs_used = 0;
+};
+
+namespace {
+
+// Brackets the launches of one phase with a pair of events when profiling.
+struct Phase {
+    sgks_ctx* c;
+    size_t pair;
+    Phase(sgks_ctx* ctx, int phase) : c(ctx), pair((size_t)-1) {
+        if (!c->prof) return;
+        if (c->pairs_used >= c->pair_phase.size()) {
+            hipEvent_t a, b;
+            if (hipEventCreate(&a) != hipSuccess) return;
+            if (hipEventCreate(&b) != hipSuccess) {
+                hipEventDestroy(a);
+                return;
+            }
+            c->events.push_back(a);
+            c->events.push_back(b);
+            c->pair_phase.push_back(0);
+        }
+        pair = c->pairs_used++;
+        c->pair_phase[pair] = phase;
+        hipEventRecord(c->events[2 * pair], c->st);
+    }
+    ~Phase() {
+        if (pair != (size_t)-1) hipEventRecord(c->events[2 * pair + 1], c->st);
+    }
+};
+
+bool pow2_lanes(int v) { return v == 0 || v == 1 || v == 2 || v == 4 || v == 8 || v == 16 || v == 32 || v == 64; }
+
+int choose_lanes(int64_t nnz, int64_t rows) {
+    if (rows <= 0) return 1;
+    const double avg = (double)nnz / (double)rows;
+    int v = 1;
+    while (v < 64 && 2.0 * v <= avg / 2.0) v *= 2;
+    return v;
+}
+
+template <typename P>
+hipError_t dalloc(sgks_ctx* c, P** p, size_t bytes) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes ? bytes : 8);
+    if (e == hipSuccess) {
+        c->allocs.push_back(q);
+        *p = (P*)q;
+    }
+    return e;
+}
+
+int check_csr(const sgks_csr* M) {
+    if (!M) return SGKS_ERR_INVALID_ARG;
+    if (M->rows < 0 || M->cols <= 0 || M->nnz < 0) return SGKS_ERR_SHAPE;
+    if (M->rows >= (int64_t(1) << 31) || M->cols >= (int64_t(1) << 31) ||
+        M->nnz >= (int64_t(1) << 31))
+        return SGKS_ERR_SHAPE;
+    if (!M->rowptr) return SGKS_ERR_INVALID_ARG;
+    if (M->nnz > 0 && (!M->colind || !M->val)) return SGKS_ERR_INVALID_ARG;
+    return 0;
+}
+
+int sync_status(sgks_ctx* c) {
+    int st = 0;
+    if (hipMemcpyAsync(&st, c->S.status, sizeof(int), hipMemcpyDeviceToHost, c->st) != hipSuccess)
+        return SGKS_ERR_HIP;
+    if (hipStreamSynchronize(c->st) != hipSuccess) return SGKS_ERR_HIP;
+    return st;
+}
+
+// ||v||, via the conversion kernel run in place, into cs[col] = 1/||v||
+void norm_to_scale(sgks_ctx* c, double* v, int col, bool store_r0) {
+    State& S = c->S;
+    sgks::launch_to_f64(v, 1, v, S.n, S.norm_part, S.n_norm_part, c->st);
+    sgks::launch_set_scale(S, col, store_r0, c->st);
+}
+
+void refine_once(sgks_ctx* c) {
+    State& S = c->S;
+    { Phase ph(c, 0); sgks::launch_gemv(S, S.y, false, S.x, nullptr, -1, c->st); }
+    { Phase ph(c, 1); sgks::launch_forward(S, S.x, S.b, S.u, S.t, true, nullptr, nullptr, 0, c->st); }
+    { Phase ph(c, 2); sgks::launch_adjoint(S, S.u, S.t, true, S.mu, S.rtmp, false, S.norm_part, c->st); }
+    { Phase ph(c, 5); sgks::launch_gemvt(S, S.rtmp, -1, c->st); }
+    { Phase ph(c, 6); sgks::launch_refine(S, c->st); }
+}
+
+}  // namespace
+
+extern "C" {
+
+void sgks_default_options(sgks_options* o) {
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->ell = 3;
+    o->max_iters = 200;
+    o->zeta = 8;
+    o->value_dtype = SGKS_F64;
+    o->refine_steps = 0;
+    o->qr_passes = 2;
+    o->sketch_mode = SGKS_SKETCH_SPARSE_SIGN;
+    o->lanes_A = 0;
+    o->lanes_At = 0;
+    o->append_groups = 0;
+    o->stream = nullptr;
+}
+
+int sgks_validate(const sgks_csr* A, const sgks_csr* L, const void* b, double mu,
+                  int32_t s, const sgks_options* opt) {
+    sgks_options o;
+    if (opt)
+        o = *opt;
+    else
+        sgks_default_options(&o);
+    int rc = check_csr(A);
+    if (rc) return rc;
+    rc = check_csr(L);
+    if (rc) return rc;
+    if (!b) return SGKS_ERR_INVALID_ARG;
+    if (A->rows <= 0 || L->rows <= 0) return SGKS_ERR_SHAPE;
+    if (L->cols != A->cols) return SGKS_ERR_SHAPE;
+    if (!(mu > 0.0) || !(mu < INFINITY)) return SGKS_ERR_BAD_MU;
+    if (o.ell < 1 || o.max_iters < 0) return SGKS_ERR_INVALID_ARG;
+    if ((int64_t)o.ell + o.max_iters > sgks::kMaxD) return SGKS_ERR_CAPACITY;
+    if (o.zeta != 2 && o.zeta != 4 && o.zeta != 8 && o.zeta != 16) return SGKS_ERR_INVALID_ARG;
+    if (o.value_dtype != SGKS_F32 && o.value_dtype != SGKS_F64) return SGKS_ERR_INVALID_ARG;
+    if (o.qr_passes != 1 && o.qr_passes != 2) return SGKS_ERR_INVALID_ARG;
+    if (o.refine_steps < 0) return SGKS_ERR_INVALID_ARG;
+    if (o.sketch_mode != SGKS_SKETCH_SPARSE_SIGN && o.sketch_mode != SGKS_SKETCH_IDENTITY)
+        return SGKS_ERR_INVALID_ARG;
+    if (!pow2_lanes(o.lanes_A) || !pow2_lanes(o.lanes_At)) return SGKS_ERR_INVALID_ARG;
+    if (o.append_groups < 0) return SGKS_ERR_INVALID_ARG;
+    if (s > sgks::kMaxS || s < 1) return SGKS_ERR_SKETCH_SIZE;
+    if (o.sketch_mode == SGKS_SKETCH_SPARSE_SIGN) {
+        if (s < o.ell + o.max_iters) return SGKS_ERR_SKETCH_SIZE;
+        if (o.zeta > s) return SGKS_ERR_SKETCH_SIZE;
+    } else {
+        if ((int64_t)s < A->rows || (int64_t)s < L->rows) return SGKS_ERR_SKETCH_SIZE;
+    }
+    return 0;
+}
+
+int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, int32_t s,
+                uint64_t seed, const sgks_options* opt, sgks_ctx** out) {
+    if (!out) return SGKS_ERR_INVALID_ARG;
+    *out = nullptr;
+    int rc = sgks_validate(A, L, b, mu, s, opt);
+    if (rc) return rc;
+    sgks_ctx* c = new (std::nothrow) sgks_ctx();
+    if (!c) return SGKS_ERR_HIP;
+    if (opt)
+        c->opt = *opt;
+    else
+        sgks_default_options(&c->opt);
+    c->st = (hipStream_t)c->opt.stream;
+    State& S = c->S;
+    memset(&S, 0, sizeof(S));
+    S.m = A->rows;
+    S.n = A->cols;
+    S.p = L->rows;
+    S.s = s;
+    S.dmax = c->opt.ell + c->opt.max_iters;
+    S.zeta = c->opt.zeta;
+    S.passes = c->opt.qr_passes;
+    S.sketch_mode = c->opt.sketch_mode;
+    S.vdt = c->opt.value_dtype;
+    S.seed = seed;
+    S.mu = mu;
+    S.sqrt_mu = sqrt(mu);
+    const size_t vsz = S.vdt == SGKS_F32 ? 4 : 8;
+    const int dmax = S.dmax;
+
+    S.A = Csr{A->rows, A->cols, A->nnz, A->rowptr, A->colind, A->val,
+              c->opt.lanes_A ? c->opt.lanes_A : choose_lanes(A->nnz, A->rows)};
+    S.L = Csr{L->rows, L->cols, L->nnz, L->rowptr, L->colind, L->val,
+              choose_lanes(L->nnz, L->rows)};
+
+#define SGKS_TRY(expr)                      \
+    do {                                    \
+        if ((expr) != hipSuccess) {         \
+            sgks_destroy(c);                \
+            return SGKS_ERR_HIP;            \
+        }                                   \
+    } while (0)
+
+    // transposes of A and L (explicit CSR, n rows)
+    SGKS_TRY(dalloc(c, &c->At_rowptr, (S.n + 1) * 4));
+    SGKS_TRY(dalloc(c, &c->At_col, S.A.nnz * 4));
+    SGKS_TRY(dalloc(c, (char**)&c->At_val, S.A.nnz * vsz));
+    SGKS_TRY(dalloc(c, &c->Lt_rowptr, (S.n + 1) * 4));
+    SGKS_TRY(dalloc(c, &c->Lt_col, S.L.nnz * 4));
+    SGKS_TRY(dalloc(c, (char**)&c->Lt_val, S.L.nnz * vsz));
+    if (sgks::transpose_csr(S.A, S.vdt, c->At_rowptr, c->At_col, c->At_val, c->st) ||
+        sgks::transpose_csr(S.L, S.vdt, c->Lt_rowptr, c->Lt_col, c->Lt_val, c->st)) {
+        sgks_destroy(c);
+        return SGKS_ERR_HIP;
+    }
+    S.At = Csr{S.n, S.m, S.A.nnz, c->At_rowptr, c->At_col, c->At_val,
+               c->opt.lanes_At ? c->opt.lanes_At : choose_lanes(S.A.nnz, S.n)};
+    S.Lt = Csr{S.n, S.p, S.L.nnz, c->Lt_rowptr, c->Lt_col, c->Lt_val,
+               choose_lanes(S.L.nnz, S.n)};
+
+    // sketch partial counts: one 64-row tile per wave, at most 1024 blocks per operator
+    auto sk_blocks = [](int64_t rows) {
+        int64_t tiles = (rows + 63) / 64;
+        int64_t nb = (tiles + sgks::kWaves - 1) / sgks::kWaves;
+        if (nb < 1) nb = 1;
+        if (nb > 1024) nb = 1024;
+        return (int)nb;
+    };
+    S.nbA = sk_blocks(S.m);
+    S.nbL = sk_blocks(S.p);
+    S.n_norm_part = sgks::adjoint_blocks(S);
+    int nbFA = 0;
+    const int nbF = sgks::forward_blocks(S, true, &nbFA);
+    c->nbF_A = nbFA;
+    c->nbF_L = nbF - nbFA;
+    // W^T v partials: at most 512 blocks, rows per block a multiple of 64
+    {
+        int64_t rpb = (S.n + 511) / 512;
+        rpb = ((rpb + 63) / 64) * 64;
+        if (rpb < 256) rpb = 256;
+        if (rpb > 4096) rpb = 4096;   // staged in LDS (32 KiB)
+        S.gt_rows = (int)rpb;
+        S.ngt = (int)((S.n + rpb - 1) / rpb);
+    }
+    // cooperative append workgroups
+    {
+        int dev = 0, coop = 0;
+        hipGetDevice(&dev);
+        hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
+        int G = c->opt.append_groups;
+        if (G == 0) {
+            G = s / 32;
+            if (G > 32) G = 32;
+        }
+        if (G < 1) G = 1;
+        const int cap = sgks::max_append_groups();
+        if (G > cap) G = cap;
+        if (!coop) G = 1;
+        c->groups = G;
+    }
+    const int regions = 2 * S.passes + 2;
+    const int CW = 2 * dmax + 8;
+
+    SGKS_TRY(dalloc(c, (double**)&S.b, S.m * 8));
+    SGKS_TRY(dalloc(c, &S.x, S.n * 8));
+    SGKS_TRY(dalloc(c, &S.u, S.m * 8));
+    SGKS_TRY(dalloc(c, &S.t, S.p * 8));
+    SGKS_TRY(dalloc(c, &S.rtmp, S.n * 8));
+    SGKS_TRY(dalloc(c, &S.W, (size_t)S.n * dmax * 8));
+    SGKS_TRY(dalloc(c, &S.cs, dmax * 8));
+    SGKS_TRY(dalloc(c, &S.QA, (size_t)s * dmax * 8));
+    SGKS_TRY(dalloc(c, &S.QL, (size_t)s * dmax * 8));
+    SGKS_TRY(dalloc(c, &S.RA, (size_t)dmax * dmax * 8));
+    SGKS_TRY(dalloc(c, &S.RL, (size_t)dmax * dmax * 8));
+    SGKS_TRY(dalloc(c, &S.U, (size_t)2 * dmax * dmax * 8));
+    SGKS_TRY(dalloc(c, &S.G, (size_t)2 * dmax * dmax * 8));   // G, then G^{-1}
+    SGKS_TRY(dalloc(c, &S.h, dmax * 8));
+    SGKS_TRY(dalloc(c, &S.dA, dmax * 8));
+    SGKS_TRY(dalloc(c, &S.cb, s * 8));
+    SGKS_TRY(dalloc(c, &S.y, dmax * 8));
+    SGKS_TRY(dalloc(c, &S.yprev, dmax * 8));
+    SGKS_TRY(dalloc(c, &S.norm_part, S.n_norm_part * 8));
+    SGKS_TRY(dalloc(c, &S.binA, (size_t)S.nbA * s * 8));
+    SGKS_TRY(dalloc(c, &S.binL, (size_t)S.nbL * s * 8));
+    SGKS_TRY(dalloc(c, &S.gpart, (size_t)S.ngt * dmax * 8));
+    SGKS_TRY(dalloc(c, &S.coop, (size_t)regions * c->groups * CW * 8));
+    SGKS_TRY(dalloc(c, &S.bar, 64));
+    SGKS_TRY(dalloc(c, &S.scal, (16 + 2 * dmax) * 8));
+    SGKS_TRY(dalloc(c, &S.d, 64));
+    SGKS_TRY(dalloc(c, &S.status, 64));
+    SGKS_TRY(dalloc(c, &S.degenerate, 64));
+    SGKS_TRY(dalloc(c, &c->upart, c->nbF_A * 8));
+    SGKS_TRY(dalloc(c, &c->tpart, (c->nbF_L > 0 ? c->nbF_L : 1) * 8));
+    SGKS_TRY(dalloc(c, &c->coefbuf, dmax * 8));
+    SGKS_TRY(dalloc(c, &c->sbuf, s * 8));
+    hipStream_t st = c->st;
+    SGKS_TRY(hipMemsetAsync(S.cs, 0, dmax * 8, st));
+    SGKS_TRY(hipMemsetAsync(S.QA, 0, (size_t)s * dmax * 8, st));
+    SGKS_TRY(hipMemsetAsync(S.QL, 0, (size_t)s * dmax * 8, st));
+    SGKS_TRY(hipMemsetAsync(S.RA, 0, (size_t)dmax * dmax * 8, st));
+    SGKS_TRY(hipMemsetAsync(S.RL, 0, (size_t)dmax * dmax * 8, st));
+    SGKS_TRY(hipMemsetAsync(S.U, 0, (size_t)2 * dmax * dmax * 8, st));
+    SGKS_TRY(hipMemsetAsync(S.G, 0, (size_t)2 * dmax * dmax * 8, st));
+    SGKS_TRY(hipMemsetAsync(S.h, 0, dmax * 8, st));
+    SGKS_TRY(hipMemsetAsync(S.dA, 0, dmax * 8, st));
+    SGKS_TRY(hipMemsetAsync(S.y, 0, dmax * 8, st));
+    SGKS_TRY(hipMemsetAsync(S.yprev, 0, dmax * 8, st));
+    SGKS_TRY(hipMemsetAsync(S.bar, 0, 64, st));
+    SGKS_TRY(hipMemsetAsync(S.scal, 0, (16 + 2 * dmax) * 8, st));
+    SGKS_TRY(hipMemsetAsync(S.d, 0, 64, st));
+    SGKS_TRY(hipMemsetAsync(S.status, 0, 64, st));
+    SGKS_TRY(hipMemsetAsync(S.degenerate, 0, 64, st));
+
+    // b in FP64, finiteness and zero checks
+    sgks::launch_to_f64(b, S.vdt, (double*)S.b, S.m, S.norm_part, S.n_norm_part, st);
+    sgks::launch_sum_parts(S.norm_part, S.n_norm_part, S.scal + 2, st);
+    double bn2 = 0.0;
+    SGKS_TRY(hipMemcpyAsync(&bn2, S.scal + 2, 8, hipMemcpyDeviceToHost, st));
+    SGKS_TRY(hipStreamSynchronize(st));
+    if (!(bn2 < INFINITY)) {
+        sgks_destroy(c);
+        return SGKS_ERR_NONFINITE;
+    }
+    if (!(bn2 > 0.0)) {
+        sgks_destroy(c);
+        return SGKS_ERR_ZERO_RHS;
+    }
+
+    // c_b = S_A b
+    sgks::launch_sketch(S, 0, true, S.b, st);
+    sgks::launch_cb(S, st);
+
+    // initial basis: orthonormal basis of K_ell(A^T A, A^T b), CGS2 (stored
+    // unnormalised with cs[j] = 1 / ||column||)
+    sgks::launch_adjoint(S, S.b, nullptr, false, 0.0, S.W, false, S.norm_part, st);
+    sgks::launch_set_scale(S, 0, true, st);
+    for (int j = 1; j < c->opt.ell; ++j) {
+        double* prev = S.W + (size_t)(j - 1) * S.n;
+        double* col = S.W + (size_t)j * S.n;
+        sgks::launch_forward(S, prev, nullptr, S.u, S.t, false, nullptr, nullptr, 0, st);
+        sgks::launch_adjoint(S, S.u, nullptr, false, 0.0, col, false, S.norm_part, st);
+        // norm before the projections (to detect a Krylov space that stopped growing)
+        sgks::launch_to_f64(col, 1, col, S.n, S.norm_part, S.n_norm_part, st);
+        sgks::launch_sum_parts(S.norm_part, S.n_norm_part, S.scal + 16 + dmax + j, st);
+        for (int pass = 0; pass < 2; ++pass) {
+            sgks::launch_gemvt(S, col, j, st);
+            sgks::launch_reduce_gpart(S, j, c->coefbuf, st);
+            sgks::launch_gemv(S, c->coefbuf, false, col, col, j, st);
+        }
+        norm_to_scale(c, col, j, false);
+    }
+    std::vector<double> sc(16 + 2 * dmax, 0.0);
+    SGKS_TRY(hipMemcpyAsync(sc.data(), S.scal, sc.size() * 8, hipMemcpyDeviceToHost, st));
+    SGKS_TRY(hipStreamSynchronize(st));
+    const double r0 = sc[0];
+    if (!(r0 < INFINITY)) {
+        sgks_destroy(c);
+        return SGKS_ERR_NONFINITE;
+    }
+    if (!(r0 > 0.0)) {
+        sgks_destroy(c);
+        return SGKS_ERR_ZERO_RHS;
+    }
+    for (int j = 1; j < c->opt.ell; ++j) {
+        // after / before the projections, squared norms vs norms
+        const double after = sc[16 + j], before = sqrt(sc[16 + dmax + j]);
+        if (!(after < INFINITY) || !(before < INFINITY)) {
+            sgks_destroy(c);
+            return SGKS_ERR_NONFINITE;
+        }
+        if (!(after > 1e-12 * before)) {
+            sgks_destroy(c);
+            return SGKS_ERR_INITIAL_SPACE;
+        }
+    }
+
+    // sketch and QR-append the initial columns, then y_0
+    for (int j = 0; j < c->opt.ell; ++j) {
+        sgks::launch_sketch(S, j, false, nullptr, st);
+        if (sgks::launch_append(S, false, c->groups, st)) {
+            sgks_destroy(c);
+            return SGKS_ERR_HIP;
+        }
+    }
+    for (int r = 0; r < c->opt.refine_steps; ++r) refine_once(c);
+    c->d_host = c->opt.ell;
+    const int stw = sync_status(c);
+    if (stw != 0) {
+        sgks_destroy(c);
+        return stw == SGKS_BREAKDOWN ? SGKS_ERR_INITIAL_SPACE : stw;
+    }
+    *out = c;
+    return SGKS_OK;
+#undef SGKS_TRY
+}
+
+int sgks_iterate(sgks_ctx* c, int32_t k) {
+    if (!c || k < 0) return SGKS_ERR_INVALID_ARG;
+    if (c->d_host + k > c->S.dmax) return SGKS_ERR_CAPACITY;
+    State& S = c->S;
+    hipStream_t st = c->st;
+    for (int it = 0; it < k; ++it) {
+        { Phase ph(c, 0); sgks::launch_gemv(S, S.y, false, S.x, nullptr, -1, st); }
+        { Phase ph(c, 1); sgks::launch_forward(S, S.x, S.b, S.u, S.t, true, nullptr, nullptr, 0, st); }
+        { Phase ph(c, 2); sgks::launch_adjoint(S, S.u, S.t, true, S.mu, nullptr, true, S.norm_part, st); }
+        { Phase ph(c, 3); sgks::launch_sketch(S, -1, false, nullptr, st); }
+        {
+            Phase ph(c, 4);
+            if (sgks::launch_append(S, true, c->groups, st)) return SGKS_ERR_HIP;
+        }
+        for (int r = 0; r < c->opt.refine_steps; ++r) refine_once(c);
+    }
+    c->d_host += k;
+    return hipGetLastError() == hipSuccess ? SGKS_OK : SGKS_ERR_HIP;
+}
+
+int sgks_solution(sgks_ctx* c, double* x_dev) {
+    if (!c || !x_dev) return SGKS_ERR_INVALID_ARG;
+    Phase ph(c, 0);
+    sgks::launch_gemv(c->S, c->S.y, false, x_dev, nullptr, -1, c->st);
+    return hipGetLastError() == hipSuccess ? SGKS_OK : SGKS_ERR_HIP;
+}
+
+int sgks_residual_norm(sgks_ctx* c, double* true_norm, double* sketched_norm) {
+    if (!c) return SGKS_ERR_INVALID_ARG;
+    State& S = c->S;
+    hipStream_t st = c->st;
+    sgks::launch_gemv(S, S.y, false, S.x, nullptr, -1, st);
+    sgks::launch_forward(S, S.x, S.b, S.u, S.t, true, c->upart, c->tpart, 0, st);
+    sgks::launch_sum_parts(c->upart, c->nbF_A, S.scal + 8, st);
+    sgks::launch_sum_parts(c->tpart, c->nbF_L, S.scal + 9, st);
+    sgks::launch_residual_small(S, S.scal + 10, st);
+    double v[3] = {0, 0, 0};
+    if (hipMemcpyAsync(v, S.scal + 8, 24, hipMemcpyDeviceToHost, st) != hipSuccess)
+        return SGKS_ERR_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return SGKS_ERR_HIP;
+    if (true_norm) *true_norm = sqrt(v[0] + S.mu * v[1]);
+    if (sketched_norm) *sketched_norm = sqrt(v[2] > 0.0 ? v[2] : 0.0);
+    return SGKS_OK;
+}
+
+int sgks_status(sgks_ctx* c, int32_t* iters_done) {
+    if (!c) return SGKS_ERR_INVALID_ARG;
+    int st = sync_status(c);
+    int d = 0;
+    if (hipMemcpy(&d, c->S.d, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+        return SGKS_ERR_HIP;
+    if (iters_done) *iters_done = d - c->opt.ell;
+    return st;
+}
+
+int sgks_backward(sgks_ctx* c, const double* grad_x, double* grad_b, double* grad_mu) {
+    if (!c || !grad_x || !grad_b) return SGKS_ERR_INVALID_ARG;
+    State& S = c->S;
+    hipStream_t st = c->st;
+    sgks::launch_gemvt(S, grad_x, -1, st);
+    sgks::launch_backward_small(S, c->sbuf, S.scal + 11, st);
+    sgks::launch_sketch_transpose(S, c->sbuf, grad_b, st);
+    double gm = 0.0;
+    if (hipMemcpyAsync(&gm, S.scal + 11, 8, hipMemcpyDeviceToHost, st) != hipSuccess)
+        return SGKS_ERR_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return SGKS_ERR_HIP;
+    if (grad_mu) *grad_mu = gm;
+    return SGKS_OK;
+}
+
+int64_t sgks_copy_state(sgks_ctx* c, int32_t which, double* dst, int64_t count) {
+    if (!c || !dst) return SGKS_ERR_INVALID_ARG;
+    State& S = c->S;
+    hipStream_t st = c->st;
+    if (hipStreamSynchronize(st) != hipSuccess) return SGKS_ERR_HIP;
+    int d = 0;
+    if (hipMemcpy(&d, S.d, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return SGKS_ERR_HIP;
+    const int dmax = S.dmax;
+    auto copy = [&](const double* src, int64_t n) -> int64_t {
+        if (n > count) return SGKS_ERR_INVALID_ARG;
+        if (n > 0 && hipMemcpy(dst, src, n * 8, hipMemcpyDeviceToHost) != hipSuccess)
+            return SGKS_ERR_HIP;
+        return n;
+    };
+    auto copy2d = [&](const double* src, int64_t rows, int64_t cols, int64_t ld) -> int64_t {
+        if (rows * cols > count) return SGKS_ERR_INVALID_ARG;
+        if (rows * cols > 0 &&
+            hipMemcpy2D(dst, rows * 8, src, ld * 8, rows * 8, cols, hipMemcpyDeviceToHost) !=
+                hipSuccess)
+            return SGKS_ERR_HIP;
+        return rows * cols;
+    };
+    switch (which) {
+        case 0: {
+            const int64_t n = S.n * (int64_t)d;
+            if (n > count) return SGKS_ERR_INVALID_ARG;
+            double* tmp = nullptr;
+            if (hipMalloc(&tmp, (n > 0 ? n : 1) * 8) != hipSuccess) return SGKS_ERR_HIP;
+            sgks::launch_copy_scaled_W(S, tmp, st);
+            hipStreamSynchronize(st);
+            int64_t r = copy(tmp, n);
+            hipFree(tmp);
+            return r;
+        }
+        case 1: return copy(S.y, d);
+        case 2: return copy2d(S.QA, S.s, d, S.s);
+        case 3: return copy2d(S.RA, d, d, dmax);
+        case 4: return copy2d(S.QL, S.s, d, S.s);
+        case 5: return copy2d(S.RL, d, d, dmax);
+        case 6: return copy(S.dA, d);
+        case 7: return copy2d(S.G, d, d, dmax);
+        case 8: return copy(S.cb, S.s);
+        default: return SGKS_ERR_INVALID_ARG;
+    }
+}
+
+int sgks_profile_enable(sgks_ctx* c, int32_t on) {
+    if (!c) return SGKS_ERR_INVALID_ARG;
+    c->prof = on != 0;
+    return SGKS_OK;
+}
+
+int sgks_profile_read(sgks_ctx* c, double* ms, int64_t* launches) {
+    if (!c) return SGKS_ERR_INVALID_ARG;
+    if (hipStreamSynchronize(c->st) != hipSuccess) return SGKS_ERR_HIP;
+    double acc[SGKS_PHASES] = {0};
+    int64_t cnt[SGKS_PHASES] = {0};
+    for (size_t i = 0; i < c->pairs_used; ++i) {
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, c->events[2 * i], c->events[2 * i + 1]) != hipSuccess)
+            return SGKS_ERR_HIP;
+        acc[c->pair_phase[i]] += t;
+        cnt[c->pair_phase[i]] += 1;
+    }
+    c->pairs_used = 0;
+    for (int p = 0; p < SGKS_PHASES; ++p) {
+        if (ms) ms[p] = acc[p];
+        if (launches) launches[p] = cnt[p];
+    }
+    return SGKS_OK;
+}
+
+int32_t sgks_dim(const sgks_ctx* c) { return c ? c->d_host : 0; }
+
+void sgks_destroy(sgks_ctx* c) {
+    if (!c) return;
+    hipStreamSynchronize(c->st);
+    for (void* p : c->allocs) hipFree(p);
+    for (hipEvent_t e : c->events) hipEventDestroy(e);
+    delete c;
+}
+
+const char* sgks_strerror(int code) {
+    switch (code) {
+        case SGKS_OK: return "ok";
+        case SGKS_BREAKDOWN: return "breakdown: the gradient vanished (invariant subspace)";
+        case SGKS_ERR_INVALID_ARG: return "invalid argument";
+        case SGKS_ERR_SHAPE: return "shape mismatch";
+        case SGKS_ERR_BAD_MU: return "mu must be positive and finite";
+        case SGKS_ERR_SKETCH_SIZE: return "sketch size out of range";
+        case SGKS_ERR_CAPACITY: return "basis capacity exceeded";
+        case SGKS_ERR_ZERO_RHS: return "b (or A^T b) is zero";
+        case SGKS_ERR_NONFINITE: return "non-finite value";
+        case SGKS_ERR_HIP: return "HIP runtime error";
+        case SGKS_ERR_DEVICE: return "device-side failure";
+        case SGKS_ERR_INITIAL_SPACE: return "initial Krylov space has dimension below ell";
+        default: return "unknown error";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,111 @@
+// Internal declarations shared by the host runtime (sgks_api.hip) and the
+// kernels (sgks_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sgks {
+
+constexpr int kBlock = 256;         // threads per block of the bulk kernels
+constexpr int kWaves = kBlock / 64; // waves per block
+constexpr int kMaxS = 2048;         // largest sketch size (per-wave LDS bins)
+constexpr int kMaxD = 512;          // largest basis dimension
+constexpr int kAppendThreads = 256; // threads per workgroup of the append kernel
+
+// Device status word values (mirrors the public codes).
+constexpr int kStatusOk = 0;
+constexpr int kStatusBreakdown = 1;
+constexpr int kStatusNonfinite = -7;
+constexpr int kStatusDevice = -9;
+
+// A CSR operator as the kernels see it.  vdt: 0 = float values, 1 = double.
+struct Csr {
+    int64_t rows;
+    int64_t cols;
+    int64_t nnz;
+    const int32_t* rowptr;
+    const int32_t* col;
+    const void* val;
+    int lanes;      // lanes of a wavefront that share one row (1..64, power of 2)
+};
+
+// Everything the iteration kernels read or write.  Column-major layouts.
+struct State {
+    int64_t m, n, p;
+    int s;           // sketch rows
+    int dmax;        // capacity of the basis
+    int zeta;
+    int passes;      // projections per QR append (1 or 2)
+    int sketch_mode; // 0 sparse-sign, 1 identity
+    int vdt;         // value dtype of A, L
+    uint64_t seed;
+    double mu;
+    double sqrt_mu;
+
+    Csr A, At, L, Lt;
+
+    const double* b;   // m
+    double* x;         // n
+    double* u;         // m
+    double* t;         // p
+    double* rtmp;      // n (refinement gradient, adjoint input)
+    double* W;         // n x dmax, column j = r_j (unnormalised), scaled by cs[j]
+    double* cs;        // dmax column scales (1 / ||column||)
+
+    double* QA;        // s x dmax
+    double* RA;        // dmax x dmax
+    double* QL;        // s x dmax
+    double* RL;        // dmax x dmax
+    double* U;         // (2 dmax) x dmax: rows [0,dmax) pair with R_A, rows [dmax,2dmax) with R_L
+    double* G;         // dmax x dmax, R factor of [R_A; sqrt(mu) R_L]
+    double* h;         // dmax, U^T [d_A; 0]
+    double* dA;        // dmax
+    double* cb;        // s, S_A b
+    double* y;         // dmax
+    double* yprev;     // dmax
+
+    double* norm_part; // partial sums of ||r||^2 (one per block of the adjoint kernel)
+    int n_norm_part;
+    double* binA;      // nbA x s partial sketch bins of the A column
+    double* binL;      // nbL x s partial sketch bins of the L column
+    int nbA, nbL;
+    double* gpart;     // ngt x dmax partial W^T v sums
+    int ngt;
+    int gt_rows;       // rows per block of the W^T v kernel
+    double* coop;      // scratch of the append kernel
+    unsigned* bar;     // grid barrier words [count, generation]
+    double* scal;      // scalars: [0] ||A^T b||, [1] ||S_A b||^2, [2..] scratch
+    int* d;            // current number of basis columns
+    int* status;       // device status word
+    int* degenerate;   // count of numerically absent QR columns
+};
+
+// ----- launchers (sgks_kernels.hip) -----------------------------------------
+void launch_to_f64(const void* src, int vdt, double* dst, int64_t n, double* part, int nb,
+                   hipStream_t st);
+void launch_sum_parts(const double* part, int nb, double* out, hipStream_t st);
+void launch_forward(const State& S, const double* x, const double* b, double* u, double* t,
+                    bool with_L, double* upart, double* tpart, int nbF, hipStream_t st);
+int forward_blocks(const State& S, bool with_L, int* nbA_out);
+void launch_adjoint(const State& S, const double* u, const double* t, bool with_L, double mu,
+                    double* dst_fixed, bool dst_is_basis_column, double* part, hipStream_t st);
+int adjoint_blocks(const State& S);
+void launch_sketch(const State& S, int col, bool vec_mode, const double* vec, hipStream_t st);
+void launch_gemv(const State& S, const double* coef, bool coef_from_cs, double* out,
+                 const double* base, int ncols_fixed, hipStream_t st);
+void launch_gemvt(const State& S, const double* v, int ncols_fixed, hipStream_t st);
+void launch_reduce_gpart(const State& S, int ncols_fixed, double* out, hipStream_t st);
+void launch_set_scale(const State& S, int col, bool store_r0, hipStream_t st);
+int launch_append(const State& S, bool scale_from_norm, int groups, hipStream_t st);
+void launch_refine(const State& S, hipStream_t st);
+void launch_cb(const State& S, hipStream_t st);
+void launch_residual_small(const State& S, double* out2, hipStream_t st);
+void launch_backward_small(const State& S, double* v_out, double* gmu_out, hipStream_t st);
+void launch_sketch_transpose(const State& S, const double* v, double* out, hipStream_t st);
+void launch_copy_scaled_W(const State& S, double* dst, hipStream_t st);
+int transpose_csr(const Csr& M, int vdt, int32_t* rowptrT, int32_t* colT, void* valT,
+                  hipStream_t st);
+int max_append_groups();
+
+}  // namespace sgks

@@ -1,0 +1,270 @@
+"""Python binding of libsgks.so (ctypes).  Argument marshalling only.
+
+PyTorch supplies device memory and the stream; every step of the solver runs in
+the library's HIP kernels.  The library must be built (``python -m
+paper_2606_18073_amd.build``); a missing library raises at import of the
+binding's first use -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libsgks.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "sgks.h")
+
+OK = 0
+BREAKDOWN = 1
+ERRORS = {
+    -1: "INVALID_ARG", -2: "SHAPE", -3: "BAD_MU", -4: "SKETCH_SIZE", -5: "CAPACITY",
+    -6: "ZERO_RHS", -7: "NONFINITE", -8: "HIP", -9: "DEVICE", -10: "INITIAL_SPACE",
+}
+F32, F64 = 0, 1
+SKETCH_SPARSE_SIGN, SKETCH_IDENTITY = 0, 1
+PHASES = 8
+PHASE_NAMES = ["gemv_Wy", "forward_Ax_Lx", "adjoint_ATu_LTt", "spmv_sketch", "qr_append_solve",
+               "gemvt_WTr", "refine_step", "other"]
+STATE = {"W": 0, "y": 1, "Q_A": 2, "R_A": 3, "Q_L": 4, "R_L": 5, "d_A": 6, "G": 7, "c_b": 8}
+
+
+class SgksError(RuntimeError):
+    def __init__(self, code, where=""):
+        self.code = code
+        super().__init__(f"{where}: sgks error {code} ({ERRORS.get(code, 'unknown')})")
+
+
+class CsrStruct(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int64), ("cols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("rowptr", ctypes.c_void_p), ("colind", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("ell", ctypes.c_int32), ("max_iters", ctypes.c_int32),
+                ("zeta", ctypes.c_int32), ("value_dtype", ctypes.c_int32),
+                ("refine_steps", ctypes.c_int32), ("qr_passes", ctypes.c_int32),
+                ("sketch_mode", ctypes.c_int32), ("lanes_A", ctypes.c_int32),
+                ("lanes_At", ctypes.c_int32), ("append_groups", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libsgks.so and declare the prototypes (fails loudly if it is missing)."""
+    global _lib
+    if _lib is not None and path == LIB_PATH:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2606_18073_amd.build`")
+    L = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    L.sgks_default_options.argtypes = [P(Options)]
+    L.sgks_default_options.restype = None
+    L.sgks_validate.argtypes = [P(CsrStruct), P(CsrStruct), ctypes.c_void_p, ctypes.c_double,
+                                ctypes.c_int32, P(Options)]
+    L.sgks_validate.restype = ctypes.c_int
+    L.sgks_create.argtypes = [P(CsrStruct), P(CsrStruct), ctypes.c_void_p, ctypes.c_double,
+                              ctypes.c_int32, ctypes.c_uint64, P(Options), P(ctypes.c_void_p)]
+    L.sgks_create.restype = ctypes.c_int
+    L.sgks_iterate.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    L.sgks_iterate.restype = ctypes.c_int
+    L.sgks_solution.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    L.sgks_solution.restype = ctypes.c_int
+    L.sgks_residual_norm.argtypes = [ctypes.c_void_p, P(ctypes.c_double), P(ctypes.c_double)]
+    L.sgks_residual_norm.restype = ctypes.c_int
+    L.sgks_status.argtypes = [ctypes.c_void_p, P(ctypes.c_int32)]
+    L.sgks_status.restype = ctypes.c_int
+    L.sgks_backward.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                P(ctypes.c_double)]
+    L.sgks_backward.restype = ctypes.c_int
+    L.sgks_copy_state.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                  ctypes.c_int64]
+    L.sgks_copy_state.restype = ctypes.c_int64
+    L.sgks_profile_enable.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    L.sgks_profile_enable.restype = ctypes.c_int
+    L.sgks_profile_read.argtypes = [ctypes.c_void_p, P(ctypes.c_double), P(ctypes.c_int64)]
+    L.sgks_profile_read.restype = ctypes.c_int
+    L.sgks_dim.argtypes = [ctypes.c_void_p]
+    L.sgks_dim.restype = ctypes.c_int32
+    L.sgks_destroy.argtypes = [ctypes.c_void_p]
+    L.sgks_destroy.restype = None
+    L.sgks_strerror.argtypes = [ctypes.c_int]
+    L.sgks_strerror.restype = ctypes.c_char_p
+    if path == LIB_PATH:
+        _lib = L
+    return L
+
+
+def header_functions(header=HEADER):
+    """Names of the functions declared in include/sgks.h."""
+    text = open(header).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sgks_[a-z_]+)\s*\(", text)))
+
+
+def default_options():
+    o = Options()
+    load_library().sgks_default_options(ctypes.byref(o))
+    return o
+
+
+class DeviceCsr:
+    """A CSR matrix resident on the GPU (int32 rowptr / colind, f32 or f64 values)."""
+
+    def __init__(self, rowptr, colind, val, shape):
+        self.rowptr, self.colind, self.val = rowptr, colind, val
+        self.shape = tuple(int(v) for v in shape)
+
+    @classmethod
+    def from_scipy(cls, M, dtype="f64", device="cuda"):
+        import torch
+        vt = torch.float32 if dtype == "f32" else torch.float64
+        rp = torch.as_tensor(np.ascontiguousarray(M.indptr, dtype=np.int32), device=device)
+        ci = torch.as_tensor(np.ascontiguousarray(M.indices, dtype=np.int32), device=device)
+        va = torch.as_tensor(np.ascontiguousarray(M.data), device=device).to(vt)
+        return cls(rp, ci, va, M.shape)
+
+    @property
+    def nnz(self):
+        return int(self.colind.numel())
+
+    def struct(self):
+        return CsrStruct(self.shape[0], self.shape[1], self.nnz, self.rowptr.data_ptr(),
+                         self.colind.data_ptr(), self.val.data_ptr())
+
+
+def _check(code, where):
+    if code < 0:
+        raise SgksError(code, where)
+    return code
+
+
+class SGKS:
+    """One sGKS solve on the GPU: sgks_create / sgks_iterate / sgks_solution / ..."""
+
+    def __init__(self, A: DeviceCsr, L: DeviceCsr, b, mu, s, seed=0, *, ell=3, max_iters=200,
+                 zeta=8, refine_steps=0, qr_passes=2, sketch="sparse_sign", lanes_A=0,
+                 lanes_At=0, append_groups=0, stream=None):
+        import torch
+        self._lib = load_library()
+        self.A, self.L, self.b = A, L, b
+        vdt = F32 if A.val.dtype == torch.float32 else F64
+        if L.val.dtype != A.val.dtype or b.dtype != A.val.dtype:
+            raise TypeError("A, L and b must share one value dtype")
+        if stream is None:
+            stream = torch.cuda.current_stream(b.device)
+        self.stream = stream
+        o = Options()
+        self._lib.sgks_default_options(ctypes.byref(o))
+        o.ell, o.max_iters, o.zeta, o.value_dtype = ell, max_iters, zeta, vdt
+        o.refine_steps, o.qr_passes = refine_steps, qr_passes
+        o.sketch_mode = SKETCH_IDENTITY if sketch == "identity" else SKETCH_SPARSE_SIGN
+        o.lanes_A, o.lanes_At, o.append_groups = lanes_A, lanes_At, append_groups
+        o.stream = ctypes.c_void_p(stream.cuda_stream)
+        self.options = o
+        self.mu, self.s, self.seed, self.ell = float(mu), int(s), int(seed), int(ell)
+        self.n = A.shape[1]
+        self.m = A.shape[0]
+        self._As, self._Ls = A.struct(), L.struct()
+        h = ctypes.c_void_p()
+        rc = self._lib.sgks_create(ctypes.byref(self._As), ctypes.byref(self._Ls),
+                                   ctypes.c_void_p(b.data_ptr()), float(mu), int(s),
+                                   ctypes.c_uint64(seed), ctypes.byref(o), ctypes.byref(h))
+        _check(rc, "sgks_create")
+        self._h = h
+
+    def iterate(self, k):
+        _check(self._lib.sgks_iterate(self._h, int(k)), "sgks_iterate")
+        return self
+
+    def solution(self, out=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float64, device=self.b.device)
+        _check(self._lib.sgks_solution(self._h, ctypes.c_void_p(out.data_ptr())), "sgks_solution")
+        return out
+
+    def residual_norm(self):
+        t, s = ctypes.c_double(), ctypes.c_double()
+        _check(self._lib.sgks_residual_norm(self._h, ctypes.byref(t), ctypes.byref(s)),
+               "sgks_residual_norm")
+        return t.value, s.value
+
+    def status(self):
+        it = ctypes.c_int32()
+        rc = self._lib.sgks_status(self._h, ctypes.byref(it))
+        return rc, it.value
+
+    def backward(self, grad_x):
+        import torch
+        grad_x = grad_x.to(torch.float64).contiguous()
+        gb = torch.empty(self.m, dtype=torch.float64, device=self.b.device)
+        gm = ctypes.c_double()
+        _check(self._lib.sgks_backward(self._h, ctypes.c_void_p(grad_x.data_ptr()),
+                                       ctypes.c_void_p(gb.data_ptr()), ctypes.byref(gm)),
+               "sgks_backward")
+        return gb, gm.value
+
+    def profile(self, on=True):
+        _check(self._lib.sgks_profile_enable(self._h, 1 if on else 0), "sgks_profile_enable")
+        return self
+
+    def profile_read(self):
+        """(ms, launches) per phase since the last read (synchronising)."""
+        ms = (ctypes.c_double * PHASES)()
+        cnt = (ctypes.c_int64 * PHASES)()
+        _check(self._lib.sgks_profile_read(self._h, ms, cnt), "sgks_profile_read")
+        return list(ms), list(cnt)
+
+    def dim(self):
+        return int(self._lib.sgks_dim(self._h))
+
+    def state(self, which):
+        """Copy one state array to host (numpy, column-major shapes as in sgks.h)."""
+        rc, it = self.status()
+        d = self.ell + it
+        shapes = {"W": (self.n, d), "y": (d,), "Q_A": (self.s, d), "R_A": (d, d),
+                  "Q_L": (self.s, d), "R_L": (d, d), "d_A": (d,), "G": (d, d), "c_b": (self.s,)}
+        shp = shapes[which]
+        buf = np.zeros(int(np.prod(shp)), dtype=np.float64)
+        got = self._lib.sgks_copy_state(self._h, STATE[which],
+                                        buf.ctypes.data_as(ctypes.c_void_p), buf.size)
+        _check(int(got), "sgks_copy_state")
+        return buf.reshape(shp[::-1]).T if len(shp) == 2 else buf
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.sgks_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def upload_problem(P, device="cuda"):
+    """DeviceCsr A, L and the device b of a workloads.Problem in its storage dtype."""
+    import torch
+    A = DeviceCsr.from_scipy(P.A, P.dtype, device)
+    L = DeviceCsr.from_scipy(P.L, P.dtype, device)
+    vt = torch.float32 if P.dtype == "f32" else torch.float64
+    b = torch.as_tensor(P.b, device=device).to(vt)
+    return A, L, b
+
+
+def solve_problem(P, k=None, device="cuda", **kw):
+    """Create, iterate k (default P.k) times; returns (solver, x as float64 tensor)."""
+    A, L, b = upload_problem(P, device)
+    k = P.k if k is None else k
+    opts = dict(ell=P.ell, max_iters=max(k, 1), zeta=P.zeta, refine_steps=P.refine_steps)
+    opts.update(kw)
+    S = SGKS(A, L, b, P.mu, P.s, P.seed, **opts)
+    S.iterate(k)
+    return S, S.solution()

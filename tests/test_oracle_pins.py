@@ -356,6 +356,18 @@ def test_breakdown_on_invariant_subspace():
     assert res.status == O.STATUS_BREAKDOWN and res.iters == 0
     assert np.allclose(res.x, b / 1.5)
     assert np.allclose(V[:, 0], b / np.linalg.norm(b))
+    with pytest.raises(O.DegenerateInitialSpace):
+        O.initial_basis(A, b, 2)
+
+
+def test_breakdown_on_dependent_sketched_column():
+    """A = L = I with a sparse-sign sketch: r(x) is parallel to b, so the new column
+    repeats w_1; the stacked projected column is dependent and the expansion stops."""
+    n = 64
+    A = sp.identity(n, format="csr")
+    b = np.linspace(1, 2, n)
+    res = O.sgks(A, A, b, 0.5, 4, 16, 0, ell=1)
+    assert res.status == O.STATUS_BREAKDOWN and res.iters == 0 and res.W.shape[1] == 1
 
 
 # ----------------------------------------------------------------------------

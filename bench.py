@@ -1,0 +1,206 @@
+#!/usr/bin/env python3
+"""Benchmark of the sGKS hot path on one MI355X.
+
+A step is one complete solve of the 2D deblurring workload (256x256 image,
+n = 65536, 9x9 Gaussian PSF as CSR with FP32 values, L = [Dx; Dy], s = 400,
+k = 100): sgks_create (transposes, sketch of b, initial Krylov basis, QR
+factors), k expansions, and x_k = W y written to device memory.  The inputs
+(A, L, b) are resident in device memory before the timed region starts.
+
+Printed: one JSON line with the metric (sGKS iterations per second over whole
+solves), the roofline of the dominant kernel (algorithmic bytes per launch /
+average launch time, measured with HIP events on the library's stream over
+the timed region), the SpMV+sketch bandwidth, the per-phase breakdown and the
+FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def source_hash():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2606_18073_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(P, d_avg_gemv):
+    """Minimal HBM bytes per launch of each bulk kernel (CSR read once, vectors once)."""
+    vsz = 4 if P.dtype == "f32" else 8
+    nnzA, nnzL = P.A.nnz, P.L.nnz
+    m, n, p, s = P.m, P.n, P.p, P.s
+    csr = (vsz + 4) * (nnzA + nnzL)
+    return {
+        "forward_Ax_Lx": csr + 4 * (m + 1) + 4 * (p + 1) + 8 * n + 8 * m + 8 * m + 8 * p,
+        "adjoint_ATu_LTt": csr + 8 * (n + 1) + 8 * m + 8 * p + 8 * n,
+        "spmv_sketch": csr + 4 * (m + 1) + 4 * (p + 1) + 8 * n + 16 * s,
+        "gemv_Wy": 8 * n * d_avg_gemv + 8 * n,
+    }
+
+
+def load_traffic(kernel, workload, shash):
+    """HBM traffic per launch from committed rocprofv3 counter runs, if still current."""
+    f = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(f):
+        return None
+    try:
+        t = json.load(open(f))
+    except Exception:
+        return None
+    if t.get("source_hash") != shash:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(P, reps):
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import sgks_oracle as O
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ref = O.sgks(P.A, P.L, P.b, P.mu, P.k, P.s, P.seed, zeta=P.zeta, ell=P.ell,
+                         refine_steps=P.refine_steps)
+        dt = time.perf_counter() - t0
+    return ref, {"value": reps * P.k / dt, "unit": "iters/s", "cores": 1, "kind": "oracle",
+                 "sample": f"{reps} complete solves (set-up + {P.k} iterations) of the same "
+                           f"workload, FP64 numpy/scipy, 1 thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="deblur2d")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-reps", type=int, default=2)
+    ap.add_argument("--no-profile", action="store_true",
+                    help="time without the per-phase events (no roofline)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see the sharding design notes); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2606_18073_amd import sgks as G
+    from workloads import make
+
+    P = make(args.workload, 0, "full")
+    dev = torch.device("cuda:0")
+    A, L, b = G.upload_problem(P, dev)
+    x = torch.empty(P.n, dtype=torch.float64, device=dev)
+    prof = not args.no_profile
+
+    def step(acc):
+        t0 = time.perf_counter()
+        S = G.SGKS(A, L, b, P.mu, P.s, P.seed, ell=P.ell, max_iters=P.k, zeta=P.zeta,
+                   refine_steps=P.refine_steps)
+        t1 = time.perf_counter()
+        if prof:
+            S.profile(True)
+        S.iterate(P.k)
+        S.solution(out=x)
+        if prof:
+            ms, cnt = S.profile_read()
+            for i in range(G.PHASES):
+                acc["ms"][i] += ms[i]
+                acc["n"][i] += cnt[i]
+        rc, it = S.status()
+        S.close()
+        acc["setup_s"] += t1 - t0
+        assert rc == 0 and it == P.k, (rc, it)
+
+    for _ in range(args.warmup):
+        step({"ms": [0.0] * G.PHASES, "n": [0] * G.PHASES, "setup_s": 0.0})
+    acc = {"ms": [0.0] * G.PHASES, "n": [0] * G.PHASES, "setup_s": 0.0}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(acc)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1e3 * wall / args.steps
+    value = args.steps * P.k / wall
+    iter_s = wall - acc["setup_s"]
+    xg = x.cpu().numpy()
+
+    out = {
+        "metric": "sGKS iters/s + SpMV/sketch HBM GB/s; batched & adjoint vs plain at equal rel err",
+        "value": value,
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{P.name}: {P.meta.get('N')}x{P.meta.get('N')} image, n={P.n}, "
+                         f"A 9x9 Gaussian PSF CSR nnz={P.A.nnz} ({P.dtype} values), "
+                         f"L=[Dx;Dy] {P.p}x{P.n} nnz={P.L.nnz}, sparse-sign s={P.s} "
+                         f"zeta={P.zeta}, k={P.k}, mu={P.mu}, ell={P.ell}; one step = "
+                         f"create + {P.k} iterations + x_k"),
+            "operator_storage": P.dtype,
+            "vectors": "f64",
+            "k": P.k, "n": P.n, "s": P.s,
+        },
+        "setup_ms_per_step": 1e3 * acc["setup_s"] / args.steps,
+        "iterate_only_iters_per_s": args.steps * P.k / iter_s if iter_s > 0 else None,
+    }
+    if prof:
+        names = G.PHASE_NAMES
+        phase = {names[i]: {"ms_total": acc["ms"][i], "launches": acc["n"][i],
+                            "us_avg": (1e3 * acc["ms"][i] / acc["n"][i]) if acc["n"][i] else None}
+                 for i in range(G.PHASES) if acc["n"][i]}
+        out["phases"] = phase
+        # average d over the x = W y launches: iterations use d = ell .. ell + k - 1,
+        # the solution uses ell + k
+        ds = list(range(P.ell, P.ell + P.k)) + [P.ell + P.k]
+        ab = algorithmic_bytes(P, sum(ds) / len(ds))
+        bulk = {k: v for k, v in phase.items() if k in ab}
+        dom = max(bulk, key=lambda k: bulk[k]["ms_total"])
+        avg_s = bulk[dom]["us_avg"] * 1e-6
+        achieved = ab[dom] / avg_s / 1e9
+        shash = source_hash()
+        traffic = load_traffic(dom, P.name, shash)
+        out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": achieved,
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                           "traffic": traffic, "algorithmic_bytes_per_launch": ab[dom],
+                           "source_hash": shash}
+        sk = ["forward_Ax_Lx", "adjoint_ATu_LTt", "spmv_sketch"]
+        tb = sum(ab[k] * bulk[k]["launches"] for k in sk if k in bulk)
+        tt = sum(bulk[k]["ms_total"] for k in sk if k in bulk) * 1e-3
+        out["spmv_sketch_GBps"] = tb / tt / 1e9 if tt > 0 else None
+        out["spmv_sketch_frac_of_hbm_peak"] = out["spmv_sketch_GBps"] / HBM_PEAK_GBS
+    if not args.no_cpu_baseline:
+        ref, cb = cpu_baseline(P, args.cpu_reps)
+        out["cpu_baseline"] = cb
+        out["rel_err_vs_oracle"] = float(np.linalg.norm(xg - ref.x) / np.linalg.norm(ref.x))
+        out["rre_gpu"] = float(np.linalg.norm(xg - P.x_true) / np.linalg.norm(P.x_true))
+        out["rre_oracle"] = float(np.linalg.norm(ref.x - P.x_true) / np.linalg.norm(P.x_true))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

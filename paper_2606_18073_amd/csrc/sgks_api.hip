@@ -237,12 +237,12 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
     S.Lt = Csr{S.n, S.p, S.L.nnz, c->Lt_rowptr, c->Lt_col, c->Lt_val,
                choose_lanes(S.L.nnz, S.n)};
 
-    // sketch partial counts: one 64-row tile per wave, at most 1024 blocks per operator
+    // scatter blocks: about two 64-entry tiles per wave, at most kMaxSketchBlocks per operator
     auto sk_blocks = [](int64_t rows) {
         int64_t tiles = (rows + 63) / 64;
-        int64_t nb = (tiles + sgks::kWaves - 1) / sgks::kWaves;
+        int64_t nb = (tiles + 2 * sgks::kSketchWaves - 1) / (2 * sgks::kSketchWaves);
         if (nb < 1) nb = 1;
-        if (nb > 1024) nb = 1024;
+        if (nb > sgks::kMaxSketchBlocks) nb = sgks::kMaxSketchBlocks;
         return (int)nb;
     };
     S.nbA = sk_blocks(S.m);
@@ -263,18 +263,14 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
     }
     // cooperative append workgroups
     {
-        int dev = 0, coop = 0;
-        hipGetDevice(&dev);
-        hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
-        int G = c->opt.append_groups;
-        if (G == 0) {
-            G = s / 32;
-            if (G > 32) G = 32;
-        }
-        if (G < 1) G = 1;
         const int cap = sgks::max_append_groups();
+        int G = c->opt.append_groups;
+        if (G == 0) G = sgks::choose_append_groups(s, dmax, cap < 64 ? cap : 64);
         if (G > cap) G = cap;
-        if (!coop) G = 1;
+        if (sgks::append_lds_bytes(s, dmax, G) > sgks::kAppendLdsBudget) {
+            sgks_destroy(c);
+            return SGKS_ERR_SKETCH_SIZE;
+        }
         c->groups = G;
     }
     const int regions = 2 * S.passes + 2;
@@ -301,9 +297,11 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
     SGKS_TRY(dalloc(c, &S.norm_part, S.n_norm_part * 8));
     SGKS_TRY(dalloc(c, &S.binA, (size_t)S.nbA * s * 8));
     SGKS_TRY(dalloc(c, &S.binL, (size_t)S.nbL * s * 8));
+    SGKS_TRY(dalloc(c, &S.wa, s * 8));
+    SGKS_TRY(dalloc(c, &S.wl, s * 8));
+    SGKS_TRY(dalloc(c, &S.wu, 2 * dmax * 8));
     SGKS_TRY(dalloc(c, &S.gpart, (size_t)S.ngt * dmax * 8));
     SGKS_TRY(dalloc(c, &S.coop, (size_t)regions * c->groups * CW * 8));
-    SGKS_TRY(dalloc(c, &S.bar, 64));
     SGKS_TRY(dalloc(c, &S.scal, (16 + 2 * dmax) * 8));
     SGKS_TRY(dalloc(c, &S.d, 64));
     SGKS_TRY(dalloc(c, &S.status, 64));
@@ -324,7 +322,7 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
     SGKS_TRY(hipMemsetAsync(S.dA, 0, dmax * 8, st));
     SGKS_TRY(hipMemsetAsync(S.y, 0, dmax * 8, st));
     SGKS_TRY(hipMemsetAsync(S.yprev, 0, dmax * 8, st));
-    SGKS_TRY(hipMemsetAsync(S.bar, 0, 64, st));
+    SGKS_TRY(hipMemsetAsync(S.wu, 0, 2 * dmax * 8, st));
     SGKS_TRY(hipMemsetAsync(S.scal, 0, (16 + 2 * dmax) * 8, st));
     SGKS_TRY(hipMemsetAsync(S.d, 0, 64, st));
     SGKS_TRY(hipMemsetAsync(S.status, 0, 64, st));

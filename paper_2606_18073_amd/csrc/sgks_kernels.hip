@@ -46,9 +46,46 @@ __device__ double block_sum(double v, double* red) {
     return t;
 }
 
-template <typename T>
-__device__ __forceinline__ double ldv(const void* p, int64_t k) {
-    return (double)((const T*)p)[k];
+// Sum of p[0], p[stride], ..., p[(n-1) stride] in that order, with eight
+// independent loads in flight at a time (the small kernels are latency
+// bound: a load-then-add loop would pay one memory latency per term).
+__device__ __forceinline__ double strided_sum(const double* __restrict__ p, int64_t stride,
+                                              int n) {
+    double acc = 0.0;
+    int k = 0;
+    for (; k + 8 <= n; k += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = p[(int64_t)(k + u) * stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    for (; k < n; ++k) acc += p[(int64_t)k * stride];
+    return acc;
+}
+
+// sum_k p[k stride] v[k], k < n, in order, eight loads in flight
+__device__ __forceinline__ double strided_dot(const double* __restrict__ p, int64_t stride,
+                                              const double* v, int n) {
+    double acc = 0.0;
+    int k = 0;
+    for (; k + 8 <= n; k += 8) {
+        double w[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) w[u] = p[(int64_t)(k + u) * stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += w[u] * v[k + u];
+    }
+    for (; k < n; ++k) acc += p[(int64_t)k * stride] * v[k];
+    return acc;
+}
+
+// Thread-strided sum of p[i], i = threadIdx.x, threadIdx.x + T, ... < n,
+// eight loads in flight (per-thread order fixed).
+__device__ __forceinline__ double thread_strided_sum(const double* __restrict__ p, int n, int T) {
+    const int tid = threadIdx.x;
+    const int cnt = tid < n ? (n - tid + T - 1) / T : 0;
+    return strided_sum(p + tid, T, cnt);
 }
 
 // Dot product of one CSR row with x by the V lanes of a group (lane g of V).
@@ -142,9 +179,7 @@ __global__ __launch_bounds__(kBlock) void k_to_f64(const T* __restrict__ src,
 
 __global__ __launch_bounds__(kBlock) void k_sum_parts(const double* part, int nb, double* out) {
     __shared__ double red[kWaves];
-    double a = 0.0;
-    for (int i = threadIdx.x; i < nb; i += kBlock) a += part[i];
-    const double t = block_sum(a, red);
+    const double t = block_sum(thread_strided_sum(part, nb, kBlock), red);
     if (threadIdx.x == 0) out[0] = t;
 }
 
@@ -154,11 +189,15 @@ __global__ __launch_bounds__(kBlock) void k_sum_parts(const double* part, int nb
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_forward(Csr A, Csr L, int nbA,
-                                                   const double* __restrict__ x,
-                                                   const double* __restrict__ b,
+                                                   const double* __restrict__ xfixed,
+                                                   const double* __restrict__ W, const int* dptr,
+                                                   int64_t n, const double* __restrict__ b,
                                                    double* __restrict__ u, double* __restrict__ t,
-                                                   double* upart, double* tpart) {
+                                                   double* upart, double* tpart,
+                                                   const int* status) {
     __shared__ double red[kWaves];
+    if (status && *status != 0) return;
+    const double* __restrict__ x = xfixed ? xfixed : W + (int64_t)(*dptr) * n;
     const bool isA = (int)blockIdx.x < nbA;
     const Csr M = isA ? A : L;
     const int blk = isA ? (int)blockIdx.x : (int)blockIdx.x - nbA;
@@ -216,71 +255,56 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(Csr At, Csr Lt, int withL, d
 }
 
 // ---------------------------------------------------------------------------
-// fused SpMV + sparse-sign sketch:  bins_A += S_A (A x),  bins_L += S_L (L x)
-// (or of a vector directly).  Blocks [0, nbA) take A rows, the rest L rows.
-// Each wave handles tiles of 64 rows: first the 64 row products (groups of V
-// lanes, V passes, each lane collecting the value of "its" row), then every
-// lane regenerates the pattern of its row and adds its value into the wave's
-// private bins.  Raw bins (no 1/sqrt(zeta), no column scale) per block.
+// sparse-sign sketch of two vectors: bins_A += S_A zA (m entries, stream 0),
+// bins_L += S_L zL (p entries, stream 1).  Blocks [0, nbA) take zA.  Each
+// wave walks 64-entry tiles: a coalesced load, the pattern of every entry
+// regenerated from its hash, and zeta LDS atomic adds into the wave's private
+// copy of the s bins.  Each block writes its raw bins (no 1/sqrt(zeta), no
+// column scale); partial bins are merged in fixed orders downstream.
 // ---------------------------------------------------------------------------
 
-template <typename T, int Z>
-__global__ __launch_bounds__(kBlock) void k_sketch(Csr A, Csr L, int nbA, int nbL,
-                                                  const double* xfixed, const double* W,
-                                                  const int* dptr, int64_t n, int col,
-                                                  int vec_mode, int s, uint64_t seed,
-                                                  int identity, double* binA, double* binL,
-                                                  const int* status) {
+template <int Z>
+__global__ __launch_bounds__(kSketchBlock) void k_scatter(const double* __restrict__ zA,
+                                                         int64_t m,
+                                                         const double* __restrict__ zL,
+                                                         int64_t p, int nbA, int nbL, int s,
+                                                         uint64_t seed, int identity,
+                                                         double* partA, double* partL,
+                                                         const int* status) {
     extern __shared__ double sm[];
     if (status && *status != 0) return;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int i = threadIdx.x; i < kWaves * s; i += kBlock) sm[i] = 0.0;
+    for (int i = threadIdx.x; i < kSketchWaves * s; i += kSketchBlock) sm[i] = 0.0;
     __syncthreads();
     double* bins = sm + wave * s;
     const bool isA = (int)blockIdx.x < nbA;
-    const Csr M = isA ? A : L;
+    const double* __restrict__ z = isA ? zA : zL;
+    const int64_t rows = isA ? m : p;
     const int blk = isA ? (int)blockIdx.x : (int)blockIdx.x - nbA;
     const int nblk = isA ? nbA : nbL;
     const int stream = isA ? 0 : 1;
-    const double* x = xfixed ? xfixed : W + (int64_t)(col >= 0 ? col : *dptr) * n;
-    const int64_t ntiles = (M.rows + 63) / 64;
-    for (int64_t tile = (int64_t)blk * kWaves + wave; tile < ntiles;
-         tile += (int64_t)nblk * kWaves) {
-        const int64_t row0 = tile * 64;
-        double z = 0.0;
-        if (vec_mode) {
-            if (row0 + lane < M.rows) z = x[row0 + lane];
-        } else {
-            SGKS_LANES_SWITCH(M.lanes, {
-                constexpr int GP = 64 / V;   // rows per pass
-                const int g = lane % V;
-                for (int pass = 0; pass < V; ++pass) {
-                    const int64_t row = row0 + pass * GP + lane / V;
-                    double v = 0.0;
-                    if (row < M.rows) v = row_dot<V, T>(M, x, row, g);
-                    const double tv = __shfl(v, (lane % GP) * V);
-                    if (lane / GP == pass) z = tv;
-                }
-            })
-        }
-        const int64_t i = row0 + lane;
-        if (i < M.rows) {
+    const int64_t ntiles = (rows + 63) / 64;
+    for (int64_t tile = (int64_t)blk * kSketchWaves + wave; tile < ntiles;
+         tile += (int64_t)nblk * kSketchWaves) {
+        const int64_t i = tile * 64 + lane;
+        if (i < rows) {
+            const double v = z[i];
             if (identity) {
-                atomicAdd(&bins[i], z);
+                atomicAdd(&bins[i], v);
             } else {
                 int bin[Z];
                 double sg[Z];
                 sketch_column<Z>(seed, stream, i, s, bin, sg);
 #pragma unroll
-                for (int q = 0; q < Z; ++q) atomicAdd(&bins[bin[q]], sg[q] * z);
+                for (int q = 0; q < Z; ++q) atomicAdd(&bins[bin[q]], sg[q] * v);
             }
         }
     }
     __syncthreads();
-    double* out = (isA ? binA : binL) + (int64_t)blk * s;
-    for (int j = threadIdx.x; j < s; j += kBlock) {
+    double* out = (isA ? partA : partL) + (int64_t)blk * s;
+    for (int j = threadIdx.x; j < s; j += kSketchBlock) {
         double a = 0.0;
-        for (int w = 0; w < kWaves; ++w) a += sm[w * s + j];
+        for (int w = 0; w < kSketchWaves; ++w) a += sm[w * s + j];
         out[j] = a;
     }
 }
@@ -305,13 +329,12 @@ __global__ __launch_bounds__(kBlock) void k_gemv(const double* __restrict__ W,
         const double* w = W + i;
         double acc = 0.0;
         int j = 0;
-        for (; j + 4 <= d; j += 4) {
-            const double w0 = w[(int64_t)j * n], w1 = w[(int64_t)(j + 1) * n];
-            const double w2 = w[(int64_t)(j + 2) * n], w3 = w[(int64_t)(j + 3) * n];
-            acc += w0 * yt[j];
-            acc += w1 * yt[j + 1];
-            acc += w2 * yt[j + 2];
-            acc += w3 * yt[j + 3];
+        for (; j + 8 <= d; j += 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = w[(int64_t)(j + u) * n];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += v[u] * yt[j + u];
         }
         for (; j < d; ++j) acc += w[(int64_t)j * n] * yt[j];
         out[i] = base ? base[i] - acc : acc;
@@ -345,11 +368,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_cols(const double* __restrict
                                                        int ld, const int* dptr, int ncols_fixed,
                                                        double* __restrict__ out) {
     const int d = ncols_fixed >= 0 ? ncols_fixed : *dptr;
-    for (int j = threadIdx.x; j < d; j += kBlock) {
-        double a = 0.0;
-        for (int b = 0; b < nb; ++b) a += part[(int64_t)b * ld + j];
-        out[j] = a;
-    }
+    for (int j = threadIdx.x; j < d; j += kBlock) out[j] = strided_sum(part + j, ld, nb);
 }
 
 // cs[col] = 1 / ||v|| from the norm partials; optionally scal[0] = ||v||.
@@ -357,9 +376,7 @@ __global__ __launch_bounds__(kBlock) void k_set_scale(const double* part, int nb
                                                      int col, int store_r0, double* scal,
                                                      int* status) {
     __shared__ double red[kWaves];
-    double a = 0.0;
-    for (int i = threadIdx.x; i < nb; i += kBlock) a += part[i];
-    const double t = block_sum(a, red);
+    const double t = block_sum(thread_strided_sum(part, nb, kBlock), red);
     if (threadIdx.x == 0) {
         const double nr = sqrt(t);
         scal[16 + col] = nr;
@@ -375,8 +392,7 @@ __global__ __launch_bounds__(kBlock) void k_cb(const double* __restrict__ bins, 
     __shared__ double red[kWaves];
     double sq = 0.0;
     for (int i = threadIdx.x; i < s; i += kBlock) {
-        double a = 0.0;
-        for (int b = 0; b < nb; ++b) a += bins[(int64_t)b * s + i];
+        double a = strided_sum(bins + i, s, nb);
         a *= scale;
         cb[i] = a;
         sq += a * a;
@@ -391,67 +407,155 @@ __global__ __launch_bounds__(kBlock) void k_cb(const double* __restrict__ bins, 
 // update G^{-1} and y = G^{-1} h.
 // ---------------------------------------------------------------------------
 
-__device__ bool grid_sync(unsigned* bar, int G) {
-    if (G <= 1) {
-        __syncthreads();
-        return true;
-    }
-    __shared__ int ok_sh;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned arrived =
-            __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        int ok = 1;
-        if (arrived == (unsigned)G - 1u) {
-            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&bar[1], gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            unsigned spins = 0;
-            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > (1u << 22)) {
-                    ok = 0;
-                    break;
-                }
-            }
-        }
-        ok_sh = ok;
-    }
-    __syncthreads();
-    __threadfence();
-    return ok_sh != 0;
-}
+// The append runs as a chain of small kernels, each with G workgroups.
+// Workgroup g owns sketch rows [lo, hi) of Q_A and Q_L and rows [ulo, uhi)
+// of both halves of U; each kernel stages its slab in LDS (leading dimension
+// padded to an odd count of doubles), finishes the previous projection with the
+// coefficients reduced in workgroup order from the previous kernel's partial
+// vectors, and writes its own partial vector to one region of S.coop:
+//   region r < P          : Q coefficients of projection pass r   (+ ||a||^2, ||l||^2 in r = 0)
+//   region P              : U coefficients of U pass 0, ||a_perp||^2, ||l_perp||^2, a_perp . S_A b
+//   region P + u, 0<u<P   : U coefficients of U pass u
+//   region 2P             : gamma^2 and the new h numerator
+// with P = S.passes.  Kernel boundaries order the phases.
 
-struct AppendSh {
-    double aS[kMaxS];
-    double lS[kMaxS];
-    double pA[kMaxD];
-    double pL[kMaxD];
-    double cA[kMaxD];
-    double cL[kMaxD];
-    double cu[2 * kMaxD];
-    double red[kAppendThreads / 64];
-    double sc[8];
+struct ApDims {
+    int d, s, dmax, ld2, CW;
+    int lo, ns, nsp;      // sketch-row slab, padded leading dimension
+    int ulo, nu, nup, nua;
 };
 
-__global__ __launch_bounds__(kAppendThreads) void k_append(State S, int scale_from_norm, int G) {
-    __shared__ AppendSh sh;
-    const int g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int nw = kAppendThreads / 64;
+__device__ ApDims ap_dims(const State& S, int G, int d) {
+    ApDims D;
+    const int g = blockIdx.x;
+    D.d = d;
+    D.s = S.s;
+    D.dmax = S.dmax;
+    D.ld2 = 2 * S.dmax;
+    D.CW = 2 * S.dmax + 8;
+    D.lo = (int)((int64_t)S.s * g / G);
+    D.ns = (int)((int64_t)S.s * (g + 1) / G) - D.lo;
+    D.nsp = D.ns | 1;
+    D.ulo = (int)((int64_t)S.dmax * g / G);
+    D.nu = (int)((int64_t)S.dmax * (g + 1) / G) - D.ulo;
+    D.nup = D.nu | 1;
+    D.nua = max(0, min(D.ulo + D.nu, d) - D.ulo);
+    return D;
+}
+
+__device__ __forceinline__ double* ap_region(const State& S, int G, int region, int g, int CW) {
+    return S.coop + ((int64_t)region * G + g) * CW;
+}
+
+// LDS slab <- columns [0, d) of rows [row0, row0 + nrows) of a column-major matrix
+__device__ void load_slab(const double* __restrict__ src, int64_t ld, int row0, int nrows, int d,
+                          double* dst, int ldd) {
+    const int total = nrows * d, T = kAppendThreads;
+    for (int k0 = threadIdx.x; k0 < total; k0 += 8 * T) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = k0 + u * T;
+            v[u] = k < total ? src[(int64_t)(k / nrows) * ld + row0 + k % nrows] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = k0 + u * T;
+            if (k < total) dst[k % nrows + (k / nrows) * ldd] = v[u];
+        }
+    }
+}
+
+// out[j] = sum over workgroups of region[q * CW + off + j], j < cnt (workgroup order)
+__device__ void reduce_region(const double* region0, int G, int CW, int off, int cnt, double* out) {
+    for (int j = threadIdx.x; j < cnt; j += kAppendThreads)
+        out[j] = strided_sum(region0 + off + j, CW, G);
+}
+
+__device__ double reduce_scalar(const double* region0, int G, int CW, int off) {
+    return strided_sum(region0 + off, CW, G);
+}
+
+// partial[j] = sum_i M[i + j ldm] v[i] for j < d (M, v in LDS)
+__device__ void slab_dots(const double* M, int ldm, int nrows, int d, const double* v,
+                          double* partial) {
+    for (int j = threadIdx.x; j < d; j += kAppendThreads) {
+        const double* mc = M + j * ldm;
+        double e = 0.0;
+        for (int i = 0; i < nrows; ++i) e += mc[i] * v[i];
+        partial[j] = e;
+    }
+}
+
+// two slabs at once (the A and L halves): partial[j] = sum_i Ma v_a + Ml v_l
+__device__ void slab_dots2(const double* Ma, const double* Ml, int ldm, int nrows, int d,
+                           const double* va, const double* vl, double* partial) {
+    for (int j = threadIdx.x; j < d; j += kAppendThreads) {
+        const double* a = Ma + j * ldm;
+        const double* l = Ml + j * ldm;
+        double e = 0.0;
+        for (int i = 0; i < nrows; ++i) e += a[i] * va[i] + l[i] * vl[i];
+        partial[j] = e;
+    }
+}
+
+// out[i] -= sum_j M[i + j ldm] c[j], i < nrows; threads split rows and, when
+// rows are few, contiguous chunks of j (chunk sums added in chunk order).
+__device__ void slab_apply(const double* M, int ldm, int nrows, int d, const double* c,
+                           double* out, double* scratch) {
+    const int T = kAppendThreads, tid = threadIdx.x;
+    __syncthreads();
+    if (nrows <= 0 || d <= 0) {
+        __syncthreads();
+        return;
+    }
+    if (nrows >= T) {
+        for (int i = tid; i < nrows; i += T) {
+            double a = 0.0;
+            for (int j = 0; j < d; ++j) a += M[i + j * ldm] * c[j];
+            out[i] -= a;
+        }
+        __syncthreads();
+        return;
+    }
+    const int nq = T / nrows;
+    const int i = tid % nrows, q = tid / nrows;
+    if (q < nq) {
+        const int j0 = (int)((int64_t)d * q / nq), j1 = (int)((int64_t)d * (q + 1) / nq);
+        double a = 0.0;
+        for (int j = j0; j < j1; ++j) a += M[i + j * ldm] * c[j];
+        scratch[q * nrows + i] = a;
+    }
+    __syncthreads();
+    if (tid < nrows) {
+        double a = 0.0;
+        for (int qq = 0; qq < nq; ++qq) a += scratch[qq * nrows + tid];
+        out[tid] -= a;
+    }
+    __syncthreads();
+}
+
+struct ApShared {
+    double red[kAppendThreads / 64];
+    double cA[kMaxD];
+    double cL[kMaxD];
+    double pA[kMaxD];
+    double pL[kMaxD];
+    double gacc[kMaxD];
+};
+
+// Q pass 0: column scale (breakdown test), reduce the sketch bins of this
+// slab, first projection coefficients.
+__global__ __launch_bounds__(kAppendThreads) void k_ap_q0(State S, int G, int scale_from_norm) {
+    extern __shared__ double dyn[];
+    __shared__ ApShared sh;
     if (*S.status != 0) return;
     const int d = *S.d;
-    const int s = S.s, dmax = S.dmax, ld2 = 2 * dmax;
-    const int CW = 2 * dmax + 8;
-    double* coop = S.coop;
-
-    // ---- column scale (breakdown test on ||r||, identical in every workgroup)
+    const ApDims D = ap_dims(S, G, d);
+    const int g = blockIdx.x, tid = threadIdx.x, T = kAppendThreads;
     double scale;
     if (scale_from_norm) {
-        double a = 0.0;
-        for (int i = tid; i < S.n_norm_part; i += kAppendThreads) a += S.norm_part[i];
-        const double nr2 = block_sum(a, sh.red);
+        const double nr2 = block_sum(thread_strided_sum(S.norm_part, S.n_norm_part, T), sh.red);
         const double nr = sqrt(nr2);
         if (!(nr2 < INFINITY)) {
             if (g == 0 && tid == 0) *S.status = kStatusNonfinite;
@@ -466,118 +570,233 @@ __global__ __launch_bounds__(kAppendThreads) void k_append(State S, int scale_fr
     } else {
         scale = S.cs[d];
     }
-
-    // ---- this workgroup's slab of sketch rows; reduce the partial bins
-    const int lo = (int)((int64_t)s * g / G), hi = (int)((int64_t)s * (g + 1) / G);
-    const int ns = hi - lo;
+    double* Qa = dyn;
+    double* Ql = Qa + (size_t)D.nsp * S.dmax;
+    double* av = Ql + (size_t)D.nsp * S.dmax;
+    double* lv = av + D.nsp;
+    double* scr = lv + D.nsp;   // 2 T
+    load_slab(S.QA, D.s, D.lo, D.ns, d, Qa, D.nsp);
+    load_slab(S.QL, D.s, D.lo, D.ns, d, Ql, D.nsp);
+    // bins of this slab: thread (row i, chunk q) sums a contiguous range of blocks
     const double bscale = S.sketch_mode == 1 ? scale : scale / sqrt((double)S.zeta);
+    const int nq = D.ns > 0 ? T / D.ns : 1;
+    {
+        const int i = D.ns > 0 ? tid % D.ns : 0, q = D.ns > 0 ? tid / D.ns : T;
+        if (q < nq) {
+            const int a0 = (int)((int64_t)S.nbA * q / nq), a1 = (int)((int64_t)S.nbA * (q + 1) / nq);
+            const int l0 = (int)((int64_t)S.nbL * q / nq), l1 = (int)((int64_t)S.nbL * (q + 1) / nq);
+            scr[q * D.ns + i] = strided_sum(S.binA + (int64_t)a0 * D.s + D.lo + i, D.s, a1 - a0);
+            scr[T + q * D.ns + i] = strided_sum(S.binL + (int64_t)l0 * D.s + D.lo + i, D.s, l1 - l0);
+        }
+    }
+    __syncthreads();
     double na2 = 0.0, nl2 = 0.0;
-    for (int i = tid; i < ns; i += kAppendThreads) {
+    if (tid < D.ns) {
         double a = 0.0, l = 0.0;
-        for (int b = 0; b < S.nbA; ++b) a += S.binA[(int64_t)b * s + lo + i];
-        for (int b = 0; b < S.nbL; ++b) l += S.binL[(int64_t)b * s + lo + i];
+        for (int q = 0; q < nq; ++q) {
+            a += scr[q * D.ns + tid];
+            l += scr[T + q * D.ns + tid];
+        }
         a *= bscale;
         l *= bscale;
-        sh.aS[i] = a;
-        sh.lS[i] = l;
-        na2 += a * a;
-        nl2 += l * l;
-    }
-    for (int j = tid; j < d; j += kAppendThreads) {
-        sh.pA[j] = 0.0;
-        sh.pL[j] = 0.0;
+        av[tid] = a;
+        lv[tid] = l;
+        S.wa[D.lo + tid] = a;
+        S.wl[D.lo + tid] = l;
+        na2 = a * a;
+        nl2 = l * l;
     }
     na2 = block_sum(na2, sh.red);
     nl2 = block_sum(nl2, sh.red);
-
-    // ---- projections (CGS when passes = 1, CGS2 when 2)
-    double naTot = 0.0, nlTot = 0.0;
-    int region = 0;
-    for (int pass = 0; pass < S.passes; ++pass, ++region) {
-        double* mine = coop + ((int64_t)region * G + g) * CW;
-        for (int j = wave; j < d; j += nw) {
-            const double* qa = S.QA + (int64_t)j * s + lo;
-            const double* ql = S.QL + (int64_t)j * s + lo;
-            double ea = 0.0, el = 0.0;
-            for (int i = lane; i < ns; i += 64) {
-                ea += qa[i] * sh.aS[i];
-                el += ql[i] * sh.lS[i];
-            }
-            ea = wave_sum(ea);
-            el = wave_sum(el);
-            if (lane == 0) {
-                mine[j] = ea;
-                mine[dmax + j] = el;
-            }
-        }
-        if (pass == 0 && tid == 0) {
-            mine[2 * dmax] = na2;
-            mine[2 * dmax + 1] = nl2;
-        }
-        if (!grid_sync(S.bar, G)) {
-            if (tid == 0) *S.status = kStatusDevice;
-            return;
-        }
-        const double* all = coop + (int64_t)region * G * CW;
-        for (int j = tid; j < d; j += kAppendThreads) {
-            double ca = 0.0, cl = 0.0;
-            for (int q = 0; q < G; ++q) {
-                ca += all[(int64_t)q * CW + j];
-                cl += all[(int64_t)q * CW + dmax + j];
-            }
-            sh.cA[j] = ca;
-            sh.cL[j] = cl;
-            sh.pA[j] += ca;
-            sh.pL[j] += cl;
-        }
-        if (pass == 0) {
-            for (int q = 0; q < G; ++q) {
-                naTot += all[(int64_t)q * CW + 2 * dmax];
-                nlTot += all[(int64_t)q * CW + 2 * dmax + 1];
-            }
-        }
-        __syncthreads();
-        for (int i = tid; i < ns; i += kAppendThreads) {
-            double ea = 0.0, el = 0.0;
-            for (int j = 0; j < d; ++j) {
-                ea += S.QA[(int64_t)j * s + lo + i] * sh.cA[j];
-                el += S.QL[(int64_t)j * s + lo + i] * sh.cL[j];
-            }
-            sh.aS[i] -= ea;
-            sh.lS[i] -= el;
-        }
-        __syncthreads();
+    double* mine = ap_region(S, G, 0, g, D.CW);
+    slab_dots(Qa, D.nsp, D.ns, d, av, mine);
+    slab_dots(Ql, D.nsp, D.ns, d, lv, mine + S.dmax);
+    if (tid == 0) {
+        mine[2 * S.dmax] = na2;
+        mine[2 * S.dmax + 1] = nl2;
     }
+}
 
-    // ---- norms of the projected columns and the new d_A entry
+// Q pass `pass` >= 1: finish the previous projection, next coefficients.
+__global__ __launch_bounds__(kAppendThreads) void k_ap_qp(State S, int G, int pass) {
+    extern __shared__ double dyn[];
+    __shared__ ApShared sh;
+    if (*S.status != 0) return;
+    const int d = *S.d;
+    const ApDims D = ap_dims(S, G, d);
+    const int g = blockIdx.x, tid = threadIdx.x;
+    double* Qa = dyn;
+    double* Ql = Qa + (size_t)D.nsp * S.dmax;
+    double* av = Ql + (size_t)D.nsp * S.dmax;
+    double* lv = av + D.nsp;
+    double* scr = lv + D.nsp;
+    load_slab(S.QA, D.s, D.lo, D.ns, d, Qa, D.nsp);
+    load_slab(S.QL, D.s, D.lo, D.ns, d, Ql, D.nsp);
+    for (int i = tid; i < D.ns; i += kAppendThreads) {
+        av[i] = S.wa[D.lo + i];
+        lv[i] = S.wl[D.lo + i];
+    }
+    const double* prev = S.coop + (int64_t)(pass - 1) * G * D.CW;
+    reduce_region(prev, G, D.CW, 0, d, sh.cA);
+    reduce_region(prev, G, D.CW, S.dmax, d, sh.cL);
+    slab_apply(Qa, D.nsp, D.ns, d, sh.cA, av, scr);
+    slab_apply(Ql, D.nsp, D.ns, d, sh.cL, lv, scr + kAppendThreads);
+    for (int i = tid; i < D.ns; i += kAppendThreads) {
+        S.wa[D.lo + i] = av[i];
+        S.wl[D.lo + i] = lv[i];
+    }
+    double* mine = ap_region(S, G, pass, g, D.CW);
+    slab_dots(Qa, D.nsp, D.ns, d, av, mine);
+    slab_dots(Ql, D.nsp, D.ns, d, lv, mine + S.dmax);
+}
+
+// Q finish: last projection, norms and d_A numerator, U pass 0 on
+// c = [p_A; sqrt(mu) p_L] (rows < d; the new rows are orthogonal to U).
+__global__ __launch_bounds__(kAppendThreads) void k_ap_qf(State S, int G) {
+    extern __shared__ double dyn[];
+    __shared__ ApShared sh;
+    if (*S.status != 0) return;
+    const int d = *S.d;
+    const ApDims D = ap_dims(S, G, d);
+    const int g = blockIdx.x, tid = threadIdx.x, P = S.passes;
+    double* Qa = dyn;
+    double* Ql = Qa + (size_t)D.nsp * S.dmax;
+    double* av = Ql + (size_t)D.nsp * S.dmax;
+    double* lv = av + D.nsp;
+    double* scr = lv + D.nsp;
+    load_slab(S.QA, D.s, D.lo, D.ns, d, Qa, D.nsp);
+    load_slab(S.QL, D.s, D.lo, D.ns, d, Ql, D.nsp);
+    for (int i = tid; i < D.ns; i += kAppendThreads) {
+        av[i] = S.wa[D.lo + i];
+        lv[i] = S.wl[D.lo + i];
+    }
+    const double* last = S.coop + (int64_t)(P - 1) * G * D.CW;
+    reduce_region(last, G, D.CW, 0, d, sh.cA);
+    reduce_region(last, G, D.CW, S.dmax, d, sh.cL);
+    for (int j = tid; j < d; j += kAppendThreads) {
+        double a = 0.0, l = 0.0;
+        for (int r = 0; r < P; ++r) {
+            const double* rg = S.coop + (int64_t)r * G * D.CW;
+            a += strided_sum(rg + j, D.CW, G);
+            l += strided_sum(rg + S.dmax + j, D.CW, G);
+        }
+        sh.pA[j] = a;
+        sh.pL[j] = l;
+    }
+    slab_apply(Qa, D.nsp, D.ns, d, sh.cA, av, scr);
+    slab_apply(Ql, D.nsp, D.ns, d, sh.cL, lv, scr + kAppendThreads);
     double ra = 0.0, rl = 0.0, dl = 0.0;
-    for (int i = tid; i < ns; i += kAppendThreads) {
-        ra += sh.aS[i] * sh.aS[i];
-        rl += sh.lS[i] * sh.lS[i];
-        dl += sh.aS[i] * S.cb[lo + i];
+    for (int i = tid; i < D.ns; i += kAppendThreads) {
+        S.wa[D.lo + i] = av[i];
+        S.wl[D.lo + i] = lv[i];
+        ra += av[i] * av[i];
+        rl += lv[i] * lv[i];
+        dl += av[i] * S.cb[D.lo + i];
     }
     ra = block_sum(ra, sh.red);
     rl = block_sum(rl, sh.red);
-    dl = block_sum(dl, sh.red);
-    {
-        double* mine = coop + ((int64_t)region * G + g) * CW;
-        if (tid == 0) {
-            mine[0] = ra;
-            mine[1] = rl;
-            mine[2] = dl;
+    dl = block_sum(dl, sh.red);   // its barriers also retire every use of the Q slab
+    // U slab over the same LDS
+    double* Ua = dyn;
+    double* Ul = Ua + (size_t)D.nup * S.dmax;
+    double* cuA = Ul + (size_t)D.nup * S.dmax;
+    double* cuL = cuA + D.nup;
+    load_slab(S.U, D.ld2, D.ulo, D.nua, d, Ua, D.nup);
+    load_slab(S.U, D.ld2, S.dmax + D.ulo, D.nua, d, Ul, D.nup);
+    for (int i = tid; i < D.nua; i += kAppendThreads) {
+        const int r = D.ulo + i;
+        cuA[i] = sh.pA[r];
+        cuL[i] = S.sqrt_mu * sh.pL[r];
+        S.wu[r] = cuA[i];
+        S.wu[S.dmax + r] = cuL[i];
+    }
+    __syncthreads();
+    double* mine = ap_region(S, G, P, g, D.CW);
+    slab_dots2(Ua, Ul, D.nup, D.nua, d, cuA, cuL, mine);
+    if (tid == 0) {
+        mine[2 * S.dmax] = ra;
+        mine[2 * S.dmax + 1] = rl;
+        mine[2 * S.dmax + 2] = dl;
+    }
+}
+
+// U pass `upass` >= 1 (or, with last != 0, the finish: gamma^2 and h numerator)
+__global__ __launch_bounds__(kAppendThreads) void k_ap_u(State S, int G, int upass, int last) {
+    extern __shared__ double dyn[];
+    __shared__ ApShared sh;
+    if (*S.status != 0) return;
+    const int d = *S.d;
+    const ApDims D = ap_dims(S, G, d);
+    const int g = blockIdx.x, tid = threadIdx.x, P = S.passes;
+    double* Ua = dyn;
+    double* Ul = Ua + (size_t)D.nup * S.dmax;
+    double* cuA = Ul + (size_t)D.nup * S.dmax;
+    double* cuL = cuA + D.nup;
+    double* scr = cuL + D.nup;
+    load_slab(S.U, D.ld2, D.ulo, D.nua, d, Ua, D.nup);
+    load_slab(S.U, D.ld2, S.dmax + D.ulo, D.nua, d, Ul, D.nup);
+    for (int i = tid; i < D.nua; i += kAppendThreads) {
+        cuA[i] = S.wu[D.ulo + i];
+        cuL[i] = S.wu[S.dmax + D.ulo + i];
+    }
+    const double* prev = S.coop + (int64_t)(P + upass - 1) * G * D.CW;
+    reduce_region(prev, G, D.CW, 0, d, sh.cA);
+    slab_apply(Ua, D.nup, D.nua, d, sh.cA, cuA, scr);
+    slab_apply(Ul, D.nup, D.nua, d, sh.cA, cuL, scr + kAppendThreads);
+    for (int i = tid; i < D.nua; i += kAppendThreads) {
+        S.wu[D.ulo + i] = cuA[i];
+        S.wu[S.dmax + D.ulo + i] = cuL[i];
+    }
+    if (!last) {
+        double* mine = ap_region(S, G, P + upass, g, D.CW);
+        slab_dots2(Ua, Ul, D.nup, D.nua, d, cuA, cuL, mine);
+        return;
+    }
+    double gam2 = 0.0, hnum = 0.0;
+    for (int i = tid; i < D.nua; i += kAppendThreads) {
+        gam2 += cuA[i] * cuA[i] + cuL[i] * cuL[i];
+        hnum += cuA[i] * S.dA[D.ulo + i];
+    }
+    gam2 = block_sum(gam2, sh.red);
+    hnum = block_sum(hnum, sh.red);
+    if (tid == 0) {
+        double* mine = ap_region(S, G, 2 * P, g, D.CW);
+        mine[0] = gam2;
+        mine[1] = hnum;
+    }
+}
+
+// Commit: new columns of Q_A, Q_L, R_A, R_L, U, G, entries of d_A and h, the
+// new column of G^{-1} (row-major: element (r, j) at r * dmax + j) and
+// y = G^{-1} h.  Breakdown when the new stacked column is dependent.
+__global__ __launch_bounds__(kAppendThreads) void k_ap_commit(State S, int G) {
+    __shared__ ApShared sh;
+    if (*S.status != 0) return;
+    const int d = *S.d;
+    const ApDims D = ap_dims(S, G, d);
+    const int g = blockIdx.x, tid = threadIdx.x, P = S.passes, T = kAppendThreads;
+    const double* r0 = S.coop;
+    const double* rP = S.coop + (int64_t)P * G * D.CW;
+    const double naTot = reduce_scalar(r0, G, D.CW, 2 * S.dmax);
+    const double nlTot = reduce_scalar(r0, G, D.CW, 2 * S.dmax + 1);
+    const double ra = reduce_scalar(rP, G, D.CW, 2 * S.dmax);
+    const double rl = reduce_scalar(rP, G, D.CW, 2 * S.dmax + 1);
+    const double dl = reduce_scalar(rP, G, D.CW, 2 * S.dmax + 2);
+    const double* r2P = S.coop + (int64_t)2 * P * G * D.CW;
+    double gam2 = reduce_scalar(r2P, G, D.CW, 0);
+    double hnum = reduce_scalar(r2P, G, D.CW, 1);
+    for (int j = tid; j < d; j += T) {
+        double a = 0.0, l = 0.0, u = 0.0;
+        for (int r = 0; r < P; ++r) {
+            const double* rg = S.coop + (int64_t)r * G * D.CW;
+            const double* ru = S.coop + (int64_t)(P + r) * G * D.CW;
+            a += strided_sum(rg + j, D.CW, G);
+            l += strided_sum(rg + S.dmax + j, D.CW, G);
+            u += strided_sum(ru + j, D.CW, G);
         }
-        if (!grid_sync(S.bar, G)) {
-            if (tid == 0) *S.status = kStatusDevice;
-            return;
-        }
-        const double* all = coop + (int64_t)region * G * CW;
-        ra = rl = dl = 0.0;
-        for (int q = 0; q < G; ++q) {
-            ra += all[(int64_t)q * CW + 0];
-            rl += all[(int64_t)q * CW + 1];
-            dl += all[(int64_t)q * CW + 2];
-        }
-        ++region;
+        sh.pA[j] = a;
+        sh.pL[j] = l;
+        sh.gacc[j] = u;
     }
     double rhoA = sqrt(ra), rhoL = sqrt(rl);
     const bool degA = !(rhoA > 1e-14 * sqrt(naTot));
@@ -586,153 +805,112 @@ __global__ __launch_bounds__(kAppendThreads) void k_append(State S, int scale_fr
     if (degL) rhoL = 0.0;
     const double qsA = degA ? 0.0 : 1.0 / rhoA, qsL = degL ? 0.0 : 1.0 / rhoL;
     const double dAnew = degA ? 0.0 : dl / rhoA;
-    for (int i = tid; i < ns; i += kAppendThreads) {
-        S.QA[(int64_t)d * s + lo + i] = sh.aS[i] * qsA;
-        S.QL[(int64_t)d * s + lo + i] = sh.lS[i] * qsL;
-    }
-    if (g == 0) {
-        for (int j = tid; j < d; j += kAppendThreads) {
-            S.RA[(int64_t)d * dmax + j] = sh.pA[j];
-            S.RL[(int64_t)d * dmax + j] = sh.pL[j];
-        }
-        if (tid == 0) {
-            S.RA[(int64_t)d * dmax + d] = rhoA;
-            S.RL[(int64_t)d * dmax + d] = rhoL;
-            S.dA[d] = dAnew;
-            if (degA || degL) *S.degenerate += (int)degA + (int)degL;
-        }
-    }
-
-    // ---- stacked factor: append c = [p_A, rho_A ; sqrt(mu) p_L, sqrt(mu) rho_L]
-    // to U (orthonormal columns) with the same projections; rows of U pair with
-    // rows 0..d of R_A (physical rows 0..d) and of R_L (rows dmax..dmax+d).
-    const int nrow = d + 1;
-    const int ulo = (int)((int64_t)nrow * g / G), uhi = (int)((int64_t)nrow * (g + 1) / G);
-    const int nu = uhi - ulo;
-    double* cuA = sh.cu;
-    double* cuL = sh.cu + kMaxD;
-    for (int i = tid; i < nu; i += kAppendThreads) {
-        const int r = ulo + i;
-        cuA[i] = r < d ? sh.pA[r] : rhoA;
-        cuL[i] = S.sqrt_mu * (r < d ? sh.pL[r] : rhoL);
-    }
-    __syncthreads();
-    double* gtmp = sh.cA;   // free after the Q projections
-    double* gacc = sh.cL;
-    for (int j = tid; j < d; j += kAppendThreads) gacc[j] = 0.0;
-    for (int pass = 0; pass < S.passes; ++pass, ++region) {
-        double* mine = coop + ((int64_t)region * G + g) * CW;
-        for (int j = wave; j < d; j += nw) {
-            const double* uc = S.U + (int64_t)j * ld2;
-            double e = 0.0;
-            for (int i = lane; i < nu; i += 64)
-                e += uc[ulo + i] * cuA[i] + uc[dmax + ulo + i] * cuL[i];
-            e = wave_sum(e);
-            if (lane == 0) mine[j] = e;
-        }
-        if (!grid_sync(S.bar, G)) {
-            if (tid == 0) *S.status = kStatusDevice;
-            return;
-        }
-        const double* all = coop + (int64_t)region * G * CW;
-        for (int j = tid; j < d; j += kAppendThreads) {
-            double c = 0.0;
-            for (int q = 0; q < G; ++q) c += all[(int64_t)q * CW + j];
-            gtmp[j] = c;
-            gacc[j] += c;
-        }
-        __syncthreads();
-        for (int i = tid; i < nu; i += kAppendThreads) {
-            double ea = 0.0, el = 0.0;
-            for (int j = 0; j < d; ++j) {
-                const double* uc = S.U + (int64_t)j * ld2;
-                ea += uc[ulo + i] * gtmp[j];
-                el += uc[dmax + ulo + i] * gtmp[j];
-            }
-            cuA[i] -= ea;
-            cuL[i] -= el;
-        }
-        __syncthreads();
-    }
-    double gam2 = 0.0, hnum = 0.0;
-    for (int i = tid; i < nu; i += kAppendThreads) {
-        const int r = ulo + i;
-        gam2 += cuA[i] * cuA[i] + cuL[i] * cuL[i];
-        hnum += cuA[i] * (r < d ? S.dA[r] : dAnew);
-    }
-    gam2 = block_sum(gam2, sh.red);
-    hnum = block_sum(hnum, sh.red);
-    {
-        double* mine = coop + ((int64_t)region * G + g) * CW;
-        if (tid == 0) {
-            mine[0] = gam2;
-            mine[1] = hnum;
-        }
-        if (!grid_sync(S.bar, G)) {
-            if (tid == 0) *S.status = kStatusDevice;
-            return;
-        }
-        const double* all = coop + (int64_t)region * G * CW;
-        gam2 = hnum = 0.0;
-        for (int q = 0; q < G; ++q) {
-            gam2 += all[(int64_t)q * CW + 0];
-            hnum += all[(int64_t)q * CW + 1];
-        }
-    }
+    // the new rows (rho_A, sqrt(mu) rho_L) are orthogonal to U's old columns
+    gam2 += rhoA * rhoA + S.mu * rhoL * rhoL;
+    hnum += rhoA * dAnew;
     const double gam = sqrt(gam2);
+    __syncthreads();
     if (!(gam < INFINITY)) {
         if (g == 0 && tid == 0) *S.status = kStatusNonfinite;
         return;
     }
-    {
-        // the new stacked column must keep more than 1e-14 of its norm after
-        // projection, else the expansion adds nothing: stop (breakdown) without
-        // appending (identical decision in every workgroup)
-        double c2 = rhoA * rhoA + S.mu * rhoL * rhoL;
-        for (int j = 0; j < d; ++j) c2 += sh.pA[j] * sh.pA[j] + S.mu * sh.pL[j] * sh.pL[j];
-        if (!(gam > 1e-14 * sqrt(c2))) {
-            if (g == 0 && tid == 0) *S.status = kStatusBreakdown;
-            return;
-        }
+    double c2 = 0.0;
+    for (int j = tid; j < d; j += T) c2 += sh.pA[j] * sh.pA[j] + S.mu * sh.pL[j] * sh.pL[j];
+    c2 = block_sum(c2, sh.red) + rhoA * rhoA + S.mu * rhoL * rhoL;
+    if (!(gam > 1e-14 * sqrt(c2))) {
+        // the expansion adds nothing to the projected problem: stop, no append
+        if (g == 0 && tid == 0) *S.status = kStatusBreakdown;
+        return;
     }
     const double hnew = hnum / gam;
-    for (int i = tid; i < nu; i += kAppendThreads) {
-        S.U[(int64_t)d * ld2 + ulo + i] = cuA[i] / gam;
-        S.U[(int64_t)d * ld2 + dmax + ulo + i] = cuL[i] / gam;
+    for (int i = tid; i < D.ns; i += T) {
+        S.QA[(int64_t)d * D.s + D.lo + i] = S.wa[D.lo + i] * qsA;
+        S.QL[(int64_t)d * D.s + D.lo + i] = S.wl[D.lo + i] * qsL;
+    }
+    for (int i = tid; i < D.nua; i += T) {
+        S.U[(int64_t)d * D.ld2 + D.ulo + i] = S.wu[D.ulo + i] / gam;
+        S.U[(int64_t)d * D.ld2 + S.dmax + D.ulo + i] = S.wu[S.dmax + D.ulo + i] / gam;
     }
     if (g == 0) {
-        for (int j = tid; j < d; j += kAppendThreads) S.G[(int64_t)d * dmax + j] = gacc[j];
+        for (int j = tid; j < d; j += T) {
+            S.RA[(int64_t)d * S.dmax + j] = sh.pA[j];
+            S.RL[(int64_t)d * S.dmax + j] = sh.pL[j];
+            S.G[(int64_t)d * S.dmax + j] = sh.gacc[j];
+        }
         if (tid == 0) {
-            S.G[(int64_t)d * dmax + d] = gam;
+            S.RA[(int64_t)d * S.dmax + d] = rhoA;
+            S.RL[(int64_t)d * S.dmax + d] = rhoL;
+            S.dA[d] = dAnew;
+            S.U[(int64_t)d * D.ld2 + d] = rhoA / gam;
+            S.U[(int64_t)d * D.ld2 + S.dmax + d] = S.sqrt_mu * rhoL / gam;
+            S.G[(int64_t)d * S.dmax + d] = gam;
             S.h[d] = hnew;
+            if (degA || degL) *S.degenerate += (int)degA + (int)degL;
         }
     }
-
-    // ---- G^{-1} gains column [-G^{-1} g / gam ; 1 / gam]; y = G^{-1} h.
-    // Rows [ylo, yhi) of this workgroup only need their own rows of G^{-1}.
-    // (S.G is reused below as storage of the inverse: column j of the inverse
-    // lives in Ginv = S.G + dmax*dmax.)
-    double* Ginv = S.G + (int64_t)dmax * dmax;
-    const int ylo = ulo, yhi = uhi;
-    for (int r = ylo + tid; r < yhi; r += kAppendThreads) {
-        double nc, yr = 0.0;
+    // G^{-1} gains column [-G^{-1} g / gam ; 1 / gam]; rows split over workgroups
+    double* Gi = S.G + (int64_t)S.dmax * S.dmax;
+    const int nrow = d + 1;
+    const int ylo = (int)((int64_t)nrow * g / G), yhi = (int)((int64_t)nrow * (g + 1) / G);
+    const int lane = tid & 63, wave = tid >> 6;
+    for (int r = ylo + wave; r < yhi; r += T / 64) {
+        double a = 0.0, yr = 0.0;
         if (r < d) {
-            double a = 0.0;
-            for (int j = r; j < d; ++j) {
-                const double gi = Ginv[(int64_t)j * dmax + r];
-                a += gi * gacc[j];
-                yr += gi * S.h[j];
+            const double* gr = Gi + (int64_t)r * S.dmax;
+            for (int j = r + lane; j < d; j += 64) {
+                a += gr[j] * sh.gacc[j];
+                yr += gr[j] * S.h[j];
             }
-            nc = -a / gam;
-        } else {
-            nc = 1.0 / gam;
+            a = wave_sum(a);
+            yr = wave_sum(yr);
         }
-        yr += nc * hnew;
-        Ginv[(int64_t)d * dmax + r] = nc;
-        S.y[r] = yr;
-        S.yprev[r] = yr;
+        const double nc = r < d ? -a / gam : 1.0 / gam;
+        if (lane == 0) {
+            Gi[(int64_t)r * S.dmax + d] = nc;
+            S.y[r] = yr + nc * hnew;
+            S.yprev[r] = yr + nc * hnew;
+        }
     }
     if (g == 0 && tid == 0) *S.d = d + 1;
+}
+
+// One residual correction of y = G^{-1} h with the triangular factor itself:
+// y <- y + G^{-1} (h - G y).  It brings the explicit-inverse solve to the
+// accuracy of back substitution.  One workgroup; G is column-major, G^{-1}
+// row-major.
+__global__ __launch_bounds__(1024) void k_yfix(State S) {
+    __shared__ double yv[kMaxD];
+    __shared__ double rv[kMaxD];
+    if (*S.status != 0) return;
+    const int d = *S.d, dmax = S.dmax;
+    for (int i = threadIdx.x; i < d; i += 1024) yv[i] = S.y[i];
+    __syncthreads();
+    for (int i = threadIdx.x; i < d; i += 1024) {
+        const double* gc = S.G + (int64_t)i * dmax + i;   // G[i, j] at gc[(j - i) dmax]
+        double a = 0.0;
+        int j = i;
+        for (; j + 8 <= d; j += 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = gc[(int64_t)(j - i + u) * dmax];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a += v[u] * yv[j + u];
+        }
+        for (; j < d; ++j) a += gc[(int64_t)(j - i) * dmax] * yv[j];
+        rv[i] = S.h[i] - a;
+    }
+    __syncthreads();
+    const double* Gi = S.G + (int64_t)dmax * dmax;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int i = wave; i < d; i += 16) {
+        double a = 0.0;
+        for (int j = i + lane; j < d; j += 64) a += Gi[(int64_t)i * dmax + j] * rv[j];
+        a = wave_sum(a);
+        if (lane == 0) {
+            S.y[i] = yv[i] + a;
+            S.yprev[i] = yv[i] + a;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -746,30 +924,28 @@ __global__ __launch_bounds__(kBlock) void k_refine(State S) {
     if (*S.status != 0) return;
     const int d = *S.d;
     const int dmax = S.dmax;
-    const double* Ginv = S.G + (int64_t)dmax * dmax;
+    const double* Gi = S.G + (int64_t)dmax * dmax;   // row-major G^{-1}
     for (int j = threadIdx.x; j < d; j += kBlock) {
-        double a = 0.0;
-        for (int b = 0; b < S.ngt; ++b) a += S.gpart[(int64_t)b * dmax + j];
-        gv[j] = a;
+        gv[j] = strided_sum(S.gpart + j, dmax, S.ngt);
     }
     __syncthreads();
-    // t = G^{-T} g : t_j = sum_{i <= j} Ginv[i, j] g_i
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int j = wave; j < d; j += kWaves) {
-        double a = 0.0;
-        for (int i = lane; i <= j; i += 64) a += Ginv[(int64_t)j * dmax + i] * gv[i];
-        a = wave_sum(a);
-        if (lane == 0) tv[j] = a;
+    // t = G^{-T} g : t_j = sum_{i <= j} Gi[i, j] g_i
+    for (int j = threadIdx.x; j < d; j += kBlock) {
+        tv[j] = strided_dot(Gi + j, dmax, gv, j + 1);
     }
     __syncthreads();
     const double eta2 = fmin((double)d / (double)S.s, 0.999);
     const double alpha = (1.0 - eta2) * (1.0 - eta2), beta = eta2;
-    for (int i = threadIdx.x; i < d; i += kBlock) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int i = wave; i < d; i += kWaves) {
         double a = 0.0;
-        for (int j = i; j < d; ++j) a += Ginv[(int64_t)j * dmax + i] * tv[j];
-        const double yi = S.y[i], yp = S.yprev[i];
-        S.y[i] = yi - alpha * a + beta * (yi - yp);
-        S.yprev[i] = yi;
+        for (int j = i + lane; j < d; j += 64) a += Gi[(int64_t)i * dmax + j] * tv[j];
+        a = wave_sum(a);
+        if (lane == 0) {
+            const double yi = S.y[i], yp = S.yprev[i];
+            S.y[i] = yi - alpha * a + beta * (yi - yp);
+            S.yprev[i] = yi;
+        }
     }
 }
 
@@ -783,11 +959,9 @@ __global__ __launch_bounds__(kBlock) void k_residual_small(State S, double* out2
     const int d = *S.d, dmax = S.dmax;
     double ea = 0.0, el = 0.0, dd = 0.0;
     for (int i = threadIdx.x; i < d; i += kBlock) {
-        double a = 0.0, l = 0.0;
-        for (int j = i; j < d; ++j) {
-            a += S.RA[(int64_t)j * dmax + i] * S.y[j];
-            l += S.RL[(int64_t)j * dmax + i] * S.y[j];
-        }
+        const int64_t o = (int64_t)i * dmax + i;
+        const double a = strided_dot(S.RA + o, dmax, S.y + i, d - i);
+        const double l = strided_dot(S.RL + o, dmax, S.y + i, d - i);
         const double e = a - S.dA[i];
         ea += e * e;
         el += l * l;
@@ -811,45 +985,35 @@ __global__ __launch_bounds__(kBlock) void k_backward_small(State S, double* v_ou
     __shared__ double zv[kMaxD];
     __shared__ double red[kWaves];
     const int d = *S.d, dmax = S.dmax;
-    const double* Ginv = S.G + (int64_t)dmax * dmax;
+    const double* Gi = S.G + (int64_t)dmax * dmax;   // row-major G^{-1}
     for (int j = threadIdx.x; j < d; j += kBlock) {
-        double a = 0.0;
-        for (int b = 0; b < S.ngt; ++b) a += S.gpart[(int64_t)b * dmax + j];
-        gv[j] = a;
+        gv[j] = strided_sum(S.gpart + j, dmax, S.ngt);
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < d; j += kBlock) {
+        tv[j] = strided_dot(Gi + j, dmax, gv, j + 1);
     }
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int j = wave; j < d; j += kWaves) {
+    for (int i = wave; i < d; i += kWaves) {
         double a = 0.0;
-        for (int i = lane; i <= j; i += 64) a += Ginv[(int64_t)j * dmax + i] * gv[i];
+        for (int j = i + lane; j < d; j += 64) a += Gi[(int64_t)i * dmax + j] * tv[j];
         a = wave_sum(a);
-        if (lane == 0) tv[j] = a;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < d; i += kBlock) {
-        double a = 0.0;
-        for (int j = i; j < d; ++j) a += Ginv[(int64_t)j * dmax + i] * tv[j];
-        zv[i] = a;
+        if (lane == 0) zv[i] = a;
     }
     __syncthreads();
     // tv <- R_A z, gv <- (R_L z) * (R_L y) terms
     double prod = 0.0;
     for (int i = threadIdx.x; i < d; i += kBlock) {
-        double a = 0.0, lz = 0.0, ly = 0.0;
-        for (int j = i; j < d; ++j) {
-            a += S.RA[(int64_t)j * dmax + i] * zv[j];
-            lz += S.RL[(int64_t)j * dmax + i] * zv[j];
-            ly += S.RL[(int64_t)j * dmax + i] * S.y[j];
-        }
+        const int64_t o = (int64_t)i * dmax + i;
+        const double a = strided_dot(S.RA + o, dmax, zv + i, d - i);
+        const double lz = strided_dot(S.RL + o, dmax, zv + i, d - i);
+        const double ly = strided_dot(S.RL + o, dmax, S.y + i, d - i);
         tv[i] = a;
         prod += lz * ly;
     }
     prod = block_sum(prod, red);   // contains __syncthreads
-    for (int r = threadIdx.x; r < S.s; r += kBlock) {
-        double a = 0.0;
-        for (int j = 0; j < d; ++j) a += S.QA[(int64_t)j * S.s + r] * tv[j];
-        v_out[r] = a;
-    }
+    for (int r = threadIdx.x; r < S.s; r += kBlock) v_out[r] = strided_dot(S.QA + r, S.s, tv, d);
     if (threadIdx.x == 0) gmu_out[0] = -prod;
 }
 
@@ -972,12 +1136,14 @@ void launch_forward(const State& S, const double* x, const double* b, double* u,
     int nbA = 0;
     const int nb = forward_blocks(S, with_L, &nbA);
     (void)nbF;
+    // x == nullptr: the basis column d (device counter), and skip on a set status
+    const int* status = x ? nullptr : S.status;
     if (S.vdt == 0)
-        hipLaunchKernelGGL(k_forward<float>, dim3(nb), dim3(kBlock), 0, st, S.A, S.L, nbA, x, b,
-                           u, t, upart, tpart);
+        hipLaunchKernelGGL(k_forward<float>, dim3(nb), dim3(kBlock), 0, st, S.A, S.L, nbA, x, S.W,
+                           S.d, S.n, b, u, t, upart, tpart, status);
     else
-        hipLaunchKernelGGL(k_forward<double>, dim3(nb), dim3(kBlock), 0, st, S.A, S.L, nbA, x, b,
-                           u, t, upart, tpart);
+        hipLaunchKernelGGL(k_forward<double>, dim3(nb), dim3(kBlock), 0, st, S.A, S.L, nbA, x,
+                           S.W, S.d, S.n, b, u, t, upart, tpart, status);
 }
 
 int adjoint_blocks(const State& S) {
@@ -997,31 +1163,33 @@ void launch_adjoint(const State& S, const double* u, const double* t, bool with_
                            with_L ? 1 : 0, mu, u, t, dst_fixed, S.W, S.d, S.n, part, status);
 }
 
-template <typename T>
-static void launch_sketch_t(const State& S, int col, bool vec_mode, const double* vec,
-                            hipStream_t st) {
-    const size_t shm = (size_t)kWaves * S.s * sizeof(double);
-    const int nb = S.nbA + (vec_mode ? 0 : S.nbL);
-    const int nbL = vec_mode ? 0 : S.nbL;
-    const int* status = (col < 0) ? S.status : nullptr;
-#define SGKS_SK(Zv)                                                                           \
-    hipLaunchKernelGGL((k_sketch<T, Zv>), dim3(nb), dim3(kBlock), shm, st, S.A, S.L, S.nbA,   \
-                       nbL, vec, S.W, S.d, S.n, col, vec_mode ? 1 : 0, S.s, S.seed,           \
-                       S.sketch_mode, S.binA, S.binL, status)
+void launch_scatter(const State& S, const double* zA, const double* zL, hipStream_t st,
+                    bool honor_status) {
+    const size_t shm = (size_t)kSketchWaves * S.s * sizeof(double);
+    const int nbL = zL ? S.nbL : 0;
+    const int nb = S.nbA + nbL;
+    const int* status = honor_status ? S.status : nullptr;
+#define SGKS_SC(Zv)                                                                             \
+    hipLaunchKernelGGL((k_scatter<Zv>), dim3(nb), dim3(kSketchBlock), shm, st, zA, S.m, zL, S.p, \
+                       S.nbA, nbL, S.s, S.seed, S.sketch_mode, S.binA, S.binL, status)
     switch (S.zeta) {
-        case 2: SGKS_SK(2); break;
-        case 4: SGKS_SK(4); break;
-        case 16: SGKS_SK(16); break;
-        default: SGKS_SK(8); break;
+        case 2: SGKS_SC(2); break;
+        case 4: SGKS_SC(4); break;
+        case 16: SGKS_SC(16); break;
+        default: SGKS_SC(8); break;
     }
-#undef SGKS_SK
+#undef SGKS_SC
 }
 
 void launch_sketch(const State& S, int col, bool vec_mode, const double* vec, hipStream_t st) {
-    if (S.vdt == 0)
-        launch_sketch_t<float>(S, col, vec_mode, vec, st);
-    else
-        launch_sketch_t<double>(S, col, vec_mode, vec, st);
+    if (vec_mode) {
+        launch_scatter(S, vec, nullptr, st, false);
+        return;
+    }
+    // z = A w, L w into the free u, t buffers, then the scatter
+    const double* x = col >= 0 ? S.W + (int64_t)col * S.n : nullptr;
+    launch_forward(S, x, nullptr, S.u, S.t, true, nullptr, nullptr, 0, st);
+    launch_scatter(S, S.u, S.t, st, col < 0);
 }
 
 void launch_gemv(const State& S, const double* coef, bool coef_from_cs, double* out,
@@ -1056,18 +1224,45 @@ int max_append_groups() {
     return cus > 0 ? cus : 1;
 }
 
-int launch_append(const State& S, bool scale_from_norm, int groups, hipStream_t st) {
-    int sfn = scale_from_norm ? 1 : 0;
-    int G = groups;
-    State Sc = S;
-    if (G <= 1) {
-        hipLaunchKernelGGL(k_append, dim3(1), dim3(kAppendThreads), 0, st, Sc, sfn, 1);
-        return hipGetLastError() == hipSuccess ? 0 : -1;
+size_t append_lds_bytes(int s, int dmax, int G) {
+    const int ns = ((s + G - 1) / G) | 1;
+    const int nu = ((dmax + G - 1) / G) | 1;
+    const size_t q = (size_t)2 * ns * dmax + 2 * ns + 2 * kAppendThreads;
+    const size_t u = (size_t)2 * nu * dmax + 2 * nu + 2 * kAppendThreads;
+    return sizeof(double) * (q > u ? q : u);
+}
+
+int choose_append_groups(int s, int dmax, int cap) {
+    int G = (s + 31) / 32;
+    if (G < 4) G = 4;
+    while (G < cap && append_lds_bytes(s, dmax, G) > kAppendLdsBudget) ++G;
+    if (G > cap) G = cap;
+    return G;
+}
+
+int launch_append(const State& S, bool scale_from_norm, int G, hipStream_t st) {
+    const size_t shm = append_lds_bytes(S.s, S.dmax, G);
+    if (shm > kAppendLdsBudget) return -1;
+    static thread_local bool configured = false;
+    if (shm > 64 * 1024 && !configured) {
+        const void* ks[] = {(const void*)k_ap_q0, (const void*)k_ap_qp, (const void*)k_ap_qf,
+                            (const void*)k_ap_u};
+        for (const void* k : ks)
+            if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)kAppendLdsBudget) != hipSuccess)
+                return -1;
+        configured = true;
     }
-    void* args[] = {&Sc, &sfn, &G};
-    hipError_t e = hipLaunchCooperativeKernel((const void*)k_append, dim3(G),
-                                              dim3(kAppendThreads), args, 0, st);
-    return e == hipSuccess ? 0 : -1;
+    const dim3 grid(G), block(kAppendThreads);
+    hipLaunchKernelGGL(k_ap_q0, grid, block, shm, st, S, G, scale_from_norm ? 1 : 0);
+    for (int pass = 1; pass < S.passes; ++pass)
+        hipLaunchKernelGGL(k_ap_qp, grid, block, shm, st, S, G, pass);
+    hipLaunchKernelGGL(k_ap_qf, grid, block, shm, st, S, G);
+    for (int u = 1; u < S.passes; ++u) hipLaunchKernelGGL(k_ap_u, grid, block, shm, st, S, G, u, 0);
+    hipLaunchKernelGGL(k_ap_u, grid, block, shm, st, S, G, S.passes, 1);
+    hipLaunchKernelGGL(k_ap_commit, grid, block, 0, st, S, G);
+    hipLaunchKernelGGL(k_yfix, dim3(1), dim3(1024), 0, st, S);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 void launch_refine(const State& S, hipStream_t st) {

@@ -76,16 +76,30 @@ int choose_lanes(int64_t nnz, int64_t rows) {
     return v;
 }
 
-template <typename P>
-hipError_t dalloc(sgks_ctx* c, P** p, size_t bytes) {
-    void* q = nullptr;
-    hipError_t e = hipMalloc(&q, bytes ? bytes : 8);
-    if (e == hipSuccess) {
-        c->allocs.push_back(q);
-        *p = (P*)q;
+// One device allocation carved into 256-byte aligned pieces: fewer runtime
+// allocations at create, and the small state shares a few large pages.
+struct Arena {
+    struct Req {
+        void** p;
+        size_t off;
+    };
+    std::vector<Req> reqs;
+    size_t total = 0;
+    template <typename P>
+    void add(P** p, size_t bytes) {
+        reqs.push_back({(void**)p, total});
+        total += (bytes + 255) / 256 * 256;
+        if (bytes == 0) total += 256;
     }
-    return e;
-}
+    hipError_t commit(sgks_ctx* c) {
+        char* base = nullptr;
+        hipError_t e = hipMalloc((void**)&base, total);
+        if (e != hipSuccess) return e;
+        c->allocs.push_back(base);
+        for (const Req& r : reqs) *r.p = base + r.off;
+        return hipSuccess;
+    }
+};
 
 int check_csr(const sgks_csr* M) {
     if (!M) return SGKS_ERR_INVALID_ARG;
@@ -220,22 +234,10 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
         }                                   \
     } while (0)
 
-    // transposes of A and L (explicit CSR, n rows)
-    SGKS_TRY(dalloc(c, &c->At_rowptr, (S.n + 1) * 4));
-    SGKS_TRY(dalloc(c, &c->At_col, S.A.nnz * 4));
-    SGKS_TRY(dalloc(c, (char**)&c->At_val, S.A.nnz * vsz));
-    SGKS_TRY(dalloc(c, &c->Lt_rowptr, (S.n + 1) * 4));
-    SGKS_TRY(dalloc(c, &c->Lt_col, S.L.nnz * 4));
-    SGKS_TRY(dalloc(c, (char**)&c->Lt_val, S.L.nnz * vsz));
-    if (sgks::transpose_csr(S.A, S.vdt, c->At_rowptr, c->At_col, c->At_val, c->st) ||
-        sgks::transpose_csr(S.L, S.vdt, c->Lt_rowptr, c->Lt_col, c->Lt_val, c->st)) {
-        sgks_destroy(c);
-        return SGKS_ERR_HIP;
-    }
-    S.At = Csr{S.n, S.m, S.A.nnz, c->At_rowptr, c->At_col, c->At_val,
+    // transposes of A and L (explicit CSR, n rows): shapes now, arrays below
+    S.At = Csr{S.n, S.m, S.A.nnz, nullptr, nullptr, nullptr,
                c->opt.lanes_At ? c->opt.lanes_At : choose_lanes(S.A.nnz, S.n)};
-    S.Lt = Csr{S.n, S.p, S.L.nnz, c->Lt_rowptr, c->Lt_col, c->Lt_val,
-               choose_lanes(S.L.nnz, S.n)};
+    S.Lt = Csr{S.n, S.p, S.L.nnz, nullptr, nullptr, nullptr, choose_lanes(S.L.nnz, S.n)};
 
     // scatter blocks: about two 64-entry tiles per wave, at most kMaxSketchBlocks per operator
     auto sk_blocks = [](int64_t rows) {
@@ -267,7 +269,8 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
         int G = c->opt.append_groups;
         if (G == 0) G = sgks::choose_append_groups(s, dmax, cap < 64 ? cap : 64);
         if (G > cap) G = cap;
-        if (sgks::append_lds_bytes(s, dmax, G) > sgks::kAppendLdsBudget) {
+        if (G > sgks::kMaxAppendGroups || (s + G - 1) / G > sgks::kAppendMaxSlab ||
+            (dmax + G - 1) / G > sgks::kAppendMaxSlab) {
             sgks_destroy(c);
             return SGKS_ERR_SKETCH_SIZE;
         }
@@ -276,40 +279,62 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
     const int regions = 2 * S.passes + 2;
     const int CW = 2 * dmax + 8;
 
-    SGKS_TRY(dalloc(c, (double**)&S.b, S.m * 8));
-    SGKS_TRY(dalloc(c, &S.x, S.n * 8));
-    SGKS_TRY(dalloc(c, &S.u, S.m * 8));
-    SGKS_TRY(dalloc(c, &S.t, S.p * 8));
-    SGKS_TRY(dalloc(c, &S.rtmp, S.n * 8));
-    SGKS_TRY(dalloc(c, &S.W, (size_t)S.n * dmax * 8));
-    SGKS_TRY(dalloc(c, &S.cs, dmax * 8));
-    SGKS_TRY(dalloc(c, &S.QA, (size_t)s * dmax * 8));
-    SGKS_TRY(dalloc(c, &S.QL, (size_t)s * dmax * 8));
-    SGKS_TRY(dalloc(c, &S.RA, (size_t)dmax * dmax * 8));
-    SGKS_TRY(dalloc(c, &S.RL, (size_t)dmax * dmax * 8));
-    SGKS_TRY(dalloc(c, &S.U, (size_t)2 * dmax * dmax * 8));
-    SGKS_TRY(dalloc(c, &S.G, (size_t)2 * dmax * dmax * 8));   // G, then G^{-1}
-    SGKS_TRY(dalloc(c, &S.h, dmax * 8));
-    SGKS_TRY(dalloc(c, &S.dA, dmax * 8));
-    SGKS_TRY(dalloc(c, &S.cb, s * 8));
-    SGKS_TRY(dalloc(c, &S.y, dmax * 8));
-    SGKS_TRY(dalloc(c, &S.yprev, dmax * 8));
-    SGKS_TRY(dalloc(c, &S.norm_part, S.n_norm_part * 8));
-    SGKS_TRY(dalloc(c, &S.binA, (size_t)S.nbA * s * 8));
-    SGKS_TRY(dalloc(c, &S.binL, (size_t)S.nbL * s * 8));
-    SGKS_TRY(dalloc(c, &S.wa, s * 8));
-    SGKS_TRY(dalloc(c, &S.wl, s * 8));
-    SGKS_TRY(dalloc(c, &S.wu, 2 * dmax * 8));
-    SGKS_TRY(dalloc(c, &S.gpart, (size_t)S.ngt * dmax * 8));
-    SGKS_TRY(dalloc(c, &S.coop, (size_t)regions * c->groups * CW * 8));
-    SGKS_TRY(dalloc(c, &S.scal, (16 + 2 * dmax) * 8));
-    SGKS_TRY(dalloc(c, &S.d, 64));
-    SGKS_TRY(dalloc(c, &S.status, 64));
-    SGKS_TRY(dalloc(c, &S.degenerate, 64));
-    SGKS_TRY(dalloc(c, &c->upart, c->nbF_A * 8));
-    SGKS_TRY(dalloc(c, &c->tpart, (c->nbF_L > 0 ? c->nbF_L : 1) * 8));
-    SGKS_TRY(dalloc(c, &c->coefbuf, dmax * 8));
-    SGKS_TRY(dalloc(c, &c->sbuf, s * 8));
+    Arena ar;
+    ar.add(&c->At_rowptr, (S.n + 1) * 4);
+    ar.add(&c->At_col, S.A.nnz * 4);
+    ar.add((char**)&c->At_val, S.A.nnz * vsz);
+    ar.add(&c->Lt_rowptr, (S.n + 1) * 4);
+    ar.add(&c->Lt_col, S.L.nnz * 4);
+    ar.add((char**)&c->Lt_val, S.L.nnz * vsz);
+    ar.add((double**)&S.b, S.m * 8);
+    ar.add(&S.x, S.n * 8);
+    ar.add(&S.u, S.m * 8);
+    ar.add(&S.t, S.p * 8);
+    ar.add(&S.rtmp, S.n * 8);
+    ar.add(&S.W, (size_t)S.n * dmax * 8);
+    // the small state, together
+    ar.add(&S.cs, dmax * 8);
+    ar.add(&S.QA, (size_t)s * dmax * 8);
+    ar.add(&S.QL, (size_t)s * dmax * 8);
+    ar.add(&S.RA, (size_t)dmax * dmax * 8);
+    ar.add(&S.RL, (size_t)dmax * dmax * 8);
+    ar.add(&S.U, (size_t)2 * dmax * dmax * 8);
+    ar.add(&S.G, (size_t)2 * dmax * dmax * 8);   // G, then G^{-1}
+    ar.add(&S.h, dmax * 8);
+    ar.add(&S.dA, dmax * 8);
+    ar.add(&S.cb, s * 8);
+    ar.add(&S.y, dmax * 8);
+    ar.add(&S.yprev, dmax * 8);
+    ar.add(&S.norm_part, S.n_norm_part * 8);
+    ar.add(&S.binA, (size_t)S.nbA * s * 8);
+    ar.add(&S.binL, (size_t)S.nbL * s * 8);
+    ar.add(&S.wa, s * 8);
+    ar.add(&S.wl, s * 8);
+    ar.add(&S.wu, 2 * dmax * 8);
+    ar.add(&S.pacc, 2 * dmax * 8);
+    ar.add(&S.gacc, dmax * 8);
+    ar.add(&S.gpart, (size_t)S.ngt * dmax * 8);
+    ar.add(&S.coop, (size_t)regions * c->groups * CW * 8);
+    ar.add(&S.scal, (16 + 2 * dmax) * 8);
+    ar.add(&S.d, 64);
+    ar.add(&S.status, 64);
+    ar.add(&S.degenerate, 64);
+    ar.add(&c->upart, c->nbF_A * 8);
+    ar.add(&c->tpart, (c->nbF_L > 0 ? c->nbF_L : 1) * 8);
+    ar.add(&c->coefbuf, dmax * 8);
+    ar.add(&c->sbuf, s * 8);
+    SGKS_TRY(ar.commit(c));
+    if (sgks::transpose_csr(S.A, S.vdt, c->At_rowptr, c->At_col, c->At_val, c->st) ||
+        sgks::transpose_csr(S.L, S.vdt, c->Lt_rowptr, c->Lt_col, c->Lt_val, c->st)) {
+        sgks_destroy(c);
+        return SGKS_ERR_HIP;
+    }
+    S.At.rowptr = c->At_rowptr;
+    S.At.col = c->At_col;
+    S.At.val = c->At_val;
+    S.Lt.rowptr = c->Lt_rowptr;
+    S.Lt.col = c->Lt_col;
+    S.Lt.val = c->Lt_val;
     hipStream_t st = c->st;
     SGKS_TRY(hipMemsetAsync(S.cs, 0, dmax * 8, st));
     SGKS_TRY(hipMemsetAsync(S.QA, 0, (size_t)s * dmax * 8, st));
@@ -521,7 +546,17 @@ int64_t sgks_copy_state(sgks_ctx* c, int32_t which, double* dst, int64_t count) 
         case 4: return copy2d(S.QL, S.s, d, S.s);
         case 5: return copy2d(S.RL, d, d, dmax);
         case 6: return copy(S.dA, d);
-        case 7: return copy2d(S.G, d, d, dmax);
+        case 7: {   // G is stored row-major: copy then transpose on the host
+            const int64_t r = copy2d(S.G, d, d, dmax);
+            if (r < 0) return r;
+            for (int i = 0; i < d; ++i)
+                for (int j = i + 1; j < d; ++j) {
+                    const double t = dst[i + (int64_t)j * d];
+                    dst[i + (int64_t)j * d] = dst[j + (int64_t)i * d];
+                    dst[j + (int64_t)i * d] = t;
+                }
+            return r;
+        }
         case 8: return copy(S.cb, S.s);
         default: return SGKS_ERR_INVALID_ARG;
     }

@@ -12,7 +12,8 @@ constexpr int kWaves = kBlock / 64; // waves per block
 constexpr int kMaxS = 2048;         // largest sketch size (per-wave LDS bins)
 constexpr int kMaxD = 512;          // largest basis dimension
 constexpr int kAppendThreads = 256; // threads per workgroup of the append kernel
-constexpr size_t kAppendLdsBudget = 128 * 1024;   // dynamic LDS of one append workgroup
+constexpr int kMaxAppendGroups = 32;  // workgroups of the append kernels
+constexpr int kAppendMaxSlab = 64;    // sketch rows per append workgroup
 constexpr int kSketchBlock = 512;   // threads per block of the sketch kernel
 constexpr int kSketchWaves = kSketchBlock / 64;
 constexpr int kMaxSketchBlocks = 256; // per operator
@@ -62,7 +63,7 @@ struct State {
     double* QL;        // s x dmax
     double* RL;        // dmax x dmax
     double* U;         // (2 dmax) x dmax: rows [0,dmax) pair with R_A, rows [dmax,2dmax) with R_L
-    double* G;         // dmax x dmax R factor of [R_A; sqrt(mu) R_L], then dmax x dmax G^{-1} (row-major)
+    double* G;         // dmax x dmax R factor of [R_A; sqrt(mu) R_L], then G^{-1}; both row-major
     double* h;         // dmax, U^T [d_A; 0]
     double* dA;        // dmax
     double* cb;        // s, S_A b
@@ -77,10 +78,12 @@ struct State {
     double* wa;        // s: working sketched A column of the append
     double* wl;        // s: working sketched L column
     double* wu;        // 2 dmax: working column of the stacked factor
+    double* pacc;      // 2 dmax: running sums of the Q projection coefficients
+    double* gacc;      // dmax: running sum of the U projection coefficients
     double* gpart;     // ngt x dmax partial W^T v sums
     int ngt;
     int gt_rows;       // rows per block of the W^T v kernel
-    double* coop;      // partial vectors of the append kernels (regions x G x (2 dmax + 8))
+    double* coop;      // partial vectors of the append kernels (regions x (2 dmax + 8) x G)
     double* scal;      // scalars: [0] ||A^T b||, [1] ||S_A b||^2, [2..] scratch
     int* d;            // current number of basis columns
     int* status;       // device status word
@@ -104,7 +107,6 @@ void launch_gemvt(const State& S, const double* v, int ncols_fixed, hipStream_t 
 void launch_reduce_gpart(const State& S, int ncols_fixed, double* out, hipStream_t st);
 void launch_set_scale(const State& S, int col, bool store_r0, hipStream_t st);
 int launch_append(const State& S, bool scale_from_norm, int groups, hipStream_t st);
-size_t append_lds_bytes(int s, int dmax, int G);
 int choose_append_groups(int s, int dmax, int cap);
 void launch_refine(const State& S, hipStream_t st);
 void launch_cb(const State& S, hipStream_t st);

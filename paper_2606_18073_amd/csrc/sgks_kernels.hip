@@ -46,38 +46,76 @@ __device__ double block_sum(double v, double* red) {
     return t;
 }
 
-// Sum of p[0], p[stride], ..., p[(n-1) stride] in that order, with eight
+// Sum of p[0], p[stride], ..., p[(n-1) stride] in that order, sixteen
 // independent loads in flight at a time (the small kernels are latency
 // bound: a load-then-add loop would pay one memory latency per term).
 __device__ __forceinline__ double strided_sum(const double* __restrict__ p, int64_t stride,
                                               int n) {
+    // loads are unconditional from clamped (valid) addresses so that all
+    // sixteen are issued before the first wait; the mask applies to values
     double acc = 0.0;
-    int k = 0;
-    for (; k + 8 <= n; k += 8) {
-        double v[8];
+    for (int k = 0; k < n; k += 16) {
+        double v[16];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = p[(int64_t)(k + u) * stride];
+        for (int u = 0; u < 16; ++u) v[u] = p[(int64_t)min(k + u, n - 1) * stride];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc += v[u];
+        for (int u = 0; u < 16; ++u)
+            if (k + u < n) acc += v[u];
     }
-    for (; k < n; ++k) acc += p[(int64_t)k * stride];
     return acc;
 }
 
-// sum_k p[k stride] v[k], k < n, in order, eight loads in flight
+// sum_k p[k stride] v[k], k < n, in order, sixteen loads in flight
 __device__ __forceinline__ double strided_dot(const double* __restrict__ p, int64_t stride,
                                               const double* v, int n) {
     double acc = 0.0;
-    int k = 0;
-    for (; k + 8 <= n; k += 8) {
-        double w[8];
+    for (int k = 0; k < n; k += 16) {
+        double w[16];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) w[u] = p[(int64_t)(k + u) * stride];
+        for (int u = 0; u < 16; ++u) w[u] = p[(int64_t)min(k + u, n - 1) * stride];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc += w[u] * v[k + u];
+        for (int u = 0; u < 16; ++u)
+            if (k + u < n) acc += w[u] * v[k + u];
     }
-    for (; k < n; ++k) acc += p[(int64_t)k * stride] * v[k];
     return acc;
+}
+
+// Block-wide product of an upper-triangular d x d matrix with v, element
+// (i, j), j >= i, stored at M[i * rs + j * cs]:
+//   trans = 0: out[k] = sum_{j >= k} M(k, j) v[j]
+//   trans = 1: out[k] = sum_{i <= k} M(i, k) v[i]
+// Groups of tpr lanes share one output, each lane taking every tpr-th term
+// with eight loads in flight; the group sums with shuffles (fixed order).
+__device__ void tri_mv(const double* __restrict__ M, int64_t rs, int64_t cs, int d, int trans,
+                       const double* v, double* out) {
+    const int NT = blockDim.x;
+    int tpr = 64;
+    while (tpr > 1 && NT / tpr < d) tpr >>= 1;
+    const int rpp = NT / tpr;
+    const int c = threadIdx.x % tpr;
+    for (int base = 0; base < d; base += rpp) {
+        const int k = base + threadIdx.x / tpr;
+        double acc = 0.0;
+        if (k < d) {
+            const int lo = trans ? 0 : k, hi = trans ? k + 1 : d;
+            for (int q = lo + c; q < hi; q += 8 * tpr) {
+                double w[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int idx = min(q + u * tpr, hi - 1);   // clamped: loads stay unconditional
+                    w[u] = trans ? M[(int64_t)idx * rs + (int64_t)k * cs]
+                                 : M[(int64_t)k * rs + (int64_t)idx * cs];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int idx = q + u * tpr;
+                    if (idx < hi) acc += w[u] * v[idx];
+                }
+            }
+        }
+        for (int off = tpr / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if (k < d && c == 0) out[k] = acc;
+    }
 }
 
 // Thread-strided sum of p[i], i = threadIdx.x, threadIdx.x + T, ... < n,
@@ -239,14 +277,14 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(Csr At, Csr Lt, int withL, d
     double* dst = dst_fixed ? dst_fixed : W + (int64_t)(*dptr) * n;
     double sq = 0.0;
     SGKS_LANES_SWITCH(At.lanes, {
-        const int64_t row = (int64_t)blockIdx.x * (kBlock / V) + threadIdx.x / V;
         const int g = threadIdx.x % V;
-        if (row < n) {
+        for (int64_t row = (int64_t)blockIdx.x * (kBlock / V) + threadIdx.x / V; row < n;
+             row += (int64_t)gridDim.x * (kBlock / V)) {
             double v = row_dot<V, T>(At, u, row, g);
             if (withL) v += mu * row_dot<V, T>(Lt, t, row, g);
             if (g == 0) {
                 dst[row] = v;
-                sq = v * v;
+                sq += v * v;
             }
         }
     })
@@ -407,22 +445,30 @@ __global__ __launch_bounds__(kBlock) void k_cb(const double* __restrict__ bins, 
 // update G^{-1} and y = G^{-1} h.
 // ---------------------------------------------------------------------------
 
-// The append runs as a chain of small kernels, each with G workgroups.
+// The append runs as a chain of small kernels, each with G <= 32 workgroups.
 // Workgroup g owns sketch rows [lo, hi) of Q_A and Q_L and rows [ulo, uhi)
-// of both halves of U; each kernel stages its slab in LDS (leading dimension
-// padded to an odd count of doubles), finishes the previous projection with the
-// coefficients reduced in workgroup order from the previous kernel's partial
-// vectors, and writes its own partial vector to one region of S.coop:
-//   region r < P          : Q coefficients of projection pass r   (+ ||a||^2, ||l||^2 in r = 0)
+// of both halves of U.  Each kernel finishes the previous projection with the
+// coefficients reduced (in workgroup order) from the previous kernel's
+// partial vectors and writes its own partial vector into one region of
+// S.coop; slot t of workgroup g lives at region[t * G + g] so that a reduction
+// reads G consecutive values in one batch.
+//   region r < P          : Q coefficients of projection pass r (slots [0, d) for
+//                           Q_A, [dmax, dmax + d) for Q_L) and, for r = 0, ||a||^2, ||l||^2
 //   region P              : U coefficients of U pass 0, ||a_perp||^2, ||l_perp||^2, a_perp . S_A b
 //   region P + u, 0<u<P   : U coefficients of U pass u
 //   region 2P             : gamma^2 and the new h numerator
-// with P = S.passes.  Kernel boundaries order the phases.
+// (P = S.passes).  Workgroup 0 keeps the running sums p = sum of the Q
+// coefficients and gacc = sum of the U coefficients in S.pacc, S.gacc.
+// Kernel boundaries order the phases.  Memory traffic is small (the slabs
+// stay in L2); what these kernels pay is latency, so every loop issues its
+// loads in batches.
+
+constexpr int kSlots = 8;   // scalar slots after the 2 dmax coefficient slots
 
 struct ApDims {
-    int d, s, dmax, ld2, CW;
-    int lo, ns, nsp;      // sketch-row slab, padded leading dimension
-    int ulo, nu, nup, nua;
+    int d, s, dmax, ld2, nslot;
+    int lo, ns;           // sketch-row slab
+    int ulo, nu, nua;     // U-row slab (both halves), rows < d active
 };
 
 __device__ ApDims ap_dims(const State& S, int G, int d) {
@@ -432,107 +478,106 @@ __device__ ApDims ap_dims(const State& S, int G, int d) {
     D.s = S.s;
     D.dmax = S.dmax;
     D.ld2 = 2 * S.dmax;
-    D.CW = 2 * S.dmax + 8;
+    D.nslot = 2 * S.dmax + kSlots;
     D.lo = (int)((int64_t)S.s * g / G);
     D.ns = (int)((int64_t)S.s * (g + 1) / G) - D.lo;
-    D.nsp = D.ns | 1;
     D.ulo = (int)((int64_t)S.dmax * g / G);
     D.nu = (int)((int64_t)S.dmax * (g + 1) / G) - D.ulo;
-    D.nup = D.nu | 1;
     D.nua = max(0, min(D.ulo + D.nu, d) - D.ulo);
     return D;
 }
 
-__device__ __forceinline__ double* ap_region(const State& S, int G, int region, int g, int CW) {
-    return S.coop + ((int64_t)region * G + g) * CW;
+__device__ __forceinline__ double* ap_region(const State& S, const ApDims& D, int G, int r) {
+    return S.coop + (int64_t)r * D.nslot * G;
 }
 
-// LDS slab <- columns [0, d) of rows [row0, row0 + nrows) of a column-major matrix
-__device__ void load_slab(const double* __restrict__ src, int64_t ld, int row0, int nrows, int d,
-                          double* dst, int ldd) {
-    const int total = nrows * d, T = kAppendThreads;
-    for (int k0 = threadIdx.x; k0 < total; k0 += 8 * T) {
-        double v[8];
+// sum over workgroups of one slot: G consecutive values, one batch of loads
+__device__ __forceinline__ double sum_g(const double* __restrict__ slot, int G) {
+    double v[kMaxAppendGroups];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int k = k0 + u * T;
-            v[u] = k < total ? src[(int64_t)(k / nrows) * ld + row0 + k % nrows] : 0.0;
+    for (int u = 0; u < kMaxAppendGroups; ++u) v[u] = slot[min(u, G - 1)];
+    double a = 0.0;
+#pragma unroll
+    for (int u = 0; u < kMaxAppendGroups; ++u)
+        if (u < G) a += v[u];
+    return a;
+}
+
+// partial[j * G + g] = sum_{i < nrows} (Ma[j * ld + i] va[i] + Ml[j * ld + i] vl[i])
+// for j < d (Ml may be null), nrows <= 64.  Lane = row; each wave takes 16
+// columns per batch (all their loads in flight), writes the products to an
+// LDS tile and reduces it transposed: lane l sums 16 rows of column l % 16,
+// then two shuffle levels join the four row groups (fixed order).
+// tile: kAppendThreads / 64 * 16 * 64 doubles of LDS.
+__device__ void slab_dots(const double* __restrict__ Ma, const double* __restrict__ Ml,
+                          int64_t ld, int nrows, int d, const double* va, const double* vl,
+                          double* partial, int G, double* tile) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (nrows <= 0 || d <= 0) {
+        for (int j = threadIdx.x; j < d; j += blockDim.x) partial[(int64_t)j * G + blockIdx.x] = 0.0;
+        return;
+    }
+    const int rl = min(lane, nrows - 1);   // clamped row: loads stay unconditional
+    const double a_l = lane < nrows ? va[rl] : 0.0;
+    const double l_l = (Ml && lane < nrows) ? vl[rl] : 0.0;
+    double* tw = tile + wave * 16 * 64;
+    for (int jb = 0; jb < d; jb += 16 * nw) {   // uniform trip count: barriers inside
+        const int j0 = jb + wave * 16;
+        double w[16];
+        if (Ml) {
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int64_t o = (int64_t)min(j0 + u, d - 1) * ld + rl;
+                w[u] = Ma[o] * a_l + Ml[o] * l_l;
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < 16; ++u) w[u] = Ma[(int64_t)min(j0 + u, d - 1) * ld + rl] * a_l;
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int k = k0 + u * T;
-            if (k < total) dst[k % nrows + (k / nrows) * ldd] = v[u];
-        }
+        for (int u = 0; u < 16; ++u)
+            if (j0 + u >= d) w[u] = 0.0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) tw[u * 64 + lane] = w[u];
+        __syncthreads();
+        const int c = lane & 15, rg = lane >> 4;
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) acc += tw[c * 64 + rg * 16 + k];
+        acc += __shfl_xor(acc, 16);
+        acc += __shfl_xor(acc, 32);
+        if (lane < 16 && j0 + c < d) partial[(int64_t)(j0 + c) * G + blockIdx.x] = acc;
+        __syncthreads();
     }
 }
 
-// out[j] = sum over workgroups of region[q * CW + off + j], j < cnt (workgroup order)
-__device__ void reduce_region(const double* region0, int G, int CW, int off, int cnt, double* out) {
-    for (int j = threadIdx.x; j < cnt; j += kAppendThreads)
-        out[j] = strided_sum(region0 + off + j, CW, G);
-}
-
-__device__ double reduce_scalar(const double* region0, int G, int CW, int off) {
-    return strided_sum(region0 + off, CW, G);
-}
-
-// partial[j] = sum_i M[i + j ldm] v[i] for j < d (M, v in LDS)
-__device__ void slab_dots(const double* M, int ldm, int nrows, int d, const double* v,
-                          double* partial) {
-    for (int j = threadIdx.x; j < d; j += kAppendThreads) {
-        const double* mc = M + j * ldm;
-        double e = 0.0;
-        for (int i = 0; i < nrows; ++i) e += mc[i] * v[i];
-        partial[j] = e;
-    }
-}
-
-// two slabs at once (the A and L halves): partial[j] = sum_i Ma v_a + Ml v_l
-__device__ void slab_dots2(const double* Ma, const double* Ml, int ldm, int nrows, int d,
-                           const double* va, const double* vl, double* partial) {
-    for (int j = threadIdx.x; j < d; j += kAppendThreads) {
-        const double* a = Ma + j * ldm;
-        const double* l = Ml + j * ldm;
-        double e = 0.0;
-        for (int i = 0; i < nrows; ++i) e += a[i] * va[i] + l[i] * vl[i];
-        partial[j] = e;
-    }
-}
-
-// out[i] -= sum_j M[i + j ldm] c[j], i < nrows; threads split rows and, when
-// rows are few, contiguous chunks of j (chunk sums added in chunk order).
-__device__ void slab_apply(const double* M, int ldm, int nrows, int d, const double* c,
-                           double* out, double* scratch) {
-    const int T = kAppendThreads, tid = threadIdx.x;
-    __syncthreads();
+// out[i] -= sum_j M[j * ld + i] c[j], i < nrows (M global, column-major slab;
+// c, out in LDS).  Threads split rows and contiguous chunks of j; the chunk
+// sums are added in chunk order.
+__device__ void slab_apply(const double* __restrict__ M, int64_t ld, int nrows, int d,
+                           const double* c, double* out, double* scratch) {
+    const int T = blockDim.x, tid = threadIdx.x;
+    __syncthreads();   // c and out were just written by other threads
     if (nrows <= 0 || d <= 0) {
         __syncthreads();
         return;
     }
-    if (nrows >= T) {
-        for (int i = tid; i < nrows; i += T) {
-            double a = 0.0;
-            for (int j = 0; j < d; ++j) a += M[i + j * ldm] * c[j];
-            out[i] -= a;
+    const int nq = nrows >= T ? 1 : T / nrows;
+    for (int r0 = 0; r0 < nrows; r0 += T) {
+        const int i = r0 + tid % min(nrows - r0, T), q = tid / min(nrows - r0, T);
+        const int nr = min(nrows - r0, T);
+        if (q < nq && i < nrows) {
+            const int j0 = (int)((int64_t)d * q / nq), j1 = (int)((int64_t)d * (q + 1) / nq);
+            scratch[q * nr + (i - r0)] = strided_dot(M + (int64_t)j0 * ld + i, ld, c + j0, j1 - j0);
         }
         __syncthreads();
-        return;
+        if (tid < nr) {
+            double a = 0.0;
+            for (int qq = 0; qq < nq; ++qq) a += scratch[qq * nr + tid];
+            out[r0 + tid] -= a;
+        }
+        __syncthreads();
     }
-    const int nq = T / nrows;
-    const int i = tid % nrows, q = tid / nrows;
-    if (q < nq) {
-        const int j0 = (int)((int64_t)d * q / nq), j1 = (int)((int64_t)d * (q + 1) / nq);
-        double a = 0.0;
-        for (int j = j0; j < j1; ++j) a += M[i + j * ldm] * c[j];
-        scratch[q * nrows + i] = a;
-    }
-    __syncthreads();
-    if (tid < nrows) {
-        double a = 0.0;
-        for (int qq = 0; qq < nq; ++qq) a += scratch[qq * nrows + tid];
-        out[tid] -= a;
-    }
-    __syncthreads();
 }
 
 struct ApShared {
@@ -541,13 +586,18 @@ struct ApShared {
     double cL[kMaxD];
     double pA[kMaxD];
     double pL[kMaxD];
-    double gacc[kMaxD];
+    double av[kAppendMaxSlab];
+    double lv[kAppendMaxSlab];
+    double cuA[kMaxD];
+    double cuL[kMaxD];
+    double scr[kAppendThreads];
+    double sc[kSlots];
+    double tile[kAppendThreads / 64 * 16 * 64];
 };
 
 // Q pass 0: column scale (breakdown test), reduce the sketch bins of this
 // slab, first projection coefficients.
 __global__ __launch_bounds__(kAppendThreads) void k_ap_q0(State S, int G, int scale_from_norm) {
-    extern __shared__ double dyn[];
     __shared__ ApShared sh;
     if (*S.status != 0) return;
     const int d = *S.d;
@@ -570,23 +620,18 @@ __global__ __launch_bounds__(kAppendThreads) void k_ap_q0(State S, int G, int sc
     } else {
         scale = S.cs[d];
     }
-    double* Qa = dyn;
-    double* Ql = Qa + (size_t)D.nsp * S.dmax;
-    double* av = Ql + (size_t)D.nsp * S.dmax;
-    double* lv = av + D.nsp;
-    double* scr = lv + D.nsp;   // 2 T
-    load_slab(S.QA, D.s, D.lo, D.ns, d, Qa, D.nsp);
-    load_slab(S.QL, D.s, D.lo, D.ns, d, Ql, D.nsp);
     // bins of this slab: thread (row i, chunk q) sums a contiguous range of blocks
     const double bscale = S.sketch_mode == 1 ? scale : scale / sqrt((double)S.zeta);
     const int nq = D.ns > 0 ? T / D.ns : 1;
+    double* scrA = sh.cA;   // free until the coefficients arrive
+    double* scrL = sh.cL;
     {
         const int i = D.ns > 0 ? tid % D.ns : 0, q = D.ns > 0 ? tid / D.ns : T;
         if (q < nq) {
             const int a0 = (int)((int64_t)S.nbA * q / nq), a1 = (int)((int64_t)S.nbA * (q + 1) / nq);
             const int l0 = (int)((int64_t)S.nbL * q / nq), l1 = (int)((int64_t)S.nbL * (q + 1) / nq);
-            scr[q * D.ns + i] = strided_sum(S.binA + (int64_t)a0 * D.s + D.lo + i, D.s, a1 - a0);
-            scr[T + q * D.ns + i] = strided_sum(S.binL + (int64_t)l0 * D.s + D.lo + i, D.s, l1 - l0);
+            scrA[q * D.ns + i] = strided_sum(S.binA + (int64_t)a0 * D.s + D.lo + i, D.s, a1 - a0);
+            scrL[q * D.ns + i] = strided_sum(S.binL + (int64_t)l0 * D.s + D.lo + i, D.s, l1 - l0);
         }
     }
     __syncthreads();
@@ -594,13 +639,13 @@ __global__ __launch_bounds__(kAppendThreads) void k_ap_q0(State S, int G, int sc
     if (tid < D.ns) {
         double a = 0.0, l = 0.0;
         for (int q = 0; q < nq; ++q) {
-            a += scr[q * D.ns + tid];
-            l += scr[T + q * D.ns + tid];
+            a += scrA[q * D.ns + tid];
+            l += scrL[q * D.ns + tid];
         }
         a *= bscale;
         l *= bscale;
-        av[tid] = a;
-        lv[tid] = l;
+        sh.av[tid] = a;
+        sh.lv[tid] = l;
         S.wa[D.lo + tid] = a;
         S.wl[D.lo + tid] = l;
         na2 = a * a;
@@ -608,196 +653,184 @@ __global__ __launch_bounds__(kAppendThreads) void k_ap_q0(State S, int G, int sc
     }
     na2 = block_sum(na2, sh.red);
     nl2 = block_sum(nl2, sh.red);
-    double* mine = ap_region(S, G, 0, g, D.CW);
-    slab_dots(Qa, D.nsp, D.ns, d, av, mine);
-    slab_dots(Ql, D.nsp, D.ns, d, lv, mine + S.dmax);
+    double* reg = ap_region(S, D, G, 0);
+    slab_dots(S.QA + D.lo, nullptr, D.s, D.ns, d, sh.av, nullptr, reg, G, sh.tile);
+    slab_dots(S.QL + D.lo, nullptr, D.s, D.ns, d, sh.lv, nullptr, reg + (int64_t)S.dmax * G, G,
+              sh.tile);
     if (tid == 0) {
-        mine[2 * S.dmax] = na2;
-        mine[2 * S.dmax + 1] = nl2;
+        reg[(int64_t)(2 * S.dmax) * G + g] = na2;
+        reg[(int64_t)(2 * S.dmax + 1) * G + g] = nl2;
+    }
+}
+
+// reduce the Q coefficients of region r into sh.cA, sh.cL; workgroup 0 adds
+// them to the running sum p (S.pacc) -- the first pass initialises it
+__device__ void ap_take_q(const State& S, const ApDims& D, int G, int r, ApShared& sh) {
+    const double* reg = ap_region(S, D, G, r);
+    for (int j = threadIdx.x; j < 2 * D.d; j += blockDim.x) {
+        const int slot = j < D.d ? j : S.dmax + (j - D.d);
+        const double c = sum_g(reg + (int64_t)slot * G, G);
+        if (j < D.d)
+            sh.cA[j] = c;
+        else
+            sh.cL[j - D.d] = c;
+        if (blockIdx.x == 0) S.pacc[slot] = (r == 0 ? 0.0 : S.pacc[slot]) + c;
     }
 }
 
 // Q pass `pass` >= 1: finish the previous projection, next coefficients.
 __global__ __launch_bounds__(kAppendThreads) void k_ap_qp(State S, int G, int pass) {
-    extern __shared__ double dyn[];
     __shared__ ApShared sh;
     if (*S.status != 0) return;
     const int d = *S.d;
     const ApDims D = ap_dims(S, G, d);
-    const int g = blockIdx.x, tid = threadIdx.x;
-    double* Qa = dyn;
-    double* Ql = Qa + (size_t)D.nsp * S.dmax;
-    double* av = Ql + (size_t)D.nsp * S.dmax;
-    double* lv = av + D.nsp;
-    double* scr = lv + D.nsp;
-    load_slab(S.QA, D.s, D.lo, D.ns, d, Qa, D.nsp);
-    load_slab(S.QL, D.s, D.lo, D.ns, d, Ql, D.nsp);
+    const int tid = threadIdx.x;
     for (int i = tid; i < D.ns; i += kAppendThreads) {
-        av[i] = S.wa[D.lo + i];
-        lv[i] = S.wl[D.lo + i];
+        sh.av[i] = S.wa[D.lo + i];
+        sh.lv[i] = S.wl[D.lo + i];
     }
-    const double* prev = S.coop + (int64_t)(pass - 1) * G * D.CW;
-    reduce_region(prev, G, D.CW, 0, d, sh.cA);
-    reduce_region(prev, G, D.CW, S.dmax, d, sh.cL);
-    slab_apply(Qa, D.nsp, D.ns, d, sh.cA, av, scr);
-    slab_apply(Ql, D.nsp, D.ns, d, sh.cL, lv, scr + kAppendThreads);
+    ap_take_q(S, D, G, pass - 1, sh);
+    slab_apply(S.QA + D.lo, D.s, D.ns, d, sh.cA, sh.av, sh.scr);
+    slab_apply(S.QL + D.lo, D.s, D.ns, d, sh.cL, sh.lv, sh.scr);
     for (int i = tid; i < D.ns; i += kAppendThreads) {
-        S.wa[D.lo + i] = av[i];
-        S.wl[D.lo + i] = lv[i];
+        S.wa[D.lo + i] = sh.av[i];
+        S.wl[D.lo + i] = sh.lv[i];
     }
-    double* mine = ap_region(S, G, pass, g, D.CW);
-    slab_dots(Qa, D.nsp, D.ns, d, av, mine);
-    slab_dots(Ql, D.nsp, D.ns, d, lv, mine + S.dmax);
+    double* reg = ap_region(S, D, G, pass);
+    slab_dots(S.QA + D.lo, nullptr, D.s, D.ns, d, sh.av, nullptr, reg, G, sh.tile);
+    slab_dots(S.QL + D.lo, nullptr, D.s, D.ns, d, sh.lv, nullptr, reg + (int64_t)S.dmax * G, G,
+              sh.tile);
 }
 
 // Q finish: last projection, norms and d_A numerator, U pass 0 on
 // c = [p_A; sqrt(mu) p_L] (rows < d; the new rows are orthogonal to U).
 __global__ __launch_bounds__(kAppendThreads) void k_ap_qf(State S, int G) {
-    extern __shared__ double dyn[];
     __shared__ ApShared sh;
     if (*S.status != 0) return;
     const int d = *S.d;
     const ApDims D = ap_dims(S, G, d);
     const int g = blockIdx.x, tid = threadIdx.x, P = S.passes;
-    double* Qa = dyn;
-    double* Ql = Qa + (size_t)D.nsp * S.dmax;
-    double* av = Ql + (size_t)D.nsp * S.dmax;
-    double* lv = av + D.nsp;
-    double* scr = lv + D.nsp;
-    load_slab(S.QA, D.s, D.lo, D.ns, d, Qa, D.nsp);
-    load_slab(S.QL, D.s, D.lo, D.ns, d, Ql, D.nsp);
     for (int i = tid; i < D.ns; i += kAppendThreads) {
-        av[i] = S.wa[D.lo + i];
-        lv[i] = S.wl[D.lo + i];
+        sh.av[i] = S.wa[D.lo + i];
+        sh.lv[i] = S.wl[D.lo + i];
     }
-    const double* last = S.coop + (int64_t)(P - 1) * G * D.CW;
-    reduce_region(last, G, D.CW, 0, d, sh.cA);
-    reduce_region(last, G, D.CW, S.dmax, d, sh.cL);
-    for (int j = tid; j < d; j += kAppendThreads) {
-        double a = 0.0, l = 0.0;
-        for (int r = 0; r < P; ++r) {
-            const double* rg = S.coop + (int64_t)r * G * D.CW;
-            a += strided_sum(rg + j, D.CW, G);
-            l += strided_sum(rg + S.dmax + j, D.CW, G);
+    // the last coefficients, and p = (earlier passes) + last
+    {
+        const double* reg = ap_region(S, D, G, P - 1);
+        for (int j = tid; j < 2 * d; j += kAppendThreads) {
+            const int slot = j < d ? j : S.dmax + (j - d);
+            const double c = sum_g(reg + (int64_t)slot * G, G);
+            const double p = (P > 1 ? S.pacc[slot] : 0.0) + c;
+            if (j < d) {
+                sh.cA[j] = c;
+                sh.pA[j] = p;
+            } else {
+                sh.cL[j - d] = c;
+                sh.pL[j - d] = p;
+            }
+            if (g == 0) S.pacc[slot] = p;
         }
-        sh.pA[j] = a;
-        sh.pL[j] = l;
     }
-    slab_apply(Qa, D.nsp, D.ns, d, sh.cA, av, scr);
-    slab_apply(Ql, D.nsp, D.ns, d, sh.cL, lv, scr + kAppendThreads);
+    slab_apply(S.QA + D.lo, D.s, D.ns, d, sh.cA, sh.av, sh.scr);
+    slab_apply(S.QL + D.lo, D.s, D.ns, d, sh.cL, sh.lv, sh.scr);
     double ra = 0.0, rl = 0.0, dl = 0.0;
     for (int i = tid; i < D.ns; i += kAppendThreads) {
-        S.wa[D.lo + i] = av[i];
-        S.wl[D.lo + i] = lv[i];
-        ra += av[i] * av[i];
-        rl += lv[i] * lv[i];
-        dl += av[i] * S.cb[D.lo + i];
+        S.wa[D.lo + i] = sh.av[i];
+        S.wl[D.lo + i] = sh.lv[i];
+        ra += sh.av[i] * sh.av[i];
+        rl += sh.lv[i] * sh.lv[i];
+        dl += sh.av[i] * S.cb[D.lo + i];
+    }
+    for (int i = tid; i < D.nua; i += kAppendThreads) {
+        const int r = D.ulo + i;
+        sh.cuA[i] = sh.pA[r];
+        sh.cuL[i] = S.sqrt_mu * sh.pL[r];
+        S.wu[r] = sh.cuA[i];
+        S.wu[S.dmax + r] = sh.cuL[i];
     }
     ra = block_sum(ra, sh.red);
     rl = block_sum(rl, sh.red);
-    dl = block_sum(dl, sh.red);   // its barriers also retire every use of the Q slab
-    // U slab over the same LDS
-    double* Ua = dyn;
-    double* Ul = Ua + (size_t)D.nup * S.dmax;
-    double* cuA = Ul + (size_t)D.nup * S.dmax;
-    double* cuL = cuA + D.nup;
-    load_slab(S.U, D.ld2, D.ulo, D.nua, d, Ua, D.nup);
-    load_slab(S.U, D.ld2, S.dmax + D.ulo, D.nua, d, Ul, D.nup);
-    for (int i = tid; i < D.nua; i += kAppendThreads) {
-        const int r = D.ulo + i;
-        cuA[i] = sh.pA[r];
-        cuL[i] = S.sqrt_mu * sh.pL[r];
-        S.wu[r] = cuA[i];
-        S.wu[S.dmax + r] = cuL[i];
-    }
-    __syncthreads();
-    double* mine = ap_region(S, G, P, g, D.CW);
-    slab_dots2(Ua, Ul, D.nup, D.nua, d, cuA, cuL, mine);
+    dl = block_sum(dl, sh.red);
+    double* reg = ap_region(S, D, G, P);
+    slab_dots(S.U + D.ulo, S.U + S.dmax + D.ulo, D.ld2, D.nua, d, sh.cuA, sh.cuL, reg, G, sh.tile);
     if (tid == 0) {
-        mine[2 * S.dmax] = ra;
-        mine[2 * S.dmax + 1] = rl;
-        mine[2 * S.dmax + 2] = dl;
+        reg[(int64_t)(2 * S.dmax) * G + g] = ra;
+        reg[(int64_t)(2 * S.dmax + 1) * G + g] = rl;
+        reg[(int64_t)(2 * S.dmax + 2) * G + g] = dl;
     }
 }
 
 // U pass `upass` >= 1 (or, with last != 0, the finish: gamma^2 and h numerator)
 __global__ __launch_bounds__(kAppendThreads) void k_ap_u(State S, int G, int upass, int last) {
-    extern __shared__ double dyn[];
     __shared__ ApShared sh;
     if (*S.status != 0) return;
     const int d = *S.d;
     const ApDims D = ap_dims(S, G, d);
     const int g = blockIdx.x, tid = threadIdx.x, P = S.passes;
-    double* Ua = dyn;
-    double* Ul = Ua + (size_t)D.nup * S.dmax;
-    double* cuA = Ul + (size_t)D.nup * S.dmax;
-    double* cuL = cuA + D.nup;
-    double* scr = cuL + D.nup;
-    load_slab(S.U, D.ld2, D.ulo, D.nua, d, Ua, D.nup);
-    load_slab(S.U, D.ld2, S.dmax + D.ulo, D.nua, d, Ul, D.nup);
     for (int i = tid; i < D.nua; i += kAppendThreads) {
-        cuA[i] = S.wu[D.ulo + i];
-        cuL[i] = S.wu[S.dmax + D.ulo + i];
+        sh.cuA[i] = S.wu[D.ulo + i];
+        sh.cuL[i] = S.wu[S.dmax + D.ulo + i];
     }
-    const double* prev = S.coop + (int64_t)(P + upass - 1) * G * D.CW;
-    reduce_region(prev, G, D.CW, 0, d, sh.cA);
-    slab_apply(Ua, D.nup, D.nua, d, sh.cA, cuA, scr);
-    slab_apply(Ul, D.nup, D.nua, d, sh.cA, cuL, scr + kAppendThreads);
+    {
+        const double* reg = ap_region(S, D, G, P + upass - 1);
+        for (int j = tid; j < d; j += kAppendThreads) {
+            const double c = sum_g(reg + (int64_t)j * G, G);
+            sh.cA[j] = c;
+            if (g == 0) S.gacc[j] = (upass == 1 ? 0.0 : S.gacc[j]) + c;
+        }
+    }
+    slab_apply(S.U + D.ulo, D.ld2, D.nua, d, sh.cA, sh.cuA, sh.scr);
+    slab_apply(S.U + S.dmax + D.ulo, D.ld2, D.nua, d, sh.cA, sh.cuL, sh.scr);
     for (int i = tid; i < D.nua; i += kAppendThreads) {
-        S.wu[D.ulo + i] = cuA[i];
-        S.wu[S.dmax + D.ulo + i] = cuL[i];
+        S.wu[D.ulo + i] = sh.cuA[i];
+        S.wu[S.dmax + D.ulo + i] = sh.cuL[i];
     }
     if (!last) {
-        double* mine = ap_region(S, G, P + upass, g, D.CW);
-        slab_dots2(Ua, Ul, D.nup, D.nua, d, cuA, cuL, mine);
+        slab_dots(S.U + D.ulo, S.U + S.dmax + D.ulo, D.ld2, D.nua, d, sh.cuA, sh.cuL,
+                  ap_region(S, D, G, P + upass), G, sh.tile);
         return;
     }
     double gam2 = 0.0, hnum = 0.0;
     for (int i = tid; i < D.nua; i += kAppendThreads) {
-        gam2 += cuA[i] * cuA[i] + cuL[i] * cuL[i];
-        hnum += cuA[i] * S.dA[D.ulo + i];
+        gam2 += sh.cuA[i] * sh.cuA[i] + sh.cuL[i] * sh.cuL[i];
+        hnum += sh.cuA[i] * S.dA[D.ulo + i];
     }
     gam2 = block_sum(gam2, sh.red);
     hnum = block_sum(hnum, sh.red);
     if (tid == 0) {
-        double* mine = ap_region(S, G, 2 * P, g, D.CW);
-        mine[0] = gam2;
-        mine[1] = hnum;
+        double* reg = ap_region(S, D, G, 2 * P);
+        reg[g] = gam2;
+        reg[G + g] = hnum;
     }
 }
 
-// Commit: new columns of Q_A, Q_L, R_A, R_L, U, G, entries of d_A and h, the
-// new column of G^{-1} (row-major: element (r, j) at r * dmax + j) and
-// y = G^{-1} h.  Breakdown when the new stacked column is dependent.
+// Commit: new columns of Q_A, Q_L, R_A, R_L, U, G (row-major), entries of
+// d_A and h, the new column of G^{-1} (row-major) and y0 = G^{-1} h.
+// Breakdown when the new stacked column is dependent.
 __global__ __launch_bounds__(kAppendThreads) void k_ap_commit(State S, int G) {
     __shared__ ApShared sh;
     if (*S.status != 0) return;
     const int d = *S.d;
     const ApDims D = ap_dims(S, G, d);
     const int g = blockIdx.x, tid = threadIdx.x, P = S.passes, T = kAppendThreads;
-    const double* r0 = S.coop;
-    const double* rP = S.coop + (int64_t)P * G * D.CW;
-    const double naTot = reduce_scalar(r0, G, D.CW, 2 * S.dmax);
-    const double nlTot = reduce_scalar(r0, G, D.CW, 2 * S.dmax + 1);
-    const double ra = reduce_scalar(rP, G, D.CW, 2 * S.dmax);
-    const double rl = reduce_scalar(rP, G, D.CW, 2 * S.dmax + 1);
-    const double dl = reduce_scalar(rP, G, D.CW, 2 * S.dmax + 2);
-    const double* r2P = S.coop + (int64_t)2 * P * G * D.CW;
-    double gam2 = reduce_scalar(r2P, G, D.CW, 0);
-    double hnum = reduce_scalar(r2P, G, D.CW, 1);
-    for (int j = tid; j < d; j += T) {
-        double a = 0.0, l = 0.0, u = 0.0;
-        for (int r = 0; r < P; ++r) {
-            const double* rg = S.coop + (int64_t)r * G * D.CW;
-            const double* ru = S.coop + (int64_t)(P + r) * G * D.CW;
-            a += strided_sum(rg + j, D.CW, G);
-            l += strided_sum(rg + S.dmax + j, D.CW, G);
-            u += strided_sum(ru + j, D.CW, G);
-        }
-        sh.pA[j] = a;
-        sh.pL[j] = l;
-        sh.gacc[j] = u;
+    const int dmax = S.dmax;
+    if (tid < 7) {
+        const double* r0 = ap_region(S, D, G, 0);
+        const double* rP = ap_region(S, D, G, P);
+        const double* r2P = ap_region(S, D, G, 2 * P);
+        const double* src[7] = {r0 + (int64_t)(2 * dmax) * G, r0 + (int64_t)(2 * dmax + 1) * G,
+                                rP + (int64_t)(2 * dmax) * G, rP + (int64_t)(2 * dmax + 1) * G,
+                                rP + (int64_t)(2 * dmax + 2) * G, r2P, r2P + G};
+        sh.sc[tid] = sum_g(src[tid], G);
     }
+    for (int j = tid; j < d; j += T) {
+        sh.pA[j] = S.pacc[j];
+        sh.pL[j] = S.pacc[dmax + j];
+        sh.cA[j] = S.gacc[j];            // sum of the U coefficients (the new column of G)
+    }
+    __syncthreads();
+    const double naTot = sh.sc[0], nlTot = sh.sc[1], ra = sh.sc[2], rl = sh.sc[3], dl = sh.sc[4];
+    double gam2 = sh.sc[5], hnum = sh.sc[6];
     double rhoA = sqrt(ra), rhoL = sqrt(rl);
     const bool degA = !(rhoA > 1e-14 * sqrt(naTot));
     const bool degL = !(rhoL > 1e-14 * sqrt(nlTot));
@@ -809,7 +842,6 @@ __global__ __launch_bounds__(kAppendThreads) void k_ap_commit(State S, int G) {
     gam2 += rhoA * rhoA + S.mu * rhoL * rhoL;
     hnum += rhoA * dAnew;
     const double gam = sqrt(gam2);
-    __syncthreads();
     if (!(gam < INFINITY)) {
         if (g == 0 && tid == 0) *S.status = kStatusNonfinite;
         return;
@@ -829,46 +861,46 @@ __global__ __launch_bounds__(kAppendThreads) void k_ap_commit(State S, int G) {
     }
     for (int i = tid; i < D.nua; i += T) {
         S.U[(int64_t)d * D.ld2 + D.ulo + i] = S.wu[D.ulo + i] / gam;
-        S.U[(int64_t)d * D.ld2 + S.dmax + D.ulo + i] = S.wu[S.dmax + D.ulo + i] / gam;
+        S.U[(int64_t)d * D.ld2 + dmax + D.ulo + i] = S.wu[dmax + D.ulo + i] / gam;
     }
     if (g == 0) {
         for (int j = tid; j < d; j += T) {
-            S.RA[(int64_t)d * S.dmax + j] = sh.pA[j];
-            S.RL[(int64_t)d * S.dmax + j] = sh.pL[j];
-            S.G[(int64_t)d * S.dmax + j] = sh.gacc[j];
+            S.RA[(int64_t)d * dmax + j] = sh.pA[j];
+            S.RL[(int64_t)d * dmax + j] = sh.pL[j];
+            S.G[(int64_t)j * dmax + d] = sh.cA[j];
         }
         if (tid == 0) {
-            S.RA[(int64_t)d * S.dmax + d] = rhoA;
-            S.RL[(int64_t)d * S.dmax + d] = rhoL;
+            S.RA[(int64_t)d * dmax + d] = rhoA;
+            S.RL[(int64_t)d * dmax + d] = rhoL;
             S.dA[d] = dAnew;
             S.U[(int64_t)d * D.ld2 + d] = rhoA / gam;
-            S.U[(int64_t)d * D.ld2 + S.dmax + d] = S.sqrt_mu * rhoL / gam;
-            S.G[(int64_t)d * S.dmax + d] = gam;
+            S.U[(int64_t)d * D.ld2 + dmax + d] = S.sqrt_mu * rhoL / gam;
+            S.G[(int64_t)d * dmax + d] = gam;
             S.h[d] = hnew;
             if (degA || degL) *S.degenerate += (int)degA + (int)degL;
         }
     }
     // G^{-1} gains column [-G^{-1} g / gam ; 1 / gam]; rows split over workgroups
-    double* Gi = S.G + (int64_t)S.dmax * S.dmax;
+    double* Gi = S.G + (int64_t)dmax * dmax;
     const int nrow = d + 1;
     const int ylo = (int)((int64_t)nrow * g / G), yhi = (int)((int64_t)nrow * (g + 1) / G);
     const int lane = tid & 63, wave = tid >> 6;
     for (int r = ylo + wave; r < yhi; r += T / 64) {
         double a = 0.0, yr = 0.0;
         if (r < d) {
-            const double* gr = Gi + (int64_t)r * S.dmax;
+            const double* gr = Gi + (int64_t)r * dmax;
             for (int j = r + lane; j < d; j += 64) {
-                a += gr[j] * sh.gacc[j];
-                yr += gr[j] * S.h[j];
+                const double gij = gr[j];
+                a += gij * sh.cA[j];
+                yr += gij * S.h[j];
             }
             a = wave_sum(a);
             yr = wave_sum(yr);
         }
         const double nc = r < d ? -a / gam : 1.0 / gam;
         if (lane == 0) {
-            Gi[(int64_t)r * S.dmax + d] = nc;
+            Gi[(int64_t)r * dmax + d] = nc;
             S.y[r] = yr + nc * hnew;
-            S.yprev[r] = yr + nc * hnew;
         }
     }
     if (g == 0 && tid == 0) *S.d = d + 1;
@@ -876,40 +908,24 @@ __global__ __launch_bounds__(kAppendThreads) void k_ap_commit(State S, int G) {
 
 // One residual correction of y = G^{-1} h with the triangular factor itself:
 // y <- y + G^{-1} (h - G y).  It brings the explicit-inverse solve to the
-// accuracy of back substitution.  One workgroup; G is column-major, G^{-1}
-// row-major.
+// accuracy of back substitution.  One workgroup; G and G^{-1} row-major.
 __global__ __launch_bounds__(1024) void k_yfix(State S) {
     __shared__ double yv[kMaxD];
     __shared__ double rv[kMaxD];
+    __shared__ double tv[kMaxD];
     if (*S.status != 0) return;
     const int d = *S.d, dmax = S.dmax;
     for (int i = threadIdx.x; i < d; i += 1024) yv[i] = S.y[i];
     __syncthreads();
-    for (int i = threadIdx.x; i < d; i += 1024) {
-        const double* gc = S.G + (int64_t)i * dmax + i;   // G[i, j] at gc[(j - i) dmax]
-        double a = 0.0;
-        int j = i;
-        for (; j + 8 <= d; j += 8) {
-            double v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = gc[(int64_t)(j - i + u) * dmax];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) a += v[u] * yv[j + u];
-        }
-        for (; j < d; ++j) a += gc[(int64_t)(j - i) * dmax] * yv[j];
-        rv[i] = S.h[i] - a;
-    }
+    tri_mv(S.G, dmax, 1, d, 0, yv, tv);
     __syncthreads();
-    const double* Gi = S.G + (int64_t)dmax * dmax;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int i = wave; i < d; i += 16) {
-        double a = 0.0;
-        for (int j = i + lane; j < d; j += 64) a += Gi[(int64_t)i * dmax + j] * rv[j];
-        a = wave_sum(a);
-        if (lane == 0) {
-            S.y[i] = yv[i] + a;
-            S.yprev[i] = yv[i] + a;
-        }
+    for (int i = threadIdx.x; i < d; i += 1024) rv[i] = S.h[i] - tv[i];
+    __syncthreads();
+    tri_mv(S.G + (int64_t)dmax * dmax, dmax, 1, d, 0, rv, tv);
+    __syncthreads();
+    for (int i = threadIdx.x; i < d; i += 1024) {
+        S.y[i] = yv[i] + tv[i];
+        S.yprev[i] = yv[i] + tv[i];
     }
 }
 
@@ -921,31 +937,23 @@ __global__ __launch_bounds__(1024) void k_yfix(State S) {
 __global__ __launch_bounds__(kBlock) void k_refine(State S) {
     __shared__ double gv[kMaxD];
     __shared__ double tv[kMaxD];
+    __shared__ double dv[kMaxD];
     if (*S.status != 0) return;
     const int d = *S.d;
     const int dmax = S.dmax;
     const double* Gi = S.G + (int64_t)dmax * dmax;   // row-major G^{-1}
-    for (int j = threadIdx.x; j < d; j += kBlock) {
-        gv[j] = strided_sum(S.gpart + j, dmax, S.ngt);
-    }
+    for (int j = threadIdx.x; j < d; j += kBlock) gv[j] = strided_sum(S.gpart + j, dmax, S.ngt);
     __syncthreads();
-    // t = G^{-T} g : t_j = sum_{i <= j} Gi[i, j] g_i
-    for (int j = threadIdx.x; j < d; j += kBlock) {
-        tv[j] = strided_dot(Gi + j, dmax, gv, j + 1);
-    }
+    tri_mv(Gi, dmax, 1, d, 1, gv, tv);   // t = G^{-T} g
+    __syncthreads();
+    tri_mv(Gi, dmax, 1, d, 0, tv, dv);   // delta = G^{-1} t
     __syncthreads();
     const double eta2 = fmin((double)d / (double)S.s, 0.999);
     const double alpha = (1.0 - eta2) * (1.0 - eta2), beta = eta2;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int i = wave; i < d; i += kWaves) {
-        double a = 0.0;
-        for (int j = i + lane; j < d; j += 64) a += Gi[(int64_t)i * dmax + j] * tv[j];
-        a = wave_sum(a);
-        if (lane == 0) {
-            const double yi = S.y[i], yp = S.yprev[i];
-            S.y[i] = yi - alpha * a + beta * (yi - yp);
-            S.yprev[i] = yi;
-        }
+    for (int i = threadIdx.x; i < d; i += kBlock) {
+        const double yi = S.y[i], yp = S.yprev[i];
+        S.y[i] = yi - alpha * dv[i] + beta * (yi - yp);
+        S.yprev[i] = yi;
     }
 }
 
@@ -956,15 +964,20 @@ __global__ __launch_bounds__(kBlock) void k_refine(State S) {
 
 __global__ __launch_bounds__(kBlock) void k_residual_small(State S, double* out2) {
     __shared__ double red[kWaves];
+    __shared__ double yv[kMaxD];
+    __shared__ double a_[kMaxD];
+    __shared__ double l_[kMaxD];
     const int d = *S.d, dmax = S.dmax;
+    for (int i = threadIdx.x; i < d; i += kBlock) yv[i] = S.y[i];
+    __syncthreads();
+    tri_mv(S.RA, 1, dmax, d, 0, yv, a_);   // R_A y (column-major R: element (i, j) at j dmax + i)
+    tri_mv(S.RL, 1, dmax, d, 0, yv, l_);
+    __syncthreads();
     double ea = 0.0, el = 0.0, dd = 0.0;
     for (int i = threadIdx.x; i < d; i += kBlock) {
-        const int64_t o = (int64_t)i * dmax + i;
-        const double a = strided_dot(S.RA + o, dmax, S.y + i, d - i);
-        const double l = strided_dot(S.RL + o, dmax, S.y + i, d - i);
-        const double e = a - S.dA[i];
+        const double e = a_[i] - S.dA[i];
         ea += e * e;
-        el += l * l;
+        el += l_[i] * l_[i];
         dd += S.dA[i] * S.dA[i];
     }
     ea = block_sum(ea, red);
@@ -983,36 +996,28 @@ __global__ __launch_bounds__(kBlock) void k_backward_small(State S, double* v_ou
     __shared__ double gv[kMaxD];
     __shared__ double tv[kMaxD];
     __shared__ double zv[kMaxD];
+    __shared__ double yv[kMaxD];
+    __shared__ double lz[kMaxD];
+    __shared__ double ly[kMaxD];
     __shared__ double red[kWaves];
     const int d = *S.d, dmax = S.dmax;
     const double* Gi = S.G + (int64_t)dmax * dmax;   // row-major G^{-1}
     for (int j = threadIdx.x; j < d; j += kBlock) {
         gv[j] = strided_sum(S.gpart + j, dmax, S.ngt);
+        yv[j] = S.y[j];
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < d; j += kBlock) {
-        tv[j] = strided_dot(Gi + j, dmax, gv, j + 1);
-    }
+    tri_mv(Gi, dmax, 1, d, 1, gv, tv);   // G^{-T} g
     __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int i = wave; i < d; i += kWaves) {
-        double a = 0.0;
-        for (int j = i + lane; j < d; j += 64) a += Gi[(int64_t)i * dmax + j] * tv[j];
-        a = wave_sum(a);
-        if (lane == 0) zv[i] = a;
-    }
+    tri_mv(Gi, dmax, 1, d, 0, tv, zv);   // z = G^{-1} G^{-T} g = H^{-1} W^T grad_x
     __syncthreads();
-    // tv <- R_A z, gv <- (R_L z) * (R_L y) terms
+    tri_mv(S.RA, 1, dmax, d, 0, zv, tv);   // R_A z
+    tri_mv(S.RL, 1, dmax, d, 0, zv, lz);   // R_L z
+    tri_mv(S.RL, 1, dmax, d, 0, yv, ly);   // R_L y
+    __syncthreads();
     double prod = 0.0;
-    for (int i = threadIdx.x; i < d; i += kBlock) {
-        const int64_t o = (int64_t)i * dmax + i;
-        const double a = strided_dot(S.RA + o, dmax, zv + i, d - i);
-        const double lz = strided_dot(S.RL + o, dmax, zv + i, d - i);
-        const double ly = strided_dot(S.RL + o, dmax, S.y + i, d - i);
-        tv[i] = a;
-        prod += lz * ly;
-    }
-    prod = block_sum(prod, red);   // contains __syncthreads
+    for (int i = threadIdx.x; i < d; i += kBlock) prod += lz[i] * ly[i];
+    prod = block_sum(prod, red);
     for (int r = threadIdx.x; r < S.s; r += kBlock) v_out[r] = strided_dot(S.QA + r, S.s, tv, d);
     if (threadIdx.x == 0) gmu_out[0] = -prod;
 }
@@ -1148,7 +1153,8 @@ void launch_forward(const State& S, const double* x, const double* b, double* u,
 
 int adjoint_blocks(const State& S) {
     const int per = kBlock / S.At.lanes;
-    return (int)((S.n + per - 1) / per);
+    const int64_t nb = (S.n + per - 1) / per;
+    return (int)(nb < 2048 ? nb : 2048);   // grid-stride beyond: fewer norm partials
 }
 
 void launch_adjoint(const State& S, const double* u, const double* t, bool with_L, double mu,
@@ -1224,42 +1230,26 @@ int max_append_groups() {
     return cus > 0 ? cus : 1;
 }
 
-size_t append_lds_bytes(int s, int dmax, int G) {
-    const int ns = ((s + G - 1) / G) | 1;
-    const int nu = ((dmax + G - 1) / G) | 1;
-    const size_t q = (size_t)2 * ns * dmax + 2 * ns + 2 * kAppendThreads;
-    const size_t u = (size_t)2 * nu * dmax + 2 * nu + 2 * kAppendThreads;
-    return sizeof(double) * (q > u ? q : u);
-}
-
 int choose_append_groups(int s, int dmax, int cap) {
     int G = (s + 31) / 32;
     if (G < 4) G = 4;
-    while (G < cap && append_lds_bytes(s, dmax, G) > kAppendLdsBudget) ++G;
+    while ((s + G - 1) / G > kAppendMaxSlab || (dmax + G - 1) / G > kAppendMaxSlab) ++G;
+    if (G > kMaxAppendGroups) G = kMaxAppendGroups;
     if (G > cap) G = cap;
     return G;
 }
 
 int launch_append(const State& S, bool scale_from_norm, int G, hipStream_t st) {
-    const size_t shm = append_lds_bytes(S.s, S.dmax, G);
-    if (shm > kAppendLdsBudget) return -1;
-    static thread_local bool configured = false;
-    if (shm > 64 * 1024 && !configured) {
-        const void* ks[] = {(const void*)k_ap_q0, (const void*)k_ap_qp, (const void*)k_ap_qf,
-                            (const void*)k_ap_u};
-        for (const void* k : ks)
-            if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)kAppendLdsBudget) != hipSuccess)
-                return -1;
-        configured = true;
-    }
+    if (G < 1 || G > kMaxAppendGroups || (S.s + G - 1) / G > kAppendMaxSlab ||
+        (S.dmax + G - 1) / G > kAppendMaxSlab)
+        return -1;
     const dim3 grid(G), block(kAppendThreads);
-    hipLaunchKernelGGL(k_ap_q0, grid, block, shm, st, S, G, scale_from_norm ? 1 : 0);
+    hipLaunchKernelGGL(k_ap_q0, grid, block, 0, st, S, G, scale_from_norm ? 1 : 0);
     for (int pass = 1; pass < S.passes; ++pass)
-        hipLaunchKernelGGL(k_ap_qp, grid, block, shm, st, S, G, pass);
-    hipLaunchKernelGGL(k_ap_qf, grid, block, shm, st, S, G);
-    for (int u = 1; u < S.passes; ++u) hipLaunchKernelGGL(k_ap_u, grid, block, shm, st, S, G, u, 0);
-    hipLaunchKernelGGL(k_ap_u, grid, block, shm, st, S, G, S.passes, 1);
+        hipLaunchKernelGGL(k_ap_qp, grid, block, 0, st, S, G, pass);
+    hipLaunchKernelGGL(k_ap_qf, grid, block, 0, st, S, G);
+    for (int u = 1; u < S.passes; ++u) hipLaunchKernelGGL(k_ap_u, grid, block, 0, st, S, G, u, 0);
+    hipLaunchKernelGGL(k_ap_u, grid, block, 0, st, S, G, S.passes, 1);
     hipLaunchKernelGGL(k_ap_commit, grid, block, 0, st, S, G);
     hipLaunchKernelGGL(k_yfix, dim3(1), dim3(1024), 0, st, S);
     return hipGetLastError() == hipSuccess ? 0 : -1;

@@ -43,12 +43,28 @@ def algorithmic_bytes(P, d_avg_gemv):
     nnzA, nnzL = P.A.nnz, P.L.nnz
     m, n, p, s = P.m, P.n, P.p, P.s
     csr = (vsz + 4) * (nnzA + nnzL)
+    rowptrs = 4 * (m + 1) + 4 * (p + 1)
     return {
-        "forward_Ax_Lx": csr + 4 * (m + 1) + 4 * (p + 1) + 8 * n + 8 * m + 8 * m + 8 * p,
+        # u = A x - b, t = L x: CSR, x, b read; u, t written
+        "forward_Ax_Lx": csr + rowptrs + 8 * n + 8 * m + 8 * m + 8 * p,
+        # z = A w, L w of the new column: CSR, w read; z written
+        "spmv_new_column": csr + rowptrs + 8 * n + 8 * m + 8 * p,
+        # r = A^T u + mu L^T t: transposed CSR, u, t read; r written
         "adjoint_ATu_LTt": csr + 8 * (n + 1) + 8 * m + 8 * p + 8 * n,
-        "spmv_sketch": csr + 4 * (m + 1) + 4 * (p + 1) + 8 * n + 16 * s,
+        # sketch bins of z: z read, 2 s outputs
+        "sketch_scatter": 8 * (m + p) + 16 * s,
+        # x = W y: the d columns of W read, x written
         "gemv_Wy": 8 * n * d_avg_gemv + 8 * n,
     }
+
+
+# phases that launch the same kernel
+KERNEL_PHASES = {
+    "k_forward": ["forward_Ax_Lx", "spmv_new_column"],
+    "k_adjoint": ["adjoint_ATu_LTt"],
+    "k_scatter": ["sketch_scatter"],
+    "k_gemv": ["gemv_Wy"],
+}
 
 
 def load_traffic(kernel, workload, shash):
@@ -178,19 +194,27 @@ def main():
         # the solution uses ell + k
         ds = list(range(P.ell, P.ell + P.k)) + [P.ell + P.k]
         ab = algorithmic_bytes(P, sum(ds) / len(ds))
-        bulk = {k: v for k, v in phase.items() if k in ab}
-        dom = max(bulk, key=lambda k: bulk[k]["ms_total"])
-        avg_s = bulk[dom]["us_avg"] * 1e-6
-        achieved = ab[dom] / avg_s / 1e9
+        kern = {}
+        for kname, phs in KERNEL_PHASES.items():
+            ms = sum(phase[p]["ms_total"] for p in phs if p in phase)
+            nl = sum(phase[p]["launches"] for p in phs if p in phase)
+            by = sum(ab[p] * phase[p]["launches"] for p in phs if p in phase)
+            if nl:
+                kern[kname] = {"ms_total": ms, "launches": nl, "us_avg": 1e3 * ms / nl,
+                               "bytes_per_launch": by / nl, "GBps": by / (ms * 1e-3) / 1e9}
+        out["kernels"] = kern
+        dom = max(kern, key=lambda k: kern[k]["ms_total"])
+        achieved = kern[dom]["GBps"]
         shash = source_hash()
         traffic = load_traffic(dom, P.name, shash)
         out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": achieved,
                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                           "traffic": traffic, "algorithmic_bytes_per_launch": ab[dom],
-                           "source_hash": shash}
-        sk = ["forward_Ax_Lx", "adjoint_ATu_LTt", "spmv_sketch"]
-        tb = sum(ab[k] * bulk[k]["launches"] for k in sk if k in bulk)
-        tt = sum(bulk[k]["ms_total"] for k in sk if k in bulk) * 1e-3
+                           "traffic": traffic,
+                           "algorithmic_bytes_per_launch": kern[dom]["bytes_per_launch"],
+                           "avg_launch_us": kern[dom]["us_avg"], "source_hash": shash}
+        sk = ["k_forward", "k_adjoint", "k_scatter"]
+        tb = sum(kern[k]["bytes_per_launch"] * kern[k]["launches"] for k in sk if k in kern)
+        tt = sum(kern[k]["ms_total"] for k in sk if k in kern) * 1e-3
         out["spmv_sketch_GBps"] = tb / tt / 1e9 if tt > 0 else None
         out["spmv_sketch_frac_of_hbm_peak"] = out["spmv_sketch_GBps"] / HBM_PEAK_GBS
     if not args.no_cpu_baseline:

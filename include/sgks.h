@@ -152,11 +152,11 @@ int64_t sgks_copy_state(sgks_ctx *ctx, int32_t which, double *dst, int64_t count
 /* Per-phase device timing (the per-component breakdown of Sec. 4): while
  * enabled, every kernel launch of sgks_iterate / sgks_solution is bracketed by
  * HIP events on the context's stream.  Phases: 0 x = W y, 1 forward products
- * (A x - b, L x), 2 adjoint products (A^T u + mu L^T t), 3 SpMV + sketch of
- * the new column, 4 QR appends + projected solve, 5 W^T v (refinement),
- * 6 refinement step, 7 other.  sgks_profile_read synchronises, writes the
- * summed milliseconds and launch counts of the SGKS_PHASES phases (either
- * array may be NULL) and resets them. */
+ * (A x - b, L x), 2 adjoint products (A^T u + mu L^T t), 3 SpMV of the new
+ * column (A w, L w), 4 QR appends + projected solve, 5 W^T v (refinement),
+ * 6 refinement step, 7 sketch scatter of the new column.  sgks_profile_read
+ * synchronises, writes the summed milliseconds and launch counts of the
+ * SGKS_PHASES phases (either array may be NULL) and resets them. */
 #define SGKS_PHASES 8
 int sgks_profile_enable(sgks_ctx *ctx, int32_t on);
 int sgks_profile_read(sgks_ctx *ctx, double *ms, int64_t *launches);

@@ -445,7 +445,11 @@ int sgks_iterate(sgks_ctx* c, int32_t k) {
         { Phase ph(c, 0); sgks::launch_gemv(S, S.y, false, S.x, nullptr, -1, st); }
         { Phase ph(c, 1); sgks::launch_forward(S, S.x, S.b, S.u, S.t, true, nullptr, nullptr, 0, st); }
         { Phase ph(c, 2); sgks::launch_adjoint(S, S.u, S.t, true, S.mu, nullptr, true, S.norm_part, st); }
-        { Phase ph(c, 3); sgks::launch_sketch(S, -1, false, nullptr, st); }
+        {   // z = A w, L w of the new column (basis column d), then its sketch
+            Phase ph(c, 3);
+            sgks::launch_forward(S, nullptr, nullptr, S.u, S.t, true, nullptr, nullptr, 0, st);
+        }
+        { Phase ph(c, 7); sgks::launch_scatter(S, S.u, S.t, st, true); }
         {
             Phase ph(c, 4);
             if (sgks::launch_append(S, true, c->groups, st)) return SGKS_ERR_HIP;

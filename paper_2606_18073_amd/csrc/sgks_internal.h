@@ -101,6 +101,8 @@ void launch_adjoint(const State& S, const double* u, const double* t, bool with_
                     double* dst_fixed, bool dst_is_basis_column, double* part, hipStream_t st);
 int adjoint_blocks(const State& S);
 void launch_sketch(const State& S, int col, bool vec_mode, const double* vec, hipStream_t st);
+void launch_scatter(const State& S, const double* zA, const double* zL, hipStream_t st,
+                    bool honor_status);
 void launch_gemv(const State& S, const double* coef, bool coef_from_cs, double* out,
                  const double* base, int ncols_fixed, hipStream_t st);
 void launch_gemvt(const State& S, const double* v, int ncols_fixed, hipStream_t st);

@@ -26,8 +26,8 @@ ERRORS = {
 F32, F64 = 0, 1
 SKETCH_SPARSE_SIGN, SKETCH_IDENTITY = 0, 1
 PHASES = 8
-PHASE_NAMES = ["gemv_Wy", "forward_Ax_Lx", "adjoint_ATu_LTt", "spmv_sketch", "qr_append_solve",
-               "gemvt_WTr", "refine_step", "other"]
+PHASE_NAMES = ["gemv_Wy", "forward_Ax_Lx", "adjoint_ATu_LTt", "spmv_new_column",
+               "qr_append_solve", "gemvt_WTr", "refine_step", "sketch_scatter"]
 STATE = {"W": 0, "y": 1, "Q_A": 2, "R_A": 3, "Q_L": 4, "R_L": 5, "d_A": 6, "G": 7, "c_b": 8}
 
 

@@ -268,3 +268,47 @@ def solve_problem(P, k=None, device="cuda", **kw):
     S = SGKS(A, L, b, P.mu, P.s, P.seed, **opts)
     S.iterate(k)
     return S, S.solution()
+
+
+_FUNCTION = None
+
+
+def _function_class():
+    """torch.autograd.Function whose backward is the library's frozen-basis adjoint."""
+    global _FUNCTION
+    if _FUNCTION is not None:
+        return _FUNCTION
+    import torch
+
+    class SGKSFunction(torch.autograd.Function):
+        """x_k = sGKS(b, mu).  backward: d loss/d b = S_A^T Q_A R_A z and
+        d loss/d mu = -(R_L z).(R_L y), z = H^{-1} W^T grad_x, with the basis W and
+        the factors Q_A, R_A, R_L of the forward solve held fixed (sgks_backward);
+        W stays on the device between the two calls."""
+
+        @staticmethod
+        def forward(ctx, b, mu, A, L, s, seed, k, opts):
+            S = SGKS(A, L, b.detach().contiguous(), float(mu), s, seed, **opts)
+            S.iterate(k)
+            ctx.solver = S
+            ctx.b_dtype = b.dtype
+            ctx.mu_meta = (mu.dtype, mu.device, mu.shape) if torch.is_tensor(mu) else None
+            return S.solution()
+
+        @staticmethod
+        def backward(ctx, grad_x):
+            gb, gmu = ctx.solver.backward(grad_x)
+            gmu_t = None
+            if ctx.mu_meta is not None:
+                dt, dev, shp = ctx.mu_meta
+                gmu_t = torch.full(shp, gmu, dtype=dt, device=dev)
+            return gb.to(ctx.b_dtype), gmu_t, None, None, None, None, None, None
+
+    _FUNCTION = SGKSFunction
+    return _FUNCTION
+
+
+def sgks_solve(A: DeviceCsr, L: DeviceCsr, b, mu, s, k, seed=0, **opts):
+    """Differentiable x_k (float64 tensor) of k sGKS expansions; b and mu may require grad."""
+    opts.setdefault("max_iters", max(int(k), 1))
+    return _function_class().apply(b, mu, A, L, int(s), int(seed), int(k), opts)

@@ -375,3 +375,80 @@ def test_dynamic_ct_full():
     x = S.solution().cpu().numpy()
     say(f"  k={P.k} RRE gpu {rel(x, P.x_true):.6f}")
     S.close()
+
+
+# ----------------------------------------------------------------------------
+# differentiation
+# ----------------------------------------------------------------------------
+
+def test_autograd_function_matches_backward():
+    P = problem("dynamic_ct", "small")
+    say("case autograd small")
+    A, L, b = G.upload_problem(P)
+    bg = b.clone().requires_grad_(True)
+    mu = torch.tensor(P.mu, dtype=torch.float64, device="cuda", requires_grad=True)
+    xt = torch.as_tensor(P.x_true, device="cuda")
+    x = G.sgks_solve(A, L, bg, mu, P.s, P.k, P.seed)
+    loss = ((x - xt) ** 2).sum()
+    loss.backward()
+    S, x2 = G.solve_problem(P)
+    gb, gmu = S.backward(2 * (x2 - xt))
+    assert torch.equal(x.detach(), x2)
+    assert torch.allclose(bg.grad.double(), gb.to(bg.dtype).double(), rtol=0, atol=0)
+    assert abs(mu.grad.item() - gmu) <= 1e-12 * abs(gmu)
+    S.close()
+
+
+def test_backward_is_true_derivative_at_full_space():
+    """At d = n the frozen-basis adjoint is the derivative of the whole solve: compare
+    with central differences of the GPU pipeline itself."""
+    A_ = gen.blur1d_dense(8, 0.8)
+    L_ = gen.diff1d(8)
+    rng = np.random.default_rng(1)
+    xt_ = gen.step_signal(8, rng)
+    b_ = gen.add_noise(A_ @ xt_, 0.01, rng)
+    mu_, s_, seed_ = 1e-2, 100, 5
+    A, L = G.DeviceCsr.from_scipy(A_), G.DeviceCsr.from_scipy(L_)
+    xt = torch.as_tensor(xt_, device="cuda")
+    say("case full-space derivative")
+
+    def loss_of(bv, mv):
+        x = G.sgks_solve(A, L, bv, mv, s_, 5, seed_)
+        return ((x - xt) ** 2).sum()
+
+    bg = torch.as_tensor(b_, device="cuda").requires_grad_(True)
+    mu = torch.tensor(mu_, dtype=torch.float64, device="cuda", requires_grad=True)
+    loss_of(bg, mu).backward()
+    h = 1e-6
+    for i in range(8):
+        e = torch.zeros(8, dtype=torch.float64, device="cuda")
+        e[i] = h
+        bb = torch.as_tensor(b_, device="cuda")
+        fd = (loss_of(bb + e, mu_).item() - loss_of(bb - e, mu_).item()) / (2 * h)
+        assert abs(fd - bg.grad[i].item()) <= 1e-5 * max(1.0, abs(fd)), (i, fd, bg.grad[i].item())
+    hm = 1e-6 * mu_
+    bb = torch.as_tensor(b_, device="cuda")
+    fdm = (loss_of(bb, mu_ + hm).item() - loss_of(bb, mu_ - hm).item()) / (2 * hm)
+    assert abs(fdm - mu.grad.item()) <= 1e-5 * max(1.0, abs(fdm))
+
+
+def test_backward_dynamic_ct_full_size():
+    """Dynamic CT 30 x 128^2 (n = 491,520): GPU adjoint vs the oracle's frozen adjoint on the
+    GPU's own basis and factors (k = 30)."""
+    P = problem("dynamic_ct", "full")
+    k = 30
+    say("case backward full", P.n, P.m, k)
+    S, x = G.solve_problem(P, k=k)
+    xt = torch.as_tensor(P.x_true, device="cuda")
+    gb, gmu = S.backward(2 * (x - xt))
+    xh = x.cpu().numpy()
+    res = O.Result(xh, S.state("y"), S.state("W"), S.state("Q_A"), S.state("R_A"),
+                   S.state("Q_L"), S.state("R_L"), S.state("d_A"), S.state("G"),
+                   S.state("c_b"), k, 0, [], [])
+    gb_ref, gmu_ref = O.frozen_adjoint_b(res, P.mu, 2 * (xh - P.x_true), P.A, P.L, P.s, P.seed,
+                                         P.zeta)
+    e = rel(gb.cpu().numpy(), gb_ref)
+    say(f"  grad_b rel err {e:.3e}, grad_mu {gmu:.6e} vs {gmu_ref:.6e}")
+    assert e <= 1e-8
+    assert abs(gmu - gmu_ref) <= 1e-8 * abs(gmu_ref)
+    S.close()

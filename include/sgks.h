@@ -91,7 +91,13 @@ typedef struct {
     int32_t sketch_mode;     /* SGKS_SKETCH_SPARSE_SIGN (default) or SGKS_SKETCH_IDENTITY     */
     int32_t lanes_A;         /* lanes per row for A-row SpMVs; 0 = choose from nnz/row          */
     int32_t lanes_At;        /* lanes per row for A^T rows; 0 = choose                          */
-    int32_t append_groups;   /* workgroups of the cooperative append kernel; 0 = choose         */
+    int32_t append_groups;   /* workgroups of the append kernels; 0 = choose                    */
+    int32_t graph;           /* 1 = sgks_iterate / sgks_batch_iterate replay a captured HIP
+                                graph of the expansion (default), 0 = launch kernel by kernel.
+                                Profiling (sgks_profile_enable) always launches kernel by kernel */
+    int32_t autotune;        /* 1 = time the lanes-per-row choices of the SpMVs at create and
+                                keep the fastest (cached per operator shape in the process);
+                                0 = choose from nnz/row (default)                               */
     void *stream;            /* hipStream_t the work is enqueued on (NULL = default stream)   */
 } sgks_options;
 
@@ -164,8 +170,69 @@ int sgks_profile_read(sgks_ctx *ctx, double *ms, int64_t *launches);
 /* Current number of basis columns d (host-side view, no synchronisation). */
 int32_t sgks_dim(const sgks_ctx *ctx);
 
+/* Lanes of a wavefront per CSR row in use: lanes[0] rows of A, lanes[1] rows
+ * of L (forward products), lanes[2] rows of A^T and L^T (adjoint products).
+ * Powers of two in [1, 64]; 64 / lanes rows share one wavefront. */
+int sgks_get_lanes(const sgks_ctx *ctx, int32_t lanes[3]);
+
+/* Releases the context and its device memory (synchronises its stream).  A
+ * context obtained from sgks_batch_get belongs to its batch: destroying it
+ * here does nothing. */
 void sgks_destroy(sgks_ctx *ctx);
 const char *sgks_strerror(int code);
+
+/* ------------------------------------------------------------------------
+ * Batched solves (an extension, not in the paper): many independent problems
+ * of uneven sizes advance together.  Each kernel launch of an expansion covers
+ * every problem of the batch (its workgroups are split among the problems by
+ * a block table), so the latency-bound small steps of different problems
+ * overlap and the bulk steps of small problems fill the GPU together.
+ * ------------------------------------------------------------------------ */
+
+#define SGKS_MAX_BATCH 64
+
+/* One problem of a batch: operators, right-hand side (device, value_dtype of
+ * the options), mu > 0, sketch size s and seed, as the arguments of
+ * sgks_create. */
+typedef struct {
+    sgks_csr A, L;
+    const void *b;
+    double mu;
+    int32_t sketch_rows;
+    uint64_t seed;
+} sgks_problem;
+
+typedef struct sgks_batch sgks_batch;
+
+/* Set up count (1..SGKS_MAX_BATCH) problems that share opt (value dtype,
+ * zeta, ell, max_iters, refinement, QR passes, sketch kind, stream, graph and
+ * autotune choices; lanes and append_groups must be 0).  Each problem is set
+ * up as by sgks_create; the first failing problem's code is returned and
+ * nothing is kept.  Synchronises the stream. */
+int sgks_batch_create(int32_t count, const sgks_problem *problems, const sgks_options *opt,
+                      sgks_batch **out);
+
+/* k more expansions of every problem (as sgks_iterate on each, with the same
+ * results bit for bit).  A problem that stopped (breakdown) stays as it is
+ * while the others go on.  Asynchronous; SGKS_ERR_CAPACITY if any problem
+ * would exceed ell + max_iters columns. */
+int sgks_batch_iterate(sgks_batch *batch, int32_t k);
+
+/* Problem i of the batch as a context (borrowed, valid until
+ * sgks_batch_destroy): sgks_solution, sgks_residual_norm, sgks_status,
+ * sgks_backward, sgks_copy_state and sgks_iterate apply to it.  NULL if i is
+ * out of range. */
+sgks_ctx *sgks_batch_get(sgks_batch *batch, int32_t i);
+
+/* Number of problems; 0 for NULL. */
+int32_t sgks_batch_count(const sgks_batch *batch);
+
+/* Per-phase timing of sgks_batch_iterate, as sgks_profile_enable / _read
+ * (one event pair per launch, covering every problem). */
+int sgks_batch_profile_enable(sgks_batch *batch, int32_t on);
+int sgks_batch_profile_read(sgks_batch *batch, double *ms, int64_t *launches);
+
+void sgks_batch_destroy(sgks_batch *batch);
 
 #ifdef __cplusplus
 }

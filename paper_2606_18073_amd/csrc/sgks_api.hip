@@ -4,7 +4,10 @@
 #include <math.h>
 #include <string.h>
 
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 #include <vector>
 
 #include "sgks.h"
@@ -13,12 +16,233 @@
 using sgks::Csr;
 using sgks::State;
 
+namespace {
+
+// Per-phase timing with event pairs on one stream.
+struct Profiler {
+    bool on = false;
+    hipStream_t st = nullptr;
+    std::vector<hipEvent_t> events;    // pairs (start, end)
+    std::vector<int> pair_phase;
+    size_t pairs_used = 0;
+
+    ~Profiler() {
+        for (hipEvent_t e : events) hipEventDestroy(e);
+    }
+    int read(double* ms, int64_t* launches) {
+        if (hipStreamSynchronize(st) != hipSuccess) return SGKS_ERR_HIP;
+        double acc[SGKS_PHASES] = {0};
+        int64_t cnt[SGKS_PHASES] = {0};
+        for (size_t i = 0; i < pairs_used; ++i) {
+            float t = 0.0f;
+            if (hipEventElapsedTime(&t, events[2 * i], events[2 * i + 1]) != hipSuccess)
+                return SGKS_ERR_HIP;
+            acc[pair_phase[i]] += t;
+            cnt[pair_phase[i]] += 1;
+        }
+        pairs_used = 0;
+        for (int p = 0; p < SGKS_PHASES; ++p) {
+            if (ms) ms[p] = acc[p];
+            if (launches) launches[p] = cnt[p];
+        }
+        return SGKS_OK;
+    }
+};
+
+// Brackets the launches of one phase with a pair of events when profiling.
+struct Phase {
+    Profiler* pr;
+    size_t pair;
+    Phase(Profiler* p, int phase) : pr(p), pair((size_t)-1) {
+        if (!pr || !pr->on) return;
+        if (pr->pairs_used >= pr->pair_phase.size()) {
+            hipEvent_t a, b;
+            if (hipEventCreate(&a) != hipSuccess) return;
+            if (hipEventCreate(&b) != hipSuccess) {
+                hipEventDestroy(a);
+                return;
+            }
+            pr->events.push_back(a);
+            pr->events.push_back(b);
+            pr->pair_phase.push_back(0);
+        }
+        pair = pr->pairs_used++;
+        pr->pair_phase[pair] = phase;
+        hipEventRecord(pr->events[2 * pair], pr->st);
+    }
+    ~Phase() {
+        if (pair != (size_t)-1) hipEventRecord(pr->events[2 * pair + 1], pr->st);
+    }
+};
+
+// Refinement step of every problem of the plan: x = W y, u, t, r = gradient
+// into rtmp, W^T r, y update (heavy ball).
+void enqueue_refine(const sgks::Plan& P, Profiler* pr, hipStream_t st) {
+    { Phase ph(pr, 0); sgks::plan_gemv(P, st); }
+    { Phase ph(pr, 1); sgks::plan_forward(P, false, st); }
+    { Phase ph(pr, 2); sgks::plan_adjoint(P, true, st); }
+    { Phase ph(pr, 5); sgks::plan_gemvt(P, st); }
+    { Phase ph(pr, 6); sgks::plan_refine(P, st); }
+}
+
+// One expansion of every problem of the plan (the loop body of Alg. 2):
+// x = W y, u = A x - b, t = L x, r = A^T u + mu L^T t into the next basis
+// column, A w and L w of that column, their sketches, the QR appends and
+// the projected solve; then the refinement steps.
+int enqueue_iteration(const sgks::Plan& P, int refine_steps, Profiler* pr, hipStream_t st) {
+    { Phase ph(pr, 0); sgks::plan_gemv(P, st); }
+    { Phase ph(pr, 1); sgks::plan_forward(P, false, st); }
+    { Phase ph(pr, 2); sgks::plan_adjoint(P, false, st); }
+    { Phase ph(pr, 3); sgks::plan_forward(P, true, st); }
+    { Phase ph(pr, 7); sgks::plan_scatter(P, st); }
+    {
+        Phase ph(pr, 4);
+        if (sgks::plan_append(P, true, st)) return SGKS_ERR_HIP;
+    }
+    for (int r = 0; r < refine_steps; ++r) enqueue_refine(P, pr, st);
+    return SGKS_OK;
+}
+
+// Captured HIP graphs of the expansion: one of a single expansion and one of
+// kGraphChunk expansions.  The kernels take only device-resident state (the
+// basis size d is read on the device), so one graph serves every expansion.
+constexpr int kGraphChunk = 8;
+
+struct GraphCache {
+    hipStream_t cap = nullptr;
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+
+    ~GraphCache() {
+        for (hipGraphExec_t e : exec)
+            if (e) hipGraphExecDestroy(e);
+        if (cap) hipStreamDestroy(cap);
+    }
+    int capture(const sgks::Plan& P, int refine_steps, int iters, hipGraphExec_t* out) {
+        if (!cap && hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)
+            return SGKS_ERR_HIP;
+        if (hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed) != hipSuccess)
+            return SGKS_ERR_HIP;
+        int rc = SGKS_OK;
+        for (int i = 0; i < iters && rc == SGKS_OK; ++i)
+            rc = enqueue_iteration(P, refine_steps, nullptr, cap);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(cap, &g);
+        if (e != hipSuccess || rc != SGKS_OK || !g) {
+            if (g) hipGraphDestroy(g);
+            return SGKS_ERR_HIP;
+        }
+        const hipError_t ei = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        return ei == hipSuccess ? SGKS_OK : SGKS_ERR_HIP;
+    }
+};
+
+// k expansions of every problem of the plan: graph replays, or kernel by
+// kernel while profiling or when graphs are off.
+int run_iterations(const sgks::Plan& P, int refine_steps, Profiler* pr, GraphCache* gc,
+                   bool use_graph, hipStream_t st, int k) {
+    if (!use_graph || (pr && pr->on)) {
+        for (int it = 0; it < k; ++it) {
+            const int rc = enqueue_iteration(P, refine_steps, pr, st);
+            if (rc) return rc;
+        }
+        return hipGetLastError() == hipSuccess ? SGKS_OK : SGKS_ERR_HIP;
+    }
+    while (k > 0) {
+        const int which = k >= kGraphChunk ? 1 : 0;
+        if (!gc->exec[which]) {
+            const int rc = gc->capture(P, refine_steps, which ? kGraphChunk : 1, &gc->exec[which]);
+            if (rc) return rc;
+        }
+        if (hipGraphLaunch(gc->exec[which], st) != hipSuccess) return SGKS_ERR_HIP;
+        k -= which ? kGraphChunk : 1;
+    }
+    return SGKS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner of the lanes per CSR row: every power of two is timed on the
+// operator itself (HIP events, best of a few launches); choices are cached
+// per operator shape for the life of the process.
+// ---------------------------------------------------------------------------
+
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int64_t, int64_t, int64_t, int64_t, int>, int> g_tune;
+
+template <typename F>
+float time_launches(hipStream_t st, F&& launch, int reps) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess) return INFINITY;
+    if (hipEventCreate(&b) != hipSuccess) {
+        hipEventDestroy(a);
+        return INFINITY;
+    }
+    launch();   // warm-up
+    float best = INFINITY;
+    for (int r = 0; r < reps; ++r) {
+        hipEventRecord(a, st);
+        launch();
+        hipEventRecord(b, st);
+        float ms = INFINITY;
+        if (hipEventSynchronize(b) == hipSuccess && hipEventElapsedTime(&ms, a, b) == hipSuccess &&
+            ms < best)
+            best = ms;
+    }
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    return best;
+}
+
+// kind: 0 rows of A (forward), 1 rows of L (forward), 2 rows of A^T and L^T (adjoint)
+int tune_one(const State& S, int kind, hipStream_t st) {
+    const Csr& M = kind == 0 ? S.A : kind == 1 ? S.L : S.At;
+    const auto key = std::make_tuple(kind, M.rows, M.cols, M.nnz,
+                                     kind == 2 ? S.Lt.nnz : (int64_t)0, S.vdt);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) return it->second;
+    }
+    int best = M.lanes;
+    float tbest = INFINITY;
+    for (int lanes = 1; lanes <= 64; lanes *= 2) {
+        State T = S;
+        float ms;
+        if (kind == 2) {
+            T.At.lanes = lanes;
+            ms = time_launches(st, [&] {
+                sgks::launch_adjoint(T, S.u, S.t, true, S.mu, S.rtmp, S.norm_part, st);
+            }, 5);
+        } else {
+            T.A = kind == 0 ? S.A : S.L;
+            T.A.lanes = lanes;
+            double* out = kind == 0 ? S.u : S.t;
+            ms = time_launches(st, [&] {
+                sgks::launch_forward(T, S.x, nullptr, out, nullptr, false, nullptr, nullptr, st);
+            }, 5);
+        }
+        if (ms < tbest) {
+            tbest = ms;
+            best = lanes;
+        }
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = best;
+    return best;
+}
+
+}  // namespace
+
 struct sgks_ctx {
     State S;
+    State* Sdev;         // device copy of S (the kernels of the iteration read it)
+    sgks::Plan plan;     // the iteration as a batch of one
     sgks_options opt;
     hipStream_t st;
     int d_host;          // basis columns expected on the device (no breakdown)
-    int groups;          // workgroups of the cooperative append
+    int groups;          // workgroups of the append kernels
+    bool borrowed = false;   // owned by a batch
+    GraphCache graphs;
     std::vector<void*> allocs;
     double* upart;       // partial sums of ||A x - b||^2
     double* tpart;       // partial sums of ||L x||^2
@@ -31,40 +255,10 @@ struct sgks_ctx {
     int32_t* Lt_rowptr;
     int32_t* Lt_col;
     void* Lt_val;
-    // per-phase timing
-    bool prof = false;
-    std::vector<hipEvent_t> events;    // pairs (start, end)
-    std::vector<int> pair_phase;
-    size_t pairs_used = 0;
+    Profiler prof;
 };
 
 namespace {
-
-// Brackets the launches of one phase with a pair of events when profiling.
-struct Phase {
-    sgks_ctx* c;
-    size_t pair;
-    Phase(sgks_ctx* ctx, int phase) : c(ctx), pair((size_t)-1) {
-        if (!c->prof) return;
-        if (c->pairs_used >= c->pair_phase.size()) {
-            hipEvent_t a, b;
-            if (hipEventCreate(&a) != hipSuccess) return;
-            if (hipEventCreate(&b) != hipSuccess) {
-                hipEventDestroy(a);
-                return;
-            }
-            c->events.push_back(a);
-            c->events.push_back(b);
-            c->pair_phase.push_back(0);
-        }
-        pair = c->pairs_used++;
-        c->pair_phase[pair] = phase;
-        hipEventRecord(c->events[2 * pair], c->st);
-    }
-    ~Phase() {
-        if (pair != (size_t)-1) hipEventRecord(c->events[2 * pair + 1], c->st);
-    }
-};
 
 bool pow2_lanes(int v) { return v == 0 || v == 1 || v == 2 || v == 4 || v == 8 || v == 16 || v == 32 || v == 64; }
 
@@ -127,15 +321,6 @@ void norm_to_scale(sgks_ctx* c, double* v, int col, bool store_r0) {
     sgks::launch_set_scale(S, col, store_r0, c->st);
 }
 
-void refine_once(sgks_ctx* c) {
-    State& S = c->S;
-    { Phase ph(c, 0); sgks::launch_gemv(S, S.y, false, S.x, nullptr, -1, c->st); }
-    { Phase ph(c, 1); sgks::launch_forward(S, S.x, S.b, S.u, S.t, true, nullptr, nullptr, 0, c->st); }
-    { Phase ph(c, 2); sgks::launch_adjoint(S, S.u, S.t, true, S.mu, S.rtmp, false, S.norm_part, c->st); }
-    { Phase ph(c, 5); sgks::launch_gemvt(S, S.rtmp, -1, c->st); }
-    { Phase ph(c, 6); sgks::launch_refine(S, c->st); }
-}
-
 }  // namespace
 
 extern "C" {
@@ -153,6 +338,8 @@ void sgks_default_options(sgks_options* o) {
     o->lanes_A = 0;
     o->lanes_At = 0;
     o->append_groups = 0;
+    o->graph = 1;
+    o->autotune = 0;
     o->stream = nullptr;
 }
 
@@ -181,6 +368,8 @@ int sgks_validate(const sgks_csr* A, const sgks_csr* L, const void* b, double mu
         return SGKS_ERR_INVALID_ARG;
     if (!pow2_lanes(o.lanes_A) || !pow2_lanes(o.lanes_At)) return SGKS_ERR_INVALID_ARG;
     if (o.append_groups < 0) return SGKS_ERR_INVALID_ARG;
+    if ((o.graph != 0 && o.graph != 1) || (o.autotune != 0 && o.autotune != 1))
+        return SGKS_ERR_INVALID_ARG;
     if (s > sgks::kMaxS || s < 1) return SGKS_ERR_SKETCH_SIZE;
     if (o.sketch_mode == SGKS_SKETCH_SPARSE_SIGN) {
         if (s < o.ell + o.max_iters) return SGKS_ERR_SKETCH_SIZE;
@@ -269,8 +458,7 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
         int G = c->opt.append_groups;
         if (G == 0) G = sgks::choose_append_groups(s, dmax, cap < 64 ? cap : 64);
         if (G > cap) G = cap;
-        if (G > sgks::kMaxAppendGroups || (s + G - 1) / G > sgks::kAppendMaxSlab ||
-            (dmax + G - 1) / G > sgks::kAppendMaxSlab) {
+        if (!sgks::append_groups_ok(s, dmax, G)) {
             sgks_destroy(c);
             return SGKS_ERR_SKETCH_SIZE;
         }
@@ -305,13 +493,13 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
     ar.add(&S.cb, s * 8);
     ar.add(&S.y, dmax * 8);
     ar.add(&S.yprev, dmax * 8);
-    ar.add(&S.norm_part, S.n_norm_part * 8);
+    ar.add(&S.norm_part, 2048 * 8);   // adjoint workgroups are capped at 2048
     ar.add(&S.binA, (size_t)S.nbA * s * 8);
     ar.add(&S.binL, (size_t)S.nbL * s * 8);
     ar.add(&S.wa, s * 8);
     ar.add(&S.wl, s * 8);
     ar.add(&S.wu, 2 * dmax * 8);
-    ar.add(&S.pacc, 2 * dmax * 8);
+    ar.add(&S.pacc, 4 * dmax * 8);
     ar.add(&S.gacc, dmax * 8);
     ar.add(&S.gpart, (size_t)S.ngt * dmax * 8);
     ar.add(&S.coop, (size_t)regions * c->groups * CW * 8);
@@ -319,10 +507,12 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
     ar.add(&S.d, 64);
     ar.add(&S.status, 64);
     ar.add(&S.degenerate, 64);
-    ar.add(&c->upart, c->nbF_A * 8);
-    ar.add(&c->tpart, (c->nbF_L > 0 ? c->nbF_L : 1) * 8);
+    // forward workgroups for any lanes choice (at most four rows per workgroup fewer)
+    ar.add(&c->upart, ((S.m + 3) / 4 + 1) * 8);
+    ar.add(&c->tpart, ((S.p + 3) / 4 + 1) * 8);
     ar.add(&c->coefbuf, dmax * 8);
     ar.add(&c->sbuf, s * 8);
+    ar.add(&c->Sdev, sizeof(State));
     SGKS_TRY(ar.commit(c));
     if (sgks::transpose_csr(S.A, S.vdt, c->At_rowptr, c->At_col, c->At_val, c->st) ||
         sgks::transpose_csr(S.L, S.vdt, c->Lt_rowptr, c->Lt_col, c->Lt_val, c->st)) {
@@ -336,6 +526,28 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
     S.Lt.col = c->Lt_col;
     S.Lt.val = c->Lt_val;
     hipStream_t st = c->st;
+    c->prof.st = st;
+    if (c->opt.autotune) {
+        SGKS_TRY(hipMemsetAsync(S.x, 0, S.n * 8, st));
+        SGKS_TRY(hipMemsetAsync(S.u, 0, S.m * 8, st));
+        SGKS_TRY(hipMemsetAsync(S.t, 0, S.p * 8, st));
+        if (!c->opt.lanes_A) S.A.lanes = tune_one(S, 0, st);
+        S.L.lanes = tune_one(S, 1, st);
+        if (!c->opt.lanes_At) S.At.lanes = tune_one(S, 2, st);
+        S.Lt.lanes = S.At.lanes;
+        SGKS_TRY(hipGetLastError());
+        S.n_norm_part = sgks::adjoint_blocks(S);
+        int nbFA2 = 0;
+        const int nbF2 = sgks::forward_blocks(S, true, &nbFA2);
+        c->nbF_A = nbFA2;
+        c->nbF_L = nbF2 - nbFA2;
+    }
+    // the kernels of the iteration read the State from device memory
+    SGKS_TRY(hipMemcpyAsync(c->Sdev, &S, sizeof(State), hipMemcpyHostToDevice, st));
+    if (sgks::plan_build(c->plan, &S, c->Sdev, 1, &c->groups)) {
+        sgks_destroy(c);
+        return SGKS_ERR_INVALID_ARG;
+    }
     SGKS_TRY(hipMemsetAsync(S.cs, 0, dmax * 8, st));
     SGKS_TRY(hipMemsetAsync(S.QA, 0, (size_t)s * dmax * 8, st));
     SGKS_TRY(hipMemsetAsync(S.QL, 0, (size_t)s * dmax * 8, st));
@@ -369,25 +581,25 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
     }
 
     // c_b = S_A b
-    sgks::launch_sketch(S, 0, true, S.b, st);
+    sgks::launch_scatter(S, S.b, nullptr, st);
     sgks::launch_cb(S, st);
 
     // initial basis: orthonormal basis of K_ell(A^T A, A^T b), CGS2 (stored
     // unnormalised with cs[j] = 1 / ||column||)
-    sgks::launch_adjoint(S, S.b, nullptr, false, 0.0, S.W, false, S.norm_part, st);
+    sgks::launch_adjoint(S, S.b, nullptr, false, 0.0, S.W, S.norm_part, st);
     sgks::launch_set_scale(S, 0, true, st);
     for (int j = 1; j < c->opt.ell; ++j) {
         double* prev = S.W + (size_t)(j - 1) * S.n;
         double* col = S.W + (size_t)j * S.n;
-        sgks::launch_forward(S, prev, nullptr, S.u, S.t, false, nullptr, nullptr, 0, st);
-        sgks::launch_adjoint(S, S.u, nullptr, false, 0.0, col, false, S.norm_part, st);
+        sgks::launch_forward(S, prev, nullptr, S.u, S.t, false, nullptr, nullptr, st);
+        sgks::launch_adjoint(S, S.u, nullptr, false, 0.0, col, S.norm_part, st);
         // norm before the projections (to detect a Krylov space that stopped growing)
         sgks::launch_to_f64(col, 1, col, S.n, S.norm_part, S.n_norm_part, st);
         sgks::launch_sum_parts(S.norm_part, S.n_norm_part, S.scal + 16 + dmax + j, st);
         for (int pass = 0; pass < 2; ++pass) {
             sgks::launch_gemvt(S, col, j, st);
             sgks::launch_reduce_gpart(S, j, c->coefbuf, st);
-            sgks::launch_gemv(S, c->coefbuf, false, col, col, j, st);
+            sgks::launch_gemv(S, c->coefbuf, col, col, j, st);
         }
         norm_to_scale(c, col, j, false);
     }
@@ -418,13 +630,13 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
 
     // sketch and QR-append the initial columns, then y_0
     for (int j = 0; j < c->opt.ell; ++j) {
-        sgks::launch_sketch(S, j, false, nullptr, st);
-        if (sgks::launch_append(S, false, c->groups, st)) {
+        sgks::launch_sketch_column(S, j, st);
+        if (sgks::plan_append(c->plan, false, st)) {
             sgks_destroy(c);
             return SGKS_ERR_HIP;
         }
     }
-    for (int r = 0; r < c->opt.refine_steps; ++r) refine_once(c);
+    for (int r = 0; r < c->opt.refine_steps; ++r) enqueue_refine(c->plan, nullptr, st);
     c->d_host = c->opt.ell;
     const int stw = sync_status(c);
     if (stw != 0) {
@@ -439,31 +651,17 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
 int sgks_iterate(sgks_ctx* c, int32_t k) {
     if (!c || k < 0) return SGKS_ERR_INVALID_ARG;
     if (c->d_host + k > c->S.dmax) return SGKS_ERR_CAPACITY;
-    State& S = c->S;
-    hipStream_t st = c->st;
-    for (int it = 0; it < k; ++it) {
-        { Phase ph(c, 0); sgks::launch_gemv(S, S.y, false, S.x, nullptr, -1, st); }
-        { Phase ph(c, 1); sgks::launch_forward(S, S.x, S.b, S.u, S.t, true, nullptr, nullptr, 0, st); }
-        { Phase ph(c, 2); sgks::launch_adjoint(S, S.u, S.t, true, S.mu, nullptr, true, S.norm_part, st); }
-        {   // z = A w, L w of the new column (basis column d), then its sketch
-            Phase ph(c, 3);
-            sgks::launch_forward(S, nullptr, nullptr, S.u, S.t, true, nullptr, nullptr, 0, st);
-        }
-        { Phase ph(c, 7); sgks::launch_scatter(S, S.u, S.t, st, true); }
-        {
-            Phase ph(c, 4);
-            if (sgks::launch_append(S, true, c->groups, st)) return SGKS_ERR_HIP;
-        }
-        for (int r = 0; r < c->opt.refine_steps; ++r) refine_once(c);
-    }
+    const int rc = run_iterations(c->plan, c->opt.refine_steps, &c->prof, &c->graphs,
+                                  c->opt.graph != 0, c->st, k);
+    if (rc) return rc;
     c->d_host += k;
-    return hipGetLastError() == hipSuccess ? SGKS_OK : SGKS_ERR_HIP;
+    return SGKS_OK;
 }
 
 int sgks_solution(sgks_ctx* c, double* x_dev) {
     if (!c || !x_dev) return SGKS_ERR_INVALID_ARG;
-    Phase ph(c, 0);
-    sgks::launch_gemv(c->S, c->S.y, false, x_dev, nullptr, -1, c->st);
+    Phase ph(&c->prof, 0);
+    sgks::launch_gemv(c->S, c->S.y, x_dev, nullptr, -1, c->st);
     return hipGetLastError() == hipSuccess ? SGKS_OK : SGKS_ERR_HIP;
 }
 
@@ -471,8 +669,8 @@ int sgks_residual_norm(sgks_ctx* c, double* true_norm, double* sketched_norm) {
     if (!c) return SGKS_ERR_INVALID_ARG;
     State& S = c->S;
     hipStream_t st = c->st;
-    sgks::launch_gemv(S, S.y, false, S.x, nullptr, -1, st);
-    sgks::launch_forward(S, S.x, S.b, S.u, S.t, true, c->upart, c->tpart, 0, st);
+    sgks::launch_gemv(S, S.y, S.x, nullptr, -1, st);
+    sgks::launch_forward(S, S.x, S.b, S.u, S.t, true, c->upart, c->tpart, st);
     sgks::launch_sum_parts(c->upart, c->nbF_A, S.scal + 8, st);
     sgks::launch_sum_parts(c->tpart, c->nbF_L, S.scal + 9, st);
     sgks::launch_residual_small(S, S.scal + 10, st);
@@ -568,38 +766,140 @@ int64_t sgks_copy_state(sgks_ctx* c, int32_t which, double* dst, int64_t count) 
 
 int sgks_profile_enable(sgks_ctx* c, int32_t on) {
     if (!c) return SGKS_ERR_INVALID_ARG;
-    c->prof = on != 0;
+    c->prof.on = on != 0;
     return SGKS_OK;
 }
 
 int sgks_profile_read(sgks_ctx* c, double* ms, int64_t* launches) {
     if (!c) return SGKS_ERR_INVALID_ARG;
-    if (hipStreamSynchronize(c->st) != hipSuccess) return SGKS_ERR_HIP;
-    double acc[SGKS_PHASES] = {0};
-    int64_t cnt[SGKS_PHASES] = {0};
-    for (size_t i = 0; i < c->pairs_used; ++i) {
-        float t = 0.0f;
-        if (hipEventElapsedTime(&t, c->events[2 * i], c->events[2 * i + 1]) != hipSuccess)
-            return SGKS_ERR_HIP;
-        acc[c->pair_phase[i]] += t;
-        cnt[c->pair_phase[i]] += 1;
-    }
-    c->pairs_used = 0;
-    for (int p = 0; p < SGKS_PHASES; ++p) {
-        if (ms) ms[p] = acc[p];
-        if (launches) launches[p] = cnt[p];
-    }
-    return SGKS_OK;
+    return c->prof.read(ms, launches);
 }
 
 int32_t sgks_dim(const sgks_ctx* c) { return c ? c->d_host : 0; }
 
-void sgks_destroy(sgks_ctx* c) {
-    if (!c) return;
+int sgks_get_lanes(const sgks_ctx* c, int32_t lanes[3]) {
+    if (!c || !lanes) return SGKS_ERR_INVALID_ARG;
+    lanes[0] = c->S.A.lanes;
+    lanes[1] = c->S.L.lanes;
+    lanes[2] = c->S.At.lanes;
+    return SGKS_OK;
+}
+
+static void destroy_ctx(sgks_ctx* c) {
     hipStreamSynchronize(c->st);
     for (void* p : c->allocs) hipFree(p);
-    for (hipEvent_t e : c->events) hipEventDestroy(e);
     delete c;
+}
+
+void sgks_destroy(sgks_ctx* c) {
+    if (!c || c->borrowed) return;
+    destroy_ctx(c);
+}
+
+// ---------------------------------------------------------------------------
+// batches
+// ---------------------------------------------------------------------------
+
+}  // extern "C"
+
+struct sgks_batch {
+    std::vector<sgks_ctx*> ctx;
+    State* Sdev = nullptr;      // device array of the problems' States
+    sgks::Plan plan;
+    sgks_options opt;
+    hipStream_t st = nullptr;
+    Profiler prof;
+    GraphCache graphs;
+};
+
+extern "C" {
+
+int sgks_batch_create(int32_t count, const sgks_problem* probs, const sgks_options* opt,
+                      sgks_batch** out) {
+    if (!out) return SGKS_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (count < 1 || count > sgks::kMaxBatch || !probs) return SGKS_ERR_INVALID_ARG;
+    sgks_options o;
+    if (opt)
+        o = *opt;
+    else
+        sgks_default_options(&o);
+    if (o.lanes_A || o.lanes_At || o.append_groups) return SGKS_ERR_INVALID_ARG;
+    for (int i = 0; i < count; ++i) {
+        const int rc = sgks_validate(&probs[i].A, &probs[i].L, probs[i].b, probs[i].mu,
+                                     probs[i].sketch_rows, &o);
+        if (rc) return rc;
+    }
+    sgks_batch* B = new (std::nothrow) sgks_batch();
+    if (!B) return SGKS_ERR_HIP;
+    B->opt = o;
+    B->st = (hipStream_t)o.stream;
+    B->prof.st = B->st;
+    auto fail = [&](int rc) {
+        sgks_batch_destroy(B);
+        return rc;
+    };
+    std::vector<State> host(count);
+    std::vector<int> groups(count);
+    for (int i = 0; i < count; ++i) {
+        sgks_ctx* c = nullptr;
+        const int rc = sgks_create(&probs[i].A, &probs[i].L, probs[i].b, probs[i].mu,
+                                   probs[i].sketch_rows, probs[i].seed, &o, &c);
+        if (rc) return fail(rc);
+        c->borrowed = true;
+        B->ctx.push_back(c);
+        host[i] = c->S;
+        groups[i] = c->groups;
+    }
+    if (hipMalloc((void**)&B->Sdev, sizeof(State) * count) != hipSuccess) {
+        B->Sdev = nullptr;
+        return fail(SGKS_ERR_HIP);
+    }
+    if (hipMemcpyAsync(B->Sdev, host.data(), sizeof(State) * count, hipMemcpyHostToDevice,
+                       B->st) != hipSuccess ||
+        hipStreamSynchronize(B->st) != hipSuccess)
+        return fail(SGKS_ERR_HIP);
+    if (sgks::plan_build(B->plan, host.data(), B->Sdev, count, groups.data()))
+        return fail(SGKS_ERR_INVALID_ARG);
+    *out = B;
+    return SGKS_OK;
+}
+
+int sgks_batch_iterate(sgks_batch* B, int32_t k) {
+    if (!B || k < 0) return SGKS_ERR_INVALID_ARG;
+    for (sgks_ctx* c : B->ctx)
+        if (c->d_host + k > c->S.dmax) return SGKS_ERR_CAPACITY;
+    const int rc = run_iterations(B->plan, B->opt.refine_steps, &B->prof, &B->graphs,
+                                  B->opt.graph != 0, B->st, k);
+    if (rc) return rc;
+    for (sgks_ctx* c : B->ctx) c->d_host += k;
+    return SGKS_OK;
+}
+
+sgks_ctx* sgks_batch_get(sgks_batch* B, int32_t i) {
+    if (!B || i < 0 || i >= (int32_t)B->ctx.size()) return nullptr;
+    return B->ctx[i];
+}
+
+int32_t sgks_batch_count(const sgks_batch* B) { return B ? (int32_t)B->ctx.size() : 0; }
+
+int sgks_batch_profile_enable(sgks_batch* B, int32_t on) {
+    if (!B) return SGKS_ERR_INVALID_ARG;
+    B->prof.on = on != 0;
+    return SGKS_OK;
+}
+
+int sgks_batch_profile_read(sgks_batch* B, double* ms, int64_t* launches) {
+    if (!B) return SGKS_ERR_INVALID_ARG;
+    return B->prof.read(ms, launches);
+}
+
+void sgks_batch_destroy(sgks_batch* B) {
+    if (!B) return;
+    hipStreamSynchronize(B->st);
+    for (sgks_ctx* c : B->ctx) destroy_ctx(c);
+    if (B->Sdev) hipFree(B->Sdev);
+    delete B;
 }
 
 const char* sgks_strerror(int code) {

@@ -17,6 +17,7 @@ constexpr int kAppendMaxSlab = 64;    // sketch rows per append workgroup
 constexpr int kSketchBlock = 512;   // threads per block of the sketch kernel
 constexpr int kSketchWaves = kSketchBlock / 64;
 constexpr int kMaxSketchBlocks = 256; // per operator
+constexpr int kMaxBatch = 64;       // problems of one batched launch
 
 // Device status word values (mirrors the public codes).
 constexpr int kStatusOk = 0;
@@ -78,7 +79,7 @@ struct State {
     double* wa;        // s: working sketched A column of the append
     double* wl;        // s: working sketched L column
     double* wu;        // 2 dmax: working column of the stacked factor
-    double* pacc;      // 2 dmax: running sums of the Q projection coefficients
+    double* pacc;      // 4 dmax: running sums of the Q projection coefficients, final sums
     double* gacc;      // dmax: running sum of the U projection coefficients
     double* gpart;     // ngt x dmax partial W^T v sums
     int ngt;
@@ -90,27 +91,51 @@ struct State {
     int* degenerate;   // count of numerically absent QR columns
 };
 
+// Block table of one batched launch: problem q owns the workgroups
+// [pref[q], pref[q + 1]) of the grid, q < np.  Passed by value.
+struct BTab {
+    int np;
+    int pref[kMaxBatch + 1];
+};
+
+// Launch plan of the iteration over a set of problems whose States live in
+// device memory (SS[q]).  Options that select kernel instantiations (value
+// dtype, zeta, projection passes) are common to the set.
+struct Plan {
+    const State* SS;
+    int np;
+    int vdt, zeta, passes, sketch_mode;
+    int max_s;          // largest sketch size (LDS bins of the scatter)
+    int max_gt_rows;    // largest row slab of the W^T v kernel
+    BTab fwd;           // k_forward: A rows then L rows
+    BTab adj;           // adjoint products
+    BTab sc;            // scatter: S_A blocks then S_L blocks
+    BTab gemv;          // x = W y
+    BTab gemvt;         // W^T v partials
+    BTab ap;            // append workgroups
+    BTab one;           // one workgroup per problem
+};
+
 // ----- launchers (sgks_kernels.hip) -----------------------------------------
 void launch_to_f64(const void* src, int vdt, double* dst, int64_t n, double* part, int nb,
                    hipStream_t st);
 void launch_sum_parts(const double* part, int nb, double* out, hipStream_t st);
 void launch_forward(const State& S, const double* x, const double* b, double* u, double* t,
-                    bool with_L, double* upart, double* tpart, int nbF, hipStream_t st);
+                    bool with_L, double* upart, double* tpart, hipStream_t st);
 int forward_blocks(const State& S, bool with_L, int* nbA_out);
 void launch_adjoint(const State& S, const double* u, const double* t, bool with_L, double mu,
-                    double* dst_fixed, bool dst_is_basis_column, double* part, hipStream_t st);
+                    double* dst, double* part, hipStream_t st);
 int adjoint_blocks(const State& S);
-void launch_sketch(const State& S, int col, bool vec_mode, const double* vec, hipStream_t st);
-void launch_scatter(const State& S, const double* zA, const double* zL, hipStream_t st,
-                    bool honor_status);
-void launch_gemv(const State& S, const double* coef, bool coef_from_cs, double* out,
-                 const double* base, int ncols_fixed, hipStream_t st);
+void launch_sketch_column(const State& S, int col, hipStream_t st);
+void launch_scatter(const State& S, const double* zA, const double* zL, hipStream_t st);
+void launch_gemv(const State& S, const double* coef, double* out, const double* base,
+                 int ncols_fixed, hipStream_t st);
+int gemv_blocks(const State& S);
 void launch_gemvt(const State& S, const double* v, int ncols_fixed, hipStream_t st);
 void launch_reduce_gpart(const State& S, int ncols_fixed, double* out, hipStream_t st);
 void launch_set_scale(const State& S, int col, bool store_r0, hipStream_t st);
-int launch_append(const State& S, bool scale_from_norm, int groups, hipStream_t st);
 int choose_append_groups(int s, int dmax, int cap);
-void launch_refine(const State& S, hipStream_t st);
+bool append_groups_ok(int s, int dmax, int G);
 void launch_cb(const State& S, hipStream_t st);
 void launch_residual_small(const State& S, double* out2, hipStream_t st);
 void launch_backward_small(const State& S, double* v_out, double* gmu_out, hipStream_t st);
@@ -119,5 +144,16 @@ void launch_copy_scaled_W(const State& S, double* dst, hipStream_t st);
 int transpose_csr(const Csr& M, int vdt, int32_t* rowptrT, int32_t* colT, void* valT,
                   hipStream_t st);
 int max_append_groups();
+
+// plan from the host copies of the States (same order as SS)
+int plan_build(Plan& P, const State* host, const State* dev, int np, const int* groups);
+// one iteration step of every problem of the plan
+void plan_gemv(const Plan& P, hipStream_t st);                 // x = W y
+void plan_forward(const Plan& P, bool newcol, hipStream_t st); // u = A x - b, t = L x / A w, L w
+void plan_adjoint(const Plan& P, bool to_rtmp, hipStream_t st);// r = A^T u + mu L^T t
+void plan_scatter(const Plan& P, hipStream_t st);              // sketch bins of (u, t)
+int plan_append(const Plan& P, bool scale_from_norm, hipStream_t st);
+void plan_gemvt(const Plan& P, hipStream_t st);                // W^T rtmp partials
+void plan_refine(const Plan& P, hipStream_t st);
 
 }  // namespace sgks

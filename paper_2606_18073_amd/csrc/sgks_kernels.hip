@@ -222,23 +222,50 @@ __global__ __launch_bounds__(kBlock) void k_sum_parts(const double* part, int nb
 }
 
 // ---------------------------------------------------------------------------
+// batched launches: workgroup -> (problem, local workgroup)
+// ---------------------------------------------------------------------------
+
+struct Slot {
+    int p;      // problem
+    int blk;    // workgroup within the problem
+    int nblk;   // workgroups of the problem
+};
+
+// Static indices only, so the table stays in scalar registers.
+__device__ __forceinline__ Slot find_slot(const BTab& t) {
+    const int b = blockIdx.x;
+    Slot r{0, b, t.pref[1]};
+#pragma unroll
+    for (int q = 1; q < kMaxBatch; ++q) {
+        if (q < t.np && b >= t.pref[q]) {
+            r.p = q;
+            r.blk = b - t.pref[q];
+            r.nblk = t.pref[q + 1] - t.pref[q];
+        }
+    }
+    return r;
+}
+
+__device__ __forceinline__ int rows_blocks_of(const Csr& M) {
+    const int per = kBlock / M.lanes;
+    return (int)((M.rows + per - 1) / per);
+}
+
+// ---------------------------------------------------------------------------
 // forward products: u = A x - b (optional b), t = L x
+// workgroups [0, nbA) take rows of A, the rest rows of L
 // ---------------------------------------------------------------------------
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_forward(Csr A, Csr L, int nbA,
-                                                   const double* __restrict__ xfixed,
-                                                   const double* __restrict__ W, const int* dptr,
-                                                   int64_t n, const double* __restrict__ b,
-                                                   double* __restrict__ u, double* __restrict__ t,
-                                                   double* upart, double* tpart,
-                                                   const int* status) {
-    __shared__ double red[kWaves];
-    if (status && *status != 0) return;
-    const double* __restrict__ x = xfixed ? xfixed : W + (int64_t)(*dptr) * n;
-    const bool isA = (int)blockIdx.x < nbA;
-    const Csr M = isA ? A : L;
-    const int blk = isA ? (int)blockIdx.x : (int)blockIdx.x - nbA;
+__device__ __forceinline__ void forward_body(const Csr& A, const Csr& L, int nbA,
+                                             const double* __restrict__ x,
+                                             const double* __restrict__ b,
+                                             double* __restrict__ u, double* __restrict__ t,
+                                             double* upart, double* tpart, int blk_all,
+                                             double* red) {
+    const bool isA = blk_all < nbA;
+    const Csr& M = isA ? A : L;
+    const int blk = isA ? blk_all : blk_all - nbA;
     double* out = isA ? u : t;
     const double* sub = isA ? b : nullptr;
     double* part = isA ? upart : tpart;
@@ -261,25 +288,46 @@ __global__ __launch_bounds__(kBlock) void k_forward(Csr A, Csr L, int nbA,
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_forward(Csr A, Csr L, int nbA,
+                                                   const double* __restrict__ x,
+                                                   const double* __restrict__ b,
+                                                   double* __restrict__ u, double* __restrict__ t,
+                                                   double* upart, double* tpart) {
+    __shared__ double red[kWaves];
+    forward_body<T>(A, L, nbA, x, b, u, t, upart, tpart, (int)blockIdx.x, red);
+}
+
+// Iteration form: newcol = 0: u = A x - b, t = L x from the state's x;
+// newcol = 1: u = A w, t = L w for the basis column d (skipped on a set status).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void kb_forward(const State* __restrict__ SS, BTab tab,
+                                                    int newcol) {
+    __shared__ double red[kWaves];
+    const Slot sl = find_slot(tab);
+    const State& S = SS[sl.p];
+    if (newcol && *S.status != 0) return;
+    const double* x = newcol ? S.W + (int64_t)(*S.d) * S.n : S.x;
+    forward_body<T>(S.A, S.L, rows_blocks_of(S.A), x, newcol ? nullptr : S.b, S.u, S.t, nullptr,
+                    nullptr, sl.blk, red);
+}
+
 // ---------------------------------------------------------------------------
-// adjoint products: r = A^T u + mu L^T t, written to dst (or basis column d),
-// with per-block partial sums of r^2
+// adjoint products: r = A^T u + mu L^T t written to dst, with per-workgroup
+// partial sums of r^2 (grid-stride over the n rows)
 // ---------------------------------------------------------------------------
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_adjoint(Csr At, Csr Lt, int withL, double mu,
-                                                   const double* __restrict__ u,
-                                                   const double* __restrict__ t,
-                                                   double* dst_fixed, double* W, const int* dptr,
-                                                   int64_t n, double* part, const int* status) {
-    __shared__ double red[kWaves];
-    if (status && *status != 0) return;
-    double* dst = dst_fixed ? dst_fixed : W + (int64_t)(*dptr) * n;
+__device__ __forceinline__ void adjoint_body(const Csr& At, const Csr& Lt, int withL, double mu,
+                                             const double* __restrict__ u,
+                                             const double* __restrict__ t,
+                                             double* __restrict__ dst, int64_t n, double* part,
+                                             int blk, int nblk, double* red) {
     double sq = 0.0;
     SGKS_LANES_SWITCH(At.lanes, {
         const int g = threadIdx.x % V;
-        for (int64_t row = (int64_t)blockIdx.x * (kBlock / V) + threadIdx.x / V; row < n;
-             row += (int64_t)gridDim.x * (kBlock / V)) {
+        for (int64_t row = (int64_t)blk * (kBlock / V) + threadIdx.x / V; row < n;
+             row += (int64_t)nblk * (kBlock / V)) {
             double v = row_dot<V, T>(At, u, row, g);
             if (withL) v += mu * row_dot<V, T>(Lt, t, row, g);
             if (g == 0) {
@@ -289,36 +337,55 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(Csr At, Csr Lt, int withL, d
         }
     })
     const double tot = block_sum(sq, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+    if (threadIdx.x == 0) part[blk] = tot;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_adjoint(Csr At, Csr Lt, int withL, double mu,
+                                                   const double* __restrict__ u,
+                                                   const double* __restrict__ t,
+                                                   double* __restrict__ dst, int64_t n,
+                                                   double* part) {
+    __shared__ double red[kWaves];
+    adjoint_body<T>(At, Lt, withL, mu, u, t, dst, n, part, (int)blockIdx.x, (int)gridDim.x, red);
+}
+
+// Iteration form: to_rtmp = 0 writes the new basis column d (skipped on a set
+// status), to_rtmp = 1 writes the refinement gradient.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void kb_adjoint(const State* __restrict__ SS, BTab tab,
+                                                    int to_rtmp) {
+    __shared__ double red[kWaves];
+    const Slot sl = find_slot(tab);
+    const State& S = SS[sl.p];
+    if (!to_rtmp && *S.status != 0) return;
+    double* dst = to_rtmp ? S.rtmp : S.W + (int64_t)(*S.d) * S.n;
+    adjoint_body<T>(S.At, S.Lt, 1, S.mu, S.u, S.t, dst, S.n, S.norm_part, sl.blk, sl.nblk, red);
 }
 
 // ---------------------------------------------------------------------------
 // sparse-sign sketch of two vectors: bins_A += S_A zA (m entries, stream 0),
-// bins_L += S_L zL (p entries, stream 1).  Blocks [0, nbA) take zA.  Each
+// bins_L += S_L zL (p entries, stream 1).  Workgroups [0, nbA) take zA.  Each
 // wave walks 64-entry tiles: a coalesced load, the pattern of every entry
 // regenerated from its hash, and zeta LDS atomic adds into the wave's private
-// copy of the s bins.  Each block writes its raw bins (no 1/sqrt(zeta), no
+// copy of the s bins.  Each workgroup writes its raw bins (no 1/sqrt(zeta), no
 // column scale); partial bins are merged in fixed orders downstream.
 // ---------------------------------------------------------------------------
 
 template <int Z>
-__global__ __launch_bounds__(kSketchBlock) void k_scatter(const double* __restrict__ zA,
-                                                         int64_t m,
-                                                         const double* __restrict__ zL,
-                                                         int64_t p, int nbA, int nbL, int s,
-                                                         uint64_t seed, int identity,
-                                                         double* partA, double* partL,
-                                                         const int* status) {
-    extern __shared__ double sm[];
-    if (status && *status != 0) return;
+__device__ __forceinline__ void scatter_body(const double* __restrict__ zA, int64_t m,
+                                             const double* __restrict__ zL, int64_t p, int nbA,
+                                             int nbL, int s, uint64_t seed, int identity,
+                                             double* partA, double* partL, int blk_all,
+                                             double* sm) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int i = threadIdx.x; i < kSketchWaves * s; i += kSketchBlock) sm[i] = 0.0;
     __syncthreads();
     double* bins = sm + wave * s;
-    const bool isA = (int)blockIdx.x < nbA;
+    const bool isA = blk_all < nbA;
     const double* __restrict__ z = isA ? zA : zL;
     const int64_t rows = isA ? m : p;
-    const int blk = isA ? (int)blockIdx.x : (int)blockIdx.x - nbA;
+    const int blk = isA ? blk_all : blk_all - nbA;
     const int nblk = isA ? nbA : nbL;
     const int stream = isA ? 0 : 1;
     const int64_t ntiles = (rows + 63) / 64;
@@ -347,23 +414,44 @@ __global__ __launch_bounds__(kSketchBlock) void k_scatter(const double* __restri
     }
 }
 
+template <int Z>
+__global__ __launch_bounds__(kSketchBlock) void k_scatter(const double* __restrict__ zA,
+                                                         int64_t m,
+                                                         const double* __restrict__ zL,
+                                                         int64_t p, int nbA, int nbL, int s,
+                                                         uint64_t seed, int identity,
+                                                         double* partA, double* partL) {
+    extern __shared__ double sm[];
+    scatter_body<Z>(zA, m, zL, p, nbA, nbL, s, seed, identity, partA, partL, (int)blockIdx.x, sm);
+}
+
+// Iteration form: the sketch of the new column's images (u, t); skipped on a
+// set status.
+template <int Z>
+__global__ __launch_bounds__(kSketchBlock) void kb_scatter(const State* __restrict__ SS,
+                                                          BTab tab) {
+    extern __shared__ double sm[];
+    const Slot sl = find_slot(tab);
+    const State& S = SS[sl.p];
+    if (*S.status != 0) return;
+    scatter_body<Z>(S.u, S.m, S.t, S.p, S.nbA, S.nbL, S.s, S.seed, S.sketch_mode, S.binA, S.binL,
+                    sl.blk, sm);
+}
+
 // ---------------------------------------------------------------------------
 // dense basis products
 // ---------------------------------------------------------------------------
 
-// out = [base -] sum_j W[:, j] * cs[j] * coef[j], j < d
-__global__ __launch_bounds__(kBlock) void k_gemv(const double* __restrict__ W,
-                                                const double* __restrict__ cs,
-                                                const double* __restrict__ coef, const int* dptr,
-                                                int ncols_fixed, int64_t n,
-                                                const double* __restrict__ base,
-                                                double* __restrict__ out) {
-    __shared__ double yt[kMaxD];
-    const int d = ncols_fixed >= 0 ? ncols_fixed : *dptr;
+// out = [base -] sum_j W[:, j] * cs[j] * coef[j], j < d (grid-stride rows)
+__device__ __forceinline__ void gemv_body(const double* __restrict__ W,
+                                          const double* __restrict__ cs,
+                                          const double* __restrict__ coef, int d, int64_t n,
+                                          const double* __restrict__ base,
+                                          double* __restrict__ out, int blk, int nblk,
+                                          double* yt) {
     for (int j = threadIdx.x; j < d; j += kBlock) yt[j] = cs[j] * coef[j];
     __syncthreads();
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock) {
+    for (int64_t i = (int64_t)blk * kBlock + threadIdx.x; i < n; i += (int64_t)nblk * kBlock) {
         const double* w = W + i;
         double acc = 0.0;
         int j = 0;
@@ -379,15 +467,32 @@ __global__ __launch_bounds__(kBlock) void k_gemv(const double* __restrict__ W,
     }
 }
 
-// part[blk * ld + j] = cs[j] * sum_{i in block rows} W[i, j] v[i], j < d
-__global__ __launch_bounds__(kBlock) void k_gemvt(const double* __restrict__ W,
-                                                 const double* __restrict__ cs,
-                                                 const double* __restrict__ v, const int* dptr,
-                                                 int ncols_fixed, int64_t n, int rows_per_block,
-                                                 double* __restrict__ part, int ld) {
-    extern __shared__ double vs[];
+__global__ __launch_bounds__(kBlock) void k_gemv(const double* __restrict__ W,
+                                                const double* __restrict__ cs,
+                                                const double* __restrict__ coef, const int* dptr,
+                                                int ncols_fixed, int64_t n,
+                                                const double* __restrict__ base,
+                                                double* __restrict__ out) {
+    __shared__ double yt[kMaxD];
     const int d = ncols_fixed >= 0 ? ncols_fixed : *dptr;
-    const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+    gemv_body(W, cs, coef, d, n, base, out, (int)blockIdx.x, (int)gridDim.x, yt);
+}
+
+// Iteration form: x = W y on the current d columns.
+__global__ __launch_bounds__(kBlock) void kb_gemv(const State* __restrict__ SS, BTab tab) {
+    __shared__ double yt[kMaxD];
+    const Slot sl = find_slot(tab);
+    const State& S = SS[sl.p];
+    gemv_body(S.W, S.cs, S.y, *S.d, S.n, nullptr, S.x, sl.blk, sl.nblk, yt);
+}
+
+// part[blk * ld + j] = cs[j] * sum_{i in the workgroup's rows} W[i, j] v[i], j < d
+__device__ __forceinline__ void gemvt_body(const double* __restrict__ W,
+                                           const double* __restrict__ cs,
+                                           const double* __restrict__ v, int d, int64_t n,
+                                           int rows_per_block, double* __restrict__ part, int ld,
+                                           int blk, double* vs) {
+    const int64_t r0 = (int64_t)blk * rows_per_block;
     const int nr = (int)min((int64_t)rows_per_block, n - r0);
     for (int i = threadIdx.x; i < nr; i += kBlock) vs[i] = v[r0 + i];
     __syncthreads();
@@ -397,8 +502,27 @@ __global__ __launch_bounds__(kBlock) void k_gemvt(const double* __restrict__ W,
         double acc = 0.0;
         for (int i = lane; i < nr; i += 64) acc += wc[i] * vs[i];
         acc = wave_sum(acc);
-        if (lane == 0) part[(int64_t)blockIdx.x * ld + j] = acc * cs[j];
+        if (lane == 0) part[(int64_t)blk * ld + j] = acc * cs[j];
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_gemvt(const double* __restrict__ W,
+                                                 const double* __restrict__ cs,
+                                                 const double* __restrict__ v, const int* dptr,
+                                                 int ncols_fixed, int64_t n, int rows_per_block,
+                                                 double* __restrict__ part, int ld) {
+    extern __shared__ double vs[];
+    const int d = ncols_fixed >= 0 ? ncols_fixed : *dptr;
+    gemvt_body(W, cs, v, d, n, rows_per_block, part, ld, (int)blockIdx.x, vs);
+}
+
+// Iteration form: partials of W^T rtmp (refinement gradient).
+__global__ __launch_bounds__(kBlock) void kb_gemvt(const State* __restrict__ SS, BTab tab) {
+    extern __shared__ double vs[];
+    const Slot sl = find_slot(tab);
+    const State& S = SS[sl.p];
+    if (*S.status != 0) return;
+    gemvt_body(S.W, S.cs, S.rtmp, *S.d, S.n, S.gt_rows, S.gpart, S.dmax, sl.blk, vs);
 }
 
 // out[j] = sum_b part[b * ld + j], j < d
@@ -458,22 +582,26 @@ __global__ __launch_bounds__(kBlock) void k_cb(const double* __restrict__ bins, 
 //   region P + u, 0<u<P   : U coefficients of U pass u
 //   region 2P             : gamma^2 and the new h numerator
 // (P = S.passes).  Workgroup 0 keeps the running sums p = sum of the Q
-// coefficients and gacc = sum of the U coefficients in S.pacc, S.gacc.
-// Kernel boundaries order the phases.  Memory traffic is small (the slabs
+// coefficients (S.pacc[0, 2 dmax), the final p in S.pacc[2 dmax, 4 dmax)) and
+// gacc = sum of the U coefficients (S.gacc).  No workgroup writes memory that
+// another workgroup of the same launch reads; kernel boundaries order the
+// phases, and the basis size d advances in the single-workgroup k_yfix.  Memory traffic is small (the slabs
 // stay in L2); what these kernels pay is latency, so every loop issues its
 // loads in batches.
 
 constexpr int kSlots = 8;   // scalar slots after the 2 dmax coefficient slots
 
 struct ApDims {
+    int g, G;             // this workgroup, workgroups of the problem
     int d, s, dmax, ld2, nslot;
     int lo, ns;           // sketch-row slab
     int ulo, nu, nua;     // U-row slab (both halves), rows < d active
 };
 
-__device__ ApDims ap_dims(const State& S, int G, int d) {
+__device__ ApDims ap_dims(const State& S, int g, int G, int d) {
     ApDims D;
-    const int g = blockIdx.x;
+    D.g = g;
+    D.G = G;
     D.d = d;
     D.s = S.s;
     D.dmax = S.dmax;
@@ -511,10 +639,10 @@ __device__ __forceinline__ double sum_g(const double* __restrict__ slot, int G) 
 // tile: kAppendThreads / 64 * 16 * 64 doubles of LDS.
 __device__ void slab_dots(const double* __restrict__ Ma, const double* __restrict__ Ml,
                           int64_t ld, int nrows, int d, const double* va, const double* vl,
-                          double* partial, int G, double* tile) {
+                          double* partial, int g, int G, double* tile) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     if (nrows <= 0 || d <= 0) {
-        for (int j = threadIdx.x; j < d; j += blockDim.x) partial[(int64_t)j * G + blockIdx.x] = 0.0;
+        for (int j = threadIdx.x; j < d; j += blockDim.x) partial[(int64_t)j * G + g] = 0.0;
         return;
     }
     const int rl = min(lane, nrows - 1);   // clamped row: loads stay unconditional
@@ -546,7 +674,7 @@ __device__ void slab_dots(const double* __restrict__ Ma, const double* __restric
         for (int k = 0; k < 16; ++k) acc += tw[c * 64 + rg * 16 + k];
         acc += __shfl_xor(acc, 16);
         acc += __shfl_xor(acc, 32);
-        if (lane < 16 && j0 + c < d) partial[(int64_t)(j0 + c) * G + blockIdx.x] = acc;
+        if (lane < 16 && j0 + c < d) partial[(int64_t)(j0 + c) * G + g] = acc;
         __syncthreads();
     }
 }
@@ -597,12 +725,16 @@ struct ApShared {
 
 // Q pass 0: column scale (breakdown test), reduce the sketch bins of this
 // slab, first projection coefficients.
-__global__ __launch_bounds__(kAppendThreads) void k_ap_q0(State S, int G, int scale_from_norm) {
+__global__ __launch_bounds__(kAppendThreads) void k_ap_q0(const State* __restrict__ SS, BTab tab,
+                                                     int scale_from_norm) {
     __shared__ ApShared sh;
+    const Slot sl = find_slot(tab);
+    const State& S = SS[sl.p];
+    const int G = sl.nblk;
     if (*S.status != 0) return;
     const int d = *S.d;
-    const ApDims D = ap_dims(S, G, d);
-    const int g = blockIdx.x, tid = threadIdx.x, T = kAppendThreads;
+    const ApDims D = ap_dims(S, sl.blk, G, d);
+    const int g = sl.blk, tid = threadIdx.x, T = kAppendThreads;
     double scale;
     if (scale_from_norm) {
         const double nr2 = block_sum(thread_strided_sum(S.norm_part, S.n_norm_part, T), sh.red);
@@ -654,8 +786,8 @@ __global__ __launch_bounds__(kAppendThreads) void k_ap_q0(State S, int G, int sc
     na2 = block_sum(na2, sh.red);
     nl2 = block_sum(nl2, sh.red);
     double* reg = ap_region(S, D, G, 0);
-    slab_dots(S.QA + D.lo, nullptr, D.s, D.ns, d, sh.av, nullptr, reg, G, sh.tile);
-    slab_dots(S.QL + D.lo, nullptr, D.s, D.ns, d, sh.lv, nullptr, reg + (int64_t)S.dmax * G, G,
+    slab_dots(S.QA + D.lo, nullptr, D.s, D.ns, d, sh.av, nullptr, reg, D.g, G, sh.tile);
+    slab_dots(S.QL + D.lo, nullptr, D.s, D.ns, d, sh.lv, nullptr, reg + (int64_t)S.dmax * G, D.g, G,
               sh.tile);
     if (tid == 0) {
         reg[(int64_t)(2 * S.dmax) * G + g] = na2;
@@ -674,16 +806,20 @@ __device__ void ap_take_q(const State& S, const ApDims& D, int G, int r, ApShare
             sh.cA[j] = c;
         else
             sh.cL[j - D.d] = c;
-        if (blockIdx.x == 0) S.pacc[slot] = (r == 0 ? 0.0 : S.pacc[slot]) + c;
+        if (D.g == 0) S.pacc[slot] = (r == 0 ? 0.0 : S.pacc[slot]) + c;
     }
 }
 
 // Q pass `pass` >= 1: finish the previous projection, next coefficients.
-__global__ __launch_bounds__(kAppendThreads) void k_ap_qp(State S, int G, int pass) {
+__global__ __launch_bounds__(kAppendThreads) void k_ap_qp(const State* __restrict__ SS, BTab tab,
+                                                     int pass) {
     __shared__ ApShared sh;
+    const Slot sl = find_slot(tab);
+    const State& S = SS[sl.p];
+    const int G = sl.nblk;
     if (*S.status != 0) return;
     const int d = *S.d;
-    const ApDims D = ap_dims(S, G, d);
+    const ApDims D = ap_dims(S, sl.blk, G, d);
     const int tid = threadIdx.x;
     for (int i = tid; i < D.ns; i += kAppendThreads) {
         sh.av[i] = S.wa[D.lo + i];
@@ -697,19 +833,23 @@ __global__ __launch_bounds__(kAppendThreads) void k_ap_qp(State S, int G, int pa
         S.wl[D.lo + i] = sh.lv[i];
     }
     double* reg = ap_region(S, D, G, pass);
-    slab_dots(S.QA + D.lo, nullptr, D.s, D.ns, d, sh.av, nullptr, reg, G, sh.tile);
-    slab_dots(S.QL + D.lo, nullptr, D.s, D.ns, d, sh.lv, nullptr, reg + (int64_t)S.dmax * G, G,
+    slab_dots(S.QA + D.lo, nullptr, D.s, D.ns, d, sh.av, nullptr, reg, D.g, G, sh.tile);
+    slab_dots(S.QL + D.lo, nullptr, D.s, D.ns, d, sh.lv, nullptr, reg + (int64_t)S.dmax * G, D.g, G,
               sh.tile);
 }
 
 // Q finish: last projection, norms and d_A numerator, U pass 0 on
 // c = [p_A; sqrt(mu) p_L] (rows < d; the new rows are orthogonal to U).
-__global__ __launch_bounds__(kAppendThreads) void k_ap_qf(State S, int G) {
+__global__ __launch_bounds__(kAppendThreads) void k_ap_qf(const State* __restrict__ SS,
+                                                     BTab tab) {
     __shared__ ApShared sh;
+    const Slot sl = find_slot(tab);
+    const State& S = SS[sl.p];
+    const int G = sl.nblk;
     if (*S.status != 0) return;
     const int d = *S.d;
-    const ApDims D = ap_dims(S, G, d);
-    const int g = blockIdx.x, tid = threadIdx.x, P = S.passes;
+    const ApDims D = ap_dims(S, sl.blk, G, d);
+    const int g = sl.blk, tid = threadIdx.x, P = S.passes;
     for (int i = tid; i < D.ns; i += kAppendThreads) {
         sh.av[i] = S.wa[D.lo + i];
         sh.lv[i] = S.wl[D.lo + i];
@@ -728,7 +868,7 @@ __global__ __launch_bounds__(kAppendThreads) void k_ap_qf(State S, int G) {
                 sh.cL[j - d] = c;
                 sh.pL[j - d] = p;
             }
-            if (g == 0) S.pacc[slot] = p;
+            if (g == 0) S.pacc[2 * S.dmax + slot] = p;   // the running sums stay intact
         }
     }
     slab_apply(S.QA + D.lo, D.s, D.ns, d, sh.cA, sh.av, sh.scr);
@@ -752,7 +892,7 @@ __global__ __launch_bounds__(kAppendThreads) void k_ap_qf(State S, int G) {
     rl = block_sum(rl, sh.red);
     dl = block_sum(dl, sh.red);
     double* reg = ap_region(S, D, G, P);
-    slab_dots(S.U + D.ulo, S.U + S.dmax + D.ulo, D.ld2, D.nua, d, sh.cuA, sh.cuL, reg, G, sh.tile);
+    slab_dots(S.U + D.ulo, S.U + S.dmax + D.ulo, D.ld2, D.nua, d, sh.cuA, sh.cuL, reg, D.g, G, sh.tile);
     if (tid == 0) {
         reg[(int64_t)(2 * S.dmax) * G + g] = ra;
         reg[(int64_t)(2 * S.dmax + 1) * G + g] = rl;
@@ -761,12 +901,16 @@ __global__ __launch_bounds__(kAppendThreads) void k_ap_qf(State S, int G) {
 }
 
 // U pass `upass` >= 1 (or, with last != 0, the finish: gamma^2 and h numerator)
-__global__ __launch_bounds__(kAppendThreads) void k_ap_u(State S, int G, int upass, int last) {
+__global__ __launch_bounds__(kAppendThreads) void k_ap_u(const State* __restrict__ SS, BTab tab,
+                                                    int upass, int last) {
     __shared__ ApShared sh;
+    const Slot sl = find_slot(tab);
+    const State& S = SS[sl.p];
+    const int G = sl.nblk;
     if (*S.status != 0) return;
     const int d = *S.d;
-    const ApDims D = ap_dims(S, G, d);
-    const int g = blockIdx.x, tid = threadIdx.x, P = S.passes;
+    const ApDims D = ap_dims(S, sl.blk, G, d);
+    const int g = sl.blk, tid = threadIdx.x, P = S.passes;
     for (int i = tid; i < D.nua; i += kAppendThreads) {
         sh.cuA[i] = S.wu[D.ulo + i];
         sh.cuL[i] = S.wu[S.dmax + D.ulo + i];
@@ -787,7 +931,7 @@ __global__ __launch_bounds__(kAppendThreads) void k_ap_u(State S, int G, int upa
     }
     if (!last) {
         slab_dots(S.U + D.ulo, S.U + S.dmax + D.ulo, D.ld2, D.nua, d, sh.cuA, sh.cuL,
-                  ap_region(S, D, G, P + upass), G, sh.tile);
+                  ap_region(S, D, G, P + upass), D.g, G, sh.tile);
         return;
     }
     double gam2 = 0.0, hnum = 0.0;
@@ -807,12 +951,16 @@ __global__ __launch_bounds__(kAppendThreads) void k_ap_u(State S, int G, int upa
 // Commit: new columns of Q_A, Q_L, R_A, R_L, U, G (row-major), entries of
 // d_A and h, the new column of G^{-1} (row-major) and y0 = G^{-1} h.
 // Breakdown when the new stacked column is dependent.
-__global__ __launch_bounds__(kAppendThreads) void k_ap_commit(State S, int G) {
+__global__ __launch_bounds__(kAppendThreads) void k_ap_commit(const State* __restrict__ SS,
+                                                         BTab tab) {
     __shared__ ApShared sh;
+    const Slot sl = find_slot(tab);
+    const State& S = SS[sl.p];
+    const int G = sl.nblk;
     if (*S.status != 0) return;
     const int d = *S.d;
-    const ApDims D = ap_dims(S, G, d);
-    const int g = blockIdx.x, tid = threadIdx.x, P = S.passes, T = kAppendThreads;
+    const ApDims D = ap_dims(S, sl.blk, G, d);
+    const int g = sl.blk, tid = threadIdx.x, P = S.passes, T = kAppendThreads;
     const int dmax = S.dmax;
     if (tid < 7) {
         const double* r0 = ap_region(S, D, G, 0);
@@ -824,8 +972,8 @@ __global__ __launch_bounds__(kAppendThreads) void k_ap_commit(State S, int G) {
         sh.sc[tid] = sum_g(src[tid], G);
     }
     for (int j = tid; j < d; j += T) {
-        sh.pA[j] = S.pacc[j];
-        sh.pL[j] = S.pacc[dmax + j];
+        sh.pA[j] = S.pacc[2 * dmax + j];
+        sh.pL[j] = S.pacc[3 * dmax + j];
         sh.cA[j] = S.gacc[j];            // sum of the U coefficients (the new column of G)
     }
     __syncthreads();
@@ -903,18 +1051,19 @@ __global__ __launch_bounds__(kAppendThreads) void k_ap_commit(State S, int G) {
             S.y[r] = yr + nc * hnew;
         }
     }
-    if (g == 0 && tid == 0) *S.d = d + 1;
 }
 
 // One residual correction of y = G^{-1} h with the triangular factor itself:
 // y <- y + G^{-1} (h - G y).  It brings the explicit-inverse solve to the
-// accuracy of back substitution.  One workgroup; G and G^{-1} row-major.
-__global__ __launch_bounds__(1024) void k_yfix(State S) {
+// accuracy of back substitution.  One workgroup per problem; G and G^{-1}
+// row-major.  Ends the append: the basis size becomes d + 1.
+__global__ __launch_bounds__(1024) void k_yfix(const State* __restrict__ SS, BTab tab) {
     __shared__ double yv[kMaxD];
     __shared__ double rv[kMaxD];
     __shared__ double tv[kMaxD];
-    if (*S.status != 0) return;
-    const int d = *S.d, dmax = S.dmax;
+    const State& S = SS[find_slot(tab).p];
+    if (*S.status != 0) return;   // no append (breakdown) or an earlier stop
+    const int d = *S.d + 1, dmax = S.dmax;
     for (int i = threadIdx.x; i < d; i += 1024) yv[i] = S.y[i];
     __syncthreads();
     tri_mv(S.G, dmax, 1, d, 0, yv, tv);
@@ -927,6 +1076,7 @@ __global__ __launch_bounds__(1024) void k_yfix(State S) {
         S.y[i] = yv[i] + tv[i];
         S.yprev[i] = yv[i] + tv[i];
     }
+    if (threadIdx.x == 0) *S.d = d;   // every thread read *S.d before the barriers above
 }
 
 // ---------------------------------------------------------------------------
@@ -934,10 +1084,11 @@ __global__ __launch_bounds__(1024) void k_yfix(State S) {
 // delta = G^{-1} G^{-T} g, y <- y - alpha delta + beta (y - y_prev)
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kBlock) void k_refine(State S) {
+__global__ __launch_bounds__(kBlock) void k_refine(const State* __restrict__ SS, BTab tab) {
     __shared__ double gv[kMaxD];
     __shared__ double tv[kMaxD];
     __shared__ double dv[kMaxD];
+    const State& S = SS[find_slot(tab).p];
     if (*S.status != 0) return;
     const int d = *S.d;
     const int dmax = S.dmax;
@@ -1137,18 +1288,15 @@ int forward_blocks(const State& S, bool with_L, int* nbA_out) {
 }
 
 void launch_forward(const State& S, const double* x, const double* b, double* u, double* t,
-                    bool with_L, double* upart, double* tpart, int nbF, hipStream_t st) {
+                    bool with_L, double* upart, double* tpart, hipStream_t st) {
     int nbA = 0;
     const int nb = forward_blocks(S, with_L, &nbA);
-    (void)nbF;
-    // x == nullptr: the basis column d (device counter), and skip on a set status
-    const int* status = x ? nullptr : S.status;
     if (S.vdt == 0)
-        hipLaunchKernelGGL(k_forward<float>, dim3(nb), dim3(kBlock), 0, st, S.A, S.L, nbA, x, S.W,
-                           S.d, S.n, b, u, t, upart, tpart, status);
+        hipLaunchKernelGGL(k_forward<float>, dim3(nb), dim3(kBlock), 0, st, S.A, S.L, nbA, x, b,
+                           u, t, upart, tpart);
     else
-        hipLaunchKernelGGL(k_forward<double>, dim3(nb), dim3(kBlock), 0, st, S.A, S.L, nbA, x,
-                           S.W, S.d, S.n, b, u, t, upart, tpart, status);
+        hipLaunchKernelGGL(k_forward<double>, dim3(nb), dim3(kBlock), 0, st, S.A, S.L, nbA, x, b,
+                           u, t, upart, tpart);
 }
 
 int adjoint_blocks(const State& S) {
@@ -1158,26 +1306,23 @@ int adjoint_blocks(const State& S) {
 }
 
 void launch_adjoint(const State& S, const double* u, const double* t, bool with_L, double mu,
-                    double* dst_fixed, bool dst_is_basis_column, double* part, hipStream_t st) {
+                    double* dst, double* part, hipStream_t st) {
     const int nb = adjoint_blocks(S);
-    const int* status = dst_is_basis_column ? S.status : nullptr;
     if (S.vdt == 0)
         hipLaunchKernelGGL(k_adjoint<float>, dim3(nb), dim3(kBlock), 0, st, S.At, S.Lt,
-                           with_L ? 1 : 0, mu, u, t, dst_fixed, S.W, S.d, S.n, part, status);
+                           with_L ? 1 : 0, mu, u, t, dst, S.n, part);
     else
         hipLaunchKernelGGL(k_adjoint<double>, dim3(nb), dim3(kBlock), 0, st, S.At, S.Lt,
-                           with_L ? 1 : 0, mu, u, t, dst_fixed, S.W, S.d, S.n, part, status);
+                           with_L ? 1 : 0, mu, u, t, dst, S.n, part);
 }
 
-void launch_scatter(const State& S, const double* zA, const double* zL, hipStream_t st,
-                    bool honor_status) {
+void launch_scatter(const State& S, const double* zA, const double* zL, hipStream_t st) {
     const size_t shm = (size_t)kSketchWaves * S.s * sizeof(double);
     const int nbL = zL ? S.nbL : 0;
     const int nb = S.nbA + nbL;
-    const int* status = honor_status ? S.status : nullptr;
 #define SGKS_SC(Zv)                                                                             \
     hipLaunchKernelGGL((k_scatter<Zv>), dim3(nb), dim3(kSketchBlock), shm, st, zA, S.m, zL, S.p, \
-                       S.nbA, nbL, S.s, S.seed, S.sketch_mode, S.binA, S.binL, status)
+                       S.nbA, nbL, S.s, S.seed, S.sketch_mode, S.binA, S.binL)
     switch (S.zeta) {
         case 2: SGKS_SC(2); break;
         case 4: SGKS_SC(4); break;
@@ -1187,23 +1332,18 @@ void launch_scatter(const State& S, const double* zA, const double* zL, hipStrea
 #undef SGKS_SC
 }
 
-void launch_sketch(const State& S, int col, bool vec_mode, const double* vec, hipStream_t st) {
-    if (vec_mode) {
-        launch_scatter(S, vec, nullptr, st, false);
-        return;
-    }
-    // z = A w, L w into the free u, t buffers, then the scatter
-    const double* x = col >= 0 ? S.W + (int64_t)col * S.n : nullptr;
-    launch_forward(S, x, nullptr, S.u, S.t, true, nullptr, nullptr, 0, st);
-    launch_scatter(S, S.u, S.t, st, col < 0);
+// z = A w, L w of basis column col into the u, t buffers, then their sketch bins
+void launch_sketch_column(const State& S, int col, hipStream_t st) {
+    launch_forward(S, S.W + (int64_t)col * S.n, nullptr, S.u, S.t, true, nullptr, nullptr, st);
+    launch_scatter(S, S.u, S.t, st);
 }
 
-void launch_gemv(const State& S, const double* coef, bool coef_from_cs, double* out,
-                 const double* base, int ncols_fixed, hipStream_t st) {
-    (void)coef_from_cs;
-    const int nb = grid_for(S.n, kBlock, 4096);
-    hipLaunchKernelGGL(k_gemv, dim3(nb), dim3(kBlock), 0, st, S.W, S.cs, coef, S.d, ncols_fixed,
-                       S.n, base, out);
+int gemv_blocks(const State& S) { return grid_for(S.n, kBlock, 4096); }
+
+void launch_gemv(const State& S, const double* coef, double* out, const double* base,
+                 int ncols_fixed, hipStream_t st) {
+    hipLaunchKernelGGL(k_gemv, dim3(gemv_blocks(S)), dim3(kBlock), 0, st, S.W, S.cs, coef, S.d,
+                       ncols_fixed, S.n, base, out);
 }
 
 void launch_gemvt(const State& S, const double* v, int ncols_fixed, hipStream_t st) {
@@ -1230,6 +1370,11 @@ int max_append_groups() {
     return cus > 0 ? cus : 1;
 }
 
+bool append_groups_ok(int s, int dmax, int G) {
+    return G >= 1 && G <= kMaxAppendGroups && (s + G - 1) / G <= kAppendMaxSlab &&
+           (dmax + G - 1) / G <= kAppendMaxSlab;
+}
+
 int choose_append_groups(int s, int dmax, int cap) {
     int G = (s + 31) / 32;
     if (G < 4) G = 4;
@@ -1237,26 +1382,6 @@ int choose_append_groups(int s, int dmax, int cap) {
     if (G > kMaxAppendGroups) G = kMaxAppendGroups;
     if (G > cap) G = cap;
     return G;
-}
-
-int launch_append(const State& S, bool scale_from_norm, int G, hipStream_t st) {
-    if (G < 1 || G > kMaxAppendGroups || (S.s + G - 1) / G > kAppendMaxSlab ||
-        (S.dmax + G - 1) / G > kAppendMaxSlab)
-        return -1;
-    const dim3 grid(G), block(kAppendThreads);
-    hipLaunchKernelGGL(k_ap_q0, grid, block, 0, st, S, G, scale_from_norm ? 1 : 0);
-    for (int pass = 1; pass < S.passes; ++pass)
-        hipLaunchKernelGGL(k_ap_qp, grid, block, 0, st, S, G, pass);
-    hipLaunchKernelGGL(k_ap_qf, grid, block, 0, st, S, G);
-    for (int u = 1; u < S.passes; ++u) hipLaunchKernelGGL(k_ap_u, grid, block, 0, st, S, G, u, 0);
-    hipLaunchKernelGGL(k_ap_u, grid, block, 0, st, S, G, S.passes, 1);
-    hipLaunchKernelGGL(k_ap_commit, grid, block, 0, st, S, G);
-    hipLaunchKernelGGL(k_yfix, dim3(1), dim3(1024), 0, st, S);
-    return hipGetLastError() == hipSuccess ? 0 : -1;
-}
-
-void launch_refine(const State& S, hipStream_t st) {
-    hipLaunchKernelGGL(k_refine, dim3(1), dim3(kBlock), 0, st, S);
 }
 
 void launch_cb(const State& S, hipStream_t st) {
@@ -1291,14 +1416,124 @@ void launch_sketch_transpose(const State& S, const double* v, double* out, hipSt
 }
 
 void launch_copy_scaled_W(const State& S, double* dst, hipStream_t st) {
-    const int d = 0;
-    (void)d;
     int dh = 0;
     hipMemcpyAsync(&dh, S.d, sizeof(int), hipMemcpyDeviceToHost, st);
     hipStreamSynchronize(st);
     if (dh <= 0) return;
     const int nb = grid_for(S.n * (int64_t)dh, kBlock, 8192);
     hipLaunchKernelGGL(k_scaled_W, dim3(nb), dim3(kBlock), 0, st, S.W, S.cs, S.n, dh, dst);
+}
+
+// ---------------------------------------------------------------------------
+// plans: one launch per step for every problem of a set
+// ---------------------------------------------------------------------------
+
+static void tab_set(BTab& t, int np, const int* counts) {
+    t.np = np;
+    t.pref[0] = 0;
+    for (int q = 0; q < np; ++q) t.pref[q + 1] = t.pref[q] + counts[q];
+    for (int q = np + 1; q <= kMaxBatch; ++q) t.pref[q] = t.pref[np];
+}
+
+static int tab_total(const BTab& t) { return t.pref[t.np]; }
+
+int plan_build(Plan& P, const State* host, const State* dev, int np, const int* groups) {
+    if (np < 1 || np > kMaxBatch) return -1;
+    P.SS = dev;
+    P.np = np;
+    P.vdt = host[0].vdt;
+    P.zeta = host[0].zeta;
+    P.passes = host[0].passes;
+    P.sketch_mode = host[0].sketch_mode;
+    P.max_s = 0;
+    P.max_gt_rows = 0;
+    int fwd[kMaxBatch], adj[kMaxBatch], sc[kMaxBatch], gv[kMaxBatch], gt[kMaxBatch],
+        ap[kMaxBatch], one[kMaxBatch];
+    for (int q = 0; q < np; ++q) {
+        const State& S = host[q];
+        if (S.vdt != P.vdt || S.zeta != P.zeta || S.passes != P.passes ||
+            S.sketch_mode != P.sketch_mode)
+            return -1;
+        if (!append_groups_ok(S.s, S.dmax, groups[q])) return -1;
+        fwd[q] = forward_blocks(S, true, nullptr);
+        adj[q] = adjoint_blocks(S);
+        sc[q] = S.nbA + S.nbL;
+        gv[q] = gemv_blocks(S);
+        gt[q] = S.ngt;
+        ap[q] = groups[q];
+        one[q] = 1;
+        P.max_s = S.s > P.max_s ? S.s : P.max_s;
+        P.max_gt_rows = S.gt_rows > P.max_gt_rows ? S.gt_rows : P.max_gt_rows;
+    }
+    tab_set(P.fwd, np, fwd);
+    tab_set(P.adj, np, adj);
+    tab_set(P.sc, np, sc);
+    tab_set(P.gemv, np, gv);
+    tab_set(P.gemvt, np, gt);
+    tab_set(P.ap, np, ap);
+    tab_set(P.one, np, one);
+    return 0;
+}
+
+void plan_gemv(const Plan& P, hipStream_t st) {
+    hipLaunchKernelGGL(kb_gemv, dim3(tab_total(P.gemv)), dim3(kBlock), 0, st, P.SS, P.gemv);
+}
+
+void plan_forward(const Plan& P, bool newcol, hipStream_t st) {
+    const dim3 grid(tab_total(P.fwd));
+    if (P.vdt == 0)
+        hipLaunchKernelGGL(kb_forward<float>, grid, dim3(kBlock), 0, st, P.SS, P.fwd,
+                           newcol ? 1 : 0);
+    else
+        hipLaunchKernelGGL(kb_forward<double>, grid, dim3(kBlock), 0, st, P.SS, P.fwd,
+                           newcol ? 1 : 0);
+}
+
+void plan_adjoint(const Plan& P, bool to_rtmp, hipStream_t st) {
+    const dim3 grid(tab_total(P.adj));
+    if (P.vdt == 0)
+        hipLaunchKernelGGL(kb_adjoint<float>, grid, dim3(kBlock), 0, st, P.SS, P.adj,
+                           to_rtmp ? 1 : 0);
+    else
+        hipLaunchKernelGGL(kb_adjoint<double>, grid, dim3(kBlock), 0, st, P.SS, P.adj,
+                           to_rtmp ? 1 : 0);
+}
+
+void plan_scatter(const Plan& P, hipStream_t st) {
+    const size_t shm = (size_t)kSketchWaves * P.max_s * sizeof(double);
+    const dim3 grid(tab_total(P.sc));
+#define SGKS_SC(Zv) \
+    hipLaunchKernelGGL((kb_scatter<Zv>), grid, dim3(kSketchBlock), shm, st, P.SS, P.sc)
+    switch (P.zeta) {
+        case 2: SGKS_SC(2); break;
+        case 4: SGKS_SC(4); break;
+        case 16: SGKS_SC(16); break;
+        default: SGKS_SC(8); break;
+    }
+#undef SGKS_SC
+}
+
+int plan_append(const Plan& P, bool scale_from_norm, hipStream_t st) {
+    const dim3 grid(tab_total(P.ap)), block(kAppendThreads);
+    hipLaunchKernelGGL(k_ap_q0, grid, block, 0, st, P.SS, P.ap, scale_from_norm ? 1 : 0);
+    for (int pass = 1; pass < P.passes; ++pass)
+        hipLaunchKernelGGL(k_ap_qp, grid, block, 0, st, P.SS, P.ap, pass);
+    hipLaunchKernelGGL(k_ap_qf, grid, block, 0, st, P.SS, P.ap);
+    for (int u = 1; u < P.passes; ++u)
+        hipLaunchKernelGGL(k_ap_u, grid, block, 0, st, P.SS, P.ap, u, 0);
+    hipLaunchKernelGGL(k_ap_u, grid, block, 0, st, P.SS, P.ap, P.passes, 1);
+    hipLaunchKernelGGL(k_ap_commit, grid, block, 0, st, P.SS, P.ap);
+    hipLaunchKernelGGL(k_yfix, dim3(P.np), dim3(1024), 0, st, P.SS, P.one);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+void plan_gemvt(const Plan& P, hipStream_t st) {
+    const size_t shm = (size_t)P.max_gt_rows * sizeof(double);
+    hipLaunchKernelGGL(kb_gemvt, dim3(tab_total(P.gemvt)), dim3(kBlock), shm, st, P.SS, P.gemvt);
+}
+
+void plan_refine(const Plan& P, hipStream_t st) {
+    hipLaunchKernelGGL(k_refine, dim3(P.np), dim3(kBlock), 0, st, P.SS, P.one);
 }
 
 int transpose_csr(const Csr& M, int vdt, int32_t* rowptrT, int32_t* colT, void* valT,

@@ -48,7 +48,17 @@ class Options(ctypes.Structure):
                 ("refine_steps", ctypes.c_int32), ("qr_passes", ctypes.c_int32),
                 ("sketch_mode", ctypes.c_int32), ("lanes_A", ctypes.c_int32),
                 ("lanes_At", ctypes.c_int32), ("append_groups", ctypes.c_int32),
+                ("graph", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("stream", ctypes.c_void_p)]
+
+
+class ProblemStruct(ctypes.Structure):
+    _fields_ = [("A", CsrStruct), ("L", CsrStruct), ("b", ctypes.c_void_p),
+                ("mu", ctypes.c_double), ("sketch_rows", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
+
+
+MAX_BATCH = 64
 
 
 _lib = None
@@ -91,6 +101,24 @@ def load_library(path=LIB_PATH):
     L.sgks_profile_read.restype = ctypes.c_int
     L.sgks_dim.argtypes = [ctypes.c_void_p]
     L.sgks_dim.restype = ctypes.c_int32
+    L.sgks_get_lanes.argtypes = [ctypes.c_void_p, P(ctypes.c_int32)]
+    L.sgks_get_lanes.restype = ctypes.c_int
+    L.sgks_batch_create.argtypes = [ctypes.c_int32, P(ProblemStruct), P(Options),
+                                    P(ctypes.c_void_p)]
+    L.sgks_batch_create.restype = ctypes.c_int
+    L.sgks_batch_iterate.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    L.sgks_batch_iterate.restype = ctypes.c_int
+    L.sgks_batch_get.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    L.sgks_batch_get.restype = ctypes.c_void_p
+    L.sgks_batch_count.argtypes = [ctypes.c_void_p]
+    L.sgks_batch_count.restype = ctypes.c_int32
+    L.sgks_batch_profile_enable.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    L.sgks_batch_profile_enable.restype = ctypes.c_int
+    L.sgks_batch_profile_read.argtypes = [ctypes.c_void_p, P(ctypes.c_double),
+                                          P(ctypes.c_int64)]
+    L.sgks_batch_profile_read.restype = ctypes.c_int
+    L.sgks_batch_destroy.argtypes = [ctypes.c_void_p]
+    L.sgks_batch_destroy.restype = None
     L.sgks_destroy.argtypes = [ctypes.c_void_p]
     L.sgks_destroy.restype = None
     L.sgks_strerror.argtypes = [ctypes.c_int]
@@ -144,12 +172,25 @@ def _check(code, where):
     return code
 
 
+def make_options(lib, vdt, stream, *, ell=3, max_iters=200, zeta=8, refine_steps=0, qr_passes=2,
+                 sketch="sparse_sign", lanes_A=0, lanes_At=0, append_groups=0, graph=True,
+                 autotune=False):
+    o = Options()
+    lib.sgks_default_options(ctypes.byref(o))
+    o.ell, o.max_iters, o.zeta, o.value_dtype = ell, max_iters, zeta, vdt
+    o.refine_steps, o.qr_passes = refine_steps, qr_passes
+    o.sketch_mode = SKETCH_IDENTITY if sketch == "identity" else SKETCH_SPARSE_SIGN
+    o.lanes_A, o.lanes_At, o.append_groups = lanes_A, lanes_At, append_groups
+    o.graph, o.autotune = int(bool(graph)), int(bool(autotune))
+    o.stream = ctypes.c_void_p(stream.cuda_stream)
+    return o
+
+
 class SGKS:
     """One sGKS solve on the GPU: sgks_create / sgks_iterate / sgks_solution / ..."""
 
-    def __init__(self, A: DeviceCsr, L: DeviceCsr, b, mu, s, seed=0, *, ell=3, max_iters=200,
-                 zeta=8, refine_steps=0, qr_passes=2, sketch="sparse_sign", lanes_A=0,
-                 lanes_At=0, append_groups=0, stream=None):
+    def __init__(self, A: DeviceCsr, L: DeviceCsr, b, mu, s, seed=0, *, ell=3, stream=None,
+                 **opts):
         import torch
         self._lib = load_library()
         self.A, self.L, self.b = A, L, b
@@ -159,14 +200,9 @@ class SGKS:
         if stream is None:
             stream = torch.cuda.current_stream(b.device)
         self.stream = stream
-        o = Options()
-        self._lib.sgks_default_options(ctypes.byref(o))
-        o.ell, o.max_iters, o.zeta, o.value_dtype = ell, max_iters, zeta, vdt
-        o.refine_steps, o.qr_passes = refine_steps, qr_passes
-        o.sketch_mode = SKETCH_IDENTITY if sketch == "identity" else SKETCH_SPARSE_SIGN
-        o.lanes_A, o.lanes_At, o.append_groups = lanes_A, lanes_At, append_groups
-        o.stream = ctypes.c_void_p(stream.cuda_stream)
+        o = make_options(self._lib, vdt, stream, ell=ell, **opts)
         self.options = o
+        self._owner = None
         self.mu, self.s, self.seed, self.ell = float(mu), int(s), int(seed), int(ell)
         self.n = A.shape[1]
         self.m = A.shape[0]
@@ -224,6 +260,25 @@ class SGKS:
     def dim(self):
         return int(self._lib.sgks_dim(self._h))
 
+    def lanes(self):
+        """Lanes per CSR row in use: (rows of A, rows of L, rows of A^T / L^T)."""
+        v = (ctypes.c_int32 * 3)()
+        _check(self._lib.sgks_get_lanes(self._h, v), "sgks_get_lanes")
+        return tuple(v)
+
+    @classmethod
+    def _borrowed(cls, owner, handle, A, L, b, mu, s, seed, ell, stream):
+        S = cls.__new__(cls)
+        S._lib = owner._lib
+        S.A, S.L, S.b = A, L, b
+        S.stream = stream
+        S.options = owner.options
+        S.mu, S.s, S.seed, S.ell = float(mu), int(s), int(seed), int(ell)
+        S.n, S.m = A.shape[1], A.shape[0]
+        S._h = ctypes.c_void_p(handle)
+        S._owner = owner   # keeps the batch (which owns the context) alive
+        return S
+
     def state(self, which):
         """Copy one state array to host (numpy, column-major shapes as in sgks.h)."""
         rc, it = self.status()
@@ -239,7 +294,90 @@ class SGKS:
 
     def close(self):
         if getattr(self, "_h", None):
-            self._lib.sgks_destroy(self._h)
+            if getattr(self, "_owner", None) is None:
+                self._lib.sgks_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SGKSBatch:
+    """Batched sGKS (sgks_batch_*): many problems of uneven sizes, one launch per step.
+
+    problems: sequence of (A: DeviceCsr, L: DeviceCsr, b, mu, s, seed); the options
+    (ell, max_iters, zeta, refine_steps, qr_passes, sketch, graph, autotune) are
+    shared.  problem(i) gives problem i as an SGKS view (solution, residual_norm,
+    status, state, backward)."""
+
+    def __init__(self, problems, *, ell=3, stream=None, **opts):
+        import torch
+        self._lib = load_library()
+        problems = list(problems)
+        if not 1 <= len(problems) <= MAX_BATCH:
+            raise ValueError(f"a batch holds 1..{MAX_BATCH} problems")
+        b0 = problems[0][2]
+        vdt = F32 if b0.dtype == torch.float32 else F64
+        for A, L, b, *_ in problems:
+            if A.val.dtype != b0.dtype or L.val.dtype != b0.dtype or b.dtype != b0.dtype:
+                raise TypeError("all operators and right-hand sides must share one value dtype")
+        if stream is None:
+            stream = torch.cuda.current_stream(b0.device)
+        self.stream = stream
+        self.options = make_options(self._lib, vdt, stream, ell=ell, **opts)
+        self.problems = problems
+        self.ell = int(ell)
+        arr = (ProblemStruct * len(problems))()
+        for i, (A, L, b, mu, s, seed) in enumerate(problems):
+            arr[i].A, arr[i].L = A.struct(), L.struct()
+            arr[i].b = b.data_ptr()
+            arr[i].mu, arr[i].sketch_rows, arr[i].seed = float(mu), int(s), int(seed)
+        h = ctypes.c_void_p()
+        _check(self._lib.sgks_batch_create(len(problems), arr, ctypes.byref(self.options),
+                                           ctypes.byref(h)), "sgks_batch_create")
+        self._h = h
+        self._views = [None] * len(problems)
+
+    def __len__(self):
+        return int(self._lib.sgks_batch_count(self._h))
+
+    def iterate(self, k):
+        _check(self._lib.sgks_batch_iterate(self._h, int(k)), "sgks_batch_iterate")
+        return self
+
+    def problem(self, i):
+        if self._views[i] is None:
+            hdl = self._lib.sgks_batch_get(self._h, int(i))
+            if not hdl:
+                raise IndexError(i)
+            A, L, b, mu, s, seed = self.problems[i]
+            self._views[i] = SGKS._borrowed(self, hdl, A, L, b, mu, s, seed, self.ell,
+                                            self.stream)
+        return self._views[i]
+
+    def solutions(self):
+        return [self.problem(i).solution() for i in range(len(self.problems))]
+
+    def profile(self, on=True):
+        _check(self._lib.sgks_batch_profile_enable(self._h, 1 if on else 0),
+               "sgks_batch_profile_enable")
+        return self
+
+    def profile_read(self):
+        ms = (ctypes.c_double * PHASES)()
+        cnt = (ctypes.c_int64 * PHASES)()
+        _check(self._lib.sgks_batch_profile_read(self._h, ms, cnt), "sgks_batch_profile_read")
+        return list(ms), list(cnt)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            for v in self._views:
+                if v is not None:
+                    v._h = None
+            self._lib.sgks_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -257,6 +395,26 @@ def upload_problem(P, device="cuda"):
     vt = torch.float32 if P.dtype == "f32" else torch.float64
     b = torch.as_tensor(P.b, device=device).to(vt)
     return A, L, b
+
+
+def upload_batch(Ps, device="cuda"):
+    """(A, L, b, mu, s, seed) tuples of device data for a list of workloads.Problem."""
+    out = []
+    for P in Ps:
+        A, L, b = upload_problem(P, device)
+        out.append((A, L, b, P.mu, P.s, P.seed))
+    return out
+
+
+def solve_batch(Ps, k=None, device="cuda", **kw):
+    """Batched create + k iterations of a list of problems sharing ell, zeta, refinement."""
+    k = Ps[0].k if k is None else k
+    opts = dict(ell=Ps[0].ell, max_iters=max(k, 1), zeta=Ps[0].zeta,
+                refine_steps=Ps[0].refine_steps)
+    opts.update(kw)
+    B = SGKSBatch(upload_batch(Ps, device), **opts)
+    B.iterate(k)
+    return B, B.solutions()
 
 
 def solve_problem(P, k=None, device="cuda", **kw):

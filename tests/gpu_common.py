@@ -1,0 +1,83 @@
+"""Helpers shared by the GPU test modules (imported only after the GPU check)."""
+import math
+import sys
+
+import numpy as np
+
+from oracle import sgks_oracle as O
+from workloads import make
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+_cache = {}
+
+
+def problem(name, scale, seed=0):
+    key = (name, scale, seed)
+    if key not in _cache:
+        _cache[key] = make(name, seed, scale)
+    return _cache[key]
+
+
+def oracle_run(P, k=None, **kw):
+    k = P.k if k is None else k
+    return O.sgks(P.A, P.L, P.b, P.mu, k, P.s, P.seed, zeta=P.zeta, ell=P.ell,
+                  refine_steps=P.refine_steps, **kw)
+
+
+def check_state_consistency(S, P, tol=1e-9):
+    """Relations that hold at any k: the GPU's factors are factors of the GPU's basis."""
+    W = S.state("W")
+    y = S.state("y")
+    QA, RA, QL, RL = S.state("Q_A"), S.state("R_A"), S.state("Q_L"), S.state("R_L")
+    dA, cb = S.state("d_A"), S.state("c_b")
+    S_A, S_L = O.make_sketches(P.m, P.p, P.s, P.seed, P.zeta)
+    d = W.shape[1]
+    # unit columns (normalised basis)
+    assert np.allclose(np.linalg.norm(W, axis=0), 1.0, atol=1e-12)
+    # c_b = S_A b (integer-exact pattern, FP64 sums)
+    cb_ref = S_A @ P.b
+    assert rel(cb, cb_ref) < 1e-13
+    SAW = S_A @ (P.A @ W)
+    SLW = S_L @ (P.L @ W)
+    assert np.linalg.norm(QA @ RA - SAW) <= tol * np.linalg.norm(SAW)
+    assert np.linalg.norm(QL @ RL - SLW) <= tol * np.linalg.norm(SLW)
+    assert np.linalg.norm(QA.T @ QA - np.eye(d)) < 1e-8
+    assert np.linalg.norm(QL.T @ QL - np.eye(d)) < 1e-8
+    assert np.allclose(np.triu(RA), RA) and np.allclose(np.triu(RL), RL)
+    assert rel(dA, QA.T @ cb_ref) < 1e-10
+    # y solves the projected problem built from the GPU factors (before refinement)
+    y_ref, Gf = O.projected_solve(RA, RL, dA, P.mu)
+    kap = np.linalg.cond(np.vstack([RA, math.sqrt(P.mu) * RL]))
+    if P.refine_steps == 0:
+        assert rel(y, y_ref) <= max(1e-10, 1e-15 * kap * 10), (rel(y, y_ref), kap)
+    else:
+        # refined y: the oracle's heavy-ball steps from y_ref on the GPU basis
+        y_ir = O.refine(P.A, P.L, P.b, P.mu, W, y_ref, Gf, P.s, P.refine_steps)
+        assert rel(y, y_ir) <= max(1e-9, 1e-15 * kap * 100), (rel(y, y_ir), kap)
+    # last column is the normalised gradient at the previous iterate (if any expansion done)
+    return W, y
+
+
+def cond_at(ref, P, k):
+    """kappa of the stacked projected matrix [R_A; sqrt(mu) R_L] of the oracle after k
+    expansions (the factors only grow by appended columns, so the leading block is it)."""
+    d = P.ell + k
+    Gs = np.vstack([ref.R_A[:d, :d], math.sqrt(P.mu) * ref.R_L[:d, :d]])
+    return float(np.linalg.cond(Gs))
+
+
+# Trajectory parity is asserted while kappa(G_k) <= KAPPA_TRUSTED: two FP64
+# evaluations of the same iteration then agree to about kappa * 1e-16 times a
+# modest growth factor, below the 1e-5 bound of the FP32-operator path.  Beyond
+# it the projected problem is numerically singular in FP64 and only the
+# relations that hold for any rounding are checked.
+KAPPA_TRUSTED = 1e10

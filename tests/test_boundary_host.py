@@ -2,6 +2,8 @@
 function declared in include/sgks.h, and validates arguments without touching
 the device."""
 import ctypes
+import os
+import subprocess
 
 import pytest
 
@@ -24,6 +26,7 @@ def test_default_options(lib):
     o = G.default_options()
     assert (o.ell, o.max_iters, o.zeta, o.qr_passes, o.value_dtype) == (3, 200, 8, 2, G.F64)
     assert o.sketch_mode == G.SKETCH_SPARSE_SIGN and o.refine_steps == 0
+    assert (o.graph, o.autotune, o.lanes_A, o.lanes_At, o.append_groups) == (1, 0, 0, 0, 0)
 
 
 def _csr(rows, cols, nnz):
@@ -55,6 +58,8 @@ def test_validation_codes(lib):
     assert _v(lib, A, L, qr_passes=3) == -1
     assert _v(lib, A, L, value_dtype=7) == -1
     assert _v(lib, A, L, lanes_A=3) == -1
+    assert _v(lib, A, L, graph=2) == -1
+    assert _v(lib, A, L, autotune=-1) == -1
     assert _v(lib, A, L, max_iters=600, s=2000) == -5           # capacity above 512 columns
     assert _v(lib, A, L, b=0) == -1                             # null b
     assert _v(lib, _csr(0, 80, 0), L) == -2                     # empty A
@@ -76,3 +81,64 @@ def test_null_handles_are_rejected(lib):
     assert lib.sgks_solution(None, None) == -1
     assert lib.sgks_dim(None) == 0
     lib.sgks_destroy(None)
+
+
+def test_null_batch_handles_are_rejected(lib):
+    assert lib.sgks_batch_iterate(None, 1) == -1
+    assert lib.sgks_batch_get(None, 0) is None
+    assert lib.sgks_batch_count(None) == 0
+    assert lib.sgks_batch_profile_enable(None, 1) == -1
+    assert lib.sgks_batch_profile_read(None, None, None) == -1
+    assert lib.sgks_get_lanes(None, None) == -1
+    lib.sgks_batch_destroy(None)
+
+
+def test_batch_argument_checks_before_device_work(lib):
+    out = ctypes.c_void_p()
+    probs = (G.ProblemStruct * 2)()
+    for p in probs:
+        p.A, p.L = _csr(100, 80, 500), _csr(160, 80, 320)
+        p.b, p.mu, p.sketch_rows, p.seed = 0x4000, 1e-2, 400, 0
+    o = G.default_options()
+    o.max_iters = 100
+    assert lib.sgks_batch_create(0, probs, ctypes.byref(o), ctypes.byref(out)) == -1
+    assert lib.sgks_batch_create(G.MAX_BATCH + 1, probs, ctypes.byref(o),
+                                 ctypes.byref(out)) == -1
+    assert lib.sgks_batch_create(2, None, ctypes.byref(o), ctypes.byref(out)) == -1
+    o.lanes_A = 4          # per-problem choices are not shared options
+    assert lib.sgks_batch_create(2, probs, ctypes.byref(o), ctypes.byref(out)) == -1
+    o.lanes_A = 0
+    probs[1].mu = -1.0     # each problem is validated before any set-up
+    assert lib.sgks_batch_create(2, probs, ctypes.byref(o), ctypes.byref(out)) == -3
+    probs[1].mu = 1e-2
+    probs[1].sketch_rows = 50
+    assert lib.sgks_batch_create(2, probs, ctypes.byref(o), ctypes.byref(out)) == -4
+    assert out.value is None
+
+
+LAYOUT_C = r"""
+#include <stddef.h>
+#include <stdio.h>
+#include "sgks.h"
+int main(void) {
+    printf("%zu %zu %zu %zu %zu %zu\n", sizeof(sgks_options), offsetof(sgks_options, graph),
+           offsetof(sgks_options, stream), sizeof(sgks_problem), offsetof(sgks_problem, b),
+           offsetof(sgks_problem, seed));
+    printf("%zu %zu\n", sizeof(sgks_csr), offsetof(sgks_problem, sketch_rows));
+    return 0;
+}
+"""
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors of sgks_options, sgks_csr and sgks_problem have the C layout."""
+    src = tmp_path / "layout.c"
+    src.write_text(LAYOUT_C)
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run(["gcc", "-std=c99", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    got = [int(v) for v in out]
+    O, P = G.Options, G.ProblemStruct
+    assert got == [ctypes.sizeof(O), O.graph.offset, O.stream.offset, ctypes.sizeof(P),
+                   P.b.offset, P.seed.offset, ctypes.sizeof(G.CsrStruct), P.sketch_rows.offset]

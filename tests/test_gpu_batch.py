@@ -1,0 +1,206 @@
+"""Graph replay, batched solves and the lanes autotuner on the GPU (through the C ABI).
+
+The batched iteration runs the same kernel bodies on the same per-problem
+workgroup partition as a single solve, so a batch must reproduce the plain
+per-problem solves bit for bit; the plain solves are in turn held to the FP64
+oracle.  A captured graph replays the same kernels with the same arguments, so
+graph and kernel-by-kernel iteration must agree bit for bit as well.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from gpu_common import (KAPPA_TRUSTED, check_state_consistency, cond_at, oracle_run,  # noqa: E402
+                        problem, rel, say)
+from oracle import sgks_oracle as O  # noqa: E402
+from paper_2606_18073_amd import sgks as G  # noqa: E402
+
+
+def eager_work():
+    """Unrelated work and a synchronisation between graph replays."""
+    v = torch.randn(4096, device="cuda", dtype=torch.float64)
+    return float((v * v).sum().item())
+
+
+@pytest.mark.parametrize("name", ["deblur2d", "ct2d"])
+def test_graph_replay_matches_eager_bitwise(name):
+    """Every replay (single-expansion graph and the 8-expansion graph) against eager."""
+    P = problem(name, "small")
+    say("case graph vs eager", name, P.k, P.refine_steps)
+    A, L, b = G.upload_problem(P)
+    kw = dict(max_iters=P.k, refine_steps=P.refine_steps)
+    Se = G.SGKS(A, L, b, P.mu, P.s, P.seed, graph=False, **kw)
+    Sg = G.SGKS(A, L, b, P.mu, P.s, P.seed, graph=True, **kw)
+    steps = [1, 1, 1, 9, 8]
+    steps.append(P.k - sum(steps))
+    for st in steps:
+        Se.iterate(st)
+        Sg.iterate(st)
+        eager_work()
+        xe, xg = Se.solution().cpu().numpy(), Sg.solution().cpu().numpy()
+        assert np.array_equal(xe, xg), st
+        assert np.array_equal(Se.state("y"), Sg.state("y"))
+        assert Se.status() == Sg.status()
+    assert Sg.status() == (0, P.k)
+    Se.close()
+    Sg.close()
+
+
+def _plain(P, **kw):
+    S, x = G.solve_problem(P, graph=False, **kw)
+    out = (x.cpu().numpy(), S.state("y"), S.status())
+    S.close()
+    return out
+
+
+def test_batch_small_matches_plain_and_oracle():
+    Ps = problem("batch", "small")
+    say("case batch small", [(P.name, P.n) for P in Ps])
+    B, xs = G.solve_batch(Ps)
+    for i, P in enumerate(Ps):
+        xb = xs[i].cpu().numpy()
+        xp, yp, stp = _plain(P)
+        assert np.array_equal(xb, xp), i
+        assert np.array_equal(B.problem(i).state("y"), yp), i
+        assert B.problem(i).status() == stp == (0, P.k)
+        ref = oracle_run(P)
+        e = rel(xb, ref.x)
+        say(f"  problem {i} {P.name} n={P.n} rel err {e:.3e}")
+        assert e <= 1e-8
+        check_state_consistency(B.problem(i), P)
+    B.close()
+
+
+def test_batch_resume_profile_and_views():
+    """Iterate in pieces with profiling (kernel by kernel) then graphs; a problem
+    iterated alone through its view keeps its own basis size."""
+    Ps = problem("batch", "small")
+    say("case batch resume/profile")
+    data = G.upload_batch(Ps)
+    B1 = G.SGKSBatch(data, max_iters=Ps[0].k)
+    B1.profile(True).iterate(3)
+    ms, cnt = B1.profile_read()
+    assert cnt[G.PHASE_NAMES.index("qr_append_solve")] == 3
+    assert cnt[G.PHASE_NAMES.index("sketch_scatter")] == 3
+    assert all(v >= 0 for v in ms)
+    B1.profile(False).iterate(Ps[0].k - 3)
+    B2 = G.SGKSBatch(data, max_iters=Ps[0].k)
+    B2.iterate(Ps[0].k)
+    for i in range(len(Ps)):
+        assert np.array_equal(B1.problem(i).solution().cpu().numpy(),
+                              B2.problem(i).solution().cpu().numpy())
+    with pytest.raises(G.SgksError) as e:
+        B2.iterate(1)
+    assert e.value.code == -5
+    B1.close()
+    B2.close()
+    # a view advanced alone, then the batch: each problem at its own d
+    B3 = G.SGKSBatch(data, max_iters=Ps[0].k)
+    B3.problem(0).iterate(2)
+    B3.iterate(3)
+    assert B3.problem(0).status() == (0, 5)
+    assert B3.problem(1).status() == (0, 3)
+    B3.close()
+
+
+def test_batch_with_breakdown_keeps_others_going():
+    """One problem stops (invariant subspace); the rest match their plain solves."""
+    import scipy.sparse as sp
+    Ps = problem("batch", "small")[:3]
+    say("case batch breakdown")
+    n = 64
+    I = sp.identity(n, format="csr")
+    I.indices = I.indices.astype(np.int32)
+    I.indptr = I.indptr.astype(np.int32)
+    bh = np.linspace(1.0, 2.0, n).astype(np.float32)
+    Id = G.DeviceCsr.from_scipy(I, "f32")
+    bb = torch.as_tensor(bh, device="cuda")
+    data = G.upload_batch(Ps)
+    k = Ps[0].k
+    # A = L = I: K(A^T A, A^T b) = span{b} holds the solution, so the first
+    # expansion stops (ell = 1 for the whole batch)
+    data.insert(1, (Id, Id, bb, 0.5, Ps[0].s, 7))
+    B = G.SGKSBatch(data, ell=1, max_iters=k)
+    B.iterate(k)
+    rc, it = B.problem(1).status()
+    assert rc == G.BREAKDOWN and it == 0
+    ref = O.sgks(sp.identity(n, format="csr"), sp.identity(n, format="csr"), bh.astype(np.float64),
+                 0.5, k, Ps[0].s, 7, ell=1)
+    assert ref.status == O.STATUS_BREAKDOWN and ref.iters == 0
+    assert rel(B.problem(1).solution().cpu().numpy(), ref.x) <= 1e-10
+    for j, P in zip([0, 2, 3], Ps):
+        xp, yp, stp = _plain(P, ell=1)
+        assert np.array_equal(B.problem(j).solution().cpu().numpy(), xp), j
+        assert B.problem(j).status() == stp == (0, k)
+    B.close()
+
+
+def test_autotune_lanes_and_parity():
+    P = problem("deblur2d", "small")
+    say("case autotune")
+    A, L, b = G.upload_problem(P)
+    S = G.SGKS(A, L, b, P.mu, P.s, P.seed, max_iters=P.k, autotune=True)
+    lanes = S.lanes()
+    say("  lanes", lanes)
+    assert all(v in (1, 2, 4, 8, 16, 32, 64) for v in lanes)
+    S.iterate(P.k)
+    ref = oracle_run(P)
+    assert rel(S.solution().cpu().numpy(), ref.x) <= 1e-8
+    # the choice is cached per shape: a second context makes the same choice and
+    # reproduces the first bit for bit
+    S2 = G.SGKS(A, L, b, P.mu, P.s, P.seed, max_iters=P.k, autotune=True)
+    assert S2.lanes() == lanes
+    S2.iterate(P.k)
+    assert np.array_equal(S.solution().cpu().numpy(), S2.solution().cpu().numpy())
+    S.close()
+    S2.close()
+
+
+def test_batch_full_size_32_problems():
+    """32 uneven problems (deblurring, CT, travel time; sides 64..256), k = 80, s = 320:
+    bitwise equal to the 32 plain solves; the smallest problem of each type held to
+    the oracle along its trajectory (while the projected problem is trustworthy in
+    FP64) as a batch of its own, which must also reproduce the 32-problem batch
+    bit for bit; factors consistent with the basis at full k."""
+    Ps = problem("batch", "full")
+    say("case batch full", len(Ps), "problems, total n", sum(P.n for P in Ps))
+    B, xs = G.solve_batch(Ps)
+    xs = [x.cpu().numpy() for x in xs]
+    for i, P in enumerate(Ps):
+        xp, yp, stp = _plain(P)
+        same = np.array_equal(xs[i], xp)
+        say(f"  problem {i} {P.name} n={P.n} status {B.problem(i).status()} bitwise {same}")
+        assert same, i
+        assert B.problem(i).status() == stp
+    small = sorted(range(len(Ps)), key=lambda i: Ps[i].n)
+    sample = [next(i for i in small if Ps[i].name == kind)
+              for kind in ("deblur2d", "ct2d", "traveltime2d")]
+    refs = {i: oracle_run(Ps[i], keep_history=True) for i in sample}
+    Bs = G.SGKSBatch(G.upload_batch([Ps[i] for i in sample]), ell=Ps[0].ell,
+                     max_iters=Ps[0].k, zeta=Ps[0].zeta)
+    done = 0
+    for k in range(10, Ps[0].k + 1, 10):
+        Bs.iterate(k - done)
+        done = k
+        for j, i in enumerate(sample):
+            P, ref = Ps[i], refs[i]
+            assert Bs.problem(j).status() == (0, k)
+            e = rel(Bs.problem(j).solution().cpu().numpy(), ref.x_hist[k])
+            kap = cond_at(ref, P, k)
+            say(f"  k={k} problem {i} {P.name} n={P.n} kappa {kap:.2e} rel err {e:.3e}")
+            if kap <= KAPPA_TRUSTED:
+                assert e <= 1e-5, (i, k, e, kap)
+    for j, i in enumerate(sample):
+        assert refs[i].iters == Ps[i].k
+        assert np.array_equal(Bs.problem(j).solution().cpu().numpy(), xs[i]), i
+        check_state_consistency(Bs.problem(j), Ps[i])
+    Bs.close()
+    big = max(range(len(Ps)), key=lambda i: Ps[i].A.nnz)
+    say("  consistency of problem", big, Ps[big].name, Ps[big].A.nnz)
+    check_state_consistency(B.problem(big), Ps[big])
+    B.close()

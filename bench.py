@@ -7,11 +7,17 @@ k = 100): sgks_create (transposes, sketch of b, initial Krylov basis, QR
 factors), k expansions, and x_k = W y written to device memory.  The inputs
 (A, L, b) are resident in device memory before the timed region starts.
 
-Printed: one JSON line with the metric (sGKS iterations per second over whole
-solves), the roofline of the dominant kernel (algorithmic bytes per launch /
-average launch time, measured with HIP events on the library's stream over
-the timed region), the SpMV+sketch bandwidth, the per-phase breakdown and the
-FP64 CPU oracle timed on a bounded sample of the same workload.
+The timed region replays the captured graphs of the expansion (the production
+path; --eager launches kernel by kernel).  A second, profiled pass runs the same
+steps kernel by kernel with every phase between HIP events on the library's
+stream; kernel durations from it give the roofline of the dominant kernel
+(algorithmic bytes per launch / average launch time) and the SpMV+sketch
+bandwidth.  Then the batched solve of the 32-problem uneven batch is compared
+with its 32 plain solves, and the forward solve of the dynamic CT workload with
+forward + backward.  Finally the FP64 CPU oracle is timed on a bounded sample of
+the main workload.
+
+Printed: one JSON line on stdout (progress goes to stderr).
 """
 import argparse
 import hashlib
@@ -26,6 +32,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    """Progress on stderr (the JSON line is the only stdout output)."""
+    print("[bench]", *a, file=sys.stderr, flush=True)
 
 
 def source_hash():
@@ -96,6 +107,112 @@ def cpu_baseline(P, reps):
                            f"workload, FP64 numpy/scipy, 1 thread, {dt:.1f} s"}
 
 
+def bulk_bytes_per_iteration(P):
+    """Algorithmic bytes of the bulk kernels of one expansion at the mean basis size."""
+    d_avg = P.ell + (P.k - 1) / 2.0
+    ab = algorithmic_bytes(P, d_avg)
+    return (ab["gemv_Wy"] + ab["forward_Ax_Lx"] + ab["adjoint_ATu_LTt"] + ab["spmv_new_column"]
+            + ab["sketch_scatter"])
+
+
+def bench_batch(G, torch, np, make):
+    """The 32-problem uneven batch: one batched solve against the 32 plain solves."""
+    Ps = make("batch", 0, "full")
+    data = G.upload_batch(Ps)
+    k = Ps[0].k
+    opts = dict(ell=Ps[0].ell, max_iters=k, zeta=Ps[0].zeta)
+    # warm-up (module load, graph capture paths)
+    B = G.SGKSBatch(data, **opts)
+    B.iterate(2)
+    B.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B = G.SGKSBatch(data, **opts)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    B.iterate(k)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    xb = [x.cpu().numpy() for x in B.solutions()]
+    st_b = [B.problem(i).status() for i in range(len(Ps))]
+    B.close()
+    setup_p = iter_p = 0.0
+    same = True
+    for i, (A, L, b, mu, s, seed) in enumerate(data):
+        torch.cuda.synchronize()
+        u0 = time.perf_counter()
+        S = G.SGKS(A, L, b, mu, s, seed, **opts)
+        torch.cuda.synchronize()
+        u1 = time.perf_counter()
+        S.iterate(k)
+        torch.cuda.synchronize()
+        u2 = time.perf_counter()
+        setup_p += u1 - u0
+        iter_p += u2 - u1
+        same = same and np.array_equal(S.solution().cpu().numpy(), xb[i]) and S.status() == st_b[i]
+        S.close()
+    total = sum(st[1] for st in st_b)
+    bulk = sum(bulk_bytes_per_iteration(P) for P in Ps)
+    return {
+        "workload": (f"{len(Ps)} problems (deblurring / CT / travel time, sides 64..256 "
+                     f"log-uniform, own mu), total n={sum(P.n for P in Ps)}, total nnz(A)="
+                     f"{sum(P.A.nnz for P in Ps)}, s={Ps[0].s}, k={k}, FP32 operators"),
+        "problem_iterations": total,
+        "batched_iters_per_s": total / (t2 - t0),
+        "batched_iterate_only_iters_per_s": total / (t2 - t1),
+        "batched_setup_ms": 1e3 * (t1 - t0),
+        "plain_iters_per_s": total / (setup_p + iter_p),
+        "plain_iterate_only_iters_per_s": total / iter_p,
+        "plain_setup_ms": 1e3 * setup_p,
+        "speedup_whole": (setup_p + iter_p) / (t2 - t0),
+        "speedup_iterate_only": iter_p / (t2 - t1),
+        "batched_iteration_ms": 1e3 * (t2 - t1) / k,
+        "bulk_algorithmic_GBps_batched": bulk * k / (t2 - t1) / 1e9,
+        "equal_rel_err": "bitwise-identical x_k to the plain solves" if same else "MISMATCH",
+        "bitwise_equal_to_plain": bool(same),
+    }
+
+
+def bench_adjoint(G, torch, np, make):
+    """Forward solve vs forward + frozen-basis backward on the dynamic CT workload."""
+    P = make("dynamic_ct", 0, "full")
+    A, L, b = G.upload_problem(P)
+    opts = dict(ell=P.ell, max_iters=P.k, zeta=P.zeta, refine_steps=P.refine_steps)
+    xt = torch.as_tensor(P.x_true, device=b.device)
+    S = G.SGKS(A, L, b, P.mu, P.s, P.seed, **opts)   # warm-up
+    S.iterate(2)
+    S.backward(2.0 * (S.solution() - xt))
+    S.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S = G.SGKS(A, L, b, P.mu, P.s, P.seed, **opts)
+    S.iterate(P.k)
+    x = S.solution()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    gx = 2.0 * (x - xt)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    gb, gmu = S.backward(gx)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    rc, it = S.status()
+    S.close()
+    fwd, bwd = t1 - t0, t3 - t2
+    return {
+        "workload": (f"{P.name}: {P.meta.get('nt')} frames of {P.meta.get('N')}^2, n={P.n}, "
+                     f"m={P.m}, p={P.p}, nnz(A)={P.A.nnz}, s={P.s}, k={P.k}; loss ||x_k - "
+                     f"x_true||^2, gradients w.r.t. b and mu"),
+        "forward_ms": 1e3 * fwd,
+        "backward_ms": 1e3 * bwd,
+        "forward_iters_per_s": it / fwd,
+        "forward_plus_backward_over_forward": (fwd + bwd) / fwd,
+        "equal_rel_err": "the forward x_k is the one the backward differentiates (same run)",
+        "grad_mu": gmu,
+        "status": [rc, it],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,13 +220,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="deblur2d")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-reps", type=int, default=2)
+    ap.add_argument("--cpu-reps", type=int, default=8)
     ap.add_argument("--no-profile", action="store_true",
-                    help="time without the per-phase events (no roofline)")
+                    help="skip the profiled pass (no per-phase times, no roofline)")
+    ap.add_argument("--eager", action="store_true",
+                    help="time kernel-by-kernel launches instead of graph replays")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched and adjoint comparisons")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: there is no multi-GPU path "
               "(see the sharding design notes); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
@@ -121,14 +242,13 @@ def main():
 
     P = make(args.workload, 0, "full")
     dev = torch.device("cuda:0")
-    A, L, b = G.upload_problem(P, dev)
+    A, L, b = G.upload_problem(P)
     x = torch.empty(P.n, dtype=torch.float64, device=dev)
-    prof = not args.no_profile
 
-    def step(acc):
+    def step(acc, prof):
         t0 = time.perf_counter()
         S = G.SGKS(A, L, b, P.mu, P.s, P.seed, ell=P.ell, max_iters=P.k, zeta=P.zeta,
-                   refine_steps=P.refine_steps)
+                   refine_steps=P.refine_steps, graph=not args.eager)
         t1 = time.perf_counter()
         if prof:
             S.profile(True)
@@ -144,15 +264,19 @@ def main():
         acc["setup_s"] += t1 - t0
         assert rc == 0 and it == P.k, (rc, it)
 
+    def fresh():
+        return {"ms": [0.0] * G.PHASES, "n": [0] * G.PHASES, "setup_s": 0.0}
+
     for _ in range(args.warmup):
-        step({"ms": [0.0] * G.PHASES, "n": [0] * G.PHASES, "setup_s": 0.0})
-    acc = {"ms": [0.0] * G.PHASES, "n": [0] * G.PHASES, "setup_s": 0.0}
+        step(fresh(), False)
+    acc = fresh()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step(acc)
+        step(acc, False)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    log(f"timed region: {args.steps} steps in {wall:.3f} s")
     ms_per_step = 1e3 * wall / args.steps
     value = args.steps * P.k / wall
     iter_s = wall - acc["setup_s"]
@@ -180,15 +304,27 @@ def main():
             "operator_storage": P.dtype,
             "vectors": "f64",
             "k": P.k, "n": P.n, "s": P.s,
+            "launch": "kernel by kernel" if args.eager else "graph replay (8 expansions per graph)",
         },
         "setup_ms_per_step": 1e3 * acc["setup_s"] / args.steps,
         "iterate_only_iters_per_s": args.steps * P.k / iter_s if iter_s > 0 else None,
     }
-    if prof:
+    if not args.no_profile:
+        # profiled pass: the same steps kernel by kernel, every phase between HIP
+        # events on the library's stream (kernel durations do not depend on how
+        # the launches were issued)
+        pacc = fresh()
+        torch.cuda.synchronize()
+        p0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(pacc, True)
+        torch.cuda.synchronize()
+        out["profiled_ms_per_step"] = 1e3 * (time.perf_counter() - p0) / args.steps
+        log("profiled pass done")
         names = G.PHASE_NAMES
-        phase = {names[i]: {"ms_total": acc["ms"][i], "launches": acc["n"][i],
-                            "us_avg": (1e3 * acc["ms"][i] / acc["n"][i]) if acc["n"][i] else None}
-                 for i in range(G.PHASES) if acc["n"][i]}
+        phase = {names[i]: {"ms_total": pacc["ms"][i], "launches": pacc["n"][i],
+                            "us_avg": (1e3 * pacc["ms"][i] / pacc["n"][i]) if pacc["n"][i] else None}
+                 for i in range(G.PHASES) if pacc["n"][i]}
         out["phases"] = phase
         # average d over the x = W y launches: iterations use d = ell .. ell + k - 1,
         # the solution uses ell + k
@@ -217,7 +353,13 @@ def main():
         tt = sum(kern[k]["ms_total"] for k in sk if k in kern) * 1e-3
         out["spmv_sketch_GBps"] = tb / tt / 1e9 if tt > 0 else None
         out["spmv_sketch_frac_of_hbm_peak"] = out["spmv_sketch_GBps"] / HBM_PEAK_GBS
+    if not args.no_extras:
+        out["batched_vs_plain"] = bench_batch(G, torch, np, make)
+        log("batched comparison done")
+        out["adjoint_vs_plain"] = bench_adjoint(G, torch, np, make)
+        log("adjoint comparison done")
     if not args.no_cpu_baseline:
+        log("oracle on the host ...")
         ref, cb = cpu_baseline(P, args.cpu_reps)
         out["cpu_baseline"] = cb
         out["rel_err_vs_oracle"] = float(np.linalg.norm(xg - ref.x) / np.linalg.norm(ref.x))

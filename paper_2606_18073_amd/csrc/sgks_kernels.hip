@@ -231,24 +231,38 @@ struct Slot {
     int nblk;   // workgroups of the problem
 };
 
-// Static indices only, so the table stays in scalar registers.
+// One problem: the grid is the problem's.  Several: binary search of the
+// prefix table in the kernel-argument segment (a few scalar loads).
 __device__ __forceinline__ Slot find_slot(const BTab& t) {
     const int b = blockIdx.x;
-    Slot r{0, b, t.pref[1]};
-#pragma unroll
-    for (int q = 1; q < kMaxBatch; ++q) {
-        if (q < t.np && b >= t.pref[q]) {
-            r.p = q;
-            r.blk = b - t.pref[q];
-            r.nblk = t.pref[q + 1] - t.pref[q];
-        }
+    if (t.np == 1) return Slot{0, b, t.pref[1]};
+    int lo = 0, hi = t.np;   // pref[lo] <= b < pref[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (b >= t.pref[mid])
+            lo = mid;
+        else
+            hi = mid;
     }
-    return r;
+    return Slot{lo, b - t.pref[lo], t.pref[lo + 1] - t.pref[lo]};
 }
 
 __device__ __forceinline__ int rows_blocks_of(const Csr& M) {
-    const int per = kBlock / M.lanes;
-    return (int)((M.rows + per - 1) / per);
+    const uint32_t per = (uint32_t)(kBlock / M.lanes);   // rows < 2^31: 32-bit arithmetic
+    return (int)(((uint32_t)M.rows + per - 1u) / per);
+}
+
+// The States are read-only while any kernel runs, so they are read through the
+// constant address space: the fields become scalar loads and every pointer
+// loaded from them is known to address global memory (global, not flat,
+// memory instructions in the loops that use it).
+__device__ __forceinline__ State load_state(const State* SS, int p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef __attribute__((address_space(4))) const State ConstState;
+    return ((ConstState*)SS)[p];
+#else
+    return SS[p];   // the host pass never runs device functions
+#endif
 }
 
 // ---------------------------------------------------------------------------
@@ -305,7 +319,7 @@ __global__ __launch_bounds__(kBlock) void kb_forward(const State* __restrict__ S
                                                     int newcol) {
     __shared__ double red[kWaves];
     const Slot sl = find_slot(tab);
-    const State& S = SS[sl.p];
+    const State S = load_state(SS, sl.p);
     if (newcol && *S.status != 0) return;
     const double* x = newcol ? S.W + (int64_t)(*S.d) * S.n : S.x;
     forward_body<T>(S.A, S.L, rows_blocks_of(S.A), x, newcol ? nullptr : S.b, S.u, S.t, nullptr,
@@ -357,7 +371,7 @@ __global__ __launch_bounds__(kBlock) void kb_adjoint(const State* __restrict__ S
                                                     int to_rtmp) {
     __shared__ double red[kWaves];
     const Slot sl = find_slot(tab);
-    const State& S = SS[sl.p];
+    const State S = load_state(SS, sl.p);
     if (!to_rtmp && *S.status != 0) return;
     double* dst = to_rtmp ? S.rtmp : S.W + (int64_t)(*S.d) * S.n;
     adjoint_body<T>(S.At, S.Lt, 1, S.mu, S.u, S.t, dst, S.n, S.norm_part, sl.blk, sl.nblk, red);
@@ -432,7 +446,7 @@ __global__ __launch_bounds__(kSketchBlock) void kb_scatter(const State* __restri
                                                           BTab tab) {
     extern __shared__ double sm[];
     const Slot sl = find_slot(tab);
-    const State& S = SS[sl.p];
+    const State S = load_state(SS, sl.p);
     if (*S.status != 0) return;
     scatter_body<Z>(S.u, S.m, S.t, S.p, S.nbA, S.nbL, S.s, S.seed, S.sketch_mode, S.binA, S.binL,
                     sl.blk, sm);
@@ -482,7 +496,7 @@ __global__ __launch_bounds__(kBlock) void k_gemv(const double* __restrict__ W,
 __global__ __launch_bounds__(kBlock) void kb_gemv(const State* __restrict__ SS, BTab tab) {
     __shared__ double yt[kMaxD];
     const Slot sl = find_slot(tab);
-    const State& S = SS[sl.p];
+    const State S = load_state(SS, sl.p);
     gemv_body(S.W, S.cs, S.y, *S.d, S.n, nullptr, S.x, sl.blk, sl.nblk, yt);
 }
 
@@ -520,7 +534,7 @@ __global__ __launch_bounds__(kBlock) void k_gemvt(const double* __restrict__ W,
 __global__ __launch_bounds__(kBlock) void kb_gemvt(const State* __restrict__ SS, BTab tab) {
     extern __shared__ double vs[];
     const Slot sl = find_slot(tab);
-    const State& S = SS[sl.p];
+    const State S = load_state(SS, sl.p);
     if (*S.status != 0) return;
     gemvt_body(S.W, S.cs, S.rtmp, *S.d, S.n, S.gt_rows, S.gpart, S.dmax, sl.blk, vs);
 }
@@ -729,7 +743,7 @@ __global__ __launch_bounds__(kAppendThreads) void k_ap_q0(const State* __restric
                                                      int scale_from_norm) {
     __shared__ ApShared sh;
     const Slot sl = find_slot(tab);
-    const State& S = SS[sl.p];
+    const State S = load_state(SS, sl.p);
     const int G = sl.nblk;
     if (*S.status != 0) return;
     const int d = *S.d;
@@ -815,7 +829,7 @@ __global__ __launch_bounds__(kAppendThreads) void k_ap_qp(const State* __restric
                                                      int pass) {
     __shared__ ApShared sh;
     const Slot sl = find_slot(tab);
-    const State& S = SS[sl.p];
+    const State S = load_state(SS, sl.p);
     const int G = sl.nblk;
     if (*S.status != 0) return;
     const int d = *S.d;
@@ -844,7 +858,7 @@ __global__ __launch_bounds__(kAppendThreads) void k_ap_qf(const State* __restric
                                                      BTab tab) {
     __shared__ ApShared sh;
     const Slot sl = find_slot(tab);
-    const State& S = SS[sl.p];
+    const State S = load_state(SS, sl.p);
     const int G = sl.nblk;
     if (*S.status != 0) return;
     const int d = *S.d;
@@ -905,7 +919,7 @@ __global__ __launch_bounds__(kAppendThreads) void k_ap_u(const State* __restrict
                                                     int upass, int last) {
     __shared__ ApShared sh;
     const Slot sl = find_slot(tab);
-    const State& S = SS[sl.p];
+    const State S = load_state(SS, sl.p);
     const int G = sl.nblk;
     if (*S.status != 0) return;
     const int d = *S.d;
@@ -955,7 +969,7 @@ __global__ __launch_bounds__(kAppendThreads) void k_ap_commit(const State* __res
                                                          BTab tab) {
     __shared__ ApShared sh;
     const Slot sl = find_slot(tab);
-    const State& S = SS[sl.p];
+    const State S = load_state(SS, sl.p);
     const int G = sl.nblk;
     if (*S.status != 0) return;
     const int d = *S.d;
@@ -1061,7 +1075,7 @@ __global__ __launch_bounds__(1024) void k_yfix(const State* __restrict__ SS, BTa
     __shared__ double yv[kMaxD];
     __shared__ double rv[kMaxD];
     __shared__ double tv[kMaxD];
-    const State& S = SS[find_slot(tab).p];
+    const State S = load_state(SS, find_slot(tab).p);
     if (*S.status != 0) return;   // no append (breakdown) or an earlier stop
     const int d = *S.d + 1, dmax = S.dmax;
     for (int i = threadIdx.x; i < d; i += 1024) yv[i] = S.y[i];
@@ -1088,7 +1102,7 @@ __global__ __launch_bounds__(kBlock) void k_refine(const State* __restrict__ SS,
     __shared__ double gv[kMaxD];
     __shared__ double tv[kMaxD];
     __shared__ double dv[kMaxD];
-    const State& S = SS[find_slot(tab).p];
+    const State S = load_state(SS, find_slot(tab).p);
     if (*S.status != 0) return;
     const int d = *S.d;
     const int dmax = S.dmax;

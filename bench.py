@@ -48,34 +48,41 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(P, d_avg_gemv):
-    """Minimal HBM bytes per launch of each bulk kernel (CSR read once, vectors once)."""
+def algorithmic_bytes(P, d_avg, form="maintained"):
+    """Minimal HBM bytes per launch of each bulk kernel: CSR values and indices once,
+    rowptrs once, vectors read and written once, the d columns of W (or H W) for the
+    dense products, the hashed pattern (2 zeta bytes per entry) for the scatter."""
     vsz = 4 if P.dtype == "f32" else 8
     nnzA, nnzL = P.A.nnz, P.L.nnz
     m, n, p, s = P.m, P.n, P.p, P.s
     csr = (vsz + 4) * (nnzA + nnzL)
-    rowptrs = 4 * (m + 1) + 4 * (p + 1)
-    return {
-        # u = A x - b, t = L x: CSR, x, b read; u, t written
-        "forward_Ax_Lx": csr + rowptrs + 8 * n + 8 * m + 8 * m + 8 * p,
+    out = {
         # z = A w, L w of the new column: CSR, w read; z written
-        "spmv_new_column": csr + rowptrs + 8 * n + 8 * m + 8 * p,
-        # r = A^T u + mu L^T t: transposed CSR, u, t read; r written
-        "adjoint_ATu_LTt": csr + 8 * (n + 1) + 8 * m + 8 * p + 8 * n,
-        # sketch bins of z: z read, 2 s outputs
-        "sketch_scatter": 8 * (m + p) + 16 * s,
-        # x = W y: the d columns of W read, x written
-        "gemv_Wy": 8 * n * d_avg_gemv + 8 * n,
+        "spmv_new_column": csr + 4 * (m + 1) + 4 * (p + 1) + 8 * n + 8 * m + 8 * p,
+        # sketch bins of z: z and the pattern read, partial bins written (counted once)
+        "sketch_scatter": (8 + 2 * P.zeta) * (m + p) + 16 * s,
+        # adjoint products: transposed CSR, (u, t) read, one n-vector written
+        "adjoint": csr + 8 * (n + 1) + 8 * m + 8 * p + 8 * n,
     }
+    if form == "maintained":
+        # r = (H W) y - A^T b: d columns of H W and A^T b read, r written
+        out["gemv"] = 8 * n * d_avg + 16 * n
+    else:
+        # x = W y: the d columns of W read, x written
+        out["gemv"] = 8 * n * d_avg + 8 * n
+        # u = A x - b, t = L x: CSR, x, b read; u, t written
+        out["forward_Ax_Lx"] = csr + 4 * (m + 1) + 4 * (p + 1) + 8 * n + 8 * m + 8 * m + 8 * p
+    return out
 
 
-# phases that launch the same kernel
-KERNEL_PHASES = {
-    "k_forward": ["forward_Ax_Lx", "spmv_new_column"],
-    "k_adjoint": ["adjoint_ATu_LTt"],
-    "k_scatter": ["sketch_scatter"],
-    "k_gemv": ["gemv_Wy"],
-}
+# the kernel each phase launches
+def kernel_phases(form):
+    return {
+        "kb_forward": ["forward_Ax_Lx", "spmv_new_column"],
+        "kb_adjoint": ["adjoint"],
+        "kb_scatter": ["sketch_scatter"],
+        "kb_gradient" if form == "maintained" else "kb_gemv": ["gemv"],
+    }
 
 
 def load_traffic(kernel, workload, shash):
@@ -107,12 +114,10 @@ def cpu_baseline(P, reps):
                            f"workload, FP64 numpy/scipy, 1 thread, {dt:.1f} s"}
 
 
-def bulk_bytes_per_iteration(P):
+def bulk_bytes_per_iteration(P, form="maintained"):
     """Algorithmic bytes of the bulk kernels of one expansion at the mean basis size."""
     d_avg = P.ell + (P.k - 1) / 2.0
-    ab = algorithmic_bytes(P, d_avg)
-    return (ab["gemv_Wy"] + ab["forward_Ax_Lx"] + ab["adjoint_ATu_LTt"] + ab["spmv_new_column"]
-            + ab["sketch_scatter"])
+    return sum(algorithmic_bytes(P, d_avg, form).values())
 
 
 def bench_batch(G, torch, np, make):
@@ -227,6 +232,10 @@ def main():
                     help="time kernel-by-kernel launches instead of graph replays")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched and adjoint comparisons")
+    ap.add_argument("--gradient", choices=["maintained", "direct"], default="maintained",
+                    help="gradient form of the expansion")
+    ap.add_argument("--autotune", action="store_true",
+                    help="let the library time its launch shapes at create (cached per shape)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -248,7 +257,9 @@ def main():
     def step(acc, prof):
         t0 = time.perf_counter()
         S = G.SGKS(A, L, b, P.mu, P.s, P.seed, ell=P.ell, max_iters=P.k, zeta=P.zeta,
-                   refine_steps=P.refine_steps, graph=not args.eager)
+                   refine_steps=P.refine_steps, graph=not args.eager, autotune=args.autotune,
+                   gradient=args.gradient)
+        acc["tuning"] = S.tuning()
         t1 = time.perf_counter()
         if prof:
             S.profile(True)
@@ -305,8 +316,10 @@ def main():
             "vectors": "f64",
             "k": P.k, "n": P.n, "s": P.s,
             "launch": "kernel by kernel" if args.eager else "graph replay (8 expansions per graph)",
+            "gradient_form": args.gradient,
         },
         "setup_ms_per_step": 1e3 * acc["setup_s"] / args.steps,
+        "launch_shapes": acc.get("tuning"),
         "iterate_only_iters_per_s": args.steps * P.k / iter_s if iter_s > 0 else None,
     }
     if not args.no_profile:
@@ -326,15 +339,15 @@ def main():
                             "us_avg": (1e3 * pacc["ms"][i] / pacc["n"][i]) if pacc["n"][i] else None}
                  for i in range(G.PHASES) if pacc["n"][i]}
         out["phases"] = phase
-        # average d over the x = W y launches: iterations use d = ell .. ell + k - 1,
+        # average d over the dense launches: iterations use d = ell .. ell + k - 1,
         # the solution uses ell + k
         ds = list(range(P.ell, P.ell + P.k)) + [P.ell + P.k]
-        ab = algorithmic_bytes(P, sum(ds) / len(ds))
+        ab = algorithmic_bytes(P, sum(ds) / len(ds), args.gradient)
         kern = {}
-        for kname, phs in KERNEL_PHASES.items():
+        for kname, phs in kernel_phases(args.gradient).items():
             ms = sum(phase[p]["ms_total"] for p in phs if p in phase)
             nl = sum(phase[p]["launches"] for p in phs if p in phase)
-            by = sum(ab[p] * phase[p]["launches"] for p in phs if p in phase)
+            by = sum(ab.get(p, 0.0) * phase[p]["launches"] for p in phs if p in phase)
             if nl:
                 kern[kname] = {"ms_total": ms, "launches": nl, "us_avg": 1e3 * ms / nl,
                                "bytes_per_launch": by / nl, "GBps": by / (ms * 1e-3) / 1e9}
@@ -348,7 +361,7 @@ def main():
                            "traffic": traffic,
                            "algorithmic_bytes_per_launch": kern[dom]["bytes_per_launch"],
                            "avg_launch_us": kern[dom]["us_avg"], "source_hash": shash}
-        sk = ["k_forward", "k_adjoint", "k_scatter"]
+        sk = ["kb_forward", "kb_adjoint", "kb_scatter"]
         tb = sum(kern[k]["bytes_per_launch"] * kern[k]["launches"] for k in sk if k in kern)
         tt = sum(kern[k]["ms_total"] for k in sk if k in kern) * 1e-3
         out["spmv_sketch_GBps"] = tb / tt / 1e9 if tt > 0 else None

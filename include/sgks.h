@@ -71,6 +71,17 @@ extern "C" {
 #define SGKS_SKETCH_SPARSE_SIGN 0
 #define SGKS_SKETCH_IDENTITY 1
 
+/* Gradient forms (the same vector, two associations; eq: gradient).  DIRECT:
+ * x = W y, u = A x - b, t = L x, r = A^T u + mu L^T t (two SpMVs and a GEMV per
+ * expansion and per refinement step).  MAINTAINED: the context keeps
+ * H W = (A^T A + mu L^T L) W column by column (the new column's A w and L w are
+ * formed for its sketch anyway, one adjoint SpMV adds its H w) and evaluates
+ * r = (H W) y - A^T b with one GEMV (A^T b is the first, unnormalised basis
+ * column).  It saves an SpMV pass per expansion and both SpMVs of every
+ * refinement step, for n * (ell + max_iters) more doubles of device memory. */
+#define SGKS_GRADIENT_MAINTAINED 0
+#define SGKS_GRADIENT_DIRECT 1
+
 /* CSR matrix with int32 indices; column indices sorted within each row.  All
  * three arrays are device pointers; val holds nnz values of the options'
  * value_dtype. */
@@ -91,13 +102,19 @@ typedef struct {
     int32_t sketch_mode;     /* SGKS_SKETCH_SPARSE_SIGN (default) or SGKS_SKETCH_IDENTITY     */
     int32_t lanes_A;         /* lanes per row for A-row SpMVs; 0 = choose from nnz/row          */
     int32_t lanes_At;        /* lanes per row for A^T rows; 0 = choose                          */
-    int32_t append_groups;   /* workgroups of the append kernels; 0 = choose                    */
+    int32_t append_groups;   /* QR append: 1 = compact (one workgroup per sketch side, then one
+                                for the stacked factor), 2..32 = chain of kernels on that many
+                                workgroups (slabs of <= 64 sketch rows); 0 = choose by s * dmax */
     int32_t graph;           /* 1 = sgks_iterate / sgks_batch_iterate replay a captured HIP
                                 graph of the expansion (default), 0 = launch kernel by kernel.
                                 Profiling (sgks_profile_enable) always launches kernel by kernel */
-    int32_t autotune;        /* 1 = time the lanes-per-row choices of the SpMVs at create and
-                                keep the fastest (cached per operator shape in the process);
-                                0 = choose from nnz/row (default)                               */
+    int32_t gradient_form;   /* SGKS_GRADIENT_MAINTAINED (default) or SGKS_GRADIENT_DIRECT:
+                                how the gradient r = A^T (A x - b) + mu L^T L x is evaluated
+                                each expansion (see below)                                      */
+    int32_t autotune;        /* 1 = time the lanes-per-row choices of the SpMVs and the tiles
+                                per wave of the sketch scatter at create and keep the fastest
+                                (cached per operator shape in the process); 0 = choose from
+                                nnz/row and a fixed tile count (default)                        */
     void *stream;            /* hipStream_t the work is enqueued on (NULL = default stream)   */
 } sgks_options;
 
@@ -170,10 +187,13 @@ int sgks_profile_read(sgks_ctx *ctx, double *ms, int64_t *launches);
 /* Current number of basis columns d (host-side view, no synchronisation). */
 int32_t sgks_dim(const sgks_ctx *ctx);
 
-/* Lanes of a wavefront per CSR row in use: lanes[0] rows of A, lanes[1] rows
- * of L (forward products), lanes[2] rows of A^T and L^T (adjoint products).
- * Powers of two in [1, 64]; 64 / lanes rows share one wavefront. */
-int sgks_get_lanes(const sgks_ctx *ctx, int32_t lanes[3]);
+/* Launch shapes in use (chosen at create, by the autotuner when enabled):
+ * out[0], out[1] lanes of a wavefront per CSR row for the rows of A and of L
+ * (forward products), out[2] for the rows of A^T and L^T (adjoint products),
+ * powers of two in [1, 64] (64 / lanes rows share one wavefront); out[3],
+ * out[4] workgroups of the sketch scatter over the m (S_A) and p (S_L)
+ * entries; out[5] append groups (1 = compact append). */
+int sgks_get_tuning(const sgks_ctx *ctx, int32_t out[6]);
 
 /* Releases the context and its device memory (synchronises its stream).  A
  * context obtained from sgks_batch_get belongs to its batch: destroying it

@@ -75,26 +75,45 @@ struct Phase {
     }
 };
 
-// Refinement step of every problem of the plan: x = W y, u, t, r = gradient
-// into rtmp, W^T r, y update (heavy ball).
+// Refinement step of every problem of the plan: the gradient r(y) into rtmp,
+// W^T r, y update (heavy ball).
 void enqueue_refine(const sgks::Plan& P, Profiler* pr, hipStream_t st) {
-    { Phase ph(pr, 0); sgks::plan_gemv(P, st); }
-    { Phase ph(pr, 1); sgks::plan_forward(P, false, st); }
-    { Phase ph(pr, 2); sgks::plan_adjoint(P, true, st); }
+    if (P.gradient_form == SGKS_GRADIENT_MAINTAINED) {
+        Phase ph(pr, 0);
+        sgks::plan_gradient(P, true, st);
+    } else {
+        { Phase ph(pr, 0); sgks::plan_gemv(P, st); }
+        { Phase ph(pr, 1); sgks::plan_forward(P, false, st); }
+        { Phase ph(pr, 2); sgks::plan_adjoint(P, 1, st); }
+    }
     { Phase ph(pr, 5); sgks::plan_gemvt(P, st); }
     { Phase ph(pr, 6); sgks::plan_refine(P, st); }
 }
 
-// One expansion of every problem of the plan (the loop body of Alg. 2):
-// x = W y, u = A x - b, t = L x, r = A^T u + mu L^T t into the next basis
-// column, A w and L w of that column, their sketches, the QR appends and
-// the projected solve; then the refinement steps.
+// One expansion of every problem of the plan (the loop body of Alg. 2): the
+// gradient r at x = W y into the next basis column, A w and L w of that
+// column, their sketches, the QR appends and the projected solve; then the
+// refinement steps.  Maintained form: r = (H W) y - A^T b from the kept
+// columns of H W = (A^T A + mu L^T L) W, whose new column is A^T (A w) +
+// mu L^T (L w) from the images the sketch needs anyway.  Direct form:
+// x = W y, u = A x - b, t = L x, r = A^T u + mu L^T t.
 int enqueue_iteration(const sgks::Plan& P, int refine_steps, Profiler* pr, hipStream_t st) {
-    { Phase ph(pr, 0); sgks::plan_gemv(P, st); }
-    { Phase ph(pr, 1); sgks::plan_forward(P, false, st); }
-    { Phase ph(pr, 2); sgks::plan_adjoint(P, false, st); }
+    const bool maintained = P.gradient_form == SGKS_GRADIENT_MAINTAINED;
+    if (maintained) {
+        Phase ph(pr, 0);
+        sgks::plan_gradient(P, false, st);
+    } else {
+        { Phase ph(pr, 0); sgks::plan_gemv(P, st); }
+        { Phase ph(pr, 1); sgks::plan_forward(P, false, st); }
+        { Phase ph(pr, 2); sgks::plan_adjoint(P, 0, st); }
+    }
     { Phase ph(pr, 3); sgks::plan_forward(P, true, st); }
     { Phase ph(pr, 7); sgks::plan_scatter(P, st); }
+    if (maintained) {
+        // column d of H W, before the append advances d
+        Phase ph(pr, 2);
+        sgks::plan_adjoint(P, 2, st);
+    }
     {
         Phase ph(pr, 4);
         if (sgks::plan_append(P, true, st)) return SGKS_ERR_HIP;
@@ -107,6 +126,9 @@ int enqueue_iteration(const sgks::Plan& P, int refine_steps, Profiler* pr, hipSt
 // kGraphChunk expansions.  The kernels take only device-resident state (the
 // basis size d is read on the device), so one graph serves every expansion.
 constexpr int kGraphChunk = 8;
+
+// default 64-entry tiles per wave of the sketch scatter
+constexpr int kScatterTilesPerWave = 4;
 
 struct GraphCache {
     hipStream_t cap = nullptr;
@@ -231,6 +253,40 @@ int tune_one(const State& S, int kind, hipStream_t st) {
     return best;
 }
 
+// tiles per wave of the sketch scatter: each count is timed as the scatter of
+// both images plus the reduction of its partial bins (fewer, fuller workgroups
+// leave fewer partial bins to reduce)
+int tune_scatter(const State& S, hipStream_t st) {
+    const auto key = std::make_tuple(3, S.m, S.p, (int64_t)S.s, (int64_t)S.zeta, S.vdt);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) return it->second;
+    }
+    int best = kScatterTilesPerWave;
+    float tbest = INFINITY;
+    for (int tpw = 1; tpw <= 16; tpw *= 2) {
+        State T = S;
+        T.nbA = sgks::scatter_blocks(S.m, tpw);
+        T.nbL = sgks::scatter_blocks(S.p, tpw);
+        State TL = T;
+        TL.binA = T.binL;
+        TL.nbA = T.nbL;
+        const float ms = time_launches(st, [&] {
+            sgks::launch_scatter(T, S.u, S.t, st);
+            sgks::launch_cb(T, st);
+            sgks::launch_cb(TL, st);
+        }, 5);
+        if (ms < tbest) {
+            tbest = ms;
+            best = tpw;
+        }
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = best;
+    return best;
+}
+
 }  // namespace
 
 struct sgks_ctx {
@@ -340,6 +396,7 @@ void sgks_default_options(sgks_options* o) {
     o->append_groups = 0;
     o->graph = 1;
     o->autotune = 0;
+    o->gradient_form = SGKS_GRADIENT_MAINTAINED;
     o->stream = nullptr;
 }
 
@@ -369,6 +426,8 @@ int sgks_validate(const sgks_csr* A, const sgks_csr* L, const void* b, double mu
     if (!pow2_lanes(o.lanes_A) || !pow2_lanes(o.lanes_At)) return SGKS_ERR_INVALID_ARG;
     if (o.append_groups < 0) return SGKS_ERR_INVALID_ARG;
     if ((o.graph != 0 && o.graph != 1) || (o.autotune != 0 && o.autotune != 1))
+        return SGKS_ERR_INVALID_ARG;
+    if (o.gradient_form != SGKS_GRADIENT_MAINTAINED && o.gradient_form != SGKS_GRADIENT_DIRECT)
         return SGKS_ERR_INVALID_ARG;
     if (s > sgks::kMaxS || s < 1) return SGKS_ERR_SKETCH_SIZE;
     if (o.sketch_mode == SGKS_SKETCH_SPARSE_SIGN) {
@@ -404,6 +463,7 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
     S.passes = c->opt.qr_passes;
     S.sketch_mode = c->opt.sketch_mode;
     S.vdt = c->opt.value_dtype;
+    S.gradient_form = c->opt.gradient_form;
     S.seed = seed;
     S.mu = mu;
     S.sqrt_mu = sqrt(mu);
@@ -428,17 +488,17 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
                c->opt.lanes_At ? c->opt.lanes_At : choose_lanes(S.A.nnz, S.n)};
     S.Lt = Csr{S.n, S.p, S.L.nnz, nullptr, nullptr, nullptr, choose_lanes(S.L.nnz, S.n)};
 
-    // scatter blocks: about two 64-entry tiles per wave, at most kMaxSketchBlocks per operator
-    auto sk_blocks = [](int64_t rows) {
-        int64_t tiles = (rows + 63) / 64;
-        int64_t nb = (tiles + 2 * sgks::kSketchWaves - 1) / (2 * sgks::kSketchWaves);
-        if (nb < 1) nb = 1;
-        if (nb > sgks::kMaxSketchBlocks) nb = sgks::kMaxSketchBlocks;
-        return (int)nb;
+    // scatter workgroups: kScatterTilesPerWave 64-entry tiles per wave (the
+    // autotuner may choose another count; the partial bins are sized for one)
+    S.nbA = sgks::scatter_blocks(S.m, kScatterTilesPerWave);
+    S.nbL = sgks::scatter_blocks(S.p, kScatterTilesPerWave);
+    const int nbA_max = sgks::scatter_blocks(S.m, 1), nbL_max = sgks::scatter_blocks(S.p, 1);
+    const bool sparse = S.sketch_mode == SGKS_SKETCH_SPARSE_SIGN;
+    auto norm_parts = [](const State& T) {
+        return T.gradient_form == SGKS_GRADIENT_MAINTAINED ? sgks::gradient_blocks(T)
+                                                           : sgks::adjoint_blocks(T);
     };
-    S.nbA = sk_blocks(S.m);
-    S.nbL = sk_blocks(S.p);
-    S.n_norm_part = sgks::adjoint_blocks(S);
+    S.n_norm_part = norm_parts(S);
     int nbFA = 0;
     const int nbF = sgks::forward_blocks(S, true, &nbFA);
     c->nbF_A = nbFA;
@@ -480,6 +540,7 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
     ar.add(&S.t, S.p * 8);
     ar.add(&S.rtmp, S.n * 8);
     ar.add(&S.W, (size_t)S.n * dmax * 8);
+    if (S.gradient_form == SGKS_GRADIENT_MAINTAINED) ar.add(&S.HW, (size_t)S.n * dmax * 8);
     // the small state, together
     ar.add(&S.cs, dmax * 8);
     ar.add(&S.QA, (size_t)s * dmax * 8);
@@ -494,8 +555,13 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
     ar.add(&S.y, dmax * 8);
     ar.add(&S.yprev, dmax * 8);
     ar.add(&S.norm_part, 2048 * 8);   // adjoint workgroups are capped at 2048
-    ar.add(&S.binA, (size_t)S.nbA * s * 8);
-    ar.add(&S.binL, (size_t)S.nbL * s * 8);
+    ar.add(&S.binA, (size_t)nbA_max * s * 8);
+    ar.add(&S.binL, (size_t)nbL_max * s * 8);
+    int16_t *patA = nullptr, *patL = nullptr;
+    if (sparse) {
+        ar.add(&patA, (size_t)S.m * S.zeta * 2);
+        ar.add(&patL, (size_t)S.p * S.zeta * 2);
+    }
     ar.add(&S.wa, s * 8);
     ar.add(&S.wl, s * 8);
     ar.add(&S.wu, 2 * dmax * 8);
@@ -527,6 +593,13 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
     S.Lt.val = c->Lt_val;
     hipStream_t st = c->st;
     c->prof.st = st;
+    if (sparse) {
+        // the sparse-sign pattern, once, from the hash
+        sgks::launch_make_pattern(patA, S.m, s, S.zeta, seed, 0, st);
+        sgks::launch_make_pattern(patL, S.p, s, S.zeta, seed, 1, st);
+        S.patA = patA;
+        S.patL = patL;
+    }
     if (c->opt.autotune) {
         SGKS_TRY(hipMemsetAsync(S.x, 0, S.n * 8, st));
         SGKS_TRY(hipMemsetAsync(S.u, 0, S.m * 8, st));
@@ -535,8 +608,13 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
         S.L.lanes = tune_one(S, 1, st);
         if (!c->opt.lanes_At) S.At.lanes = tune_one(S, 2, st);
         S.Lt.lanes = S.At.lanes;
+        if (sparse) {
+            const int tpw = tune_scatter(S, st);
+            S.nbA = sgks::scatter_blocks(S.m, tpw);
+            S.nbL = sgks::scatter_blocks(S.p, tpw);
+        }
         SGKS_TRY(hipGetLastError());
-        S.n_norm_part = sgks::adjoint_blocks(S);
+        S.n_norm_part = norm_parts(S);
         int nbFA2 = 0;
         const int nbF2 = sgks::forward_blocks(S, true, &nbFA2);
         c->nbF_A = nbFA2;
@@ -587,7 +665,7 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
     // initial basis: orthonormal basis of K_ell(A^T A, A^T b), CGS2 (stored
     // unnormalised with cs[j] = 1 / ||column||)
     sgks::launch_adjoint(S, S.b, nullptr, false, 0.0, S.W, S.norm_part, st);
-    sgks::launch_set_scale(S, 0, true, st);
+    norm_to_scale(c, S.W, 0, true);   // partials of this context's norm layout
     for (int j = 1; j < c->opt.ell; ++j) {
         double* prev = S.W + (size_t)(j - 1) * S.n;
         double* col = S.W + (size_t)j * S.n;
@@ -631,6 +709,9 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
     // sketch and QR-append the initial columns, then y_0
     for (int j = 0; j < c->opt.ell; ++j) {
         sgks::launch_sketch_column(S, j, st);
+        if (S.HW)   // H W[:, j] = A^T (A w) + mu L^T (L w) from the images just formed
+            sgks::launch_adjoint(S, S.u, S.t, true, S.mu, S.HW + (size_t)j * S.n, S.norm_part,
+                                 st);
         if (sgks::plan_append(c->plan, false, st)) {
             sgks_destroy(c);
             return SGKS_ERR_HIP;
@@ -777,11 +858,14 @@ int sgks_profile_read(sgks_ctx* c, double* ms, int64_t* launches) {
 
 int32_t sgks_dim(const sgks_ctx* c) { return c ? c->d_host : 0; }
 
-int sgks_get_lanes(const sgks_ctx* c, int32_t lanes[3]) {
-    if (!c || !lanes) return SGKS_ERR_INVALID_ARG;
-    lanes[0] = c->S.A.lanes;
-    lanes[1] = c->S.L.lanes;
-    lanes[2] = c->S.At.lanes;
+int sgks_get_tuning(const sgks_ctx* c, int32_t out[6]) {
+    if (!c || !out) return SGKS_ERR_INVALID_ARG;
+    out[0] = c->S.A.lanes;
+    out[1] = c->S.L.lanes;
+    out[2] = c->S.At.lanes;
+    out[3] = c->S.nbA;
+    out[4] = c->S.nbL;
+    out[5] = c->groups;
     return SGKS_OK;
 }
 

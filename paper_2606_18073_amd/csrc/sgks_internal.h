@@ -11,13 +11,16 @@ constexpr int kBlock = 256;         // threads per block of the bulk kernels
 constexpr int kWaves = kBlock / 64; // waves per block
 constexpr int kMaxS = 2048;         // largest sketch size (per-wave LDS bins)
 constexpr int kMaxD = 512;          // largest basis dimension
-constexpr int kAppendThreads = 256; // threads per workgroup of the append kernel
+constexpr int kAppendThreads = 256; // threads per workgroup of the append chain kernels
 constexpr int kMaxAppendGroups = 32;  // workgroups of the append kernels
 constexpr int kAppendMaxSlab = 64;    // sketch rows per append workgroup
 constexpr int kSketchBlock = 512;   // threads per block of the sketch kernel
 constexpr int kSketchWaves = kSketchBlock / 64;
 constexpr int kMaxSketchBlocks = 256; // per operator
 constexpr int kMaxBatch = 64;       // problems of one batched launch
+// s * dmax up to which the compact append (one workgroup per side) is chosen;
+// beyond, the bandwidth of one compute unit makes the multi-workgroup chain faster
+constexpr int64_t kCompactAppendMax = 120000;
 
 // Device status word values (mirrors the public codes).
 constexpr int kStatusOk = 0;
@@ -45,6 +48,7 @@ struct State {
     int passes;      // projections per QR append (1 or 2)
     int sketch_mode; // 0 sparse-sign, 1 identity
     int vdt;         // value dtype of A, L
+    int gradient_form; // 0: r from the maintained H W; 1: r = A^T (A x - b) + mu L^T L x directly
     uint64_t seed;
     double mu;
     double sqrt_mu;
@@ -57,6 +61,7 @@ struct State {
     double* t;         // p
     double* rtmp;      // n (refinement gradient, adjoint input)
     double* W;         // n x dmax, column j = r_j (unnormalised), scaled by cs[j]
+    double* HW;        // n x dmax, column j = (A^T A + mu L^T L) W[:, j] (maintained gradient form)
     double* cs;        // dmax column scales (1 / ||column||)
 
     double* QA;        // s x dmax
@@ -76,6 +81,10 @@ struct State {
     double* binA;      // nbA x s partial sketch bins of the A column (one per block)
     double* binL;      // nbL x s partial sketch bins of the L column
     int nbA, nbL;
+    // sparse-sign pattern of S_A (m x zeta) and S_L (p x zeta), computed once
+    // from the hash: entry i*zeta + q = +-(row + 1) (sign of the entry), 0 if none
+    const int16_t* patA;
+    const int16_t* patL;
     double* wa;        // s: working sketched A column of the append
     double* wl;        // s: working sketched L column
     double* wu;        // 2 dmax: working column of the stacked factor
@@ -104,15 +113,19 @@ struct BTab {
 struct Plan {
     const State* SS;
     int np;
-    int vdt, zeta, passes, sketch_mode;
+    int vdt, zeta, passes, sketch_mode, gradient_form;
     int max_s;          // largest sketch size (LDS bins of the scatter)
     int max_gt_rows;    // largest row slab of the W^T v kernel
     BTab fwd;           // k_forward: A rows then L rows
     BTab adj;           // adjoint products
     BTab sc;            // scatter: S_A blocks then S_L blocks
     BTab gemv;          // x = W y
+    BTab grad;          // gradient from H W
     BTab gemvt;         // W^T v partials
-    BTab ap;            // append workgroups
+    BTab ap;            // append chain workgroups (problems with more than one append group)
+    BTab ap_fix;        // one workgroup per chain problem (k_yfix)
+    BTab ap1_side;      // compact append: two workgroups per problem (one append group)
+    BTab ap1_stack;     // compact append: one workgroup per problem
     BTab one;           // one workgroup per problem
 };
 
@@ -131,6 +144,7 @@ void launch_scatter(const State& S, const double* zA, const double* zL, hipStrea
 void launch_gemv(const State& S, const double* coef, double* out, const double* base,
                  int ncols_fixed, hipStream_t st);
 int gemv_blocks(const State& S);
+int gradient_blocks(const State& S);
 void launch_gemvt(const State& S, const double* v, int ncols_fixed, hipStream_t st);
 void launch_reduce_gpart(const State& S, int ncols_fixed, double* out, hipStream_t st);
 void launch_set_scale(const State& S, int col, bool store_r0, hipStream_t st);
@@ -141,6 +155,9 @@ void launch_residual_small(const State& S, double* out2, hipStream_t st);
 void launch_backward_small(const State& S, double* v_out, double* gmu_out, hipStream_t st);
 void launch_sketch_transpose(const State& S, const double* v, double* out, hipStream_t st);
 void launch_copy_scaled_W(const State& S, double* dst, hipStream_t st);
+void launch_make_pattern(int16_t* pat, int64_t rows, int s, int zeta, uint64_t seed, int stream,
+                         hipStream_t st);
+int scatter_blocks(int64_t rows, int tiles_per_wave);
 int transpose_csr(const Csr& M, int vdt, int32_t* rowptrT, int32_t* colT, void* valT,
                   hipStream_t st);
 int max_append_groups();
@@ -150,7 +167,10 @@ int plan_build(Plan& P, const State* host, const State* dev, int np, const int* 
 // one iteration step of every problem of the plan
 void plan_gemv(const Plan& P, hipStream_t st);                 // x = W y
 void plan_forward(const Plan& P, bool newcol, hipStream_t st); // u = A x - b, t = L x / A w, L w
-void plan_adjoint(const Plan& P, bool to_rtmp, hipStream_t st);// r = A^T u + mu L^T t
+// r = A^T u + mu L^T t into the new basis column (0), the refinement gradient
+// (1) or column d of H W (2)
+void plan_adjoint(const Plan& P, int dst_kind, hipStream_t st);
+void plan_gradient(const Plan& P, bool to_rtmp, hipStream_t st);  // r from H W
 void plan_scatter(const Plan& P, hipStream_t st);              // sketch bins of (u, t)
 int plan_append(const Plan& P, bool scale_from_norm, hipStream_t st);
 void plan_gemvt(const Plan& P, hipStream_t st);                // W^T rtmp partials

@@ -66,15 +66,16 @@ __device__ __forceinline__ double strided_sum(const double* __restrict__ p, int6
 }
 
 // sum_k p[k stride] v[k], k < n, in order, sixteen loads in flight
+template <int B = 16>
 __device__ __forceinline__ double strided_dot(const double* __restrict__ p, int64_t stride,
                                               const double* v, int n) {
     double acc = 0.0;
-    for (int k = 0; k < n; k += 16) {
-        double w[16];
+    for (int k = 0; k < n; k += B) {
+        double w[B];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) w[u] = p[(int64_t)min(k + u, n - 1) * stride];
+        for (int u = 0; u < B; ++u) w[u] = p[(int64_t)min(k + u, n - 1) * stride];
 #pragma unroll
-        for (int u = 0; u < 16; ++u)
+        for (int u = 0; u < B; ++u)
             if (k + u < n) acc += w[u] * v[k + u];
     }
     return acc;
@@ -115,6 +116,45 @@ __device__ void tri_mv(const double* __restrict__ M, int64_t rs, int64_t cs, int
         }
         for (int off = tpr / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
         if (k < d && c == 0) out[k] = acc;
+    }
+}
+
+// out1[k] = sum_{j >= k, j < d} M(k, j) v1[j], out2[k] likewise with v2
+// (upper-triangular M, element (i, j) at M[i * rs + j * cs]); the tri_mv
+// scheme with both products sharing the loads of M.
+__device__ void tri_mv2(const double* __restrict__ M, int64_t rs, int64_t cs, int d,
+                        const double* v1, const double* v2, double* out1, double* out2) {
+    const int NT = blockDim.x;
+    int tpr = 64;
+    while (tpr > 1 && NT / tpr < d) tpr >>= 1;
+    const int rpp = NT / tpr;
+    const int c = threadIdx.x % tpr;
+    for (int base = 0; base < d; base += rpp) {
+        const int k = base + threadIdx.x / tpr;
+        double a1 = 0.0, a2 = 0.0;
+        if (k < d) {
+            for (int q = k + c; q < d; q += 8 * tpr) {
+                double w[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) w[u] = M[(int64_t)k * rs + (int64_t)min(q + u * tpr, d - 1) * cs];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int idx = q + u * tpr;
+                    if (idx < d) {
+                        a1 += w[u] * v1[idx];
+                        a2 += w[u] * v2[idx];
+                    }
+                }
+            }
+        }
+        for (int off = tpr / 2; off > 0; off >>= 1) {
+            a1 += __shfl_xor(a1, off);
+            a2 += __shfl_xor(a2, off);
+        }
+        if (k < d && c == 0) {
+            out1[k] = a1;
+            out2[k] = a2;
+        }
     }
 }
 
@@ -313,7 +353,8 @@ __global__ __launch_bounds__(kBlock) void k_forward(Csr A, Csr L, int nbA,
 }
 
 // Iteration form: newcol = 0: u = A x - b, t = L x from the state's x;
-// newcol = 1: u = A w, t = L w for the basis column d (skipped on a set status).
+// newcol = 1: u = A w, t = L w for the basis column d (skipped on a set status),
+// and workgroup 0 also sums ||w||^2 into scal[14].
 template <typename T>
 __global__ __launch_bounds__(kBlock) void kb_forward(const State* __restrict__ SS, BTab tab,
                                                     int newcol) {
@@ -324,6 +365,12 @@ __global__ __launch_bounds__(kBlock) void kb_forward(const State* __restrict__ S
     const double* x = newcol ? S.W + (int64_t)(*S.d) * S.n : S.x;
     forward_body<T>(S.A, S.L, rows_blocks_of(S.A), x, newcol ? nullptr : S.b, S.u, S.t, nullptr,
                     nullptr, sl.blk, red);
+    if (newcol && sl.blk == 0) {
+        // ||r||^2 of the new (unnormalised) column from the adjoint's partial sums,
+        // for the column scale of the append
+        const double t = block_sum(thread_strided_sum(S.norm_part, S.n_norm_part, kBlock), red);
+        if (threadIdx.x == 0) S.scal[14] = t;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -364,17 +411,67 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(Csr At, Csr Lt, int withL, d
     adjoint_body<T>(At, Lt, withL, mu, u, t, dst, n, part, (int)blockIdx.x, (int)gridDim.x, red);
 }
 
-// Iteration form: to_rtmp = 0 writes the new basis column d (skipped on a set
-// status), to_rtmp = 1 writes the refinement gradient.
+// Iteration form, from (u, t):
+//   dst = kDstBasis: the new basis column d (skipped on a set status)
+//   dst = kDstRefine: the refinement gradient
+//   dst = kDstHW: column d of H W = (A^T A + mu L^T L) W from (u, t) = (A w, L w)
+//                 of the new column (skipped on a set status)
+constexpr int kDstBasis = 0, kDstRefine = 1, kDstHW = 2;
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void kb_adjoint(const State* __restrict__ SS, BTab tab,
-                                                    int to_rtmp) {
+                                                    int dst_kind) {
+    __shared__ double red[kWaves];
+    const Slot sl = find_slot(tab);
+    const State S = load_state(SS, sl.p);
+    if (dst_kind != kDstRefine && *S.status != 0) return;
+    double* dst = dst_kind == kDstRefine ? S.rtmp
+                  : dst_kind == kDstHW   ? S.HW + (int64_t)(*S.d) * S.n
+                                         : S.W + (int64_t)(*S.d) * S.n;
+    adjoint_body<T>(S.At, S.Lt, 1, S.mu, S.u, S.t, dst, S.n, S.norm_part, sl.blk, sl.nblk, red);
+}
+
+// ---------------------------------------------------------------------------
+// gradient from the maintained H W (H = A^T A + mu L^T L):
+//   r = A^T (A x - b) + mu L^T L x = sum_j HW[:, j] cs[j] y[j] - W[:, 0],
+// x = W y, W[:, 0] = A^T b (stored unnormalised).  Written to the new basis
+// column d (skipped on a set status) or, to_rtmp, to the refinement gradient;
+// per-workgroup partial sums of r^2 into norm_part.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void kb_gradient(const State* __restrict__ SS, BTab tab,
+                                                     int to_rtmp) {
+    __shared__ double yt[kMaxD];
     __shared__ double red[kWaves];
     const Slot sl = find_slot(tab);
     const State S = load_state(SS, sl.p);
     if (!to_rtmp && *S.status != 0) return;
-    double* dst = to_rtmp ? S.rtmp : S.W + (int64_t)(*S.d) * S.n;
-    adjoint_body<T>(S.At, S.Lt, 1, S.mu, S.u, S.t, dst, S.n, S.norm_part, sl.blk, sl.nblk, red);
+    const int d = *S.d;
+    const int64_t n = S.n;
+    double* __restrict__ dst = to_rtmp ? S.rtmp : S.W + (int64_t)d * n;
+    const double* __restrict__ HW = S.HW;
+    const double* __restrict__ g0 = S.W;
+    for (int j = threadIdx.x; j < d; j += kBlock) yt[j] = S.cs[j] * S.y[j];
+    __syncthreads();
+    double sq = 0.0;
+    for (int64_t i = (int64_t)sl.blk * kBlock + threadIdx.x; i < n; i += (int64_t)sl.nblk * kBlock) {
+        const double* h = HW + i;
+        double acc = 0.0;
+        int j = 0;
+        for (; j + 8 <= d; j += 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = h[(int64_t)(j + u) * n];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += v[u] * yt[j + u];
+        }
+        for (; j < d; ++j) acc += h[(int64_t)j * n] * yt[j];
+        const double r = acc - g0[i];
+        dst[i] = r;
+        sq += r * r;
+    }
+    const double tot = block_sum(sq, red);
+    if (threadIdx.x == 0) S.norm_part[sl.blk] = tot;
 }
 
 // ---------------------------------------------------------------------------
@@ -386,10 +483,51 @@ __global__ __launch_bounds__(kBlock) void kb_adjoint(const State* __restrict__ S
 // column scale); partial bins are merged in fixed orders downstream.
 // ---------------------------------------------------------------------------
 
+// the zeta pattern entries of row i (see State::patA)
+template <int Z>
+__device__ __forceinline__ void load_pattern(const int16_t* __restrict__ pat, int64_t i,
+                                             int* bin, double* sg) {
+    uint32_t w[Z / 2];
+    const uint32_t* p = (const uint32_t*)(pat + i * Z);
+    if constexpr (Z == 2) {
+        w[0] = p[0];
+    } else if constexpr (Z == 4) {
+        const uint2 v = *(const uint2*)p;
+        w[0] = v.x; w[1] = v.y;
+    } else {
+#pragma unroll
+        for (int k = 0; k < Z / 8; ++k) {
+            const uint4 v = ((const uint4*)p)[k];
+            w[4 * k] = v.x; w[4 * k + 1] = v.y; w[4 * k + 2] = v.z; w[4 * k + 3] = v.w;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < Z; ++q) {
+        const int e = (int)(int16_t)((q & 1) ? (w[q / 2] >> 16) : (w[q / 2] & 0xffffu));
+        bin[q] = e > 0 ? e - 1 : (e < 0 ? -e - 1 : 0);
+        sg[q] = e > 0 ? 1.0 : (e < 0 ? -1.0 : 0.0);
+    }
+}
+
+template <int Z>
+__global__ __launch_bounds__(kBlock) void k_make_pattern(int16_t* __restrict__ pat, int64_t rows,
+                                                        int s, uint64_t seed, int stream) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < rows;
+         i += (int64_t)gridDim.x * kBlock) {
+        int bin[Z];
+        double sg[Z];
+        sketch_column<Z>(seed, stream, i, s, bin, sg);
+#pragma unroll
+        for (int q = 0; q < Z; ++q)
+            pat[i * Z + q] = (int16_t)(sg[q] > 0.0 ? bin[q] + 1 : (sg[q] < 0.0 ? -(bin[q] + 1) : 0));
+    }
+}
+
 template <int Z>
 __device__ __forceinline__ void scatter_body(const double* __restrict__ zA, int64_t m,
                                              const double* __restrict__ zL, int64_t p, int nbA,
                                              int nbL, int s, uint64_t seed, int identity,
+                                             const int16_t* patA, const int16_t* patL,
                                              double* partA, double* partL, int blk_all,
                                              double* sm) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -398,6 +536,7 @@ __device__ __forceinline__ void scatter_body(const double* __restrict__ zA, int6
     double* bins = sm + wave * s;
     const bool isA = blk_all < nbA;
     const double* __restrict__ z = isA ? zA : zL;
+    const int16_t* pat = isA ? patA : patL;
     const int64_t rows = isA ? m : p;
     const int blk = isA ? blk_all : blk_all - nbA;
     const int nblk = isA ? nbA : nbL;
@@ -413,7 +552,10 @@ __device__ __forceinline__ void scatter_body(const double* __restrict__ zA, int6
             } else {
                 int bin[Z];
                 double sg[Z];
-                sketch_column<Z>(seed, stream, i, s, bin, sg);
+                if (pat)
+                    load_pattern<Z>(pat, i, bin, sg);
+                else
+                    sketch_column<Z>(seed, stream, i, s, bin, sg);
 #pragma unroll
                 for (int q = 0; q < Z; ++q) atomicAdd(&bins[bin[q]], sg[q] * v);
             }
@@ -434,9 +576,12 @@ __global__ __launch_bounds__(kSketchBlock) void k_scatter(const double* __restri
                                                          const double* __restrict__ zL,
                                                          int64_t p, int nbA, int nbL, int s,
                                                          uint64_t seed, int identity,
-                                                         double* partA, double* partL) {
+                                                         const int16_t* patA,
+                                                         const int16_t* patL, double* partA,
+                                                         double* partL) {
     extern __shared__ double sm[];
-    scatter_body<Z>(zA, m, zL, p, nbA, nbL, s, seed, identity, partA, partL, (int)blockIdx.x, sm);
+    scatter_body<Z>(zA, m, zL, p, nbA, nbL, s, seed, identity, patA, patL, partA, partL,
+                    (int)blockIdx.x, sm);
 }
 
 // Iteration form: the sketch of the new column's images (u, t); skipped on a
@@ -448,8 +593,8 @@ __global__ __launch_bounds__(kSketchBlock) void kb_scatter(const State* __restri
     const Slot sl = find_slot(tab);
     const State S = load_state(SS, sl.p);
     if (*S.status != 0) return;
-    scatter_body<Z>(S.u, S.m, S.t, S.p, S.nbA, S.nbL, S.s, S.seed, S.sketch_mode, S.binA, S.binL,
-                    sl.blk, sm);
+    scatter_body<Z>(S.u, S.m, S.t, S.p, S.nbA, S.nbL, S.s, S.seed, S.sketch_mode, S.patA, S.patL,
+                    S.binA, S.binL, sl.blk, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -696,6 +841,7 @@ __device__ void slab_dots(const double* __restrict__ Ma, const double* __restric
 // out[i] -= sum_j M[j * ld + i] c[j], i < nrows (M global, column-major slab;
 // c, out in LDS).  Threads split rows and contiguous chunks of j; the chunk
 // sums are added in chunk order.
+template <int B = 16>
 __device__ void slab_apply(const double* __restrict__ M, int64_t ld, int nrows, int d,
                            const double* c, double* out, double* scratch) {
     const int T = blockDim.x, tid = threadIdx.x;
@@ -710,7 +856,8 @@ __device__ void slab_apply(const double* __restrict__ M, int64_t ld, int nrows, 
         const int nr = min(nrows - r0, T);
         if (q < nq && i < nrows) {
             const int j0 = (int)((int64_t)d * q / nq), j1 = (int)((int64_t)d * (q + 1) / nq);
-            scratch[q * nr + (i - r0)] = strided_dot(M + (int64_t)j0 * ld + i, ld, c + j0, j1 - j0);
+            scratch[q * nr + (i - r0)] =
+                strided_dot<B>(M + (int64_t)j0 * ld + i, ld, c + j0, j1 - j0);
         }
         __syncthreads();
         if (tid < nr) {
@@ -751,7 +898,7 @@ __global__ __launch_bounds__(kAppendThreads) void k_ap_q0(const State* __restric
     const int g = sl.blk, tid = threadIdx.x, T = kAppendThreads;
     double scale;
     if (scale_from_norm) {
-        const double nr2 = block_sum(thread_strided_sum(S.norm_part, S.n_norm_part, T), sh.red);
+        const double nr2 = S.scal[14];
         const double nr = sqrt(nr2);
         if (!(nr2 < INFINITY)) {
             if (g == 0 && tid == 0) *S.status = kStatusNonfinite;
@@ -1094,6 +1241,276 @@ __global__ __launch_bounds__(1024) void k_yfix(const State* __restrict__ SS, BTa
 }
 
 // ---------------------------------------------------------------------------
+// compact append: one workgroup per sketch side, then one workgroup for the
+// stacked factor.  For modest s and d the whole append fits the bandwidth of a
+// few compute units, and two launches replace the chain above (whose cost is
+// the latency of its seven kernel boundaries and of the reductions between
+// them).  Everything a workgroup reads back is kept in LDS, so no workgroup
+// reads global memory it wrote itself.
+// ---------------------------------------------------------------------------
+
+constexpr int kAp1Threads = 1024;
+
+// out[j] = sum_{i < nr} (Ma[j ld + i] va[i] [+ Mb[j ld + i] vb[i]]) for j < d
+// (va, vb, out in LDS).  Each wave takes four columns at a time, lanes over
+// rows, four row loads per column in flight (two per matrix for two) from
+// clamped addresses; the wave sums in a fixed order.
+template <bool TWO>
+__device__ void wg_col_dots(const double* __restrict__ Ma, const double* __restrict__ Mb,
+                            int64_t ld, int nr, int d, const double* va, const double* vb,
+                            double* out) {
+    constexpr int C = 4, R = TWO ? 2 : 4;   // loads in flight: C R per matrix
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (nr <= 0) {
+        for (int j = threadIdx.x; j < d; j += blockDim.x) out[j] = 0.0;
+        return;
+    }
+    for (int j0 = wave * C; j0 < d; j0 += nw * C) {
+        double acc[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[c] = 0.0;
+        for (int i0 = 0; i0 < nr; i0 += 64 * R) {
+            double wa[C][R], wb[C][R];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const int64_t col = (int64_t)min(j0 + c, d - 1) * ld;
+#pragma unroll
+                for (int u = 0; u < R; ++u) {
+                    const int i = min(i0 + lane + 64 * u, nr - 1);
+                    wa[c][u] = Ma[col + i];
+                    if (TWO) wb[c][u] = Mb[col + i];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < R; ++u) {
+                const int i = i0 + lane + 64 * u;
+                if (i < nr) {
+                    const double a = va[i];
+                    const double b = TWO ? vb[i] : 0.0;
+#pragma unroll
+                    for (int c = 0; c < C; ++c)
+                        acc[c] += TWO ? wa[c][u] * a + wb[c][u] * b : wa[c][u] * a;
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[c] = wave_sum(acc[c]);
+        if (lane == 0)
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                if (j0 + c < d) out[j0 + c] = acc[c];
+    }
+}
+
+// a[i] = scale * sum_b bins[b s + i], i < s; partial-bin blocks split among
+// threads in contiguous chunks added in chunk order.
+__device__ void wg_reduce_bins(const double* __restrict__ bins, int nb, int s, double scale,
+                               double* a, double* scr) {
+    const int T = blockDim.x, tid = threadIdx.x;
+    const int nq = s >= T ? 1 : T / s;
+    if (nq == 1) {
+        for (int i = tid; i < s; i += T) a[i] = scale * strided_sum(bins + i, s, nb);
+    } else {
+        const int i = tid % s, q = tid / s;
+        if (q < nq) {
+            const int b0 = (int)((int64_t)nb * q / nq), b1 = (int)((int64_t)nb * (q + 1) / nq);
+            scr[q * s + i] = strided_sum(bins + (int64_t)b0 * s + i, s, b1 - b0);
+        }
+        __syncthreads();
+        for (int r = tid; r < s; r += T) {
+            double acc = 0.0;
+            for (int qq = 0; qq < nq; ++qq) acc += scr[qq * s + r];
+            a[r] = scale * acc;
+        }
+    }
+    __syncthreads();
+}
+
+struct Ap1Side {
+    double a[kMaxS];
+    double p[kMaxD];     // coefficients of the current projection
+    double pt[kMaxD];    // their sum over the projections
+    double scr[kAp1Threads];
+    double red[kAp1Threads / 64];
+};
+
+// Workgroup 0 of a problem appends to (Q_A, R_A) and d_A, workgroup 1 to
+// (Q_L, R_L): scale of the new column (breakdown test), sketched column from
+// the partial bins, CGS projections, new columns of Q and R.  The column index
+// d is beyond the basis until the stacked step advances d, so these writes
+// are discarded if that step finds the expansion dependent.  rho goes to
+// scal[12 + side] (0 when the column is numerically absent), the projection
+// coefficients to pacc[(2 + side) dmax + j].
+__global__ __launch_bounds__(kAp1Threads) void k_ap1_side(const State* __restrict__ SS, BTab tab,
+                                                         int scale_from_norm) {
+    __shared__ Ap1Side sh;
+    const Slot sl = find_slot(tab);
+    const State S = load_state(SS, sl.p);
+    if (*S.status != 0) return;
+    const int side = sl.blk;
+    const int d = *S.d, s = S.s, dmax = S.dmax, tid = threadIdx.x, T = kAp1Threads;
+    double scale;
+    if (scale_from_norm) {
+        const double nr2 = S.scal[14];
+        const double nr = sqrt(nr2);
+        if (!(nr2 < INFINITY)) {
+            if (side == 0 && tid == 0) *S.status = kStatusNonfinite;
+            return;
+        }
+        if (!(nr > 1e-14 * S.scal[0])) {
+            if (side == 0 && tid == 0) *S.status = kStatusBreakdown;
+            return;
+        }
+        scale = 1.0 / nr;
+        if (side == 0 && tid == 0) S.cs[d] = scale;
+    } else {
+        scale = S.cs[d];
+    }
+    const double bscale = S.sketch_mode == 1 ? scale : scale / sqrt((double)S.zeta);
+    double* Q = side ? S.QL : S.QA;
+    double* R = side ? S.RL : S.RA;
+    wg_reduce_bins(side ? S.binL : S.binA, side ? S.nbL : S.nbA, s, bscale, sh.a, sh.scr);
+    double n2 = 0.0;
+    for (int i = tid; i < s; i += T) n2 += sh.a[i] * sh.a[i];
+    n2 = block_sum(n2, sh.red);
+    for (int pass = 0; pass < S.passes; ++pass) {
+        wg_col_dots<false>(Q, nullptr, s, s, d, sh.a, nullptr, sh.p);
+        __syncthreads();
+        for (int j = tid; j < d; j += T) sh.pt[j] = (pass ? sh.pt[j] : 0.0) + sh.p[j];
+        slab_apply<24>(Q, s, s, d, sh.p, sh.a, sh.scr);
+    }
+    double r2 = 0.0, dl = 0.0;
+    for (int i = tid; i < s; i += T) {
+        r2 += sh.a[i] * sh.a[i];
+        if (side == 0) dl += sh.a[i] * S.cb[i];
+    }
+    r2 = block_sum(r2, sh.red);
+    dl = block_sum(dl, sh.red);
+    double rho = sqrt(r2);
+    const bool deg = !(rho > 1e-14 * sqrt(n2));
+    if (deg) rho = 0.0;
+    const double qs = deg ? 0.0 : 1.0 / rho;
+    for (int i = tid; i < s; i += T) Q[(int64_t)d * s + i] = sh.a[i] * qs;
+    for (int j = tid; j < d; j += T) {
+        R[(int64_t)d * dmax + j] = sh.pt[j];
+        S.pacc[(int64_t)(2 + side) * dmax + j] = sh.pt[j];
+    }
+    if (tid == 0) {
+        R[(int64_t)d * dmax + d] = rho;
+        S.scal[12 + side] = rho;
+        if (side == 0) S.dA[d] = deg ? 0.0 : dl / rho;
+    }
+}
+
+struct Ap1Stack {
+    double cA[kMaxD];    // working stacked column, rows < d of the R_A half
+    double cL[kMaxD];    // rows < d of the sqrt(mu) R_L half
+    double g[kMaxD];     // coefficients of the current projection
+    double gt[kMaxD];    // their sum: the new column of G
+    double hv[kMaxD + 1];
+    double nc[kMaxD + 1];    // new column of G^{-1}
+    double yv[kMaxD + 1];
+    double rv[kMaxD + 1];
+    double tv[kMaxD + 1];
+    double scr[kAp1Threads];
+    double red[kAp1Threads / 64];
+};
+
+// The stacked factor of [R_A; sqrt(mu) R_L] gains the column [p_A; sqrt(mu) p_L]
+// with new-row entries (rho_A, sqrt(mu) rho_L): CGS projections on U, gamma,
+// the new columns of U, G and G^{-1}, h, y = G^{-1} h and one residual
+// correction y <- y + G^{-1} (h - G y); then d advances.  Breakdown when the
+// projected column is dependent.  One workgroup per problem.
+__global__ __launch_bounds__(kAp1Threads) void k_ap1_stack(const State* __restrict__ SS,
+                                                          BTab tab) {
+    __shared__ Ap1Stack sh;
+    const State S = load_state(SS, find_slot(tab).p);
+    if (*S.status != 0) return;
+    const int d = *S.d, dmax = S.dmax, ld2 = 2 * dmax, tid = threadIdx.x, T = kAp1Threads;
+    const double rhoA = S.scal[12], rhoL = S.scal[13];
+    const double dAnew = S.dA[d];
+    const double new2 = rhoA * rhoA + S.mu * rhoL * rhoL;   // new rows, orthogonal to U
+    double c2 = 0.0;
+    for (int j = tid; j < d; j += T) {
+        sh.cA[j] = S.pacc[(int64_t)2 * dmax + j];
+        sh.cL[j] = S.sqrt_mu * S.pacc[(int64_t)3 * dmax + j];
+        sh.hv[j] = S.h[j];
+        c2 += sh.cA[j] * sh.cA[j] + sh.cL[j] * sh.cL[j];
+    }
+    c2 = block_sum(c2, sh.red) + new2;
+    for (int pass = 0; pass < S.passes; ++pass) {
+        wg_col_dots<true>(S.U, S.U + dmax, ld2, d, d, sh.cA, sh.cL, sh.g);
+        __syncthreads();
+        for (int j = tid; j < d; j += T) sh.gt[j] = (pass ? sh.gt[j] : 0.0) + sh.g[j];
+        slab_apply(S.U, ld2, d, d, sh.g, sh.cA, sh.scr);
+        slab_apply(S.U + dmax, ld2, d, d, sh.g, sh.cL, sh.scr);
+    }
+    double gam2 = 0.0, hnum = 0.0;
+    for (int i = tid; i < d; i += T) {
+        gam2 += sh.cA[i] * sh.cA[i] + sh.cL[i] * sh.cL[i];
+        hnum += sh.cA[i] * S.dA[i];
+    }
+    gam2 = block_sum(gam2, sh.red) + new2;
+    hnum = block_sum(hnum, sh.red) + rhoA * dAnew;
+    const double gam = sqrt(gam2);
+    if (!(gam < INFINITY)) {
+        if (tid == 0) *S.status = kStatusNonfinite;
+        return;
+    }
+    if (!(gam > 1e-14 * sqrt(c2))) {
+        // the expansion adds nothing to the projected problem: stop, no append
+        if (tid == 0) *S.status = kStatusBreakdown;
+        return;
+    }
+    const double hnew = hnum / gam;
+    for (int i = tid; i < d; i += T) {
+        S.U[(int64_t)d * ld2 + i] = sh.cA[i] / gam;
+        S.U[(int64_t)d * ld2 + dmax + i] = sh.cL[i] / gam;
+        S.G[(int64_t)i * dmax + d] = sh.gt[i];
+    }
+    if (tid == 0) {
+        S.U[(int64_t)d * ld2 + d] = rhoA / gam;
+        S.U[(int64_t)d * ld2 + dmax + d] = S.sqrt_mu * rhoL / gam;
+        S.G[(int64_t)d * dmax + d] = gam;
+        S.G[(int64_t)dmax * dmax + (int64_t)d * dmax + d] = 1.0 / gam;   // G^{-1}(d, d)
+        S.h[d] = hnew;
+        sh.hv[d] = hnew;
+        sh.nc[d] = 1.0 / gam;
+        const int deg = (rhoA == 0.0 ? 1 : 0) + (rhoL == 0.0 ? 1 : 0);
+        if (deg) *S.degenerate += deg;
+    }
+    // G^{-1} gains column [-G^{-1} g / gam; 1 / gam]; y0 = G^{-1} h.  Columns
+    // below d of G^{-1} are read from memory, column d only from LDS.
+    double* Gi = S.G + (int64_t)dmax * dmax;
+    __syncthreads();
+    tri_mv2(Gi, dmax, 1, d, sh.gt, sh.hv, sh.rv, sh.tv);
+    __syncthreads();
+    for (int r = tid; r < d; r += T) {
+        const double nc = -sh.rv[r] / gam;
+        sh.nc[r] = nc;
+        sh.yv[r] = sh.tv[r] + nc * hnew;
+        Gi[(int64_t)r * dmax + d] = nc;
+    }
+    if (tid == 0) sh.yv[d] = hnew / gam;
+    __syncthreads();
+    // residual correction: t = G y (column d of G from LDS), r = h - t,
+    // y += G^{-1} r (column d of G^{-1} from LDS)
+    tri_mv(S.G, dmax, 1, d, 0, sh.yv, sh.tv);
+    __syncthreads();
+    for (int k = tid; k <= d; k += T)
+        sh.rv[k] = sh.hv[k] - (k < d ? sh.tv[k] + sh.gt[k] * sh.yv[d] : gam * sh.yv[d]);
+    __syncthreads();
+    tri_mv(Gi, dmax, 1, d, 0, sh.rv, sh.tv);
+    __syncthreads();
+    for (int k = tid; k <= d; k += T) {
+        const double yk = sh.yv[k] + (k < d ? sh.tv[k] + sh.nc[k] * sh.rv[d] : sh.nc[d] * sh.rv[d]);
+        S.y[k] = yk;
+        S.yprev[k] = yk;
+    }
+    if (tid == 0) *S.d = d + 1;   // every thread read *S.d before the barriers above
+}
+
+// ---------------------------------------------------------------------------
 // iterative refinement step (heavy ball): g = W^T r from partials,
 // delta = G^{-1} G^{-T} g, y <- y - alpha delta + beta (y - y_prev)
 // ---------------------------------------------------------------------------
@@ -1336,7 +1753,7 @@ void launch_scatter(const State& S, const double* zA, const double* zL, hipStrea
     const int nb = S.nbA + nbL;
 #define SGKS_SC(Zv)                                                                             \
     hipLaunchKernelGGL((k_scatter<Zv>), dim3(nb), dim3(kSketchBlock), shm, st, zA, S.m, zL, S.p, \
-                       S.nbA, nbL, S.s, S.seed, S.sketch_mode, S.binA, S.binL)
+                       S.nbA, nbL, S.s, S.seed, S.sketch_mode, S.patA, S.patL, S.binA, S.binL)
     switch (S.zeta) {
         case 2: SGKS_SC(2); break;
         case 4: SGKS_SC(4); break;
@@ -1346,6 +1763,29 @@ void launch_scatter(const State& S, const double* zA, const double* zL, hipStrea
 #undef SGKS_SC
 }
 
+int scatter_blocks(int64_t rows, int tiles_per_wave) {
+    const int64_t tiles = (rows + 63) / 64;
+    const int64_t per = (int64_t)tiles_per_wave * kSketchWaves;
+    int64_t nb = (tiles + per - 1) / per;
+    if (nb < 1) nb = 1;
+    if (nb > kMaxSketchBlocks) nb = kMaxSketchBlocks;
+    return (int)nb;
+}
+
+void launch_make_pattern(int16_t* pat, int64_t rows, int s, int zeta, uint64_t seed, int stream,
+                         hipStream_t st) {
+    const int nb = grid_for(rows, kBlock, 4096);
+#define SGKS_MP(Zv) \
+    hipLaunchKernelGGL((k_make_pattern<Zv>), dim3(nb), dim3(kBlock), 0, st, pat, rows, s, seed, stream)
+    switch (zeta) {
+        case 2: SGKS_MP(2); break;
+        case 4: SGKS_MP(4); break;
+        case 16: SGKS_MP(16); break;
+        default: SGKS_MP(8); break;
+    }
+#undef SGKS_MP
+}
+
 // z = A w, L w of basis column col into the u, t buffers, then their sketch bins
 void launch_sketch_column(const State& S, int col, hipStream_t st) {
     launch_forward(S, S.W + (int64_t)col * S.n, nullptr, S.u, S.t, true, nullptr, nullptr, st);
@@ -1353,6 +1793,9 @@ void launch_sketch_column(const State& S, int col, hipStream_t st) {
 }
 
 int gemv_blocks(const State& S) { return grid_for(S.n, kBlock, 4096); }
+
+// workgroups of the gradient kernel (one partial sum of ||r||^2 each)
+int gradient_blocks(const State& S) { return grid_for(S.n, kBlock, 2048); }
 
 void launch_gemv(const State& S, const double* coef, double* out, const double* base,
                  int ncols_fixed, hipStream_t st) {
@@ -1384,12 +1827,16 @@ int max_append_groups() {
     return cus > 0 ? cus : 1;
 }
 
+// G = 1 selects the compact append (one workgroup per side, then one for the
+// stacked factor); G > 1 the chain of G-workgroup kernels.
 bool append_groups_ok(int s, int dmax, int G) {
-    return G >= 1 && G <= kMaxAppendGroups && (s + G - 1) / G <= kAppendMaxSlab &&
+    if (G == 1) return s <= kMaxS && dmax <= kMaxD;
+    return G >= 2 && G <= kMaxAppendGroups && (s + G - 1) / G <= kAppendMaxSlab &&
            (dmax + G - 1) / G <= kAppendMaxSlab;
 }
 
 int choose_append_groups(int s, int dmax, int cap) {
+    if ((int64_t)s * dmax <= kCompactAppendMax) return 1;
     int G = (s + 31) / 32;
     if (G < 4) G = 4;
     while ((s + G - 1) / G > kAppendMaxSlab || (dmax + G - 1) / G > kAppendMaxSlab) ++G;
@@ -1461,20 +1908,27 @@ int plan_build(Plan& P, const State* host, const State* dev, int np, const int* 
     P.sketch_mode = host[0].sketch_mode;
     P.max_s = 0;
     P.max_gt_rows = 0;
+    P.gradient_form = host[0].gradient_form;
     int fwd[kMaxBatch], adj[kMaxBatch], sc[kMaxBatch], gv[kMaxBatch], gt[kMaxBatch],
-        ap[kMaxBatch], one[kMaxBatch];
+        ap[kMaxBatch], apf[kMaxBatch], ap1s[kMaxBatch], ap1k[kMaxBatch], one[kMaxBatch],
+        gr[kMaxBatch];
     for (int q = 0; q < np; ++q) {
         const State& S = host[q];
         if (S.vdt != P.vdt || S.zeta != P.zeta || S.passes != P.passes ||
-            S.sketch_mode != P.sketch_mode)
+            S.sketch_mode != P.sketch_mode || S.gradient_form != P.gradient_form)
             return -1;
         if (!append_groups_ok(S.s, S.dmax, groups[q])) return -1;
         fwd[q] = forward_blocks(S, true, nullptr);
         adj[q] = adjoint_blocks(S);
         sc[q] = S.nbA + S.nbL;
         gv[q] = gemv_blocks(S);
+        gr[q] = gradient_blocks(S);
         gt[q] = S.ngt;
-        ap[q] = groups[q];
+        const bool compact = groups[q] == 1;
+        ap[q] = compact ? 0 : groups[q];
+        apf[q] = compact ? 0 : 1;
+        ap1s[q] = compact ? 2 : 0;
+        ap1k[q] = compact ? 1 : 0;
         one[q] = 1;
         P.max_s = S.s > P.max_s ? S.s : P.max_s;
         P.max_gt_rows = S.gt_rows > P.max_gt_rows ? S.gt_rows : P.max_gt_rows;
@@ -1483,8 +1937,12 @@ int plan_build(Plan& P, const State* host, const State* dev, int np, const int* 
     tab_set(P.adj, np, adj);
     tab_set(P.sc, np, sc);
     tab_set(P.gemv, np, gv);
+    tab_set(P.grad, np, gr);
     tab_set(P.gemvt, np, gt);
     tab_set(P.ap, np, ap);
+    tab_set(P.ap_fix, np, apf);
+    tab_set(P.ap1_side, np, ap1s);
+    tab_set(P.ap1_stack, np, ap1k);
     tab_set(P.one, np, one);
     return 0;
 }
@@ -1503,14 +1961,17 @@ void plan_forward(const Plan& P, bool newcol, hipStream_t st) {
                            newcol ? 1 : 0);
 }
 
-void plan_adjoint(const Plan& P, bool to_rtmp, hipStream_t st) {
+void plan_adjoint(const Plan& P, int dst_kind, hipStream_t st) {
     const dim3 grid(tab_total(P.adj));
     if (P.vdt == 0)
-        hipLaunchKernelGGL(kb_adjoint<float>, grid, dim3(kBlock), 0, st, P.SS, P.adj,
-                           to_rtmp ? 1 : 0);
+        hipLaunchKernelGGL(kb_adjoint<float>, grid, dim3(kBlock), 0, st, P.SS, P.adj, dst_kind);
     else
-        hipLaunchKernelGGL(kb_adjoint<double>, grid, dim3(kBlock), 0, st, P.SS, P.adj,
-                           to_rtmp ? 1 : 0);
+        hipLaunchKernelGGL(kb_adjoint<double>, grid, dim3(kBlock), 0, st, P.SS, P.adj, dst_kind);
+}
+
+void plan_gradient(const Plan& P, bool to_rtmp, hipStream_t st) {
+    hipLaunchKernelGGL(kb_gradient, dim3(tab_total(P.grad)), dim3(kBlock), 0, st, P.SS, P.grad,
+                       to_rtmp ? 1 : 0);
 }
 
 void plan_scatter(const Plan& P, hipStream_t st) {
@@ -1528,16 +1989,25 @@ void plan_scatter(const Plan& P, hipStream_t st) {
 }
 
 int plan_append(const Plan& P, bool scale_from_norm, hipStream_t st) {
-    const dim3 grid(tab_total(P.ap)), block(kAppendThreads);
-    hipLaunchKernelGGL(k_ap_q0, grid, block, 0, st, P.SS, P.ap, scale_from_norm ? 1 : 0);
-    for (int pass = 1; pass < P.passes; ++pass)
-        hipLaunchKernelGGL(k_ap_qp, grid, block, 0, st, P.SS, P.ap, pass);
-    hipLaunchKernelGGL(k_ap_qf, grid, block, 0, st, P.SS, P.ap);
-    for (int u = 1; u < P.passes; ++u)
-        hipLaunchKernelGGL(k_ap_u, grid, block, 0, st, P.SS, P.ap, u, 0);
-    hipLaunchKernelGGL(k_ap_u, grid, block, 0, st, P.SS, P.ap, P.passes, 1);
-    hipLaunchKernelGGL(k_ap_commit, grid, block, 0, st, P.SS, P.ap);
-    hipLaunchKernelGGL(k_yfix, dim3(P.np), dim3(1024), 0, st, P.SS, P.one);
+    if (tab_total(P.ap1_side) > 0) {
+        hipLaunchKernelGGL(k_ap1_side, dim3(tab_total(P.ap1_side)), dim3(kAp1Threads), 0, st,
+                           P.SS, P.ap1_side, scale_from_norm ? 1 : 0);
+        hipLaunchKernelGGL(k_ap1_stack, dim3(tab_total(P.ap1_stack)), dim3(kAp1Threads), 0, st,
+                           P.SS, P.ap1_stack);
+    }
+    if (tab_total(P.ap) > 0) {
+        const dim3 grid(tab_total(P.ap)), block(kAppendThreads);
+        hipLaunchKernelGGL(k_ap_q0, grid, block, 0, st, P.SS, P.ap, scale_from_norm ? 1 : 0);
+        for (int pass = 1; pass < P.passes; ++pass)
+            hipLaunchKernelGGL(k_ap_qp, grid, block, 0, st, P.SS, P.ap, pass);
+        hipLaunchKernelGGL(k_ap_qf, grid, block, 0, st, P.SS, P.ap);
+        for (int u = 1; u < P.passes; ++u)
+            hipLaunchKernelGGL(k_ap_u, grid, block, 0, st, P.SS, P.ap, u, 0);
+        hipLaunchKernelGGL(k_ap_u, grid, block, 0, st, P.SS, P.ap, P.passes, 1);
+        hipLaunchKernelGGL(k_ap_commit, grid, block, 0, st, P.SS, P.ap);
+        hipLaunchKernelGGL(k_yfix, dim3(tab_total(P.ap_fix)), dim3(1024), 0, st, P.SS,
+                           P.ap_fix);
+    }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -24,9 +24,12 @@ ERRORS = {
     -6: "ZERO_RHS", -7: "NONFINITE", -8: "HIP", -9: "DEVICE", -10: "INITIAL_SPACE",
 }
 F32, F64 = 0, 1
+GRADIENT_MAINTAINED, GRADIENT_DIRECT = 0, 1
 SKETCH_SPARSE_SIGN, SKETCH_IDENTITY = 0, 1
 PHASES = 8
-PHASE_NAMES = ["gemv_Wy", "forward_Ax_Lx", "adjoint_ATu_LTt", "spmv_new_column",
+# phase 0: x = W y (direct gradient form) or r = (H W) y - A^T b (maintained);
+# phase 2: r = A^T u + mu L^T t (direct) or the new column of H W (maintained)
+PHASE_NAMES = ["gemv", "forward_Ax_Lx", "adjoint", "spmv_new_column",
                "qr_append_solve", "gemvt_WTr", "refine_step", "sketch_scatter"]
 STATE = {"W": 0, "y": 1, "Q_A": 2, "R_A": 3, "Q_L": 4, "R_L": 5, "d_A": 6, "G": 7, "c_b": 8}
 
@@ -48,7 +51,8 @@ class Options(ctypes.Structure):
                 ("refine_steps", ctypes.c_int32), ("qr_passes", ctypes.c_int32),
                 ("sketch_mode", ctypes.c_int32), ("lanes_A", ctypes.c_int32),
                 ("lanes_At", ctypes.c_int32), ("append_groups", ctypes.c_int32),
-                ("graph", ctypes.c_int32), ("autotune", ctypes.c_int32),
+                ("graph", ctypes.c_int32), ("gradient_form", ctypes.c_int32),
+                ("autotune", ctypes.c_int32),
                 ("stream", ctypes.c_void_p)]
 
 
@@ -101,8 +105,8 @@ def load_library(path=LIB_PATH):
     L.sgks_profile_read.restype = ctypes.c_int
     L.sgks_dim.argtypes = [ctypes.c_void_p]
     L.sgks_dim.restype = ctypes.c_int32
-    L.sgks_get_lanes.argtypes = [ctypes.c_void_p, P(ctypes.c_int32)]
-    L.sgks_get_lanes.restype = ctypes.c_int
+    L.sgks_get_tuning.argtypes = [ctypes.c_void_p, P(ctypes.c_int32)]
+    L.sgks_get_tuning.restype = ctypes.c_int
     L.sgks_batch_create.argtypes = [ctypes.c_int32, P(ProblemStruct), P(Options),
                                     P(ctypes.c_void_p)]
     L.sgks_batch_create.restype = ctypes.c_int
@@ -174,7 +178,7 @@ def _check(code, where):
 
 def make_options(lib, vdt, stream, *, ell=3, max_iters=200, zeta=8, refine_steps=0, qr_passes=2,
                  sketch="sparse_sign", lanes_A=0, lanes_At=0, append_groups=0, graph=True,
-                 autotune=False):
+                 autotune=False, gradient="maintained"):
     o = Options()
     lib.sgks_default_options(ctypes.byref(o))
     o.ell, o.max_iters, o.zeta, o.value_dtype = ell, max_iters, zeta, vdt
@@ -182,6 +186,7 @@ def make_options(lib, vdt, stream, *, ell=3, max_iters=200, zeta=8, refine_steps
     o.sketch_mode = SKETCH_IDENTITY if sketch == "identity" else SKETCH_SPARSE_SIGN
     o.lanes_A, o.lanes_At, o.append_groups = lanes_A, lanes_At, append_groups
     o.graph, o.autotune = int(bool(graph)), int(bool(autotune))
+    o.gradient_form = GRADIENT_DIRECT if gradient == "direct" else GRADIENT_MAINTAINED
     o.stream = ctypes.c_void_p(stream.cuda_stream)
     return o
 
@@ -260,11 +265,19 @@ class SGKS:
     def dim(self):
         return int(self._lib.sgks_dim(self._h))
 
+    def tuning(self):
+        """Launch shapes in use: lanes per row of A, L, A^T/L^T; scatter workgroups over
+        S_A's and S_L's columns; append groups (1 = compact)."""
+        v = (ctypes.c_int32 * 6)()
+        _check(self._lib.sgks_get_tuning(self._h, v), "sgks_get_tuning")
+        keys = ("lanes_A", "lanes_L", "lanes_At", "scatter_blocks_A", "scatter_blocks_L",
+                "append_groups")
+        return dict(zip(keys, v))
+
     def lanes(self):
         """Lanes per CSR row in use: (rows of A, rows of L, rows of A^T / L^T)."""
-        v = (ctypes.c_int32 * 3)()
-        _check(self._lib.sgks_get_lanes(self._h, v), "sgks_get_lanes")
-        return tuple(v)
+        t = self.tuning()
+        return t["lanes_A"], t["lanes_L"], t["lanes_At"]
 
     @classmethod
     def _borrowed(cls, owner, handle, A, L, b, mu, s, seed, ell, stream):

@@ -27,6 +27,7 @@ def test_default_options(lib):
     assert (o.ell, o.max_iters, o.zeta, o.qr_passes, o.value_dtype) == (3, 200, 8, 2, G.F64)
     assert o.sketch_mode == G.SKETCH_SPARSE_SIGN and o.refine_steps == 0
     assert (o.graph, o.autotune, o.lanes_A, o.lanes_At, o.append_groups) == (1, 0, 0, 0, 0)
+    assert o.gradient_form == G.GRADIENT_MAINTAINED
 
 
 def _csr(rows, cols, nnz):
@@ -60,6 +61,7 @@ def test_validation_codes(lib):
     assert _v(lib, A, L, lanes_A=3) == -1
     assert _v(lib, A, L, graph=2) == -1
     assert _v(lib, A, L, autotune=-1) == -1
+    assert _v(lib, A, L, gradient_form=2) == -1
     assert _v(lib, A, L, max_iters=600, s=2000) == -5           # capacity above 512 columns
     assert _v(lib, A, L, b=0) == -1                             # null b
     assert _v(lib, _csr(0, 80, 0), L) == -2                     # empty A
@@ -89,7 +91,7 @@ def test_null_batch_handles_are_rejected(lib):
     assert lib.sgks_batch_count(None) == 0
     assert lib.sgks_batch_profile_enable(None, 1) == -1
     assert lib.sgks_batch_profile_read(None, None, None) == -1
-    assert lib.sgks_get_lanes(None, None) == -1
+    assert lib.sgks_get_tuning(None, None) == -1
     lib.sgks_batch_destroy(None)
 
 

@@ -155,6 +155,7 @@ def test_autotune_lanes_and_parity():
     # reproduces the first bit for bit
     S2 = G.SGKS(A, L, b, P.mu, P.s, P.seed, max_iters=P.k, autotune=True)
     assert S2.lanes() == lanes
+    assert S2.tuning() == S.tuning()
     S2.iterate(P.k)
     assert np.array_equal(S.solution().cpu().numpy(), S2.solution().cpu().numpy())
     S.close()

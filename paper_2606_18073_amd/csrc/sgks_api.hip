@@ -109,14 +109,11 @@ int enqueue_iteration(const sgks::Plan& P, int refine_steps, Profiler* pr, hipSt
     }
     { Phase ph(pr, 3); sgks::plan_forward(P, true, st); }
     { Phase ph(pr, 7); sgks::plan_scatter(P, st); }
-    if (maintained) {
-        // column d of H W, before the append advances d
-        Phase ph(pr, 2);
-        sgks::plan_adjoint(P, 2, st);
-    }
     {
+        // maintained form: column d of H W is added by the append's first
+        // launch, beside the side appends (before d advances)
         Phase ph(pr, 4);
-        if (sgks::plan_append(P, true, st)) return SGKS_ERR_HIP;
+        if (sgks::plan_append(P, true, maintained, st)) return SGKS_ERR_HIP;
     }
     for (int r = 0; r < refine_steps; ++r) enqueue_refine(P, pr, st);
     return SGKS_OK;
@@ -712,7 +709,7 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
         if (S.HW)   // H W[:, j] = A^T (A w) + mu L^T (L w) from the images just formed
             sgks::launch_adjoint(S, S.u, S.t, true, S.mu, S.HW + (size_t)j * S.n, S.norm_part,
                                  st);
-        if (sgks::plan_append(c->plan, false, st)) {
+        if (sgks::plan_append(c->plan, false, false, st)) {
             sgks_destroy(c);
             return SGKS_ERR_HIP;
         }

@@ -126,6 +126,8 @@ struct Plan {
     BTab ap_fix;        // one workgroup per chain problem (k_yfix)
     BTab ap1_side;      // compact append: two workgroups per problem (one append group)
     BTab ap1_stack;     // compact append: one workgroup per problem
+    BTab ap1_side_hw;   // compact append with the H W column: 2 + hw_blocks per problem
+    BTab adj_hw_chain;  // H W column of the chain problems (adjoint workgroups)
     BTab one;           // one workgroup per problem
 };
 
@@ -145,6 +147,7 @@ void launch_gemv(const State& S, const double* coef, double* out, const double* 
                  int ncols_fixed, hipStream_t st);
 int gemv_blocks(const State& S);
 int gradient_blocks(const State& S);
+int hw_blocks(const State& S);
 void launch_gemvt(const State& S, const double* v, int ncols_fixed, hipStream_t st);
 void launch_reduce_gpart(const State& S, int ncols_fixed, double* out, hipStream_t st);
 void launch_set_scale(const State& S, int col, bool store_r0, hipStream_t st);
@@ -172,7 +175,8 @@ void plan_forward(const Plan& P, bool newcol, hipStream_t st); // u = A x - b, t
 void plan_adjoint(const Plan& P, int dst_kind, hipStream_t st);
 void plan_gradient(const Plan& P, bool to_rtmp, hipStream_t st);  // r from H W
 void plan_scatter(const Plan& P, hipStream_t st);              // sketch bins of (u, t)
-int plan_append(const Plan& P, bool scale_from_norm, hipStream_t st);
+// with_hw (maintained gradient form): also add column d of H W from (u, t)
+int plan_append(const Plan& P, bool scale_from_norm, bool with_hw, hipStream_t st);
 void plan_gemvt(const Plan& P, hipStream_t st);                // W^T rtmp partials
 void plan_refine(const Plan& P, hipStream_t st);
 

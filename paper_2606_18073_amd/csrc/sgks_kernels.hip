@@ -287,6 +287,16 @@ __device__ __forceinline__ Slot find_slot(const BTab& t) {
     return Slot{lo, b - t.pref[lo], t.pref[lo + 1] - t.pref[lo]};
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Logical index of workgroup j of n: the workgroups of one XCD get
+// consecutive logical indices, hence neighbouring rows, so the vector entries
+// their rows gather stay in that XCD's L2 (a bijection on [0, n)).
+__device__ __forceinline__ int xcd_order(int j, int n) {
+    constexpr int X = 8;
+    const int q = n / X, r = n % X, k = j % X;
+    return k * q + min(k, r) + j / X;
+}
+
 __device__ __forceinline__ int rows_blocks_of(const Csr& M) {
     const uint32_t per = (uint32_t)(kBlock / M.lanes);   // rows < 2^31: 32-bit arithmetic
     return (int)(((uint32_t)M.rows + per - 1u) / per);
@@ -311,7 +321,7 @@ __device__ __forceinline__ State load_state(const State* SS, int p) {
 // ---------------------------------------------------------------------------
 
 template <typename T>
-__device__ __forceinline__ void forward_body(const Csr& A, const Csr& L, int nbA,
+__device__ __forceinline__ void forward_body(const Csr& A, const Csr& L, int nbA, int nb_all,
                                              const double* __restrict__ x,
                                              const double* __restrict__ b,
                                              double* __restrict__ u, double* __restrict__ t,
@@ -319,7 +329,7 @@ __device__ __forceinline__ void forward_body(const Csr& A, const Csr& L, int nbA
                                              double* red) {
     const bool isA = blk_all < nbA;
     const Csr& M = isA ? A : L;
-    const int blk = isA ? blk_all : blk_all - nbA;
+    const int blk = isA ? xcd_order(blk_all, nbA) : xcd_order(blk_all - nbA, nb_all - nbA);
     double* out = isA ? u : t;
     const double* sub = isA ? b : nullptr;
     double* part = isA ? upart : tpart;
@@ -349,7 +359,7 @@ __global__ __launch_bounds__(kBlock) void k_forward(Csr A, Csr L, int nbA,
                                                    double* __restrict__ u, double* __restrict__ t,
                                                    double* upart, double* tpart) {
     __shared__ double red[kWaves];
-    forward_body<T>(A, L, nbA, x, b, u, t, upart, tpart, (int)blockIdx.x, red);
+    forward_body<T>(A, L, nbA, (int)gridDim.x, x, b, u, t, upart, tpart, (int)blockIdx.x, red);
 }
 
 // Iteration form: newcol = 0: u = A x - b, t = L x from the state's x;
@@ -363,8 +373,8 @@ __global__ __launch_bounds__(kBlock) void kb_forward(const State* __restrict__ S
     const State S = load_state(SS, sl.p);
     if (newcol && *S.status != 0) return;
     const double* x = newcol ? S.W + (int64_t)(*S.d) * S.n : S.x;
-    forward_body<T>(S.A, S.L, rows_blocks_of(S.A), x, newcol ? nullptr : S.b, S.u, S.t, nullptr,
-                    nullptr, sl.blk, red);
+    forward_body<T>(S.A, S.L, rows_blocks_of(S.A), sl.nblk, x, newcol ? nullptr : S.b, S.u, S.t,
+                    nullptr, nullptr, sl.blk, red);
     if (newcol && sl.blk == 0) {
         // ||r||^2 of the new (unnormalised) column from the adjoint's partial sums,
         // for the column scale of the append
@@ -378,27 +388,36 @@ __global__ __launch_bounds__(kBlock) void kb_forward(const State* __restrict__ S
 // partial sums of r^2 (grid-stride over the n rows)
 // ---------------------------------------------------------------------------
 
-template <typename T>
+template <typename T, int NT = kBlock>
 __device__ __forceinline__ void adjoint_body(const Csr& At, const Csr& Lt, int withL, double mu,
                                              const double* __restrict__ u,
                                              const double* __restrict__ t,
                                              double* __restrict__ dst, int64_t n, double* part,
                                              int blk, int nblk, double* red) {
     double sq = 0.0;
+    const int lb = xcd_order(blk, nblk);
     SGKS_LANES_SWITCH(At.lanes, {
+        // workgroup lb takes a contiguous range of row groups of NT / V rows
+        constexpr int rpg = NT / V;
+        const int64_t ng = (n + rpg - 1) / rpg;
+        const int64_t g0 = ng * lb / nblk, g1 = ng * (lb + 1) / nblk;
         const int g = threadIdx.x % V;
-        for (int64_t row = (int64_t)blk * (kBlock / V) + threadIdx.x / V; row < n;
-             row += (int64_t)nblk * (kBlock / V)) {
-            double v = row_dot<V, T>(At, u, row, g);
-            if (withL) v += mu * row_dot<V, T>(Lt, t, row, g);
-            if (g == 0) {
-                dst[row] = v;
-                sq += v * v;
+        for (int64_t grp = g0; grp < g1; ++grp) {
+            const int64_t row = grp * rpg + threadIdx.x / V;
+            if (row < n) {
+                double v = row_dot<V, T>(At, u, row, g);
+                if (withL) v += mu * row_dot<V, T>(Lt, t, row, g);
+                if (g == 0) {
+                    dst[row] = v;
+                    sq += v * v;
+                }
             }
         }
     })
-    const double tot = block_sum(sq, red);
-    if (threadIdx.x == 0) part[blk] = tot;
+    if (part) {
+        const double tot = block_sum(sq, red);
+        if (threadIdx.x == 0) part[lb] = tot;
+    }
 }
 
 template <typename T>
@@ -1341,13 +1360,7 @@ struct Ap1Side {
 // are discarded if that step finds the expansion dependent.  rho goes to
 // scal[12 + side] (0 when the column is numerically absent), the projection
 // coefficients to pacc[(2 + side) dmax + j].
-__global__ __launch_bounds__(kAp1Threads) void k_ap1_side(const State* __restrict__ SS, BTab tab,
-                                                         int scale_from_norm) {
-    __shared__ Ap1Side sh;
-    const Slot sl = find_slot(tab);
-    const State S = load_state(SS, sl.p);
-    if (*S.status != 0) return;
-    const int side = sl.blk;
+__device__ void ap1_side_body(const State& S, int side, int scale_from_norm, Ap1Side& sh) {
     const int d = *S.d, s = S.s, dmax = S.dmax, tid = threadIdx.x, T = kAp1Threads;
     double scale;
     if (scale_from_norm) {
@@ -1399,6 +1412,35 @@ __global__ __launch_bounds__(kAp1Threads) void k_ap1_side(const State* __restric
         R[(int64_t)d * dmax + d] = rho;
         S.scal[12 + side] = rho;
         if (side == 0) S.dA[d] = deg ? 0.0 : dl / rho;
+    }
+}
+
+
+__global__ __launch_bounds__(kAp1Threads) void k_ap1_side(const State* __restrict__ SS, BTab tab,
+                                                         int scale_from_norm) {
+    __shared__ Ap1Side sh;
+    const Slot sl = find_slot(tab);
+    const State S = load_state(SS, sl.p);
+    if (*S.status != 0) return;
+    ap1_side_body(S, sl.blk, scale_from_norm, sh);
+}
+
+// The side appends (workgroups 0 and 1 of each problem) together with the
+// adjoint products that add column d of H W from (u, t) = (A w, L w) (the
+// remaining workgroups): independent work in one launch, so the bandwidth-
+// bound SpMV runs beside the two latency-bound appends.
+template <typename T>
+__global__ __launch_bounds__(kAp1Threads) void k_ap1_side_hw(const State* __restrict__ SS,
+                                                            BTab tab, int scale_from_norm) {
+    __shared__ Ap1Side sh;
+    const Slot sl = find_slot(tab);
+    const State S = load_state(SS, sl.p);
+    if (*S.status != 0) return;
+    if (sl.blk < 2) {
+        ap1_side_body(S, sl.blk, scale_from_norm, sh);
+    } else {
+        adjoint_body<T, kAp1Threads>(S.At, S.Lt, 1, S.mu, S.u, S.t, S.HW + (int64_t)(*S.d) * S.n,
+                                     S.n, nullptr, sl.blk - 2, sl.nblk - 2, sh.red);
     }
 }
 
@@ -1797,6 +1839,11 @@ int gemv_blocks(const State& S) { return grid_for(S.n, kBlock, 4096); }
 // workgroups of the gradient kernel (one partial sum of ||r||^2 each)
 int gradient_blocks(const State& S) { return grid_for(S.n, kBlock, 2048); }
 
+// adjoint workgroups (kAp1Threads threads) beside the compact side appends
+int hw_blocks(const State& S) {
+    return grid_for(S.n * (int64_t)S.At.lanes, kAp1Threads, 1024);
+}
+
 void launch_gemv(const State& S, const double* coef, double* out, const double* base,
                  int ncols_fixed, hipStream_t st) {
     hipLaunchKernelGGL(k_gemv, dim3(gemv_blocks(S)), dim3(kBlock), 0, st, S.W, S.cs, coef, S.d,
@@ -1911,7 +1958,7 @@ int plan_build(Plan& P, const State* host, const State* dev, int np, const int* 
     P.gradient_form = host[0].gradient_form;
     int fwd[kMaxBatch], adj[kMaxBatch], sc[kMaxBatch], gv[kMaxBatch], gt[kMaxBatch],
         ap[kMaxBatch], apf[kMaxBatch], ap1s[kMaxBatch], ap1k[kMaxBatch], one[kMaxBatch],
-        gr[kMaxBatch];
+        gr[kMaxBatch], ap1h[kMaxBatch], ahc[kMaxBatch];
     for (int q = 0; q < np; ++q) {
         const State& S = host[q];
         if (S.vdt != P.vdt || S.zeta != P.zeta || S.passes != P.passes ||
@@ -1929,6 +1976,9 @@ int plan_build(Plan& P, const State* host, const State* dev, int np, const int* 
         apf[q] = compact ? 0 : 1;
         ap1s[q] = compact ? 2 : 0;
         ap1k[q] = compact ? 1 : 0;
+        const bool hw = S.gradient_form == 0;
+        ap1h[q] = compact ? 2 + (hw ? hw_blocks(S) : 0) : 0;
+        ahc[q] = (!compact && hw) ? adjoint_blocks(S) : 0;
         one[q] = 1;
         P.max_s = S.s > P.max_s ? S.s : P.max_s;
         P.max_gt_rows = S.gt_rows > P.max_gt_rows ? S.gt_rows : P.max_gt_rows;
@@ -1943,6 +1993,8 @@ int plan_build(Plan& P, const State* host, const State* dev, int np, const int* 
     tab_set(P.ap_fix, np, apf);
     tab_set(P.ap1_side, np, ap1s);
     tab_set(P.ap1_stack, np, ap1k);
+    tab_set(P.ap1_side_hw, np, ap1h);
+    tab_set(P.adj_hw_chain, np, ahc);
     tab_set(P.one, np, one);
     return 0;
 }
@@ -1988,10 +2040,28 @@ void plan_scatter(const Plan& P, hipStream_t st) {
 #undef SGKS_SC
 }
 
-int plan_append(const Plan& P, bool scale_from_norm, hipStream_t st) {
+int plan_append(const Plan& P, bool scale_from_norm, bool with_hw, hipStream_t st) {
+    with_hw = with_hw && P.gradient_form == 0;
+    if (with_hw && tab_total(P.adj_hw_chain) > 0) {
+        const dim3 grid(tab_total(P.adj_hw_chain));
+        if (P.vdt == 0)
+            hipLaunchKernelGGL(kb_adjoint<float>, grid, dim3(kBlock), 0, st, P.SS, P.adj_hw_chain,
+                               kDstHW);
+        else
+            hipLaunchKernelGGL(kb_adjoint<double>, grid, dim3(kBlock), 0, st, P.SS,
+                               P.adj_hw_chain, kDstHW);
+    }
     if (tab_total(P.ap1_side) > 0) {
-        hipLaunchKernelGGL(k_ap1_side, dim3(tab_total(P.ap1_side)), dim3(kAp1Threads), 0, st,
-                           P.SS, P.ap1_side, scale_from_norm ? 1 : 0);
+        const int sfn = scale_from_norm ? 1 : 0;
+        if (!with_hw)
+            hipLaunchKernelGGL(k_ap1_side, dim3(tab_total(P.ap1_side)), dim3(kAp1Threads), 0, st,
+                               P.SS, P.ap1_side, sfn);
+        else if (P.vdt == 0)
+            hipLaunchKernelGGL(k_ap1_side_hw<float>, dim3(tab_total(P.ap1_side_hw)),
+                               dim3(kAp1Threads), 0, st, P.SS, P.ap1_side_hw, sfn);
+        else
+            hipLaunchKernelGGL(k_ap1_side_hw<double>, dim3(tab_total(P.ap1_side_hw)),
+                               dim3(kAp1Threads), 0, st, P.SS, P.ap1_side_hw, sfn);
         hipLaunchKernelGGL(k_ap1_stack, dim3(tab_total(P.ap1_stack)), dim3(kAp1Threads), 0, st,
                            P.SS, P.ap1_stack);
     }

@@ -302,6 +302,7 @@ struct sgks_ctx {
     int nbF_A, nbF_L;
     double* coefbuf;     // dmax scratch
     double* sbuf;        // s scratch
+    double* init_norms;  // copy of the scalars after the initial basis (checked at the end of create)
     int32_t* At_rowptr;
     int32_t* At_col;
     void* At_val;
@@ -575,10 +576,13 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
     ar.add(&c->tpart, ((S.p + 3) / 4 + 1) * 8);
     ar.add(&c->coefbuf, dmax * 8);
     ar.add(&c->sbuf, s * 8);
+    ar.add(&c->init_norms, (16 + 2 * dmax) * 8);
     ar.add(&c->Sdev, sizeof(State));
     SGKS_TRY(ar.commit(c));
-    if (sgks::transpose_csr(S.A, S.vdt, c->At_rowptr, c->At_col, c->At_val, c->st) ||
-        sgks::transpose_csr(S.L, S.vdt, c->Lt_rowptr, c->Lt_col, c->Lt_val, c->st)) {
+    // the transposes' sort scratch lives in W (and HW), unused until they are built
+    const size_t wbytes = (size_t)S.n * dmax * 8 * (S.HW ? 2 : 1);
+    if (sgks::transpose_csr(S.A, S.vdt, c->At_rowptr, c->At_col, c->At_val, S.W, wbytes, c->st) ||
+        sgks::transpose_csr(S.L, S.vdt, c->Lt_rowptr, c->Lt_col, c->Lt_val, S.W, wbytes, c->st)) {
         sgks_destroy(c);
         return SGKS_ERR_HIP;
     }
@@ -640,20 +644,11 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
     SGKS_TRY(hipMemsetAsync(S.status, 0, 64, st));
     SGKS_TRY(hipMemsetAsync(S.degenerate, 0, 64, st));
 
-    // b in FP64, finiteness and zero checks
+    // b in FP64 and ||b||^2 (checked with everything else after the one
+    // synchronisation at the end: a zero or non-finite b only makes the
+    // set-up kernels compute zeros or NaNs)
     sgks::launch_to_f64(b, S.vdt, (double*)S.b, S.m, S.norm_part, S.n_norm_part, st);
     sgks::launch_sum_parts(S.norm_part, S.n_norm_part, S.scal + 2, st);
-    double bn2 = 0.0;
-    SGKS_TRY(hipMemcpyAsync(&bn2, S.scal + 2, 8, hipMemcpyDeviceToHost, st));
-    SGKS_TRY(hipStreamSynchronize(st));
-    if (!(bn2 < INFINITY)) {
-        sgks_destroy(c);
-        return SGKS_ERR_NONFINITE;
-    }
-    if (!(bn2 > 0.0)) {
-        sgks_destroy(c);
-        return SGKS_ERR_ZERO_RHS;
-    }
 
     // c_b = S_A b
     sgks::launch_scatter(S, S.b, nullptr, st);
@@ -678,30 +673,9 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
         }
         norm_to_scale(c, col, j, false);
     }
-    std::vector<double> sc(16 + 2 * dmax, 0.0);
-    SGKS_TRY(hipMemcpyAsync(sc.data(), S.scal, sc.size() * 8, hipMemcpyDeviceToHost, st));
-    SGKS_TRY(hipStreamSynchronize(st));
-    const double r0 = sc[0];
-    if (!(r0 < INFINITY)) {
-        sgks_destroy(c);
-        return SGKS_ERR_NONFINITE;
-    }
-    if (!(r0 > 0.0)) {
-        sgks_destroy(c);
-        return SGKS_ERR_ZERO_RHS;
-    }
-    for (int j = 1; j < c->opt.ell; ++j) {
-        // after / before the projections, squared norms vs norms
-        const double after = sc[16 + j], before = sqrt(sc[16 + dmax + j]);
-        if (!(after < INFINITY) || !(before < INFINITY)) {
-            sgks_destroy(c);
-            return SGKS_ERR_NONFINITE;
-        }
-        if (!(after > 1e-12 * before)) {
-            sgks_destroy(c);
-            return SGKS_ERR_INITIAL_SPACE;
-        }
-    }
+    // the initial norms, before the appends overwrite the scratch scalars
+    SGKS_TRY(hipMemcpyAsync(c->init_norms, S.scal, (16 + 2 * dmax) * 8, hipMemcpyDeviceToDevice,
+                            st));
 
     // sketch and QR-append the initial columns, then y_0
     for (int j = 0; j < c->opt.ell; ++j) {
@@ -716,10 +690,35 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
     }
     for (int r = 0; r < c->opt.refine_steps; ++r) enqueue_refine(c->plan, nullptr, st);
     c->d_host = c->opt.ell;
-    const int stw = sync_status(c);
-    if (stw != 0) {
+
+    // the one synchronisation of the set-up: ||b||^2, the initial norms and the status
+    std::vector<double> sc(16 + 2 * dmax, 0.0);
+    int stw = 0;
+    SGKS_TRY(hipMemcpyAsync(sc.data(), c->init_norms, sc.size() * 8, hipMemcpyDeviceToHost, st));
+    SGKS_TRY(hipMemcpyAsync(&stw, S.status, sizeof(int), hipMemcpyDeviceToHost, st));
+    SGKS_TRY(hipStreamSynchronize(st));
+    int err = SGKS_OK;
+    const double bn2 = sc[2], r0 = sc[0];
+    if (!(bn2 < INFINITY))
+        err = SGKS_ERR_NONFINITE;
+    else if (!(bn2 > 0.0))
+        err = SGKS_ERR_ZERO_RHS;
+    else if (!(r0 < INFINITY))
+        err = SGKS_ERR_NONFINITE;
+    else if (!(r0 > 0.0))
+        err = SGKS_ERR_ZERO_RHS;
+    for (int j = 1; j < c->opt.ell && err == SGKS_OK; ++j) {
+        // after / before the projections, squared norms vs norms
+        const double after = sc[16 + j], before = sqrt(sc[16 + dmax + j]);
+        if (!(after < INFINITY) || !(before < INFINITY))
+            err = SGKS_ERR_NONFINITE;
+        else if (!(after > 1e-12 * before))
+            err = SGKS_ERR_INITIAL_SPACE;
+    }
+    if (err == SGKS_OK && stw != 0) err = stw == SGKS_BREAKDOWN ? SGKS_ERR_INITIAL_SPACE : stw;
+    if (err != SGKS_OK) {
         sgks_destroy(c);
-        return stw == SGKS_BREAKDOWN ? SGKS_ERR_INITIAL_SPACE : stw;
+        return err;
     }
     *out = c;
     return SGKS_OK;

@@ -1687,13 +1687,18 @@ __global__ __launch_bounds__(kBlock) void k_scaled_W(const double* __restrict__ 
 // CSR transpose (stable: entries of a transposed row keep increasing order)
 // ---------------------------------------------------------------------------
 
+// rowid[k] = row of entry k, iota[k] = k; sixteen lanes per row write its
+// entries contiguously
 __global__ __launch_bounds__(kBlock) void k_row_ids(const int32_t* __restrict__ rowptr,
                                                    int64_t rows, int32_t* __restrict__ rowid,
                                                    int32_t* __restrict__ iota) {
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < rows;
-         i += (int64_t)gridDim.x * kBlock) {
-        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-            rowid[k] = (int32_t)i;
+    constexpr int V = 16;
+    const int g = threadIdx.x % V;
+    for (int64_t r = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / V; r < rows;
+         r += (int64_t)gridDim.x * (kBlock / V)) {
+        const int b = rowptr[r], e = rowptr[r + 1];
+        for (int k = b + g; k < e; k += V) {
+            rowid[k] = (int32_t)r;
             iota[k] = k;
         }
     }
@@ -2091,33 +2096,37 @@ void plan_refine(const Plan& P, hipStream_t st) {
 }
 
 int transpose_csr(const Csr& M, int vdt, int32_t* rowptrT, int32_t* colT, void* valT,
-                  hipStream_t st) {
+                  void* scratch, size_t scratch_bytes, hipStream_t st) {
     const int64_t nnz = M.nnz;
     if (nnz == 0) {
         hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(M.cols + 1, kBlock, 4096)), dim3(kBlock), 0,
                            st, rowptrT, M.cols + 1, 0);
         return hipGetLastError() == hipSuccess ? 0 : -1;
     }
-    int32_t *rowid = nullptr, *iota = nullptr, *keys = nullptr, *perm = nullptr;
-    void* tmp = nullptr;
-    size_t tmp_bytes = 0;
-    int rc = 0;
-    if (hipMalloc(&rowid, nnz * 4) != hipSuccess || hipMalloc(&iota, nnz * 4) != hipSuccess ||
-        hipMalloc(&keys, nnz * 4) != hipSuccess || hipMalloc(&perm, nnz * 4) != hipSuccess) {
-        rc = -1;
-    }
     int bits = 1;
     while ((int64_t(1) << bits) < M.cols) ++bits;
-    if (!rc) {
-        hipLaunchKernelGGL(k_row_ids, dim3(grid_for(M.rows, kBlock, 8192)), dim3(kBlock), 0, st,
-                           M.rowptr, M.rows, rowid, iota);
-        if (hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, M.col, keys, iota, perm,
-                                               (int)nnz, 0, bits, st) != hipSuccess ||
-            hipMalloc(&tmp, tmp_bytes) != hipSuccess)
-            rc = -1;
-    }
-    if (!rc && hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, M.col, keys, iota, perm,
-                                                  (int)nnz, 0, bits, st) != hipSuccess)
+    // sort storage (size query only: nothing is read or launched)
+    size_t tmp_bytes = 0;
+    if (hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, M.col, (int32_t*)nullptr,
+                                           (const int32_t*)nullptr, (int32_t*)nullptr, (int)nnz,
+                                           0, bits, st) != hipSuccess)
+        return -1;
+    auto up = [](size_t v) { return (v + 255) / 256 * 256; };
+    const size_t a4 = up((size_t)nnz * 4);
+    const size_t need = 4 * a4 + up(tmp_bytes);
+    char* base = (char*)scratch;
+    const bool own = !(scratch && scratch_bytes >= need);
+    if (own && hipMalloc((void**)&base, need) != hipSuccess) return -1;
+    int32_t* rowid = (int32_t*)base;
+    int32_t* iota = (int32_t*)(base + a4);
+    int32_t* keys = (int32_t*)(base + 2 * a4);
+    int32_t* perm = (int32_t*)(base + 3 * a4);
+    void* tmp = base + 4 * a4;
+    int rc = 0;
+    hipLaunchKernelGGL(k_row_ids, dim3(grid_for(M.rows * 16, kBlock, 8192)), dim3(kBlock), 0, st,
+                       M.rowptr, M.rows, rowid, iota);
+    if (hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, M.col, keys, iota, perm, (int)nnz, 0,
+                                           bits, st) != hipSuccess)
         rc = -1;
     if (!rc) {
         const int nb = grid_for(nnz, kBlock, 16384);
@@ -2131,12 +2140,10 @@ int transpose_csr(const Csr& M, int vdt, int32_t* rowptrT, int32_t* colT, void* 
                                (double*)valT);
         if (hipGetLastError() != hipSuccess) rc = -1;
     }
-    hipStreamSynchronize(st);
-    hipFree(rowid);
-    hipFree(iota);
-    hipFree(keys);
-    hipFree(perm);
-    hipFree(tmp);
+    if (own) {
+        hipStreamSynchronize(st);
+        hipFree(base);
+    }
     return rc;
 }
 

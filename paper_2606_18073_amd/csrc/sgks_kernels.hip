@@ -158,6 +158,83 @@ __device__ void tri_mv2(const double* __restrict__ M, int64_t rs, int64_t cs, in
     }
 }
 
+// Two upper-triangular d x d matrices Ma, Mb, element (i, k), i <= k, at
+// M[i * rs + k * cs]; groups of tpr lanes share one output as in tri_mv.
+//   tri_dot2t:  out[k] = sum_{i <= k} (Ma(i, k) va[i] + Mb(i, k) vb[i])
+//   tri_apply2: outa[i] = sum_{k >= i} Ma(i, k) v[k], outb[i] = sum_{k >= i} Mb(i, k) v[k]
+__device__ void tri_dot2t(const double* __restrict__ Ma, const double* __restrict__ Mb,
+                          int64_t rs, int64_t cs, int d, const double* va, const double* vb,
+                          double* out) {
+    const int NT = blockDim.x;
+    int tpr = 64;
+    while (tpr > 1 && NT / tpr < d) tpr >>= 1;
+    const int rpp = NT / tpr;
+    const int c = threadIdx.x % tpr;
+    for (int base = 0; base < d; base += rpp) {
+        const int k = base + threadIdx.x / tpr;
+        double acc = 0.0;
+        if (k < d) {
+            for (int q = c; q <= k; q += 8 * tpr) {
+                double wa[8], wb[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int64_t o = (int64_t)min(q + u * tpr, k) * rs + (int64_t)k * cs;
+                    wa[u] = Ma[o];
+                    wb[u] = Mb[o];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int i = q + u * tpr;
+                    if (i <= k) acc += wa[u] * va[i] + wb[u] * vb[i];
+                }
+            }
+        }
+        for (int off = tpr / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if (k < d && c == 0) out[k] = acc;
+    }
+}
+
+__device__ void tri_apply2(const double* __restrict__ Ma, const double* __restrict__ Mb,
+                           int64_t rs, int64_t cs, int d, const double* v, double* outa,
+                           double* outb) {
+    const int NT = blockDim.x;
+    int tpr = 64;
+    while (tpr > 1 && NT / tpr < d) tpr >>= 1;
+    const int rpp = NT / tpr;
+    const int c = threadIdx.x % tpr;
+    for (int base = 0; base < d; base += rpp) {
+        const int i = base + threadIdx.x / tpr;
+        double aa = 0.0, ab = 0.0;
+        if (i < d) {
+            for (int q = i + c; q < d; q += 8 * tpr) {
+                double wa[8], wb[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int64_t o = (int64_t)i * rs + (int64_t)min(q + u * tpr, d - 1) * cs;
+                    wa[u] = Ma[o];
+                    wb[u] = Mb[o];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int k = q + u * tpr;
+                    if (k < d) {
+                        aa += wa[u] * v[k];
+                        ab += wb[u] * v[k];
+                    }
+                }
+            }
+        }
+        for (int off = tpr / 2; off > 0; off >>= 1) {
+            aa += __shfl_xor(aa, off);
+            ab += __shfl_xor(ab, off);
+        }
+        if (i < d && c == 0) {
+            outa[i] = aa;
+            outb[i] = ab;
+        }
+    }
+}
+
 // Thread-strided sum of p[i], i = threadIdx.x, threadIdx.x + T, ... < n,
 // eight loads in flight (per-thread order fixed).
 __device__ __forceinline__ double thread_strided_sum(const double* __restrict__ p, int n, int T) {
@@ -1480,12 +1557,19 @@ __global__ __launch_bounds__(kAp1Threads) void k_ap1_stack(const State* __restri
         c2 += sh.cA[j] * sh.cA[j] + sh.cL[j] * sh.cL[j];
     }
     c2 = block_sum(c2, sh.red) + new2;
+    // U's halves are upper triangular (column k of each half has rows <= k):
+    // U(i, k) at U[i + k ld2] (top) and U[dmax + i + k ld2] (bottom)
     for (int pass = 0; pass < S.passes; ++pass) {
-        wg_col_dots<true>(S.U, S.U + dmax, ld2, d, d, sh.cA, sh.cL, sh.g);
+        tri_dot2t(S.U, S.U + dmax, 1, ld2, d, sh.cA, sh.cL, sh.g);
         __syncthreads();
         for (int j = tid; j < d; j += T) sh.gt[j] = (pass ? sh.gt[j] : 0.0) + sh.g[j];
-        slab_apply(S.U, ld2, d, d, sh.g, sh.cA, sh.scr);
-        slab_apply(S.U + dmax, ld2, d, d, sh.g, sh.cL, sh.scr);
+        tri_apply2(S.U, S.U + dmax, 1, ld2, d, sh.g, sh.rv, sh.tv);
+        __syncthreads();
+        for (int i = tid; i < d; i += T) {
+            sh.cA[i] -= sh.rv[i];
+            sh.cL[i] -= sh.tv[i];
+        }
+        __syncthreads();
     }
     double gam2 = 0.0, hnum = 0.0;
     for (int i = tid; i < d; i += T) {

@@ -638,22 +638,42 @@ __device__ __forceinline__ void scatter_body(const double* __restrict__ zA, int6
     const int nblk = isA ? nbA : nbL;
     const int stream = isA ? 0 : 1;
     const int64_t ntiles = (rows + 63) / 64;
-    for (int64_t tile = (int64_t)blk * kSketchWaves + wave; tile < ntiles;
-         tile += (int64_t)nblk * kSketchWaves) {
-        const int64_t i = tile * 64 + lane;
-        if (i < rows) {
-            const double v = z[i];
-            if (identity) {
-                atomicAdd(&bins[i], v);
-            } else {
-                int bin[Z];
-                double sg[Z];
-                if (pat)
-                    load_pattern<Z>(pat, i, bin, sg);
-                else
+    const int64_t tstride = (int64_t)nblk * kSketchWaves;
+    if (pat && !identity) {
+        // cached pattern: the loads of four tiles are issued before their atomics
+        constexpr int TB = 4;
+        for (int64_t t0 = (int64_t)blk * kSketchWaves + wave; t0 < ntiles; t0 += TB * tstride) {
+            double v[TB];
+            int bin[TB][Z];
+            double sg[TB][Z];
+#pragma unroll
+            for (int u = 0; u < TB; ++u) {
+                const int64_t i = min((t0 + u * tstride) * 64 + lane, rows - 1);
+                v[u] = z[i];
+                load_pattern<Z>(pat, i, bin[u], sg[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < TB; ++u) {
+                if ((t0 + u * tstride) * 64 + lane < rows) {
+#pragma unroll
+                    for (int q = 0; q < Z; ++q) atomicAdd(&bins[bin[u][q]], sg[u][q] * v[u]);
+                }
+            }
+        }
+    } else {
+        for (int64_t tile = (int64_t)blk * kSketchWaves + wave; tile < ntiles; tile += tstride) {
+            const int64_t i = tile * 64 + lane;
+            if (i < rows) {
+                const double v = z[i];
+                if (identity) {
+                    atomicAdd(&bins[i], v);
+                } else {
+                    int bin[Z];
+                    double sg[Z];
                     sketch_column<Z>(seed, stream, i, s, bin, sg);
 #pragma unroll
-                for (int q = 0; q < Z; ++q) atomicAdd(&bins[bin[q]], sg[q] * v);
+                    for (int q = 0; q < Z; ++q) atomicAdd(&bins[bin[q]], sg[q] * v);
+                }
             }
         }
     }

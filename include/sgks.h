@@ -52,7 +52,7 @@ extern "C" {
 #define SGKS_ERR_INVALID_ARG (-1)     /* null pointer, bad option value            */
 #define SGKS_ERR_SHAPE (-2)           /* A.cols != L.cols, bad CSR sizes           */
 #define SGKS_ERR_BAD_MU (-3)          /* mu <= 0 or not finite                     */
-#define SGKS_ERR_SKETCH_SIZE (-4)     /* s < ell + max_iters, zeta > s, s > 2048   */
+#define SGKS_ERR_SKETCH_SIZE (-4)     /* s < ell + max_iters, zeta > s, s > 1024   */
 #define SGKS_ERR_CAPACITY (-5)        /* iterate would exceed ell + max_iters      */
 #define SGKS_ERR_ZERO_RHS (-6)        /* b = 0 or A^T b = 0                        */
 #define SGKS_ERR_NONFINITE (-7)       /* NaN/Inf in b or in a computed vector      */

@@ -9,7 +9,7 @@ namespace sgks {
 
 constexpr int kBlock = 256;         // threads per block of the bulk kernels
 constexpr int kWaves = kBlock / 64; // waves per block
-constexpr int kMaxS = 2048;         // largest sketch size (per-wave LDS bins)
+constexpr int kMaxS = 1024;         // largest sketch size (8 wave-private LDS bin copies: 64 KiB)
 constexpr int kMaxD = 512;          // largest basis dimension
 constexpr int kAppendThreads = 256; // threads per workgroup of the append chain kernels
 constexpr int kMaxAppendGroups = 32;  // workgroups of the append kernels

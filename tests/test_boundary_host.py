@@ -54,6 +54,8 @@ def test_validation_codes(lib):
     assert _v(lib, A, L, mu=float("inf")) == -3
     assert _v(lib, A, L, s=50) == -4                            # s < ell + max_iters
     assert _v(lib, A, L, s=4096) == -4                          # above the LDS bin limit
+    assert _v(lib, A, L, s=1025) == -4
+    assert _v(lib, A, L, s=1024) == 0
     assert _v(lib, A, L, s=6, max_iters=0, zeta=8) == -4        # zeta > s
     assert _v(lib, A, L, zeta=3) == -1
     assert _v(lib, A, L, qr_passes=3) == -1

@@ -205,3 +205,47 @@ def test_batch_full_size_32_problems():
     say("  consistency of problem", big, Ps[big].name, Ps[big].A.nnz)
     check_state_consistency(B.problem(big), Ps[big])
     B.close()
+
+
+@pytest.mark.parametrize("name", ["deblur2d", "ct2d"])
+def test_append_chain_matches_oracle(name):
+    """The multi-workgroup append chain (with the maintained gradient, whose H W
+    column then gets a launch of its own) on the small workloads."""
+    P = problem(name, "small")
+    say("case append chain", name, P.s)
+    S, x = G.solve_problem(P, append_groups=4)
+    assert S.tuning()["append_groups"] == 4
+    ref = oracle_run(P)
+    e = rel(x.cpu().numpy(), ref.x)
+    say(f"  rel err {e:.3e}")
+    assert e <= 1e-8
+    assert S.status() == (0, P.k)
+    check_state_consistency(S, P)
+    S.close()
+
+
+def test_batch_mixing_compact_and_chain_appends():
+    """A batch whose problems take different append paths (chosen per problem from
+    s * dmax): one launch sequence, each problem bitwise equal to its plain solve."""
+    Ps = problem("batch", "small")[:3]
+    say("case batch mixed append paths")
+    k, cap = Ps[0].k, 115
+    data = G.upload_batch(Ps)
+    sizes = [120, 1024, 120]            # 1024 * (3 + 115) is above the compact limit
+    data = [(A, L, b, mu, sz, seed) for (A, L, b, mu, _, seed), sz in zip(data, sizes)]
+    B = G.SGKSBatch(data, ell=Ps[0].ell, max_iters=cap)
+    groups = [B.problem(i).tuning()["append_groups"] for i in range(3)]
+    say("  append groups", groups)
+    assert groups[0] == 1 and groups[1] > 1 and groups[2] == 1
+    B.iterate(k)
+    for i, P in enumerate(Ps):
+        S = G.SGKS(*data[i], ell=P.ell, max_iters=cap, graph=False)
+        S.iterate(k)
+        assert np.array_equal(B.problem(i).solution().cpu().numpy(), S.solution().cpu().numpy())
+        assert B.problem(i).status() == S.status() == (0, k)
+        S.close()
+        ref = O.sgks(P.A, P.L, P.b, P.mu, k, sizes[i], P.seed, zeta=P.zeta, ell=P.ell)
+        e = rel(B.problem(i).solution().cpu().numpy(), ref.x)
+        say(f"  problem {i} s = {sizes[i]} rel err {e:.3e}")
+        assert e <= 1e-8
+    B.close()

@@ -18,6 +18,11 @@ constexpr int kSketchBlock = 512;   // threads per block of the sketch kernel
 constexpr int kSketchWaves = kSketchBlock / 64;
 constexpr int kMaxSketchBlocks = 256; // per operator
 constexpr int kMaxBatch = 64;       // problems of one batched launch
+// total nonzeros of A and L (over a plan's problems) up to which the adjoint
+// products that add the H W column run inside the compact side launch: short
+// enough to hide behind the latency-bound appends; beyond, they run in a launch
+// of their own at full occupancy
+constexpr int64_t kFuseHWMaxNnz = 12000000;
 // s * dmax up to which the compact append (one workgroup per side) is chosen;
 // beyond, the bandwidth of one compute unit makes the multi-workgroup chain faster
 constexpr int64_t kCompactAppendMax = 120000;
@@ -127,7 +132,8 @@ struct Plan {
     BTab ap1_side;      // compact append: two workgroups per problem (one append group)
     BTab ap1_stack;     // compact append: one workgroup per problem
     BTab ap1_side_hw;   // compact append with the H W column: 2 + hw_blocks per problem
-    BTab adj_hw_chain;  // H W column of the chain problems (adjoint workgroups)
+    BTab adj_hw_sep;    // H W column in a launch of its own (adjoint workgroups)
+    int fuse_hw;        // H W column inside the compact side launch (small total nnz)
     BTab one;           // one workgroup per problem
 };
 

@@ -2067,7 +2067,10 @@ int plan_build(Plan& P, const State* host, const State* dev, int np, const int* 
     P.gradient_form = host[0].gradient_form;
     int fwd[kMaxBatch], adj[kMaxBatch], sc[kMaxBatch], gv[kMaxBatch], gt[kMaxBatch],
         ap[kMaxBatch], apf[kMaxBatch], ap1s[kMaxBatch], ap1k[kMaxBatch], one[kMaxBatch],
-        gr[kMaxBatch], ap1h[kMaxBatch], ahc[kMaxBatch];
+        gr[kMaxBatch], ap1h[kMaxBatch], ahs[kMaxBatch];
+    int64_t nnz_total = 0;
+    for (int q = 0; q < np; ++q) nnz_total += host[q].A.nnz + host[q].L.nnz;
+    P.fuse_hw = nnz_total <= kFuseHWMaxNnz ? 1 : 0;
     for (int q = 0; q < np; ++q) {
         const State& S = host[q];
         if (S.vdt != P.vdt || S.zeta != P.zeta || S.passes != P.passes ||
@@ -2086,8 +2089,8 @@ int plan_build(Plan& P, const State* host, const State* dev, int np, const int* 
         ap1s[q] = compact ? 2 : 0;
         ap1k[q] = compact ? 1 : 0;
         const bool hw = S.gradient_form == 0;
-        ap1h[q] = compact ? 2 + (hw ? hw_blocks(S) : 0) : 0;
-        ahc[q] = (!compact && hw) ? adjoint_blocks(S) : 0;
+        ap1h[q] = compact ? 2 + (hw && P.fuse_hw ? hw_blocks(S) : 0) : 0;
+        ahs[q] = (hw && !(compact && P.fuse_hw)) ? adjoint_blocks(S) : 0;
         one[q] = 1;
         P.max_s = S.s > P.max_s ? S.s : P.max_s;
         P.max_gt_rows = S.gt_rows > P.max_gt_rows ? S.gt_rows : P.max_gt_rows;
@@ -2103,7 +2106,7 @@ int plan_build(Plan& P, const State* host, const State* dev, int np, const int* 
     tab_set(P.ap1_side, np, ap1s);
     tab_set(P.ap1_stack, np, ap1k);
     tab_set(P.ap1_side_hw, np, ap1h);
-    tab_set(P.adj_hw_chain, np, ahc);
+    tab_set(P.adj_hw_sep, np, ahs);
     tab_set(P.one, np, one);
     return 0;
 }
@@ -2151,18 +2154,18 @@ void plan_scatter(const Plan& P, hipStream_t st) {
 
 int plan_append(const Plan& P, bool scale_from_norm, bool with_hw, hipStream_t st) {
     with_hw = with_hw && P.gradient_form == 0;
-    if (with_hw && tab_total(P.adj_hw_chain) > 0) {
-        const dim3 grid(tab_total(P.adj_hw_chain));
+    if (with_hw && tab_total(P.adj_hw_sep) > 0) {
+        const dim3 grid(tab_total(P.adj_hw_sep));
         if (P.vdt == 0)
-            hipLaunchKernelGGL(kb_adjoint<float>, grid, dim3(kBlock), 0, st, P.SS, P.adj_hw_chain,
+            hipLaunchKernelGGL(kb_adjoint<float>, grid, dim3(kBlock), 0, st, P.SS, P.adj_hw_sep,
                                kDstHW);
         else
-            hipLaunchKernelGGL(kb_adjoint<double>, grid, dim3(kBlock), 0, st, P.SS,
-                               P.adj_hw_chain, kDstHW);
+            hipLaunchKernelGGL(kb_adjoint<double>, grid, dim3(kBlock), 0, st, P.SS, P.adj_hw_sep,
+                               kDstHW);
     }
     if (tab_total(P.ap1_side) > 0) {
         const int sfn = scale_from_norm ? 1 : 0;
-        if (!with_hw)
+        if (!with_hw || !P.fuse_hw)
             hipLaunchKernelGGL(k_ap1_side, dim3(tab_total(P.ap1_side)), dim3(kAp1Threads), 0, st,
                                P.SS, P.ap1_side, sfn);
         else if (P.vdt == 0)

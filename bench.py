@@ -224,7 +224,7 @@ def bench_adjoint(G, torch, np, make):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="deblur2d")
     ap.add_argument("--no-cpu-baseline", action="store_true")

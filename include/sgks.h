@@ -116,12 +116,26 @@ typedef struct {
                                 (cached per operator shape in the process); 0 = choose from
                                 nnz/row and a fixed tile count (default)                        */
     void *stream;            /* hipStream_t the work is enqueued on (NULL = default stream)   */
+    void *workspace;         /* NULL: the context allocates its device memory (one hipMalloc in
+                                sgks_create, freed by sgks_destroy).  Else device memory of
+                                workspace_bytes >= sgks_workspace_bytes(...), 256-byte aligned,
+                                owned by the caller and used for every array of the context
+                                (no device allocation in sgks_create or afterwards, except the
+                                temporary of sgks_copy_state(W)); keep it alive until
+                                sgks_destroy.  Not accepted by sgks_batch_create.              */
+    size_t workspace_bytes;
 } sgks_options;
 
 typedef struct sgks_ctx sgks_ctx;
 
 /* Fill *opt with the defaults listed above. */
 void sgks_default_options(sgks_options *opt);
+
+/* Device bytes a context with these arguments uses (host only, no device
+ * work); 0 if the arguments are invalid.  Independent of the values, the
+ * seed, the stream and the autotuner's choices. */
+size_t sgks_workspace_bytes(const sgks_csr *A, const sgks_csr *L, int32_t sketch_rows,
+                            const sgks_options *opt);
 
 /* Check the arguments of sgks_create without touching the device (host only).
  * Returns the code sgks_create would return for an argument error, or 0. */

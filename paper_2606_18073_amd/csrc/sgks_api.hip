@@ -4,6 +4,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <new>
@@ -303,6 +304,10 @@ struct sgks_ctx {
     double* coefbuf;     // dmax scratch
     double* sbuf;        // s scratch
     double* init_norms;  // copy of the scalars after the initial basis (checked at the end of create)
+    int16_t* patA = nullptr;
+    int16_t* patL = nullptr;
+    void* sort_scratch = nullptr;   // transpose sort scratch when W (and HW) are too small
+    size_t sort_bytes = 0;
     int32_t* At_rowptr;
     int32_t* At_col;
     void* At_val;
@@ -341,6 +346,9 @@ struct Arena {
         total += (bytes + 255) / 256 * 256;
         if (bytes == 0) total += 256;
     }
+    void place(char* base) {
+        for (const Req& r : reqs) *r.p = base + r.off;
+    }
     hipError_t commit(sgks_ctx* c) {
         char* base = nullptr;
         hipError_t e = hipMalloc((void**)&base, total);
@@ -370,6 +378,144 @@ int sync_status(sgks_ctx* c) {
     return st;
 }
 
+// partial sums of ||r||^2: one per workgroup of the kernel that forms r
+int norm_parts(const State& T) {
+    return T.gradient_form == SGKS_GRADIENT_MAINTAINED ? sgks::gradient_blocks(T)
+                                                       : sgks::adjoint_blocks(T);
+}
+
+// Shapes and launch choices of a context from its arguments (validated
+// already); host only, no device memory.
+int plan_context(sgks_ctx* c, const sgks_csr* A, const sgks_csr* L, double mu, int32_t s,
+                 uint64_t seed) {
+    c->st = (hipStream_t)c->opt.stream;
+    State& S = c->S;
+    memset(&S, 0, sizeof(S));
+    S.m = A->rows;
+    S.n = A->cols;
+    S.p = L->rows;
+    S.s = s;
+    S.dmax = c->opt.ell + c->opt.max_iters;
+    S.zeta = c->opt.zeta;
+    S.passes = c->opt.qr_passes;
+    S.sketch_mode = c->opt.sketch_mode;
+    S.vdt = c->opt.value_dtype;
+    S.gradient_form = c->opt.gradient_form;
+    S.seed = seed;
+    S.mu = mu;
+    S.sqrt_mu = sqrt(mu);
+    const int dmax = S.dmax;
+
+    S.A = Csr{A->rows, A->cols, A->nnz, A->rowptr, A->colind, A->val,
+              c->opt.lanes_A ? c->opt.lanes_A : choose_lanes(A->nnz, A->rows)};
+    S.L = Csr{L->rows, L->cols, L->nnz, L->rowptr, L->colind, L->val,
+              choose_lanes(L->nnz, L->rows)};
+
+    // transposes of A and L (explicit CSR, n rows): shapes now, arrays below
+    S.At = Csr{S.n, S.m, S.A.nnz, nullptr, nullptr, nullptr,
+               c->opt.lanes_At ? c->opt.lanes_At : choose_lanes(S.A.nnz, S.n)};
+    S.Lt = Csr{S.n, S.p, S.L.nnz, nullptr, nullptr, nullptr, choose_lanes(S.L.nnz, S.n)};
+
+    // scatter workgroups: kScatterTilesPerWave 64-entry tiles per wave (the
+    // autotuner may choose another count; the partial bins are sized for one)
+    S.nbA = sgks::scatter_blocks(S.m, kScatterTilesPerWave);
+    S.nbL = sgks::scatter_blocks(S.p, kScatterTilesPerWave);
+    S.n_norm_part = norm_parts(S);
+    int nbFA = 0;
+    const int nbF = sgks::forward_blocks(S, true, &nbFA);
+    c->nbF_A = nbFA;
+    c->nbF_L = nbF - nbFA;
+    // W^T v partials: at most 512 blocks, rows per block a multiple of 64
+    {
+        int64_t rpb = (S.n + 511) / 512;
+        rpb = ((rpb + 63) / 64) * 64;
+        if (rpb < 256) rpb = 256;
+        if (rpb > 4096) rpb = 4096;   // staged in LDS (32 KiB)
+        S.gt_rows = (int)rpb;
+        S.ngt = (int)((S.n + rpb - 1) / rpb);
+    }
+    // cooperative append workgroups
+    {
+        const int cap = sgks::max_append_groups();
+        int G = c->opt.append_groups;
+        if (G == 0) G = sgks::choose_append_groups(s, dmax, cap < 64 ? cap : 64);
+        if (G > cap) G = cap;
+        if (!sgks::append_groups_ok(s, dmax, G)) return SGKS_ERR_SKETCH_SIZE;
+        c->groups = G;
+    }
+
+    return SGKS_OK;
+}
+
+// Device memory of a context: every piece registered with the arena (its
+// pointers are filled in by the commit).  The transposes' sort scratch lives
+// in W (and HW), unused until the transposes are built, or in a piece of its
+// own when that is too small.
+void layout_context(sgks_ctx* c, Arena& ar) {
+    State& S = c->S;
+    const int dmax = S.dmax, s = S.s;
+    const size_t vsz = S.vdt == SGKS_F32 ? 4 : 8;
+    const int nbA_max = sgks::scatter_blocks(S.m, 1), nbL_max = sgks::scatter_blocks(S.p, 1);
+    const bool sparse = S.sketch_mode == SGKS_SKETCH_SPARSE_SIGN;
+    const int regions = 2 * S.passes + 2;
+    const int CW = 2 * dmax + 8;
+    ar.add(&c->At_rowptr, (S.n + 1) * 4);
+    ar.add(&c->At_col, S.A.nnz * 4);
+    ar.add((char**)&c->At_val, S.A.nnz * vsz);
+    ar.add(&c->Lt_rowptr, (S.n + 1) * 4);
+    ar.add(&c->Lt_col, S.L.nnz * 4);
+    ar.add((char**)&c->Lt_val, S.L.nnz * vsz);
+    ar.add((double**)&S.b, S.m * 8);
+    ar.add(&S.x, S.n * 8);
+    ar.add(&S.u, S.m * 8);
+    ar.add(&S.t, S.p * 8);
+    ar.add(&S.rtmp, S.n * 8);
+    ar.add(&S.W, (size_t)S.n * dmax * 8);
+    if (S.gradient_form == SGKS_GRADIENT_MAINTAINED) ar.add(&S.HW, (size_t)S.n * dmax * 8);
+    // the small state, together
+    ar.add(&S.cs, dmax * 8);
+    ar.add(&S.QA, (size_t)s * dmax * 8);
+    ar.add(&S.QL, (size_t)s * dmax * 8);
+    ar.add(&S.RA, (size_t)dmax * dmax * 8);
+    ar.add(&S.RL, (size_t)dmax * dmax * 8);
+    ar.add(&S.U, (size_t)2 * dmax * dmax * 8);
+    ar.add(&S.G, (size_t)2 * dmax * dmax * 8);   // G, then G^{-1}
+    ar.add(&S.h, dmax * 8);
+    ar.add(&S.dA, dmax * 8);
+    ar.add(&S.cb, s * 8);
+    ar.add(&S.y, dmax * 8);
+    ar.add(&S.yprev, dmax * 8);
+    ar.add(&S.norm_part, 2048 * 8);   // adjoint workgroups are capped at 2048
+    ar.add(&S.binA, (size_t)nbA_max * s * 8);
+    ar.add(&S.binL, (size_t)nbL_max * s * 8);
+    if (sparse) {
+        ar.add(&c->patA, (size_t)S.m * S.zeta * 2);
+        ar.add(&c->patL, (size_t)S.p * S.zeta * 2);
+    }
+    ar.add(&S.wa, s * 8);
+    ar.add(&S.wl, s * 8);
+    ar.add(&S.wu, 2 * dmax * 8);
+    ar.add(&S.pacc, 4 * dmax * 8);
+    ar.add(&S.gacc, dmax * 8);
+    ar.add(&S.gpart, (size_t)S.ngt * dmax * 8);
+    ar.add(&S.coop, (size_t)regions * c->groups * CW * 8);
+    ar.add(&S.scal, (16 + 2 * dmax) * 8);
+    ar.add(&S.d, 64);
+    ar.add(&S.status, 64);
+    ar.add(&S.degenerate, 64);
+    // forward workgroups for any lanes choice (at most four rows per workgroup fewer)
+    ar.add(&c->upart, ((S.m + 3) / 4 + 1) * 8);
+    ar.add(&c->tpart, ((S.p + 3) / 4 + 1) * 8);
+    ar.add(&c->coefbuf, dmax * 8);
+    ar.add(&c->sbuf, s * 8);
+    ar.add(&c->init_norms, (16 + 2 * dmax) * 8);
+    ar.add(&c->Sdev, sizeof(State));
+    const size_t wbytes = (size_t)S.n * dmax * 8 * (S.gradient_form == SGKS_GRADIENT_MAINTAINED ? 2 : 1);
+    const size_t sort = std::max(sgks::transpose_scratch_bytes(S.A), sgks::transpose_scratch_bytes(S.L));
+    c->sort_bytes = sort > wbytes ? sort : 0;
+    if (c->sort_bytes) ar.add(&c->sort_scratch, c->sort_bytes);
+}
+
 // ||v||, via the conversion kernel run in place, into cs[col] = 1/||v||
 void norm_to_scale(sgks_ctx* c, double* v, int col, bool store_r0) {
     State& S = c->S;
@@ -397,6 +543,8 @@ void sgks_default_options(sgks_options* o) {
     o->graph = 1;
     o->autotune = 0;
     o->gradient_form = SGKS_GRADIENT_MAINTAINED;
+    o->workspace = nullptr;
+    o->workspace_bytes = 0;
     o->stream = nullptr;
 }
 
@@ -439,6 +587,26 @@ int sgks_validate(const sgks_csr* A, const sgks_csr* L, const void* b, double mu
     return 0;
 }
 
+size_t sgks_workspace_bytes(const sgks_csr* A, const sgks_csr* L, int32_t s,
+                            const sgks_options* opt) {
+    // b is not read: any non-null pointer passes the validation
+    if (sgks_validate(A, L, (const void*)A, 1.0, s, opt) != 0) return 0;
+    sgks_ctx* c = new (std::nothrow) sgks_ctx();
+    if (!c) return 0;
+    if (opt)
+        c->opt = *opt;
+    else
+        sgks_default_options(&c->opt);
+    size_t total = 0;
+    if (plan_context(c, A, L, 1.0, s, 0) == SGKS_OK) {
+        Arena ar;
+        layout_context(c, ar);
+        total = ar.total;
+    }
+    delete c;
+    return total;
+}
+
 int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, int32_t s,
                 uint64_t seed, const sgks_options* opt, sgks_ctx** out) {
     if (!out) return SGKS_ERR_INVALID_ARG;
@@ -451,30 +619,11 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
         c->opt = *opt;
     else
         sgks_default_options(&c->opt);
-    c->st = (hipStream_t)c->opt.stream;
-    State& S = c->S;
-    memset(&S, 0, sizeof(S));
-    S.m = A->rows;
-    S.n = A->cols;
-    S.p = L->rows;
-    S.s = s;
-    S.dmax = c->opt.ell + c->opt.max_iters;
-    S.zeta = c->opt.zeta;
-    S.passes = c->opt.qr_passes;
-    S.sketch_mode = c->opt.sketch_mode;
-    S.vdt = c->opt.value_dtype;
-    S.gradient_form = c->opt.gradient_form;
-    S.seed = seed;
-    S.mu = mu;
-    S.sqrt_mu = sqrt(mu);
-    const size_t vsz = S.vdt == SGKS_F32 ? 4 : 8;
-    const int dmax = S.dmax;
-
-    S.A = Csr{A->rows, A->cols, A->nnz, A->rowptr, A->colind, A->val,
-              c->opt.lanes_A ? c->opt.lanes_A : choose_lanes(A->nnz, A->rows)};
-    S.L = Csr{L->rows, L->cols, L->nnz, L->rowptr, L->colind, L->val,
-              choose_lanes(L->nnz, L->rows)};
-
+    rc = plan_context(c, A, L, mu, s, seed);
+    if (rc) {
+        sgks_destroy(c);
+        return rc;
+    }
 #define SGKS_TRY(expr)                      \
     do {                                    \
         if ((expr) != hipSuccess) {         \
@@ -482,109 +631,29 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
             return SGKS_ERR_HIP;            \
         }                                   \
     } while (0)
-
-    // transposes of A and L (explicit CSR, n rows): shapes now, arrays below
-    S.At = Csr{S.n, S.m, S.A.nnz, nullptr, nullptr, nullptr,
-               c->opt.lanes_At ? c->opt.lanes_At : choose_lanes(S.A.nnz, S.n)};
-    S.Lt = Csr{S.n, S.p, S.L.nnz, nullptr, nullptr, nullptr, choose_lanes(S.L.nnz, S.n)};
-
-    // scatter workgroups: kScatterTilesPerWave 64-entry tiles per wave (the
-    // autotuner may choose another count; the partial bins are sized for one)
-    S.nbA = sgks::scatter_blocks(S.m, kScatterTilesPerWave);
-    S.nbL = sgks::scatter_blocks(S.p, kScatterTilesPerWave);
-    const int nbA_max = sgks::scatter_blocks(S.m, 1), nbL_max = sgks::scatter_blocks(S.p, 1);
+    State& S = c->S;
+    const int dmax = S.dmax;
     const bool sparse = S.sketch_mode == SGKS_SKETCH_SPARSE_SIGN;
-    auto norm_parts = [](const State& T) {
-        return T.gradient_form == SGKS_GRADIENT_MAINTAINED ? sgks::gradient_blocks(T)
-                                                           : sgks::adjoint_blocks(T);
-    };
-    S.n_norm_part = norm_parts(S);
-    int nbFA = 0;
-    const int nbF = sgks::forward_blocks(S, true, &nbFA);
-    c->nbF_A = nbFA;
-    c->nbF_L = nbF - nbFA;
-    // W^T v partials: at most 512 blocks, rows per block a multiple of 64
-    {
-        int64_t rpb = (S.n + 511) / 512;
-        rpb = ((rpb + 63) / 64) * 64;
-        if (rpb < 256) rpb = 256;
-        if (rpb > 4096) rpb = 4096;   // staged in LDS (32 KiB)
-        S.gt_rows = (int)rpb;
-        S.ngt = (int)((S.n + rpb - 1) / rpb);
-    }
-    // cooperative append workgroups
-    {
-        const int cap = sgks::max_append_groups();
-        int G = c->opt.append_groups;
-        if (G == 0) G = sgks::choose_append_groups(s, dmax, cap < 64 ? cap : 64);
-        if (G > cap) G = cap;
-        if (!sgks::append_groups_ok(s, dmax, G)) {
-            sgks_destroy(c);
-            return SGKS_ERR_SKETCH_SIZE;
-        }
-        c->groups = G;
-    }
-    const int regions = 2 * S.passes + 2;
-    const int CW = 2 * dmax + 8;
-
     Arena ar;
-    ar.add(&c->At_rowptr, (S.n + 1) * 4);
-    ar.add(&c->At_col, S.A.nnz * 4);
-    ar.add((char**)&c->At_val, S.A.nnz * vsz);
-    ar.add(&c->Lt_rowptr, (S.n + 1) * 4);
-    ar.add(&c->Lt_col, S.L.nnz * 4);
-    ar.add((char**)&c->Lt_val, S.L.nnz * vsz);
-    ar.add((double**)&S.b, S.m * 8);
-    ar.add(&S.x, S.n * 8);
-    ar.add(&S.u, S.m * 8);
-    ar.add(&S.t, S.p * 8);
-    ar.add(&S.rtmp, S.n * 8);
-    ar.add(&S.W, (size_t)S.n * dmax * 8);
-    if (S.gradient_form == SGKS_GRADIENT_MAINTAINED) ar.add(&S.HW, (size_t)S.n * dmax * 8);
-    // the small state, together
-    ar.add(&S.cs, dmax * 8);
-    ar.add(&S.QA, (size_t)s * dmax * 8);
-    ar.add(&S.QL, (size_t)s * dmax * 8);
-    ar.add(&S.RA, (size_t)dmax * dmax * 8);
-    ar.add(&S.RL, (size_t)dmax * dmax * 8);
-    ar.add(&S.U, (size_t)2 * dmax * dmax * 8);
-    ar.add(&S.G, (size_t)2 * dmax * dmax * 8);   // G, then G^{-1}
-    ar.add(&S.h, dmax * 8);
-    ar.add(&S.dA, dmax * 8);
-    ar.add(&S.cb, s * 8);
-    ar.add(&S.y, dmax * 8);
-    ar.add(&S.yprev, dmax * 8);
-    ar.add(&S.norm_part, 2048 * 8);   // adjoint workgroups are capped at 2048
-    ar.add(&S.binA, (size_t)nbA_max * s * 8);
-    ar.add(&S.binL, (size_t)nbL_max * s * 8);
-    int16_t *patA = nullptr, *patL = nullptr;
-    if (sparse) {
-        ar.add(&patA, (size_t)S.m * S.zeta * 2);
-        ar.add(&patL, (size_t)S.p * S.zeta * 2);
+    layout_context(c, ar);
+    if (c->opt.workspace) {
+        // caller-owned device memory: no allocation here
+        if (c->opt.workspace_bytes < ar.total || ((uintptr_t)c->opt.workspace & 255)) {
+            sgks_destroy(c);
+            return SGKS_ERR_INVALID_ARG;
+        }
+        ar.place((char*)c->opt.workspace);
+    } else {
+        SGKS_TRY(ar.commit(c));
     }
-    ar.add(&S.wa, s * 8);
-    ar.add(&S.wl, s * 8);
-    ar.add(&S.wu, 2 * dmax * 8);
-    ar.add(&S.pacc, 4 * dmax * 8);
-    ar.add(&S.gacc, dmax * 8);
-    ar.add(&S.gpart, (size_t)S.ngt * dmax * 8);
-    ar.add(&S.coop, (size_t)regions * c->groups * CW * 8);
-    ar.add(&S.scal, (16 + 2 * dmax) * 8);
-    ar.add(&S.d, 64);
-    ar.add(&S.status, 64);
-    ar.add(&S.degenerate, 64);
-    // forward workgroups for any lanes choice (at most four rows per workgroup fewer)
-    ar.add(&c->upart, ((S.m + 3) / 4 + 1) * 8);
-    ar.add(&c->tpart, ((S.p + 3) / 4 + 1) * 8);
-    ar.add(&c->coefbuf, dmax * 8);
-    ar.add(&c->sbuf, s * 8);
-    ar.add(&c->init_norms, (16 + 2 * dmax) * 8);
-    ar.add(&c->Sdev, sizeof(State));
-    SGKS_TRY(ar.commit(c));
-    // the transposes' sort scratch lives in W (and HW), unused until they are built
-    const size_t wbytes = (size_t)S.n * dmax * 8 * (S.HW ? 2 : 1);
-    if (sgks::transpose_csr(S.A, S.vdt, c->At_rowptr, c->At_col, c->At_val, S.W, wbytes, c->st) ||
-        sgks::transpose_csr(S.L, S.vdt, c->Lt_rowptr, c->Lt_col, c->Lt_val, S.W, wbytes, c->st)) {
+    // sort scratch: W (and HW) before they are used, or its own piece
+    void* sbase = c->sort_bytes ? c->sort_scratch : (void*)S.W;
+    const size_t sbytes =
+        c->sort_bytes ? c->sort_bytes : (size_t)S.n * dmax * 8 * (S.HW ? 2 : 1);
+    if (sgks::transpose_csr(S.A, S.vdt, c->At_rowptr, c->At_col, c->At_val, sbase, sbytes,
+                            c->st) ||
+        sgks::transpose_csr(S.L, S.vdt, c->Lt_rowptr, c->Lt_col, c->Lt_val, sbase, sbytes,
+                            c->st)) {
         sgks_destroy(c);
         return SGKS_ERR_HIP;
     }
@@ -598,10 +667,10 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
     c->prof.st = st;
     if (sparse) {
         // the sparse-sign pattern, once, from the hash
-        sgks::launch_make_pattern(patA, S.m, s, S.zeta, seed, 0, st);
-        sgks::launch_make_pattern(patL, S.p, s, S.zeta, seed, 1, st);
-        S.patA = patA;
-        S.patL = patL;
+        sgks::launch_make_pattern(c->patA, S.m, s, S.zeta, seed, 0, st);
+        sgks::launch_make_pattern(c->patL, S.p, s, S.zeta, seed, 1, st);
+        S.patA = c->patA;
+        S.patL = c->patL;
     }
     if (c->opt.autotune) {
         SGKS_TRY(hipMemsetAsync(S.x, 0, S.n * 8, st));
@@ -906,7 +975,7 @@ int sgks_batch_create(int32_t count, const sgks_problem* probs, const sgks_optio
         o = *opt;
     else
         sgks_default_options(&o);
-    if (o.lanes_A || o.lanes_At || o.append_groups) return SGKS_ERR_INVALID_ARG;
+    if (o.lanes_A || o.lanes_At || o.append_groups || o.workspace) return SGKS_ERR_INVALID_ARG;
     for (int i = 0; i < count; ++i) {
         const int rc = sgks_validate(&probs[i].A, &probs[i].L, probs[i].b, probs[i].mu,
                                      probs[i].sketch_rows, &o);

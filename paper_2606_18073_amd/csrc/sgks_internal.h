@@ -167,6 +167,7 @@ void launch_copy_scaled_W(const State& S, double* dst, hipStream_t st);
 void launch_make_pattern(int16_t* pat, int64_t rows, int s, int zeta, uint64_t seed, int stream,
                          hipStream_t st);
 int scatter_blocks(int64_t rows, int tiles_per_wave);
+size_t transpose_scratch_bytes(const Csr& M);
 // scratch (device, scratch_bytes) serves the sort when large enough; else the
 // scratch is allocated and freed around the sort
 int transpose_csr(const Csr& M, int vdt, int32_t* rowptrT, int32_t* colT, void* valT,

@@ -2202,6 +2202,21 @@ void plan_refine(const Plan& P, hipStream_t st) {
     hipLaunchKernelGGL(k_refine, dim3(P.np), dim3(kBlock), 0, st, P.SS, P.one);
 }
 
+// bytes of scratch the transpose of M needs (four nnz-long int32 arrays and the
+// radix sort's storage; host-side size query only)
+size_t transpose_scratch_bytes(const Csr& M) {
+    if (M.nnz == 0) return 0;
+    int bits = 1;
+    while ((int64_t(1) << bits) < M.cols) ++bits;
+    size_t tmp_bytes = 0;
+    if (hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, M.col, (int32_t*)nullptr,
+                                           (const int32_t*)nullptr, (int32_t*)nullptr,
+                                           (int)M.nnz, 0, bits, (hipStream_t)0) != hipSuccess)
+        tmp_bytes = (size_t)M.nnz * 16;   // generous when the query fails
+    auto up = [](size_t v) { return (v + 255) / 256 * 256; };
+    return 4 * up((size_t)M.nnz * 4) + up(tmp_bytes);
+}
+
 int transpose_csr(const Csr& M, int vdt, int32_t* rowptrT, int32_t* colT, void* valT,
                   void* scratch, size_t scratch_bytes, hipStream_t st) {
     const int64_t nnz = M.nnz;

@@ -53,7 +53,8 @@ class Options(ctypes.Structure):
                 ("lanes_At", ctypes.c_int32), ("append_groups", ctypes.c_int32),
                 ("graph", ctypes.c_int32), ("gradient_form", ctypes.c_int32),
                 ("autotune", ctypes.c_int32),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
 
 
 class ProblemStruct(ctypes.Structure):
@@ -82,6 +83,8 @@ def load_library(path=LIB_PATH):
     L.sgks_validate.argtypes = [P(CsrStruct), P(CsrStruct), ctypes.c_void_p, ctypes.c_double,
                                 ctypes.c_int32, P(Options)]
     L.sgks_validate.restype = ctypes.c_int
+    L.sgks_workspace_bytes.argtypes = [P(CsrStruct), P(CsrStruct), ctypes.c_int32, P(Options)]
+    L.sgks_workspace_bytes.restype = ctypes.c_size_t
     L.sgks_create.argtypes = [P(CsrStruct), P(CsrStruct), ctypes.c_void_p, ctypes.c_double,
                               ctypes.c_int32, ctypes.c_uint64, P(Options), P(ctypes.c_void_p)]
     L.sgks_create.restype = ctypes.c_int
@@ -195,7 +198,7 @@ class SGKS:
     """One sGKS solve on the GPU: sgks_create / sgks_iterate / sgks_solution / ..."""
 
     def __init__(self, A: DeviceCsr, L: DeviceCsr, b, mu, s, seed=0, *, ell=3, stream=None,
-                 **opts):
+                 workspace=None, **opts):
         import torch
         self._lib = load_library()
         self.A, self.L, self.b = A, L, b
@@ -206,6 +209,11 @@ class SGKS:
             stream = torch.cuda.current_stream(b.device)
         self.stream = stream
         o = make_options(self._lib, vdt, stream, ell=ell, **opts)
+        if workspace is not None:
+            # caller-owned device memory (e.g. a torch uint8 tensor): no allocation inside
+            self._workspace = workspace
+            o.workspace = ctypes.c_void_p(workspace.data_ptr())
+            o.workspace_bytes = workspace.numel() * workspace.element_size()
         self.options = o
         self._owner = None
         self.mu, self.s, self.seed, self.ell = float(mu), int(s), int(seed), int(ell)
@@ -326,7 +334,7 @@ class SGKSBatch:
     shared.  problem(i) gives problem i as an SGKS view (solution, residual_norm,
     status, state, backward)."""
 
-    def __init__(self, problems, *, ell=3, stream=None, **opts):
+    def __init__(self, problems, *, ell=3, stream=None, workspace=None, **opts):
         import torch
         self._lib = load_library()
         problems = list(problems)
@@ -341,6 +349,9 @@ class SGKSBatch:
             stream = torch.cuda.current_stream(b0.device)
         self.stream = stream
         self.options = make_options(self._lib, vdt, stream, ell=ell, **opts)
+        if workspace is not None:   # not supported for batches: the library says so
+            self.options.workspace = ctypes.c_void_p(workspace.data_ptr())
+            self.options.workspace_bytes = workspace.numel() * workspace.element_size()
         self.problems = problems
         self.ell = int(ell)
         arr = (ProblemStruct * len(problems))()
@@ -398,6 +409,18 @@ class SGKSBatch:
             self.close()
         except Exception:
             pass
+
+
+def workspace_bytes(A: DeviceCsr, L: DeviceCsr, s, *, ell=3, value_dtype="f32", **opts):
+    """Device bytes a context of these shapes and options uses (sgks_workspace_bytes)."""
+    lib = load_library()
+
+    class _S:   # the stream is not needed for the size
+        cuda_stream = 0
+    o = make_options(lib, F32 if value_dtype == "f32" else F64, _S(), ell=ell, **opts)
+    As, Ls = A.struct(), L.struct()
+    return int(lib.sgks_workspace_bytes(ctypes.byref(As), ctypes.byref(Ls), int(s),
+                                        ctypes.byref(o)))
 
 
 def upload_problem(P, device="cuda"):

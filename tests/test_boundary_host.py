@@ -129,6 +129,7 @@ int main(void) {
            offsetof(sgks_options, stream), sizeof(sgks_problem), offsetof(sgks_problem, b),
            offsetof(sgks_problem, seed));
     printf("%zu %zu\n", sizeof(sgks_csr), offsetof(sgks_problem, sketch_rows));
+    printf("%zu %zu\n", offsetof(sgks_options, workspace), offsetof(sgks_options, workspace_bytes));
     return 0;
 }
 """
@@ -145,4 +146,25 @@ def test_struct_layouts_match_the_header(tmp_path):
     got = [int(v) for v in out]
     O, P = G.Options, G.ProblemStruct
     assert got == [ctypes.sizeof(O), O.graph.offset, O.stream.offset, ctypes.sizeof(P),
-                   P.b.offset, P.seed.offset, ctypes.sizeof(G.CsrStruct), P.sketch_rows.offset]
+                   P.b.offset, P.seed.offset, ctypes.sizeof(G.CsrStruct), P.sketch_rows.offset,
+                   O.workspace.offset, O.workspace_bytes.offset]
+
+
+def test_workspace_bytes_host_only(lib):
+    """Size of a context's device memory without touching the device."""
+    A, L = _csr(100, 80, 500), _csr(160, 80, 320)
+
+    def ws(s=400, **kw):
+        o = G.default_options()
+        o.max_iters = kw.pop("max_iters", 100)
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return lib.sgks_workspace_bytes(ctypes.byref(A), ctypes.byref(L), s, ctypes.byref(o))
+
+    base = ws()
+    assert base > 0
+    # W (and HW) grow with the capacity: 8 bytes per unknown per column each
+    assert ws(max_iters=150) - base >= 2 * 8 * 80 * 50
+    assert ws(gradient_form=G.GRADIENT_DIRECT) < base       # no HW
+    assert ws(s=50) == 0                                     # invalid: s < ell + max_iters
+    assert ws(zeta=3) == 0

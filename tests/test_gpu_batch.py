@@ -249,3 +249,34 @@ def test_batch_mixing_compact_and_chain_appends():
         say(f"  problem {i} s = {sizes[i]} rel err {e:.3e}")
         assert e <= 1e-8
     B.close()
+
+
+def test_caller_workspace():
+    """Every array of the context in caller-owned device memory (sgks_workspace_bytes):
+    bitwise the same solve as with the library's own allocation; too small or
+    misaligned workspaces are rejected."""
+    P = problem("ct2d", "small")
+    say("case workspace")
+    A, L, b = G.upload_problem(P)
+    kw = dict(ell=P.ell, max_iters=P.k, zeta=P.zeta, refine_steps=P.refine_steps)
+    nbytes = G.workspace_bytes(A, L, P.s, value_dtype=P.dtype, **kw)
+    say("  workspace bytes", nbytes)
+    assert nbytes > 0
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    S1 = G.SGKS(A, L, b, P.mu, P.s, P.seed, workspace=ws[:nbytes], **kw)
+    S1.iterate(P.k)
+    S2 = G.SGKS(A, L, b, P.mu, P.s, P.seed, **kw)
+    S2.iterate(P.k)
+    assert np.array_equal(S1.solution().cpu().numpy(), S2.solution().cpu().numpy())
+    assert S1.status() == S2.status() == (0, P.k)
+    S1.close()
+    S2.close()
+    with pytest.raises(G.SgksError) as e:
+        G.SGKS(A, L, b, P.mu, P.s, P.seed, workspace=ws[:nbytes - 8], **kw)
+    assert e.value.code == -1
+    with pytest.raises(G.SgksError) as e:
+        G.SGKS(A, L, b, P.mu, P.s, P.seed, workspace=ws[8:nbytes + 8], **kw)
+    assert e.value.code == -1
+    with pytest.raises(G.SgksError) as e:
+        G.SGKSBatch([(A, L, b, P.mu, P.s, P.seed)], workspace=ws, **kw)
+    assert e.value.code == -1

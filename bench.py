@@ -33,6 +33,16 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 
+# The paper's own timings, quoted as context only (another machine, another sketch,
+# other test problems; not a target): Sec. 4.2.2, Exp. 3 (seismic travel-time
+# tomography) and Sec. 4.3, Exp. 4 (dynamic CT), totals divided by the iteration count.
+PAPER_CONTEXT = {
+    "note": "context only: laptop CPU, MATLAB, FP64, SRTT sketch, other test problems",
+    "hardware": "Intel Core i7-8750H @ 2.2 GHz, 128 GB RAM",
+    "exp3_travel_time_n65536": {"sgks_total_s": 27, "iterations": 300, "iters_per_s": 11.1},
+    "exp4_dynamic_ct_n655360": {"sgks_total_s": 33, "iterations": 400, "iters_per_s": 12.1},
+}
+
 
 def log(*a):
     """Progress on stderr (the JSON line is the only stdout output)."""
@@ -321,6 +331,7 @@ def main():
             "launch": "kernel by kernel" if args.eager else "graph replay (8 expansions per graph)",
             "gradient_form": args.gradient,
         },
+        "paper_context": PAPER_CONTEXT,
         "setup_ms_per_step": 1e3 * acc["setup_s"] / args.steps,
         "launch_shapes": acc.get("tuning"),
         "iterate_only_iters_per_s": args.steps * P.k / iter_s if iter_s > 0 else None,

@@ -15,7 +15,7 @@ Large-Scale Regularization"):
     loss ratio eq:loss_criterion
   * sGKS, Alg. 2 (Sec. 3): no reorthogonalisation, sketch-and-solve projected
     problem eq:projected_sketched_bis with two independent sketches S_A, S_L
-  * iterative refinement of the projected solve (end of Sec. 3.1; Sec. 4.2.3)
+  * iterative refinement of the projected solve (end of Sec. 3.1; Sec. 4.3)
   * a frozen-basis adjoint of the final projected solve (not in the paper)
   * the sparse-sign embedding (the paper uses an SRTT, eq:sketching_trig, and
     states the method is independent of the embedding, Sec. 2.2)

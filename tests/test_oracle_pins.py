@@ -337,7 +337,7 @@ def test_refinement_converges_to_unsketched_projected_solution(s):
 
 
 def test_sgks_with_refinement_tracks_gks_better():
-    """With IR the sGKS iterate is closer to the unsketched (GKS) iterate (Sec. 4.2.3)."""
+    """With IR the sGKS iterate is closer to the unsketched (GKS) iterate (Sec. 4.3)."""
     A, L, b, mu = tiny2d(N=10)
     g = O.gks(A, L, b, mu, 10)
     plain = O.sgks(A, L, b, mu, 10, 30, 1)

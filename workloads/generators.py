@@ -14,7 +14,7 @@ Problem families (the paper's workloads stand-ins, Sec. 4):
   * Straight-ray travel-time tomography between boundary sources and
     receivers (Sec. 4.2.2 uses PRseismic, m about 6n).
   * Dynamic CT: block-diagonal A over frames, space-time difference operator
-    (Sec. 4.2.3, eq:blockF, eq:spacetime_tik).
+    (Sec. 4.3, eq:blockF, eq:spacetime_tik).
 Noise follows Sec. 4: e is white Gaussian scaled so that ||e|| / ||A x|| is
 exactly the requested level.
 

@@ -3,13 +3,17 @@
 // Bulk kernels are bandwidth bound (sparse and dense matrix-vector products,
 // O(1) flop per byte): CSR rows are processed by groups of `lanes` lanes of a
 // wavefront with a power-of-two group width, FP64 accumulation, and shuffle
-// reductions inside the group.  The sparse-sign sketch rides inside the SpMV:
-// each wave keeps a private copy of the s sketch bins in LDS, the row pattern
-// of the embedding is regenerated from its counter-based hash, and partial
-// bins are merged in a fixed order, so results are reproducible run to run.
-// The small FP64 steps (rank-one QR appends, the stacked projected factor and
-// the projected solve) run in one cooperative launch of a few workgroups that
-// each own a slab of rows and meet at a bounded-spin grid barrier.
+// reductions inside the group; workgroups take row ranges in an XCD-aware
+// order.  The sparse-sign sketch is a scatter of the new column's images
+// through the embedding's pattern (computed once from its counter-based hash
+// and kept as int16 signed rows): each wave adds its tiles into private LDS
+// bins and the partial bins are merged in a fixed order, so results are
+// reproducible run to run.  The small FP64 steps (rank-one QR appends on the
+// sketched matrices, the stacked projected factor and the projected solve)
+// are a few one-workgroup launches per problem, or, for large sketches, a
+// chain of launches whose workgroups each own a slab of rows.  Every kernel
+// reads its problem from a device array of States through a table of
+// workgroup ranges, so a batch of problems shares each launch.
 #include <hipcub/hipcub.hpp>
 
 #include "sgks_internal.h"
@@ -24,6 +28,37 @@ __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
     return v;
+}
+
+// Totals of N = 2^m values per lane over the 64 lanes of a wave, transposed:
+// each of the first m butterfly steps sends half of the lane's values to its
+// partner and keeps the other half, so that lane l ends with value
+// l / (64 / N); the remaining steps sum within groups of 64 / N lanes.  Every
+// lane of a group returns the same total (a fixed order, as for wave_sum), at
+// about 2 N + 6 - m shuffles instead of 6 N.
+template <int N>
+__device__ __forceinline__ double wave_sum_scatter(const double (&v)[N]) {
+    static_assert(N >= 1 && N <= 64 && (N & (N - 1)) == 0, "power-of-two count");
+    const int lane = threadIdx.x & 63;
+    double w[N];
+#pragma unroll
+    for (int n = 0; n < N; ++n) w[n] = v[n];
+    int off = 32;
+#pragma unroll
+    for (int half = N / 2; half >= 1; half >>= 1) {
+        const bool up = (lane & off) != 0;
+#pragma unroll
+        for (int n = 0; n < half; ++n) {
+            const double send = up ? w[n] : w[n + half];
+            const double keep = up ? w[n + half] : w[n];
+            w[n] = keep + __shfl_xor(send, off);
+        }
+        off >>= 1;
+    }
+    double t = w[0];
+#pragma unroll
+    for (int o = 32 / N; o > 0; o >>= 1) t += __shfl_xor(t, o);
+    return t;
 }
 
 template <int V>
@@ -81,15 +116,26 @@ __device__ __forceinline__ double strided_dot(const double* __restrict__ p, int6
     return acc;
 }
 
-// Block-wide product of an upper-triangular d x d matrix with v, element
-// (i, j), j >= i, stored at M[i * rs + j * cs]:
+// Element (i, j) of an upper-triangular matrix in memory at p[i rs + j cs]
+// (only i <= j is read).
+struct GTri {
+    const double* __restrict__ p;
+    int64_t rs, cs;
+    __device__ __forceinline__ double operator()(int i, int j) const {
+        return p[(int64_t)i * rs + (int64_t)j * cs];
+    }
+};
+// Product of an upper-triangular d x d matrix M with v by the first NT
+// threads of the block (the others return at once):
 //   trans = 0: out[k] = sum_{j >= k} M(k, j) v[j]
 //   trans = 1: out[k] = sum_{i <= k} M(i, k) v[i]
 // Groups of tpr lanes share one output, each lane taking every tpr-th term
-// with eight loads in flight; the group sums with shuffles (fixed order).
-__device__ void tri_mv(const double* __restrict__ M, int64_t rs, int64_t cs, int d, int trans,
-                       const double* v, double* out) {
-    const int NT = blockDim.x;
+// with eight loads in flight; the group sums with shuffles (fixed order, the
+// same for every accessor).
+template <class Mat>
+__device__ void tri_mv_t(const Mat& M, int d, int trans, const double* v, double* out,
+                         int NT) {
+    if ((int)threadIdx.x >= NT) return;
     int tpr = 64;
     while (tpr > 1 && NT / tpr < d) tpr >>= 1;
     const int rpp = NT / tpr;
@@ -104,8 +150,7 @@ __device__ void tri_mv(const double* __restrict__ M, int64_t rs, int64_t cs, int
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     const int idx = min(q + u * tpr, hi - 1);   // clamped: loads stay unconditional
-                    w[u] = trans ? M[(int64_t)idx * rs + (int64_t)k * cs]
-                                 : M[(int64_t)k * rs + (int64_t)idx * cs];
+                    w[u] = trans ? M(idx, k) : M(k, idx);
                 }
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
@@ -119,12 +164,17 @@ __device__ void tri_mv(const double* __restrict__ M, int64_t rs, int64_t cs, int
     }
 }
 
-// out1[k] = sum_{j >= k, j < d} M(k, j) v1[j], out2[k] likewise with v2
-// (upper-triangular M, element (i, j) at M[i * rs + j * cs]); the tri_mv
-// scheme with both products sharing the loads of M.
-__device__ void tri_mv2(const double* __restrict__ M, int64_t rs, int64_t cs, int d,
-                        const double* v1, const double* v2, double* out1, double* out2) {
-    const int NT = blockDim.x;
+__device__ void tri_mv(const double* __restrict__ M, int64_t rs, int64_t cs, int d, int trans,
+                       const double* v, double* out) {
+    tri_mv_t(GTri{M, rs, cs}, d, trans, v, out, blockDim.x);
+}
+
+// out1[k] = sum_{j >= k, j < d} M(k, j) v1[j], out2[k] likewise with v2; the
+// tri_mv scheme with both products sharing the loads of M.
+template <class Mat>
+__device__ void tri_mv2_t(const Mat& M, int d, const double* v1, const double* v2, double* out1,
+                          double* out2, int NT) {
+    if ((int)threadIdx.x >= NT) return;
     int tpr = 64;
     while (tpr > 1 && NT / tpr < d) tpr >>= 1;
     const int rpp = NT / tpr;
@@ -136,7 +186,7 @@ __device__ void tri_mv2(const double* __restrict__ M, int64_t rs, int64_t cs, in
             for (int q = k + c; q < d; q += 8 * tpr) {
                 double w[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) w[u] = M[(int64_t)k * rs + (int64_t)min(q + u * tpr, d - 1) * cs];
+                for (int u = 0; u < 8; ++u) w[u] = M(k, min(q + u * tpr, d - 1));
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     const int idx = q + u * tpr;
@@ -158,14 +208,14 @@ __device__ void tri_mv2(const double* __restrict__ M, int64_t rs, int64_t cs, in
     }
 }
 
-// Two upper-triangular d x d matrices Ma, Mb, element (i, k), i <= k, at
-// M[i * rs + k * cs]; groups of tpr lanes share one output as in tri_mv.
-//   tri_dot2t:  out[k] = sum_{i <= k} (Ma(i, k) va[i] + Mb(i, k) vb[i])
-//   tri_apply2: outa[i] = sum_{k >= i} Ma(i, k) v[k], outb[i] = sum_{k >= i} Mb(i, k) v[k]
-__device__ void tri_dot2t(const double* __restrict__ Ma, const double* __restrict__ Mb,
-                          int64_t rs, int64_t cs, int d, const double* va, const double* vb,
-                          double* out) {
-    const int NT = blockDim.x;
+// Two upper-triangular d x d matrices Ma, Mb; groups of tpr lanes share one
+// output as in tri_mv_t.
+//   tri_dot2t_t:  out[k] = sum_{i <= k} (Ma(i, k) va[i] + Mb(i, k) vb[i])
+//   tri_apply2_t: outa[i] = sum_{k >= i} Ma(i, k) v[k], outb[i] = sum_{k >= i} Mb(i, k) v[k]
+template <class Mat>
+__device__ void tri_dot2t_t(const Mat& Ma, const Mat& Mb, int d, const double* va,
+                            const double* vb, double* out, int NT) {
+    if ((int)threadIdx.x >= NT) return;
     int tpr = 64;
     while (tpr > 1 && NT / tpr < d) tpr >>= 1;
     const int rpp = NT / tpr;
@@ -178,9 +228,9 @@ __device__ void tri_dot2t(const double* __restrict__ Ma, const double* __restric
                 double wa[8], wb[8];
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
-                    const int64_t o = (int64_t)min(q + u * tpr, k) * rs + (int64_t)k * cs;
-                    wa[u] = Ma[o];
-                    wb[u] = Mb[o];
+                    const int i = min(q + u * tpr, k);
+                    wa[u] = Ma(i, k);
+                    wb[u] = Mb(i, k);
                 }
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
@@ -194,10 +244,10 @@ __device__ void tri_dot2t(const double* __restrict__ Ma, const double* __restric
     }
 }
 
-__device__ void tri_apply2(const double* __restrict__ Ma, const double* __restrict__ Mb,
-                           int64_t rs, int64_t cs, int d, const double* v, double* outa,
-                           double* outb) {
-    const int NT = blockDim.x;
+template <class Mat>
+__device__ void tri_apply2_t(const Mat& Ma, const Mat& Mb, int d, const double* v, double* outa,
+                             double* outb, int NT) {
+    if ((int)threadIdx.x >= NT) return;
     int tpr = 64;
     while (tpr > 1 && NT / tpr < d) tpr >>= 1;
     const int rpp = NT / tpr;
@@ -210,9 +260,9 @@ __device__ void tri_apply2(const double* __restrict__ Ma, const double* __restri
                 double wa[8], wb[8];
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
-                    const int64_t o = (int64_t)i * rs + (int64_t)min(q + u * tpr, d - 1) * cs;
-                    wa[u] = Ma[o];
-                    wb[u] = Mb[o];
+                    const int k = min(q + u * tpr, d - 1);
+                    wa[u] = Ma(i, k);
+                    wb[u] = Mb(i, k);
                 }
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
@@ -233,6 +283,23 @@ __device__ void tri_apply2(const double* __restrict__ Ma, const double* __restri
             outb[i] = ab;
         }
     }
+}
+
+__device__ void tri_mv2(const double* __restrict__ M, int64_t rs, int64_t cs, int d,
+                        const double* v1, const double* v2, double* out1, double* out2) {
+    tri_mv2_t(GTri{M, rs, cs}, d, v1, v2, out1, out2, blockDim.x);
+}
+
+__device__ void tri_dot2t(const double* __restrict__ Ma, const double* __restrict__ Mb,
+                          int64_t rs, int64_t cs, int d, const double* va, const double* vb,
+                          double* out) {
+    tri_dot2t_t(GTri{Ma, rs, cs}, GTri{Mb, rs, cs}, d, va, vb, out, blockDim.x);
+}
+
+__device__ void tri_apply2(const double* __restrict__ Ma, const double* __restrict__ Mb,
+                           int64_t rs, int64_t cs, int d, const double* v, double* outa,
+                           double* outb) {
+    tri_apply2_t(GTri{Ma, rs, cs}, GTri{Mb, rs, cs}, d, v, outa, outb, blockDim.x);
 }
 
 // Thread-strided sum of p[i], i = threadIdx.x, threadIdx.x + T, ... < n,
@@ -1367,79 +1434,131 @@ __global__ __launch_bounds__(1024) void k_yfix(const State* __restrict__ SS, BTa
 
 constexpr int kAp1Threads = 1024;
 
-// out[j] = sum_{i < nr} (Ma[j ld + i] va[i] [+ Mb[j ld + i] vb[i]]) for j < d
-// (va, vb, out in LDS).  Each wave takes four columns at a time, lanes over
-// rows, four row loads per column in flight (two per matrix for two) from
-// clamped addresses; the wave sums in a fixed order.
-template <bool TWO>
-__device__ void wg_col_dots(const double* __restrict__ Ma, const double* __restrict__ Mb,
-                            int64_t ld, int nr, int d, const double* va, const double* vb,
-                            double* out) {
-    constexpr int C = 4, R = TWO ? 2 : 4;   // loads in flight: C R per matrix
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    if (nr <= 0) {
-        for (int j = threadIdx.x; j < d; j += blockDim.x) out[j] = 0.0;
-        return;
+// Raw buffer view of the `bytes` bytes at p (the 32-bit data format of CDNA
+// buffer resources, no stride): a load whose vector offset plus immediate
+// offset reaches `bytes` returns zero instead of reading memory.  The scalar
+// offset is added to the address but not checked.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_view(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes,
+                                             0x00020000);
+}
+
+__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                           uint32_t soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
+// out[j] = sum_{i < s} Q[j s + i] a[i] for j < d: Q column-major s x d in
+// memory, a and out in LDS.  Wave w takes C consecutive columns at a time
+// (C w + C nw t); lane l holds a at rows l + 64 u (u < R, 64 R >= s, zero past
+// s), so the reads of a column past row s meet zeros, and reads past the d
+// columns return zero.  All C R loads of a lane are in flight together; the
+// C column sums of a wave are reduced together.
+template <int R, int C>
+__device__ void col_dots(const double* __restrict__ Q, int s, int d, const double* a,
+                         double* out) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nw = blockDim.x >> 6;
+    const __amdgpu_buffer_rsrc_t rq = buf_view(Q, (uint32_t)s * (uint32_t)d * 8u);
+    double av[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+        const int i = lane + 64 * u;
+        av[u] = i < s ? a[i] : 0.0;
     }
-    for (int j0 = wave * C; j0 < d; j0 += nw * C) {
+    for (int j0 = C * wave; j0 < d; j0 += C * nw) {
+        double q[C][R];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const uint32_t vo = ((uint32_t)(j0 + c) * (uint32_t)s + (uint32_t)lane) * 8u;
+#pragma unroll
+            for (int u = 0; u < R; ++u) q[c][u] = buf_load(rq, vo + 512u * u, 0u);
+        }
         double acc[C];
 #pragma unroll
-        for (int c = 0; c < C; ++c) acc[c] = 0.0;
-        for (int i0 = 0; i0 < nr; i0 += 64 * R) {
-            double wa[C][R], wb[C][R];
+        for (int c = 0; c < C; ++c) {
+            acc[c] = 0.0;
 #pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const int64_t col = (int64_t)min(j0 + c, d - 1) * ld;
-#pragma unroll
-                for (int u = 0; u < R; ++u) {
-                    const int i = min(i0 + lane + 64 * u, nr - 1);
-                    wa[c][u] = Ma[col + i];
-                    if (TWO) wb[c][u] = Mb[col + i];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < R; ++u) {
-                const int i = i0 + lane + 64 * u;
-                if (i < nr) {
-                    const double a = va[i];
-                    const double b = TWO ? vb[i] : 0.0;
-#pragma unroll
-                    for (int c = 0; c < C; ++c)
-                        acc[c] += TWO ? wa[c][u] * a + wb[c][u] * b : wa[c][u] * a;
-                }
-            }
+            for (int u = 0; u < R; ++u) acc[c] += q[c][u] * av[u];
         }
-#pragma unroll
-        for (int c = 0; c < C; ++c) acc[c] = wave_sum(acc[c]);
-        if (lane == 0)
-#pragma unroll
-            for (int c = 0; c < C; ++c)
-                if (j0 + c < d) out[j0 + c] = acc[c];
+        const double t = wave_sum_scatter<C>(acc);
+        const int j = j0 + lane / (64 / C);
+        if (lane % (64 / C) == 0 && j < d) out[j] = t;
     }
 }
 
-// a[i] = scale * sum_b bins[b s + i], i < s; partial-bin blocks split among
-// threads in contiguous chunks added in chunk order.
-__device__ void wg_reduce_bins(const double* __restrict__ bins, int nb, int s, double scale,
-                               double* a, double* scr) {
-    const int T = blockDim.x, tid = threadIdx.x;
-    const int nq = s >= T ? 1 : T / s;
-    if (nq == 1) {
-        for (int i = tid; i < s; i += T) a[i] = scale * strided_sum(bins + i, s, nb);
-    } else {
-        const int i = tid % s, q = tid / s;
-        if (q < nq) {
-            const int b0 = (int)((int64_t)nb * q / nq), b1 = (int)((int64_t)nb * (q + 1) / nq);
-            scr[q * s + i] = strided_sum(bins + (int64_t)b0 * s + i, s, b1 - b0);
+// a[i] -= sum_{j < d} Q[j s + i] p[j] for i < s (Q as in col_dots, p and a in
+// LDS).  Wave w takes the rows 64 (w % NR) + lane (NR = ceil(s / 64) chunks)
+// and the columns of contiguous part w / NR of P = max(1, nw / NR) parts, C
+// columns' loads in flight; the parts' sums meet in scr (P 64 NR <= blockDim
+// doubles) and are added in part order.
+template <int C>
+__device__ void col_apply(const double* __restrict__ Q, int s, int d, const double* p, double* a,
+                          double* scr) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nw = blockDim.x >> 6;
+    const int NR = (s + 63) / 64;
+    const int P = NR >= nw ? 1 : nw / NR;
+    const __amdgpu_buffer_rsrc_t rq = buf_view(Q, (uint32_t)s * (uint32_t)d * 8u);
+    __syncthreads();   // p and a were just written by other threads
+    for (int g = wave; g < NR * P; g += nw) {
+        const int rc = g % NR, cp = g / NR;
+        const int i = 64 * rc + lane;
+        const int j0 = (int)((int64_t)d * cp / P), j1 = (int)((int64_t)d * (cp + 1) / P);
+        double acc = 0.0;
+        for (int j = j0; j < j1; j += C) {
+            double q[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                q[c] = buf_load(rq, ((uint32_t)(j + c) * (uint32_t)s + (uint32_t)i) * 8u, 0u);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const double pj = j + c < j1 ? p[j + c] : 0.0;
+                acc += q[c] * pj;
+            }
         }
-        __syncthreads();
-        for (int r = tid; r < s; r += T) {
-            double acc = 0.0;
-            for (int qq = 0; qq < nq; ++qq) acc += scr[qq * s + r];
-            a[r] = scale * acc;
-        }
+        if (i < s) scr[cp * 64 * NR + i] = acc;
     }
     __syncthreads();
+    for (int i = threadIdx.x; i < s; i += blockDim.x) {
+        double t = 0.0;
+        for (int cp = 0; cp < P; ++cp) t += scr[cp * 64 * NR + i];
+        a[i] -= t;
+    }
+    __syncthreads();
+}
+
+// a[i] = scale * sum_{b < nb} bins[b s + i], i < s, blocks added in order,
+// sixteen loads in flight (the block offset is a scalar).
+__device__ void reduce_bins(const double* __restrict__ bins, int nb, int s, double scale,
+                            double* a) {
+    const __amdgpu_buffer_rsrc_t rb = buf_view(bins, (uint32_t)nb * (uint32_t)s * 8u);
+    for (int i = threadIdx.x; i < s; i += blockDim.x) {
+        const uint32_t vo = (uint32_t)i * 8u;
+        double acc = 0.0;
+        for (int b = 0; b < nb; b += 16) {
+            double v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                v[u] = buf_load(rb, vo + (uint32_t)min(b + u, nb - 1) * (uint32_t)s * 8u, 0u);
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                if (b + u < nb) acc += v[u];
+        }
+        a[i] = scale * acc;
+    }
+    __syncthreads();
+}
+
+// One CGS projection of the s-vector a against the d columns of Q:
+// p = Q^T a, a -= Q p.
+template <int R, int C>
+__device__ void side_project(const double* __restrict__ Q, int s, int d, double* a, double* p,
+                             double* scr) {
+    col_dots<R, C>(Q, s, d, a, p);
+    col_apply<16>(Q, s, d, p, a, scr);
 }
 
 struct Ap1Side {
@@ -1479,15 +1598,19 @@ __device__ void ap1_side_body(const State& S, int side, int scale_from_norm, Ap1
     const double bscale = S.sketch_mode == 1 ? scale : scale / sqrt((double)S.zeta);
     double* Q = side ? S.QL : S.QA;
     double* R = side ? S.RL : S.RA;
-    wg_reduce_bins(side ? S.binL : S.binA, side ? S.nbL : S.nbA, s, bscale, sh.a, sh.scr);
+    reduce_bins(side ? S.binL : S.binA, side ? S.nbL : S.nbA, s, bscale, sh.a);
     double n2 = 0.0;
     for (int i = tid; i < s; i += T) n2 += sh.a[i] * sh.a[i];
     n2 = block_sum(n2, sh.red);
     for (int pass = 0; pass < S.passes; ++pass) {
-        wg_col_dots<false>(Q, nullptr, s, s, d, sh.a, nullptr, sh.p);
-        __syncthreads();
+        if (s <= 256)
+            side_project<4, 4>(Q, s, d, sh.a, sh.p, sh.scr);
+        else if (s <= 512)
+            side_project<8, 4>(Q, s, d, sh.a, sh.p, sh.scr);
+        else
+            side_project<16, 2>(Q, s, d, sh.a, sh.p, sh.scr);
         for (int j = tid; j < d; j += T) sh.pt[j] = (pass ? sh.pt[j] : 0.0) + sh.p[j];
-        slab_apply<24>(Q, s, s, d, sh.p, sh.a, sh.scr);
+        __syncthreads();   // p is rewritten by the next projection
     }
     double r2 = 0.0, dl = 0.0;
     for (int i = tid; i < s; i += T) {

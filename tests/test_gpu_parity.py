@@ -103,6 +103,25 @@ def test_small_configs_trajectory(name):
     S.close()
 
 
+@pytest.mark.parametrize("s", [40, 64, 65, 200, 300, 520, 1000])
+def test_sketch_sizes_one_workgroup_append(s):
+    """Sketch sizes around the row-chunk and register-count boundaries of the
+    one-workgroup appends (s <= 256, <= 512, <= 1024; one and several 64-row
+    chunks, ragged last chunk), trajectory and factor relations."""
+    import dataclasses
+    P = dataclasses.replace(problem("deblur2d", "small"), s=s)
+    k = 12
+    say("case sketch size", s, "k", k)
+    ref = O.sgks(P.A, P.L, P.b, P.mu, k, P.s, P.seed, zeta=P.zeta, ell=P.ell)
+    S, x = G.solve_problem(P, k=k, append_groups=1)
+    assert S.tuning()["append_groups"] == 1   # the one-workgroup append ran
+    e = rel(x.cpu().numpy(), ref.x)
+    say("  rel err", e)
+    assert e <= 1e-8
+    check_state_consistency(S, P)
+    S.close()
+
+
 def test_identity_sketch_is_gks_prop1():
     """Prop. 1 on the GPU: with identity sketches the iterates are the GKS iterates."""
     P = problem("deblur1d", "small")

@@ -311,6 +311,25 @@ __device__ __forceinline__ double thread_strided_sum(const double* __restrict__ 
 }
 
 // Dot product of one CSR row with x by the V lanes of a group (lane g of V).
+// acc += sum_u va[k + u V] x[ci[k + u V]], u < U, in u order: all U index and
+// value loads are issued before the gathers
+template <int U, int V, typename T>
+__device__ __forceinline__ void row_chunk(const int32_t* __restrict__ ci, const T* __restrict__ va,
+                                          const double* __restrict__ x, int k, double& acc) {
+    int c[U];
+    T w[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        c[u] = ci[k + u * V];
+        w[u] = va[k + u * V];
+    }
+    double xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) xv[u] = x[c[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc += (double)w[u] * xv[u];
+}
+
 template <int V, typename T>
 __device__ __forceinline__ double row_dot(const Csr& M, const double* __restrict__ x, int64_t row,
                                           int g) {
@@ -319,9 +338,15 @@ __device__ __forceinline__ double row_dot(const Csr& M, const double* __restrict
     const int beg = M.rowptr[row], end = M.rowptr[row + 1];
     double acc = 0.0;
     int k = beg + g;
-    for (; k + V < end; k += 2 * V) {
-        acc += (double)va[k] * x[ci[k]];
-        acc += (double)va[k + V] * x[ci[k + V]];
+    // eight (then four, two) entries per lane in flight before the gathers of x
+    for (; k + 7 * V < end; k += 8 * V) row_chunk<8, V>(ci, va, x, k, acc);
+    if (k + 3 * V < end) {
+        row_chunk<4, V>(ci, va, x, k, acc);
+        k += 4 * V;
+    }
+    if (k + V < end) {
+        row_chunk<2, V>(ci, va, x, k, acc);
+        k += 2 * V;
     }
     if (k < end) acc += (double)va[k] * x[ci[k]];
     return group_sum<V>(acc);

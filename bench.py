@@ -109,6 +109,25 @@ def load_traffic(kernel, workload, shash):
     return t.get("bytes_per_launch")
 
 
+def load_trace_avg(kernel, workload, shash):
+    """Average duration (us) of a kernel in the committed rocprofv3 kernel-trace summary of
+    the workload, if that summary is of the current sources."""
+    f = os.path.join(ROOT, "profiles", f"kernel_trace_{workload}_k100.txt")
+    if not os.path.exists(f):
+        return None
+    lines = open(f).read().splitlines()
+    if not any(l.strip() == f"# source_hash: {shash}" for l in lines):
+        return None
+    for l in lines:
+        parts = l.split()
+        if parts and not l.startswith("#") and parts[0].split("<")[0].endswith("::" + kernel):
+            try:
+                return float(parts[-4])
+            except (ValueError, IndexError):
+                return None
+    return None
+
+
 def cpu_baseline(P, reps):
     import numpy as np
     from threadpoolctl import threadpool_limits
@@ -375,6 +394,12 @@ def main():
                            "traffic": traffic,
                            "algorithmic_bytes_per_launch": kern[dom]["bytes_per_launch"],
                            "avg_launch_us": kern[dom]["us_avg"], "source_hash": shash}
+        # the same kernel in the committed kernel trace (rocprofv3 times the kernel alone;
+        # the events above also hold its dispatch)
+        tavg = load_trace_avg(dom, P.name, shash)
+        if tavg:
+            out["roofline"]["rocprof_avg_us"] = tavg
+            out["roofline"]["achieved_at_rocprof_avg"] = kern[dom]["bytes_per_launch"] / (tavg * 1e-6) / 1e9
         sk = ["kb_forward", "kb_adjoint", "kb_scatter"]
         tb = sum(kern[k]["bytes_per_launch"] * kern[k]["launches"] for k in sk if k in kern)
         tt = sum(kern[k]["ms_total"] for k in sk if k in kern) * 1e-3

@@ -26,7 +26,8 @@ from workloads import generators as gen  # noqa: E402
 from workloads import make  # noqa: E402
 
 
-from gpu_common import check_state_consistency, oracle_run, problem, rel, say  # noqa: E402
+from gpu_common import (KAPPA_TRUSTED, check_state_consistency, cond_at, oracle_run,  # noqa: E402
+                        problem, rel, say)
 
 
 # ----------------------------------------------------------------------------
@@ -119,6 +120,97 @@ def test_sketch_sizes_one_workgroup_append(s):
     say("  rel err", e)
     assert e <= 1e-8
     check_state_consistency(S, P)
+    S.close()
+
+
+def _ragged_problem():
+    """A 1003 x 997 random sparse operator (FP64) with ten empty rows and seven
+    empty columns, first differences with two empty rows: every size off the
+    tile grids."""
+    import scipy.sparse as sp
+    from workloads.generators import Problem
+    rng = np.random.default_rng(11)
+    m, n = 1003, 997
+    A = sp.random(m, n, density=0.02, random_state=rng, format="csr", dtype=np.float64)
+    keep_r = np.ones(m)
+    keep_r[rng.choice(m, 10, replace=False)] = 0.0
+    keep_c = np.ones(n)
+    keep_c[rng.choice(n, 7, replace=False)] = 0.0
+    A = (sp.diags(keep_r) @ A @ sp.diags(keep_c)).tocsr()
+    A.eliminate_zeros()
+    A.sort_indices()
+    D = sp.diags([-np.ones(n - 1), np.ones(n - 1)], [0, 1], shape=(n - 1, n), format="csr")
+    keep_l = np.ones(n - 1)
+    keep_l[[5, 500]] = 0.0
+    L = (sp.diags(keep_l) @ D).tocsr()
+    L.eliminate_zeros()
+    L.sort_indices()
+    x_true = rng.standard_normal(n)
+    b = A @ x_true + 0.01 * rng.standard_normal(m)
+    assert np.count_nonzero(np.diff(A.indptr) == 0) >= 10
+    assert np.count_nonzero(np.diff(L.indptr) == 0) == 2
+    return Problem("ragged", A, L, b, x_true, mu=1e-2, k=15, s=150, seed=5, dtype="f64")
+
+
+def test_ragged_operator_with_empty_rows_and_columns():
+    P = _ragged_problem()
+    say("case ragged", P.m, P.n, P.p, "nnz", P.A.nnz)
+    ref = oracle_run(P)
+    S, x = G.solve_problem(P)
+    kap = cond_at(ref, P, P.k)
+    e = rel(x.cpu().numpy(), ref.x)
+    say(f"  rel err {e:.3e} kappa {kap:.2e}")
+    assert kap <= KAPPA_TRUSTED
+    assert e <= max(1e-10, 1e-15 * kap * 10)
+    check_state_consistency(S, P)
+    S.close()
+
+
+@pytest.mark.parametrize("s,k", [(346, 343), (512, 509)])
+def test_max_basis_size(s, k):
+    """The largest bases on the small 2D deblurring operators: ell + k = 346 = s,
+    the largest one-workgroup append (s d_max <= 120000, s >= d_max), and
+    ell + k = 512 = s, the largest basis, on the append chain.  Trajectory while
+    the projected problem is trustworthy in FP64; at the end the factor
+    relations Q R = S A W (which hold also once sketched columns turn
+    numerically dependent)."""
+    import dataclasses
+    P = dataclasses.replace(problem("deblur2d", "small"), s=s, k=k)
+    say("case max basis", s)
+    ref = oracle_run(P, keep_history=True)
+    A, L, b = G.upload_problem(P)
+    S = G.SGKS(A, L, b, P.mu, P.s, P.seed, max_iters=P.k)
+    groups = S.tuning()["append_groups"]
+    assert (groups == 1) if s * (P.ell + P.k) <= 120000 else (groups > 1)
+    done = 0
+    checked = 0
+    for kk in (20, 60, 150, 300, k):
+        if kk > k:
+            break
+        S.iterate(kk - done)
+        done = kk
+        rc, it = S.status()
+        if rc != 0:
+            say("  stopped", rc, it)
+            assert rc == G.BREAKDOWN
+            break
+        kap = cond_at(ref, P, kk)
+        if kap <= KAPPA_TRUSTED:
+            e = rel(S.solution().cpu().numpy(), ref.x_hist[kk])
+            say(f"  k={kk} rel err {e:.3e} kappa {kap:.2e}")
+            assert e <= 1e-5
+            checked += 1
+    assert checked >= 1
+    W = S.state("W")
+    d = W.shape[1]
+    say("  basis size", d, "oracle", P.ell + ref.iters)
+    assert P.ell + 60 <= d <= P.ell + P.k
+    QA, RA, QL, RL = S.state("Q_A"), S.state("R_A"), S.state("Q_L"), S.state("R_L")
+    S_A, S_L = O.make_sketches(P.m, P.p, P.s, P.seed, P.zeta)
+    SAW, SLW = S_A @ (P.A @ W), S_L @ (P.L @ W)
+    assert np.linalg.norm(QA @ RA - SAW) <= 1e-9 * np.linalg.norm(SAW)
+    assert np.linalg.norm(QL @ RL - SLW) <= 1e-9 * np.linalg.norm(SLW)
+    assert np.allclose(np.triu(RA), RA) and np.allclose(np.triu(RL), RL)
     S.close()
 
 

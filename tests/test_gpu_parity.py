@@ -214,6 +214,22 @@ def test_max_basis_size(s, k):
     S.close()
 
 
+@pytest.mark.parametrize("groups", [1, 4])
+def test_single_projection_append(groups):
+    """qr_passes = 1: one CGS projection per column append, as the rank-one QR
+    update is written in Sec. 2.1, on the one-workgroup append and the chain."""
+    P = problem("deblur2d", "small")
+    k = 16
+    say("case single projection, append groups", groups)
+    ref = O.sgks(P.A, P.L, P.b, P.mu, k, P.s, P.seed, zeta=P.zeta, ell=P.ell, qr_passes=1)
+    S, x = G.solve_problem(P, k=k, qr_passes=1, append_groups=groups)
+    assert S.tuning()["append_groups"] == groups
+    e = rel(x.cpu().numpy(), ref.x)
+    say("  rel err", e)
+    assert e <= 1e-8
+    S.close()
+
+
 def test_identity_sketch_is_gks_prop1():
     """Prop. 1 on the GPU: with identity sketches the iterates are the GKS iterates."""
     P = problem("deblur1d", "small")

@@ -476,6 +476,8 @@ void layout_context(sgks_ctx* c, Arena& ar) {
     ar.add(&S.cs, dmax * 8);
     ar.add(&S.QA, (size_t)s * dmax * 8);
     ar.add(&S.QL, (size_t)s * dmax * 8);
+    ar.add(&S.QA32, (size_t)s * dmax * 4);
+    ar.add(&S.QL32, (size_t)s * dmax * 4);
     ar.add(&S.RA, (size_t)dmax * dmax * 8);
     ar.add(&S.RL, (size_t)dmax * dmax * 8);
     ar.add(&S.U, (size_t)2 * dmax * dmax * 8);

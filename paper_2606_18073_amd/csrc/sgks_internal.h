@@ -73,6 +73,11 @@ struct State {
     double* RA;        // dmax x dmax
     double* QL;        // s x dmax
     double* RL;        // dmax x dmax
+    // FP32 copies of Q_A, Q_L, kept by the one-workgroup append for the first of
+    // two projections (whose coefficients only need to be approximate: the
+    // FP64 second projection measures and removes what the first one left)
+    float* QA32;
+    float* QL32;
     double* U;         // (2 dmax) x dmax: rows [0,dmax) pair with R_A, rows [dmax,2dmax) with R_L
     double* G;         // dmax x dmax R factor of [R_A; sqrt(mu) R_L], then G^{-1}; both row-major
     double* h;         // dmax, U^T [d_A; 0]

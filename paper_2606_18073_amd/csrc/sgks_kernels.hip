@@ -1473,19 +1473,29 @@ __device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, uint32_t vo
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
 }
 
+// one element of type E (double or float) as a double
+template <typename E>
+__device__ __forceinline__ double buf_load_as(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
+    if constexpr (sizeof(E) == 8)
+        return buf_load(r, voff, 0u);
+    else
+        return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0u, 0));
+}
+
 // out[j] = sum_{i < s} Q[j s + i] a[i] for j < d: Q column-major s x d in
 // memory, a and out in LDS.  Wave w takes C consecutive columns at a time
 // (C w + C nw t); lane l holds a at rows l + 64 u (u < R, 64 R >= s, zero past
 // s), so the reads of a column past row s meet zeros, and reads past the d
 // columns return zero.  All C R loads of a lane are in flight together; the
 // C column sums of a wave are reduced together.
-template <int R, int C>
-__device__ void col_dots(const double* __restrict__ Q, int s, int d, const double* a,
+template <int R, int C, typename E = double>
+__device__ void col_dots(const E* __restrict__ Q, int s, int d, const double* a,
                          double* out) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nw = blockDim.x >> 6;
-    const __amdgpu_buffer_rsrc_t rq = buf_view(Q, (uint32_t)s * (uint32_t)d * 8u);
+    constexpr uint32_t es = sizeof(E);
+    const __amdgpu_buffer_rsrc_t rq = buf_view(Q, (uint32_t)s * (uint32_t)d * es);
     double av[R];
 #pragma unroll
     for (int u = 0; u < R; ++u) {
@@ -1496,9 +1506,9 @@ __device__ void col_dots(const double* __restrict__ Q, int s, int d, const doubl
         double q[C][R];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            const uint32_t vo = ((uint32_t)(j0 + c) * (uint32_t)s + (uint32_t)lane) * 8u;
+            const uint32_t vo = ((uint32_t)(j0 + c) * (uint32_t)s + (uint32_t)lane) * es;
 #pragma unroll
-            for (int u = 0; u < R; ++u) q[c][u] = buf_load(rq, vo + 512u * u, 0u);
+            for (int u = 0; u < R; ++u) q[c][u] = buf_load_as<E>(rq, vo + 64u * es * u);
         }
         double acc[C];
 #pragma unroll
@@ -1578,11 +1588,16 @@ __device__ void reduce_bins(const double* __restrict__ bins, int nb, int s, doub
 }
 
 // One CGS projection of the s-vector a against the d columns of Q:
-// p = Q^T a, a -= Q p.
+// p = Q^T a, a -= Q p.  With Q32 the coefficients p come from the FP32 copy
+// (the first of two projections); the update always uses the FP64 Q, so a
+// stays a - Q p exactly up to FP64 rounding whatever p is.
 template <int R, int C>
-__device__ void side_project(const double* __restrict__ Q, int s, int d, double* a, double* p,
-                             double* scr) {
-    col_dots<R, C>(Q, s, d, a, p);
+__device__ void side_project(const double* __restrict__ Q, const float* __restrict__ Q32, int s,
+                             int d, double* a, double* p, double* scr) {
+    if (Q32)
+        col_dots<R, C, float>(Q32, s, d, a, p);
+    else
+        col_dots<R, C>(Q, s, d, a, p);
     col_apply<16>(Q, s, d, p, a, scr);
 }
 
@@ -1627,13 +1642,15 @@ __device__ void ap1_side_body(const State& S, int side, int scale_from_norm, Ap1
     double n2 = 0.0;
     for (int i = tid; i < s; i += T) n2 += sh.a[i] * sh.a[i];
     n2 = block_sum(n2, sh.red);
+    float* Q32 = side ? S.QL32 : S.QA32;
     for (int pass = 0; pass < S.passes; ++pass) {
+        const float* q32 = pass == 0 && S.passes > 1 ? Q32 : nullptr;
         if (s <= 256)
-            side_project<4, 4>(Q, s, d, sh.a, sh.p, sh.scr);
+            side_project<4, 4>(Q, q32, s, d, sh.a, sh.p, sh.scr);
         else if (s <= 512)
-            side_project<8, 4>(Q, s, d, sh.a, sh.p, sh.scr);
+            side_project<8, 4>(Q, q32, s, d, sh.a, sh.p, sh.scr);
         else
-            side_project<16, 2>(Q, s, d, sh.a, sh.p, sh.scr);
+            side_project<16, 2>(Q, q32, s, d, sh.a, sh.p, sh.scr);
         for (int j = tid; j < d; j += T) sh.pt[j] = (pass ? sh.pt[j] : 0.0) + sh.p[j];
         __syncthreads();   // p is rewritten by the next projection
     }
@@ -1648,7 +1665,11 @@ __device__ void ap1_side_body(const State& S, int side, int scale_from_norm, Ap1
     const bool deg = !(rho > 1e-14 * sqrt(n2));
     if (deg) rho = 0.0;
     const double qs = deg ? 0.0 : 1.0 / rho;
-    for (int i = tid; i < s; i += T) Q[(int64_t)d * s + i] = sh.a[i] * qs;
+    for (int i = tid; i < s; i += T) {
+        const double q = sh.a[i] * qs;
+        Q[(int64_t)d * s + i] = q;
+        Q32[(int64_t)d * s + i] = (float)q;
+    }
     for (int j = tid; j < d; j += T) {
         R[(int64_t)d * dmax + j] = sh.pt[j];
         S.pacc[(int64_t)(2 + side) * dmax + j] = sh.pt[j];

@@ -1457,7 +1457,7 @@ __global__ __launch_bounds__(1024) void k_yfix(const State* __restrict__ SS, BTa
 // reads global memory it wrote itself.
 // ---------------------------------------------------------------------------
 
-constexpr int kAp1Threads = 1024;
+constexpr int kAp1Threads = 512;
 
 // Raw buffer view of the `bytes` bytes at p (the 32-bit data format of CDNA
 // buffer resources, no stride): a load whose vector offset plus immediate
@@ -1526,8 +1526,8 @@ __device__ void col_dots(const E* __restrict__ Q, int s, int d, const double* a,
 // a[i] -= sum_{j < d} Q[j s + i] p[j] for i < s (Q as in col_dots, p and a in
 // LDS).  Wave w takes the rows 64 (w % NR) + lane (NR = ceil(s / 64) chunks)
 // and the columns of contiguous part w / NR of P = max(1, nw / NR) parts, C
-// columns' loads in flight; the parts' sums meet in scr (P 64 NR <= blockDim
-// doubles) and are added in part order.
+// columns' loads in flight; the parts' sums meet in scr (P 64 NR doubles, at
+// most max(blockDim, 64 ceil(s / 64))) and are added in part order.
 template <int C>
 __device__ void col_apply(const double* __restrict__ Q, int s, int d, const double* p, double* a,
                           double* scr) {
@@ -1605,7 +1605,7 @@ struct Ap1Side {
     double a[kMaxS];
     double p[kMaxD];     // coefficients of the current projection
     double pt[kMaxD];    // their sum over the projections
-    double scr[kAp1Threads];
+    double scr[kMaxS > kAp1Threads ? kMaxS : kAp1Threads];   // col_apply partials
     double red[kAp1Threads / 64];
 };
 
@@ -1729,12 +1729,17 @@ struct Ap1Stack {
 // the new columns of U, G and G^{-1}, h, y = G^{-1} h and one residual
 // correction y <- y + G^{-1} (h - G y); then d advances.  Breakdown when the
 // projected column is dependent.  One workgroup per problem.
-__global__ __launch_bounds__(kAp1Threads) void k_ap1_stack(const State* __restrict__ SS,
+// threads of the stacked step: its phases are short chains of dependent
+// loads and reductions, where fewer waves per SIMD cost fewer cycles per
+// instruction
+constexpr int kStackThreads = 512;
+
+__global__ __launch_bounds__(kStackThreads) void k_ap1_stack(const State* __restrict__ SS,
                                                           BTab tab) {
     __shared__ Ap1Stack sh;
     const State S = load_state(SS, find_slot(tab).p);
     if (*S.status != 0) return;
-    const int d = *S.d, dmax = S.dmax, ld2 = 2 * dmax, tid = threadIdx.x, T = kAp1Threads;
+    const int d = *S.d, dmax = S.dmax, ld2 = 2 * dmax, tid = threadIdx.x, T = kStackThreads;
     const double rhoA = S.scal[12], rhoL = S.scal[13];
     const double dAnew = S.dA[d];
     const double new2 = rhoA * rhoA + S.mu * rhoL * rhoL;   // new rows, orthogonal to U
@@ -2343,7 +2348,7 @@ int plan_append(const Plan& P, bool scale_from_norm, bool with_hw, hipStream_t s
         else
             hipLaunchKernelGGL(k_ap1_side_hw<double>, dim3(tab_total(P.ap1_side_hw)),
                                dim3(kAp1Threads), 0, st, P.SS, P.ap1_side_hw, sfn);
-        hipLaunchKernelGGL(k_ap1_stack, dim3(tab_total(P.ap1_stack)), dim3(kAp1Threads), 0, st,
+        hipLaunchKernelGGL(k_ap1_stack, dim3(tab_total(P.ap1_stack)), dim3(kStackThreads), 0, st,
                            P.SS, P.ap1_stack);
     }
     if (tab_total(P.ap) > 0) {

@@ -700,22 +700,22 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
         sgks_destroy(c);
         return SGKS_ERR_INVALID_ARG;
     }
-    SGKS_TRY(hipMemsetAsync(S.cs, 0, dmax * 8, st));
-    SGKS_TRY(hipMemsetAsync(S.QA, 0, (size_t)s * dmax * 8, st));
-    SGKS_TRY(hipMemsetAsync(S.QL, 0, (size_t)s * dmax * 8, st));
-    SGKS_TRY(hipMemsetAsync(S.RA, 0, (size_t)dmax * dmax * 8, st));
-    SGKS_TRY(hipMemsetAsync(S.RL, 0, (size_t)dmax * dmax * 8, st));
-    SGKS_TRY(hipMemsetAsync(S.U, 0, (size_t)2 * dmax * dmax * 8, st));
-    SGKS_TRY(hipMemsetAsync(S.G, 0, (size_t)2 * dmax * dmax * 8, st));
-    SGKS_TRY(hipMemsetAsync(S.h, 0, dmax * 8, st));
-    SGKS_TRY(hipMemsetAsync(S.dA, 0, dmax * 8, st));
-    SGKS_TRY(hipMemsetAsync(S.y, 0, dmax * 8, st));
-    SGKS_TRY(hipMemsetAsync(S.yprev, 0, dmax * 8, st));
-    SGKS_TRY(hipMemsetAsync(S.wu, 0, 2 * dmax * 8, st));
-    SGKS_TRY(hipMemsetAsync(S.scal, 0, (16 + 2 * dmax) * 8, st));
-    SGKS_TRY(hipMemsetAsync(S.d, 0, 64, st));
-    SGKS_TRY(hipMemsetAsync(S.status, 0, 64, st));
-    SGKS_TRY(hipMemsetAsync(S.degenerate, 0, 64, st));
+    // the small state starts at zero: two contiguous runs of the arena (cs ..
+    // yprev and wa .. degenerate, laid out in that order by layout_context;
+    // the scratch pieces between them are written before they are read)
+    {
+        char* a0 = (char*)S.cs;
+        char* a1 = (char*)(S.yprev + dmax);
+        char* b0 = (char*)S.wa;
+        char* b1 = (char*)S.degenerate + 64;
+        if (!(a0 < a1 && b0 < b1 && (char*)S.QA > a0 && (char*)S.dA < a1 &&
+              (char*)S.scal > b0 && (char*)S.d < b1)) {
+            sgks_destroy(c);
+            return SGKS_ERR_HIP;
+        }
+        SGKS_TRY(hipMemsetAsync(a0, 0, (size_t)(a1 - a0), st));
+        SGKS_TRY(hipMemsetAsync(b0, 0, (size_t)(b1 - b0), st));
+    }
 
     // b in FP64 and ||b||^2 (checked with everything else after the one
     // synchronisation at the end: a zero or non-finite b only makes the

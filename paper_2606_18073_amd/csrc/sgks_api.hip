@@ -505,6 +505,7 @@ void layout_context(sgks_ctx* c, Arena& ar) {
     ar.add(&S.d, 64);
     ar.add(&S.status, 64);
     ar.add(&S.degenerate, 64);
+    ar.add(&S.sync, 64);
     // forward workgroups for any lanes choice (at most four rows per workgroup fewer)
     ar.add(&c->upart, ((S.m + 3) / 4 + 1) * 8);
     ar.add(&c->tpart, ((S.p + 3) / 4 + 1) * 8);
@@ -701,13 +702,13 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
         return SGKS_ERR_INVALID_ARG;
     }
     // the small state starts at zero: two contiguous runs of the arena (cs ..
-    // yprev and wa .. degenerate, laid out in that order by layout_context;
+    // yprev and wa .. sync, laid out in that order by layout_context;
     // the scratch pieces between them are written before they are read)
     {
         char* a0 = (char*)S.cs;
         char* a1 = (char*)(S.yprev + dmax);
         char* b0 = (char*)S.wa;
-        char* b1 = (char*)S.degenerate + 64;
+        char* b1 = (char*)S.sync + 64;
         if (!(a0 < a1 && b0 < b1 && (char*)S.QA > a0 && (char*)S.dA < a1 &&
               (char*)S.scal > b0 && (char*)S.d < b1)) {
             sgks_destroy(c);

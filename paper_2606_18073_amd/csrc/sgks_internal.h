@@ -108,6 +108,7 @@ struct State {
     int* d;            // current number of basis columns
     int* status;       // device status word
     int* degenerate;   // count of numerically absent QR columns
+    unsigned* sync;    // side appends finished this expansion (0 between launches)
 };
 
 // Block table of one batched launch: problem q owns the workgroups
@@ -135,7 +136,6 @@ struct Plan {
     BTab ap;            // append chain workgroups (problems with more than one append group)
     BTab ap_fix;        // one workgroup per chain problem (k_yfix)
     BTab ap1_side;      // compact append: two workgroups per problem (one append group)
-    BTab ap1_stack;     // compact append: one workgroup per problem
     BTab ap1_side_hw;   // compact append with the H W column: 2 + hw_blocks per problem
     BTab adj_hw_sep;    // H W column in a launch of its own (adjoint workgroups)
     int fuse_hw;        // H W column inside the compact side launch (small total nnz)

@@ -542,6 +542,7 @@ __global__ __launch_bounds__(kBlock) void kb_forward(const State* __restrict__ S
     const State S = load_state(SS, sl.p);
     if (newcol && *S.status != 0) return;
     const double* x = newcol ? S.W + (int64_t)(*S.d) * S.n : S.x;
+    if (newcol && sl.blk == 0 && threadIdx.x == 0) S.scal[15] = (double)(*S.d);   // H W column
     forward_body<T>(S.A, S.L, rows_blocks_of(S.A), sl.nblk, x, newcol ? nullptr : S.b, S.u, S.t,
                     nullptr, nullptr, sl.blk, red);
     if (newcol && sl.blk == 0) {
@@ -1682,34 +1683,6 @@ __device__ void ap1_side_body(const State& S, int side, int scale_from_norm, Ap1
 }
 
 
-__global__ __launch_bounds__(kAp1Threads) void k_ap1_side(const State* __restrict__ SS, BTab tab,
-                                                         int scale_from_norm) {
-    __shared__ Ap1Side sh;
-    const Slot sl = find_slot(tab);
-    const State S = load_state(SS, sl.p);
-    if (*S.status != 0) return;
-    ap1_side_body(S, sl.blk, scale_from_norm, sh);
-}
-
-// The side appends (workgroups 0 and 1 of each problem) together with the
-// adjoint products that add column d of H W from (u, t) = (A w, L w) (the
-// remaining workgroups): independent work in one launch, so the bandwidth-
-// bound SpMV runs beside the two latency-bound appends.
-template <typename T>
-__global__ __launch_bounds__(kAp1Threads) void k_ap1_side_hw(const State* __restrict__ SS,
-                                                            BTab tab, int scale_from_norm) {
-    __shared__ Ap1Side sh;
-    const Slot sl = find_slot(tab);
-    const State S = load_state(SS, sl.p);
-    if (*S.status != 0) return;
-    if (sl.blk < 2) {
-        ap1_side_body(S, sl.blk, scale_from_norm, sh);
-    } else {
-        adjoint_body<T, kAp1Threads>(S.At, S.Lt, 1, S.mu, S.u, S.t, S.HW + (int64_t)(*S.d) * S.n,
-                                     S.n, nullptr, sl.blk - 2, sl.nblk - 2, sh.red);
-    }
-}
-
 struct Ap1Stack {
     double cA[kMaxD];    // working stacked column, rows < d of the R_A half
     double cL[kMaxD];    // rows < d of the sqrt(mu) R_L half
@@ -1720,7 +1693,6 @@ struct Ap1Stack {
     double yv[kMaxD + 1];
     double rv[kMaxD + 1];
     double tv[kMaxD + 1];
-    double scr[kAp1Threads];
     double red[kAp1Threads / 64];
 };
 
@@ -1728,18 +1700,10 @@ struct Ap1Stack {
 // with new-row entries (rho_A, sqrt(mu) rho_L): CGS projections on U, gamma,
 // the new columns of U, G and G^{-1}, h, y = G^{-1} h and one residual
 // correction y <- y + G^{-1} (h - G y); then d advances.  Breakdown when the
-// projected column is dependent.  One workgroup per problem.
-// threads of the stacked step: its phases are short chains of dependent
-// loads and reductions, where fewer waves per SIMD cost fewer cycles per
-// instruction
-constexpr int kStackThreads = 512;
-
-__global__ __launch_bounds__(kStackThreads) void k_ap1_stack(const State* __restrict__ SS,
-                                                          BTab tab) {
-    __shared__ Ap1Stack sh;
-    const State S = load_state(SS, find_slot(tab).p);
-    if (*S.status != 0) return;
-    const int d = *S.d, dmax = S.dmax, ld2 = 2 * dmax, tid = threadIdx.x, T = kStackThreads;
+// projected column is dependent.  Run by one workgroup of the side-append
+// launch (the one that finishes its side last).
+__device__ void ap1_stack_body(const State& S, Ap1Stack& sh) {
+    const int d = *S.d, dmax = S.dmax, ld2 = 2 * dmax, tid = threadIdx.x, T = kAp1Threads;
     const double rhoA = S.scal[12], rhoL = S.scal[13];
     const double dAnew = S.dA[d];
     const double new2 = rhoA * rhoA + S.mu * rhoL * rhoL;   // new rows, orthogonal to U
@@ -1828,6 +1792,70 @@ __global__ __launch_bounds__(kStackThreads) void k_ap1_stack(const State* __rest
         S.yprev[k] = yk;
     }
     if (tid == 0) *S.d = d + 1;   // every thread read *S.d before the barriers above
+}
+
+// LDS of the side-append launch: a side append, then (in one workgroup per
+// problem) the stacked step in the same space.
+struct AppendLds {
+    union {
+        Ap1Side side;
+        Ap1Stack stack;
+    } u;
+    int last;
+};
+
+// After its side append a workgroup counts itself in on the problem's
+// counter; the second of the two (the counter read 1) resets the counter for
+// the next expansion and runs the stacked step.  The fence before the count
+// publishes this side's results, the fence after it makes the other side's
+// visible; no workgroup waits for another.  Both side workgroups count on
+// every path (also when a status is set), so the counter always returns to 0.
+__device__ void side_then_stack(const State& S, int side, int scale_from_norm, AppendLds& sh) {
+    if (*S.status == 0) ap1_side_body(S, side, scale_from_norm, sh.u.side);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned old = atomicAdd(S.sync, 1u);
+        sh.last = 0;
+        if (old == 1u) {
+            atomicExch(S.sync, 0u);
+            __threadfence();
+            sh.last = *S.status == 0 ? 1 : 0;
+        }
+    }
+    __syncthreads();
+    if (sh.last) ap1_stack_body(S, sh.u.stack);
+}
+
+__global__ __launch_bounds__(kAp1Threads) void k_ap1_side(const State* __restrict__ SS, BTab tab,
+                                                         int scale_from_norm) {
+    __shared__ AppendLds sh;
+    const Slot sl = find_slot(tab);
+    const State S = load_state(SS, sl.p);
+    side_then_stack(S, sl.blk, scale_from_norm, sh);
+}
+
+// The side appends and the stacked step (workgroups 0 and 1 of each problem)
+// together with the adjoint products that add column d of H W from
+// (u, t) = (A w, L w) (the remaining workgroups): independent work in one
+// launch, so the bandwidth-bound SpMV runs beside the latency-bound appends.
+// The adjoint takes its column from scal[15] (written by the new-column
+// SpMV), not from d, which the stacked step advances meanwhile.
+template <typename T>
+__global__ __launch_bounds__(kAp1Threads) void k_ap1_side_hw(const State* __restrict__ SS,
+                                                            BTab tab, int scale_from_norm) {
+    __shared__ AppendLds sh;
+    const Slot sl = find_slot(tab);
+    const State S = load_state(SS, sl.p);
+    if (sl.blk < 2) {
+        side_then_stack(S, sl.blk, scale_from_norm, sh);
+        return;
+    }
+    if (*S.status != 0) return;
+    const double cf = S.scal[15];
+    const int64_t col = cf >= 0.0 && cf < (double)S.dmax ? (int64_t)cf : 0;   // always in range
+    adjoint_body<T, kAp1Threads>(S.At, S.Lt, 1, S.mu, S.u, S.t, S.HW + col * S.n, S.n, nullptr,
+                                 sl.blk - 2, sl.nblk - 2, sh.u.side.red);
 }
 
 // ---------------------------------------------------------------------------
@@ -2240,7 +2268,7 @@ int plan_build(Plan& P, const State* host, const State* dev, int np, const int* 
     P.max_gt_rows = 0;
     P.gradient_form = host[0].gradient_form;
     int fwd[kMaxBatch], adj[kMaxBatch], sc[kMaxBatch], gv[kMaxBatch], gt[kMaxBatch],
-        ap[kMaxBatch], apf[kMaxBatch], ap1s[kMaxBatch], ap1k[kMaxBatch], one[kMaxBatch],
+        ap[kMaxBatch], apf[kMaxBatch], ap1s[kMaxBatch], one[kMaxBatch],
         gr[kMaxBatch], ap1h[kMaxBatch], ahs[kMaxBatch];
     int64_t nnz_total = 0;
     for (int q = 0; q < np; ++q) nnz_total += host[q].A.nnz + host[q].L.nnz;
@@ -2261,7 +2289,6 @@ int plan_build(Plan& P, const State* host, const State* dev, int np, const int* 
         ap[q] = compact ? 0 : groups[q];
         apf[q] = compact ? 0 : 1;
         ap1s[q] = compact ? 2 : 0;
-        ap1k[q] = compact ? 1 : 0;
         const bool hw = S.gradient_form == 0;
         ap1h[q] = compact ? 2 + (hw && P.fuse_hw ? hw_blocks(S) : 0) : 0;
         ahs[q] = (hw && !(compact && P.fuse_hw)) ? adjoint_blocks(S) : 0;
@@ -2278,7 +2305,6 @@ int plan_build(Plan& P, const State* host, const State* dev, int np, const int* 
     tab_set(P.ap, np, ap);
     tab_set(P.ap_fix, np, apf);
     tab_set(P.ap1_side, np, ap1s);
-    tab_set(P.ap1_stack, np, ap1k);
     tab_set(P.ap1_side_hw, np, ap1h);
     tab_set(P.adj_hw_sep, np, ahs);
     tab_set(P.one, np, one);
@@ -2348,8 +2374,6 @@ int plan_append(const Plan& P, bool scale_from_norm, bool with_hw, hipStream_t s
         else
             hipLaunchKernelGGL(k_ap1_side_hw<double>, dim3(tab_total(P.ap1_side_hw)),
                                dim3(kAp1Threads), 0, st, P.SS, P.ap1_side_hw, sfn);
-        hipLaunchKernelGGL(k_ap1_stack, dim3(tab_total(P.ap1_stack)), dim3(kStackThreads), 0, st,
-                           P.SS, P.ap1_stack);
     }
     if (tab_total(P.ap) > 0) {
         const dim3 grid(tab_total(P.ap)), block(kAppendThreads);

@@ -280,3 +280,34 @@ def test_caller_workspace():
     with pytest.raises(G.SgksError) as e:
         G.SGKSBatch([(A, L, b, P.mu, P.s, P.seed)], workspace=ws, **kw)
     assert e.value.code == -1
+
+
+def test_two_contexts_on_two_streams_concurrently():
+    """Two solves enqueued on two streams at once (each context owns its memory,
+    counters and graphs) reproduce their one-at-a-time results bit for bit."""
+    Ps = [problem("deblur2d", "small"), problem("ct2d", "small")]
+    say("case two streams")
+    ref = []
+    for P in Ps:
+        A, L, b = G.upload_problem(P)
+        S = G.SGKS(A, L, b, P.mu, P.s, P.seed, max_iters=P.k, refine_steps=P.refine_steps)
+        S.iterate(P.k)
+        ref.append(S.solution().cpu().numpy())
+        S.close()
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    data = [G.upload_problem(P) for P in Ps]
+    torch.cuda.synchronize()
+    Ss = [G.SGKS(A, L, b, P.mu, P.s, P.seed, max_iters=P.k, refine_steps=P.refine_steps,
+                 stream=st) for (A, L, b), P, st in zip(data, Ps, streams)]
+    for step in range(0, max(P.k for P in Ps), 4):   # interleaved enqueues
+        for S, P in zip(Ss, Ps):
+            n = min(4, P.k - step)
+            if n > 0:
+                S.iterate(n)
+    xs = [S.solution() for S in Ss]   # enqueued on each context's stream
+    torch.cuda.synchronize()
+    for S, xg, x in zip(Ss, xs, ref):
+        assert np.array_equal(xg.cpu().numpy(), x)
+        S.close()
+

@@ -9,8 +9,9 @@ factors), k expansions, and x_k = W y written to device memory.  The inputs
 
 The timed region replays the captured graphs of the expansion (the production
 path; --eager launches kernel by kernel).  A second, profiled pass runs the same
-steps kernel by kernel with every phase between HIP events on the library's
-stream; kernel durations from it give the roofline of the dominant kernel
+steps kernel by kernel, every launch carrying HIP events bound to the kernel
+itself (its begin and end of execution, as a kernel trace reports them); kernel
+durations from it give the roofline of the dominant kernel
 (algorithmic bytes per launch / average launch time) and the SpMV+sketch
 bandwidth.  Then the batched solve of the 32-problem uneven batch is compared
 with its 32 plain solves, and the forward solve of the dynamic CT workload with
@@ -356,9 +357,9 @@ def main():
         "iterate_only_iters_per_s": args.steps * P.k / iter_s if iter_s > 0 else None,
     }
     if not args.no_profile:
-        # profiled pass: the same steps kernel by kernel, every phase between HIP
-        # events on the library's stream (kernel durations do not depend on how
-        # the launches were issued)
+        # profiled pass: the same steps kernel by kernel, each launch with HIP
+        # events bound to the kernel (kernel durations do not depend on how the
+        # launches were issued)
         pacc = fresh()
         torch.cuda.synchronize()
         p0 = time.perf_counter()
@@ -394,8 +395,7 @@ def main():
                            "traffic": traffic,
                            "algorithmic_bytes_per_launch": kern[dom]["bytes_per_launch"],
                            "avg_launch_us": kern[dom]["us_avg"], "source_hash": shash}
-        # the same kernel in the committed kernel trace (rocprofv3 times the kernel alone;
-        # the events above also hold its dispatch)
+        # the same kernel in the committed kernel trace of the current sources
         tavg = load_trace_avg(dom, P.name, shash)
         if tavg:
             out["roofline"]["rocprof_avg_us"] = tavg

@@ -102,9 +102,10 @@ typedef struct {
     int32_t sketch_mode;     /* SGKS_SKETCH_SPARSE_SIGN (default) or SGKS_SKETCH_IDENTITY     */
     int32_t lanes_A;         /* lanes per row for A-row SpMVs; 0 = choose from nnz/row          */
     int32_t lanes_At;        /* lanes per row for A^T rows; 0 = choose                          */
-    int32_t append_groups;   /* QR append: 1 = compact (one workgroup per sketch side, then one
-                                for the stacked factor), 2..32 = chain of kernels on that many
-                                workgroups (slabs of <= 64 sketch rows); 0 = choose by s * dmax */
+    int32_t append_groups;   /* QR append: 1 = compact (one launch, one workgroup per sketch
+                                side; the second to finish also updates the stacked factor),
+                                2..32 = chain of kernels on that many workgroups (slabs of
+                                <= 64 sketch rows); 0 = choose by s * dmax                     */
     int32_t graph;           /* 1 = sgks_iterate / sgks_batch_iterate replay a captured HIP
                                 graph of the expansion (default), 0 = launch kernel by kernel.
                                 Profiling (sgks_profile_enable) always launches kernel by kernel */
@@ -187,8 +188,11 @@ int sgks_backward(sgks_ctx *ctx, const double *grad_x, double *grad_b, double *g
 int64_t sgks_copy_state(sgks_ctx *ctx, int32_t which, double *dst, int64_t count);
 
 /* Per-phase device timing (the per-component breakdown of Sec. 4): while
- * enabled, every kernel launch of sgks_iterate / sgks_solution is bracketed by
- * HIP events on the context's stream.  Phases: 0 x = W y, 1 forward products
+ * enabled, every kernel launch of sgks_iterate / sgks_solution is issued with
+ * a pair of HIP events bound to that kernel, which hold the begin and end of
+ * its execution (the dispatch gap before it is not counted, as in a kernel
+ * trace); a phase's time is the sum over its kernels and its count the number
+ * of kernels launched.  Phases: 0 x = W y, 1 forward products
  * (A x - b, L x), 2 adjoint products (A^T u + mu L^T t), 3 SpMV of the new
  * column (A w, L w), 4 QR appends + projected solve, 5 W^T v (refinement),
  * 6 refinement step, 7 sketch scatter of the new column.  sgks_profile_read
@@ -262,7 +266,7 @@ sgks_ctx *sgks_batch_get(sgks_batch *batch, int32_t i);
 int32_t sgks_batch_count(const sgks_batch *batch);
 
 /* Per-phase timing of sgks_batch_iterate, as sgks_profile_enable / _read
- * (one event pair per launch, covering every problem). */
+ * (one event pair per kernel launch, each launch covering every problem). */
 int sgks_batch_profile_enable(sgks_batch *batch, int32_t on);
 int sgks_batch_profile_read(sgks_batch *batch, double *ms, int64_t *launches);
 

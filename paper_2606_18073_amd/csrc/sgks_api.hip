@@ -17,18 +17,42 @@
 using sgks::Csr;
 using sgks::State;
 
+thread_local sgks::LaunchTimer* sgks::tl_launch_timer = nullptr;
+
 namespace {
 
-// Per-phase timing with event pairs on one stream.
-struct Profiler {
+// Per-phase kernel timing: every launch made inside a phase gets an event
+// pair bound to the kernel itself (sgks::LaunchTimer), so a phase's time is
+// the summed execution time of its kernels and its count their number.
+struct Profiler final : sgks::LaunchTimer {
     bool on = false;
+    int phase = -1;                    // phase of the launches being enqueued
     hipStream_t st = nullptr;
-    std::vector<hipEvent_t> events;    // pairs (start, end)
+    std::vector<hipEvent_t> events;    // pairs (begin, end)
     std::vector<int> pair_phase;
     size_t pairs_used = 0;
 
     ~Profiler() {
         for (hipEvent_t e : events) hipEventDestroy(e);
+    }
+    bool pair(hipEvent_t* begin, hipEvent_t* end) override {
+        if (!on || phase < 0) return false;
+        if (pairs_used >= pair_phase.size()) {
+            hipEvent_t a, b;
+            if (hipEventCreate(&a) != hipSuccess) return false;
+            if (hipEventCreate(&b) != hipSuccess) {
+                hipEventDestroy(a);
+                return false;
+            }
+            events.push_back(a);
+            events.push_back(b);
+            pair_phase.push_back(0);
+        }
+        const size_t i = pairs_used++;
+        pair_phase[i] = phase;
+        *begin = events[2 * i];
+        *end = events[2 * i + 1];
+        return true;
     }
     int read(double* ms, int64_t* launches) {
         if (hipStreamSynchronize(st) != hipSuccess) return SGKS_ERR_HIP;
@@ -50,29 +74,21 @@ struct Profiler {
     }
 };
 
-// Brackets the launches of one phase with a pair of events when profiling.
+// Marks the launches enqueued in its scope as those of one phase when
+// profiling (installs the profiler as this thread's launch timer).
 struct Phase {
     Profiler* pr;
-    size_t pair;
-    Phase(Profiler* p, int phase) : pr(p), pair((size_t)-1) {
-        if (!pr || !pr->on) return;
-        if (pr->pairs_used >= pr->pair_phase.size()) {
-            hipEvent_t a, b;
-            if (hipEventCreate(&a) != hipSuccess) return;
-            if (hipEventCreate(&b) != hipSuccess) {
-                hipEventDestroy(a);
-                return;
-            }
-            pr->events.push_back(a);
-            pr->events.push_back(b);
-            pr->pair_phase.push_back(0);
-        }
-        pair = pr->pairs_used++;
-        pr->pair_phase[pair] = phase;
-        hipEventRecord(pr->events[2 * pair], pr->st);
+    sgks::LaunchTimer* prev = nullptr;
+    Phase(Profiler* p, int phase) : pr(p && p->on ? p : nullptr) {
+        if (!pr) return;
+        pr->phase = phase;
+        prev = sgks::tl_launch_timer;
+        sgks::tl_launch_timer = pr;
     }
     ~Phase() {
-        if (pair != (size_t)-1) hipEventRecord(pr->events[2 * pair + 1], pr->st);
+        if (!pr) return;
+        pr->phase = -1;
+        sgks::tl_launch_timer = prev;
     }
 };
 
@@ -111,8 +127,8 @@ int enqueue_iteration(const sgks::Plan& P, int refine_steps, Profiler* pr, hipSt
     { Phase ph(pr, 3); sgks::plan_forward(P, true, st); }
     { Phase ph(pr, 7); sgks::plan_scatter(P, st); }
     {
-        // maintained form: column d of H W is added by the append's first
-        // launch, beside the side appends (before d advances)
+        // maintained form: column d of H W is added in the append's launch,
+        // beside the side appends (its column index recorded by the SpMV above)
         Phase ph(pr, 4);
         if (sgks::plan_append(P, true, maintained, st)) return SGKS_ERR_HIP;
     }

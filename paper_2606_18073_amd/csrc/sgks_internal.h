@@ -2,10 +2,33 @@
 // kernels (sgks_kernels.hip).  Not part of the public ABI.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace sgks {
+
+// Kernel timing while profiling.  A timer set on the enqueueing thread hands
+// every launch of the iteration path an event pair; that launch then goes
+// through hipExtLaunchKernelGGL, whose events take the begin and end
+// timestamps of the kernel's own execution (the dispatch gap before it is not
+// included, as in a kernel trace).
+struct LaunchTimer {
+    virtual bool pair(hipEvent_t* begin, hipEvent_t* end) = 0;
+
+protected:
+    ~LaunchTimer() = default;
+};
+extern thread_local LaunchTimer* tl_launch_timer;
+
+#define SGKS_LAUNCH(K, G, B, SH, ST, ...)                                               \
+    do {                                                                                \
+        hipEvent_t sgks_e0_, sgks_e1_;                                                  \
+        if (::sgks::tl_launch_timer && ::sgks::tl_launch_timer->pair(&sgks_e0_, &sgks_e1_)) \
+            hipExtLaunchKernelGGL(K, G, B, SH, ST, sgks_e0_, sgks_e1_, 0, __VA_ARGS__);  \
+        else                                                                            \
+            hipLaunchKernelGGL(K, G, B, SH, ST, __VA_ARGS__);                           \
+    } while (0)
 
 constexpr int kBlock = 256;         // threads per block of the bulk kernels
 constexpr int kWaves = kBlock / 64; // waves per block

@@ -1450,12 +1450,12 @@ __global__ __launch_bounds__(1024) void k_yfix(const State* __restrict__ SS, BTa
 }
 
 // ---------------------------------------------------------------------------
-// compact append: one workgroup per sketch side, then one workgroup for the
-// stacked factor.  For modest s and d the whole append fits the bandwidth of a
-// few compute units, and two launches replace the chain above (whose cost is
-// the latency of its seven kernel boundaries and of the reductions between
-// them).  Everything a workgroup reads back is kept in LDS, so no workgroup
-// reads global memory it wrote itself.
+// compact append: one workgroup per sketch side; the one that finishes second
+// goes on with the stacked factor (side_then_stack).  For modest s and d the
+// whole append fits the bandwidth of a few compute units, and one launch
+// replaces the chain above (whose cost is the latency of its seven kernel
+// boundaries and of the reductions between them).  The stacked step reads the
+// other side's results only after the fences around the hand-over count.
 // ---------------------------------------------------------------------------
 
 constexpr int kAp1Threads = 512;
@@ -2157,7 +2157,7 @@ int hw_blocks(const State& S) {
 
 void launch_gemv(const State& S, const double* coef, double* out, const double* base,
                  int ncols_fixed, hipStream_t st) {
-    hipLaunchKernelGGL(k_gemv, dim3(gemv_blocks(S)), dim3(kBlock), 0, st, S.W, S.cs, coef, S.d,
+    SGKS_LAUNCH(k_gemv, dim3(gemv_blocks(S)), dim3(kBlock), 0, st, S.W, S.cs, coef, S.d,
                        ncols_fixed, S.n, base, out);
 }
 
@@ -2185,8 +2185,8 @@ int max_append_groups() {
     return cus > 0 ? cus : 1;
 }
 
-// G = 1 selects the compact append (one workgroup per side, then one for the
-// stacked factor); G > 1 the chain of G-workgroup kernels.
+// G = 1 selects the compact append (one workgroup per side, the second to
+// finish also takes the stacked factor); G > 1 the chain of G-workgroup kernels.
 bool append_groups_ok(int s, int dmax, int G) {
     if (G == 1) return s <= kMaxS && dmax <= kMaxD;
     return G >= 2 && G <= kMaxAppendGroups && (s + G - 1) / G <= kAppendMaxSlab &&
@@ -2312,29 +2312,29 @@ int plan_build(Plan& P, const State* host, const State* dev, int np, const int* 
 }
 
 void plan_gemv(const Plan& P, hipStream_t st) {
-    hipLaunchKernelGGL(kb_gemv, dim3(tab_total(P.gemv)), dim3(kBlock), 0, st, P.SS, P.gemv);
+    SGKS_LAUNCH(kb_gemv, dim3(tab_total(P.gemv)), dim3(kBlock), 0, st, P.SS, P.gemv);
 }
 
 void plan_forward(const Plan& P, bool newcol, hipStream_t st) {
     const dim3 grid(tab_total(P.fwd));
     if (P.vdt == 0)
-        hipLaunchKernelGGL(kb_forward<float>, grid, dim3(kBlock), 0, st, P.SS, P.fwd,
+        SGKS_LAUNCH(kb_forward<float>, grid, dim3(kBlock), 0, st, P.SS, P.fwd,
                            newcol ? 1 : 0);
     else
-        hipLaunchKernelGGL(kb_forward<double>, grid, dim3(kBlock), 0, st, P.SS, P.fwd,
+        SGKS_LAUNCH(kb_forward<double>, grid, dim3(kBlock), 0, st, P.SS, P.fwd,
                            newcol ? 1 : 0);
 }
 
 void plan_adjoint(const Plan& P, int dst_kind, hipStream_t st) {
     const dim3 grid(tab_total(P.adj));
     if (P.vdt == 0)
-        hipLaunchKernelGGL(kb_adjoint<float>, grid, dim3(kBlock), 0, st, P.SS, P.adj, dst_kind);
+        SGKS_LAUNCH(kb_adjoint<float>, grid, dim3(kBlock), 0, st, P.SS, P.adj, dst_kind);
     else
-        hipLaunchKernelGGL(kb_adjoint<double>, grid, dim3(kBlock), 0, st, P.SS, P.adj, dst_kind);
+        SGKS_LAUNCH(kb_adjoint<double>, grid, dim3(kBlock), 0, st, P.SS, P.adj, dst_kind);
 }
 
 void plan_gradient(const Plan& P, bool to_rtmp, hipStream_t st) {
-    hipLaunchKernelGGL(kb_gradient, dim3(tab_total(P.grad)), dim3(kBlock), 0, st, P.SS, P.grad,
+    SGKS_LAUNCH(kb_gradient, dim3(tab_total(P.grad)), dim3(kBlock), 0, st, P.SS, P.grad,
                        to_rtmp ? 1 : 0);
 }
 
@@ -2342,7 +2342,7 @@ void plan_scatter(const Plan& P, hipStream_t st) {
     const size_t shm = (size_t)kSketchWaves * P.max_s * sizeof(double);
     const dim3 grid(tab_total(P.sc));
 #define SGKS_SC(Zv) \
-    hipLaunchKernelGGL((kb_scatter<Zv>), grid, dim3(kSketchBlock), shm, st, P.SS, P.sc)
+    SGKS_LAUNCH((kb_scatter<Zv>), grid, dim3(kSketchBlock), shm, st, P.SS, P.sc)
     switch (P.zeta) {
         case 2: SGKS_SC(2); break;
         case 4: SGKS_SC(4); break;
@@ -2357,35 +2357,35 @@ int plan_append(const Plan& P, bool scale_from_norm, bool with_hw, hipStream_t s
     if (with_hw && tab_total(P.adj_hw_sep) > 0) {
         const dim3 grid(tab_total(P.adj_hw_sep));
         if (P.vdt == 0)
-            hipLaunchKernelGGL(kb_adjoint<float>, grid, dim3(kBlock), 0, st, P.SS, P.adj_hw_sep,
+            SGKS_LAUNCH(kb_adjoint<float>, grid, dim3(kBlock), 0, st, P.SS, P.adj_hw_sep,
                                kDstHW);
         else
-            hipLaunchKernelGGL(kb_adjoint<double>, grid, dim3(kBlock), 0, st, P.SS, P.adj_hw_sep,
+            SGKS_LAUNCH(kb_adjoint<double>, grid, dim3(kBlock), 0, st, P.SS, P.adj_hw_sep,
                                kDstHW);
     }
     if (tab_total(P.ap1_side) > 0) {
         const int sfn = scale_from_norm ? 1 : 0;
         if (!with_hw || !P.fuse_hw)
-            hipLaunchKernelGGL(k_ap1_side, dim3(tab_total(P.ap1_side)), dim3(kAp1Threads), 0, st,
+            SGKS_LAUNCH(k_ap1_side, dim3(tab_total(P.ap1_side)), dim3(kAp1Threads), 0, st,
                                P.SS, P.ap1_side, sfn);
         else if (P.vdt == 0)
-            hipLaunchKernelGGL(k_ap1_side_hw<float>, dim3(tab_total(P.ap1_side_hw)),
+            SGKS_LAUNCH(k_ap1_side_hw<float>, dim3(tab_total(P.ap1_side_hw)),
                                dim3(kAp1Threads), 0, st, P.SS, P.ap1_side_hw, sfn);
         else
-            hipLaunchKernelGGL(k_ap1_side_hw<double>, dim3(tab_total(P.ap1_side_hw)),
+            SGKS_LAUNCH(k_ap1_side_hw<double>, dim3(tab_total(P.ap1_side_hw)),
                                dim3(kAp1Threads), 0, st, P.SS, P.ap1_side_hw, sfn);
     }
     if (tab_total(P.ap) > 0) {
         const dim3 grid(tab_total(P.ap)), block(kAppendThreads);
-        hipLaunchKernelGGL(k_ap_q0, grid, block, 0, st, P.SS, P.ap, scale_from_norm ? 1 : 0);
+        SGKS_LAUNCH(k_ap_q0, grid, block, 0, st, P.SS, P.ap, scale_from_norm ? 1 : 0);
         for (int pass = 1; pass < P.passes; ++pass)
-            hipLaunchKernelGGL(k_ap_qp, grid, block, 0, st, P.SS, P.ap, pass);
-        hipLaunchKernelGGL(k_ap_qf, grid, block, 0, st, P.SS, P.ap);
+            SGKS_LAUNCH(k_ap_qp, grid, block, 0, st, P.SS, P.ap, pass);
+        SGKS_LAUNCH(k_ap_qf, grid, block, 0, st, P.SS, P.ap);
         for (int u = 1; u < P.passes; ++u)
-            hipLaunchKernelGGL(k_ap_u, grid, block, 0, st, P.SS, P.ap, u, 0);
-        hipLaunchKernelGGL(k_ap_u, grid, block, 0, st, P.SS, P.ap, P.passes, 1);
-        hipLaunchKernelGGL(k_ap_commit, grid, block, 0, st, P.SS, P.ap);
-        hipLaunchKernelGGL(k_yfix, dim3(tab_total(P.ap_fix)), dim3(1024), 0, st, P.SS,
+            SGKS_LAUNCH(k_ap_u, grid, block, 0, st, P.SS, P.ap, u, 0);
+        SGKS_LAUNCH(k_ap_u, grid, block, 0, st, P.SS, P.ap, P.passes, 1);
+        SGKS_LAUNCH(k_ap_commit, grid, block, 0, st, P.SS, P.ap);
+        SGKS_LAUNCH(k_yfix, dim3(tab_total(P.ap_fix)), dim3(1024), 0, st, P.SS,
                            P.ap_fix);
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;
@@ -2393,11 +2393,11 @@ int plan_append(const Plan& P, bool scale_from_norm, bool with_hw, hipStream_t s
 
 void plan_gemvt(const Plan& P, hipStream_t st) {
     const size_t shm = (size_t)P.max_gt_rows * sizeof(double);
-    hipLaunchKernelGGL(kb_gemvt, dim3(tab_total(P.gemvt)), dim3(kBlock), shm, st, P.SS, P.gemvt);
+    SGKS_LAUNCH(kb_gemvt, dim3(tab_total(P.gemvt)), dim3(kBlock), shm, st, P.SS, P.gemvt);
 }
 
 void plan_refine(const Plan& P, hipStream_t st) {
-    hipLaunchKernelGGL(k_refine, dim3(P.np), dim3(kBlock), 0, st, P.SS, P.one);
+    SGKS_LAUNCH(k_refine, dim3(P.np), dim3(kBlock), 0, st, P.SS, P.one);
 }
 
 // bytes of scratch the transpose of M needs (four nnz-long int32 arrays and the

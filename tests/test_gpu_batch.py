@@ -85,7 +85,8 @@ def test_batch_resume_profile_and_views():
     B1 = G.SGKSBatch(data, max_iters=Ps[0].k)
     B1.profile(True).iterate(3)
     ms, cnt = B1.profile_read()
-    assert cnt[G.PHASE_NAMES.index("qr_append_solve")] == 3
+    na = cnt[G.PHASE_NAMES.index("qr_append_solve")]
+    assert na >= 3 and na % 3 == 0          # one count per kernel launched
     assert cnt[G.PHASE_NAMES.index("sketch_scatter")] == 3
     assert all(v >= 0 for v in ms)
     B1.profile(False).iterate(Ps[0].k - 3)

@@ -214,6 +214,47 @@ def test_max_basis_size(s, k):
     S.close()
 
 
+@pytest.mark.parametrize("groups,refine,form", [(1, 0, "maintained"), (4, 1, "maintained"),
+                                                (1, 1, "direct")])
+def test_profiling_times_kernels_and_keeps_results(groups, refine, form):
+    """Profiled iterations run kernel by kernel, each launch carrying events bound
+    to the kernel: the same bits as graph replays, one count per kernel launched."""
+    P = problem("deblur2d", "small")
+    k = 12
+    say("case profiling, append groups", groups, "refine", refine, form)
+    A, L, b = G.upload_problem(P)
+    kw = dict(max_iters=k, append_groups=groups, refine_steps=refine, gradient=form)
+    S1 = G.SGKS(A, L, b, P.mu, P.s, P.seed, **kw)
+    S1.profile(True).iterate(k)
+    x1 = S1.solution().cpu().numpy()
+    ms, cnt = S1.profile_read()
+    S2 = G.SGKS(A, L, b, P.mu, P.s, P.seed, **kw)
+    S2.iterate(k)
+    x2 = S2.solution().cpu().numpy()
+    assert np.array_equal(x1, x2)
+    n = {name: cnt[i] for i, name in enumerate(G.PHASE_NAMES)}
+    say("  launches", n)
+    assert n["spmv_new_column"] == k and n["sketch_scatter"] == k
+    assert n["gemvt_WTr"] == k * refine and n["refine_step"] == k * refine
+    if form == "maintained":
+        # one gradient launch per expansion and refinement step, plus x = W y
+        assert n["gemv"] == k * (1 + refine) + 1
+        assert n["forward_Ax_Lx"] == 0 and n["adjoint"] == 0
+    else:
+        assert n["gemv"] == k * (1 + refine) + 1
+        assert n["forward_Ax_Lx"] == k * (1 + refine) and n["adjoint"] == k * (1 + refine)
+    if groups == 1 and form == "maintained":
+        assert n["qr_append_solve"] == k   # the compact append is one launch
+    else:
+        assert n["qr_append_solve"] >= k and n["qr_append_solve"] % k == 0
+    assert all(v >= 0 for v in ms) and ms[G.PHASE_NAMES.index("spmv_new_column")] > 0
+    # a second read starts from zero
+    ms2, cnt2 = S1.profile_read()
+    assert all(c == 0 for c in cnt2)
+    S1.close()
+    S2.close()
+
+
 @pytest.mark.parametrize("groups", [1, 4])
 def test_single_projection_append(groups):
     """qr_passes = 1: one CGS projection per column append, as the rank-one QR

@@ -33,7 +33,7 @@ struct Profiler final : sgks::LaunchTimer {
     size_t pairs_used = 0;
 
     ~Profiler() {
-        for (hipEvent_t e : events) hipEventDestroy(e);
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
     }
     bool pair(hipEvent_t* begin, hipEvent_t* end) override {
         if (!on || phase < 0) return false;
@@ -41,7 +41,7 @@ struct Profiler final : sgks::LaunchTimer {
             hipEvent_t a, b;
             if (hipEventCreate(&a) != hipSuccess) return false;
             if (hipEventCreate(&b) != hipSuccess) {
-                hipEventDestroy(a);
+                (void)hipEventDestroy(a);
                 return false;
             }
             events.push_back(a);
@@ -150,8 +150,8 @@ struct GraphCache {
 
     ~GraphCache() {
         for (hipGraphExec_t e : exec)
-            if (e) hipGraphExecDestroy(e);
-        if (cap) hipStreamDestroy(cap);
+            if (e) (void)hipGraphExecDestroy(e);
+        if (cap) (void)hipStreamDestroy(cap);
     }
     int capture(const sgks::Plan& P, int refine_steps, int iters, hipGraphExec_t* out) {
         if (!cap && hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)
@@ -164,11 +164,11 @@ struct GraphCache {
         hipGraph_t g = nullptr;
         const hipError_t e = hipStreamEndCapture(cap, &g);
         if (e != hipSuccess || rc != SGKS_OK || !g) {
-            if (g) hipGraphDestroy(g);
+            if (g) (void)hipGraphDestroy(g);
             return SGKS_ERR_HIP;
         }
         const hipError_t ei = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
-        hipGraphDestroy(g);
+        (void)hipGraphDestroy(g);
         return ei == hipSuccess ? SGKS_OK : SGKS_ERR_HIP;
     }
 };
@@ -210,22 +210,22 @@ float time_launches(hipStream_t st, F&& launch, int reps) {
     hipEvent_t a = nullptr, b = nullptr;
     if (hipEventCreate(&a) != hipSuccess) return INFINITY;
     if (hipEventCreate(&b) != hipSuccess) {
-        hipEventDestroy(a);
+        (void)hipEventDestroy(a);
         return INFINITY;
     }
     launch();   // warm-up
     float best = INFINITY;
     for (int r = 0; r < reps; ++r) {
-        hipEventRecord(a, st);
+        if (hipEventRecord(a, st) != hipSuccess) break;
         launch();
-        hipEventRecord(b, st);
+        if (hipEventRecord(b, st) != hipSuccess) break;
         float ms = INFINITY;
         if (hipEventSynchronize(b) == hipSuccess && hipEventElapsedTime(&ms, a, b) == hipSuccess &&
             ms < best)
             best = ms;
     }
-    hipEventDestroy(a);
-    hipEventDestroy(b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
     return best;
 }
 
@@ -903,10 +903,13 @@ int64_t sgks_copy_state(sgks_ctx* c, int32_t which, double* dst, int64_t count) 
             if (n > count) return SGKS_ERR_INVALID_ARG;
             double* tmp = nullptr;
             if (hipMalloc(&tmp, (n > 0 ? n : 1) * 8) != hipSuccess) return SGKS_ERR_HIP;
-            sgks::launch_copy_scaled_W(S, tmp, st);
-            hipStreamSynchronize(st);
+            if (sgks::launch_copy_scaled_W(S, tmp, st) != 0 ||
+                hipStreamSynchronize(st) != hipSuccess) {
+                (void)hipFree(tmp);
+                return SGKS_ERR_HIP;
+            }
             int64_t r = copy(tmp, n);
-            hipFree(tmp);
+            (void)hipFree(tmp);
             return r;
         }
         case 1: return copy(S.y, d);
@@ -956,8 +959,8 @@ int sgks_get_tuning(const sgks_ctx* c, int32_t out[6]) {
 }
 
 static void destroy_ctx(sgks_ctx* c) {
-    hipStreamSynchronize(c->st);
-    for (void* p : c->allocs) hipFree(p);
+    (void)hipStreamSynchronize(c->st);
+    for (void* p : c->allocs) (void)hipFree(p);
     delete c;
 }
 
@@ -1066,9 +1069,9 @@ int sgks_batch_profile_read(sgks_batch* B, double* ms, int64_t* launches) {
 
 void sgks_batch_destroy(sgks_batch* B) {
     if (!B) return;
-    hipStreamSynchronize(B->st);
+    (void)hipStreamSynchronize(B->st);
     for (sgks_ctx* c : B->ctx) destroy_ctx(c);
-    if (B->Sdev) hipFree(B->Sdev);
+    if (B->Sdev) (void)hipFree(B->Sdev);
     delete B;
 }
 

@@ -2178,10 +2178,10 @@ void launch_set_scale(const State& S, int col, bool store_r0, hipStream_t st) {
 }
 
 int max_append_groups() {
-    int dev = 0;
-    hipGetDevice(&dev);
-    int cus = 0;
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 1;
     return cus > 0 ? cus : 1;
 }
 
@@ -2234,13 +2234,15 @@ void launch_sketch_transpose(const State& S, const double* v, double* out, hipSt
 #undef SGKS_ST
 }
 
-void launch_copy_scaled_W(const State& S, double* dst, hipStream_t st) {
+int launch_copy_scaled_W(const State& S, double* dst, hipStream_t st) {
     int dh = 0;
-    hipMemcpyAsync(&dh, S.d, sizeof(int), hipMemcpyDeviceToHost, st);
-    hipStreamSynchronize(st);
-    if (dh <= 0) return;
+    if (hipMemcpyAsync(&dh, S.d, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return -1;
+    if (dh <= 0) return 0;
     const int nb = grid_for(S.n * (int64_t)dh, kBlock, 8192);
     hipLaunchKernelGGL(k_scaled_W, dim3(nb), dim3(kBlock), 0, st, S.W, S.cs, S.n, dh, dst);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 // ---------------------------------------------------------------------------
@@ -2461,8 +2463,8 @@ int transpose_csr(const Csr& M, int vdt, int32_t* rowptrT, int32_t* colT, void* 
         if (hipGetLastError() != hipSuccess) rc = -1;
     }
     if (own) {
-        hipStreamSynchronize(st);
-        hipFree(base);
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(base);
     }
     return rc;
 }

@@ -192,7 +192,8 @@ int64_t sgks_copy_state(sgks_ctx *ctx, int32_t which, double *dst, int64_t count
  * a pair of HIP events bound to that kernel, which hold the begin and end of
  * its execution (the dispatch gap before it is not counted, as in a kernel
  * trace); a phase's time is the sum over its kernels and its count the number
- * of kernels launched.  Phases: 0 x = W y, 1 forward products
+ * of kernels launched.  On a stream under capture the launches are recorded
+ * without events and are not counted.  Phases: 0 x = W y, 1 forward products
  * (A x - b, L x), 2 adjoint products (A^T u + mu L^T t), 3 SpMV of the new
  * column (A w, L w), 4 QR appends + projected solve, 5 W^T v (refinement),
  * 6 refinement step, 7 sketch scatter of the new column.  sgks_profile_read

@@ -37,6 +37,10 @@ struct Profiler final : sgks::LaunchTimer {
     }
     bool pair(hipEvent_t* begin, hipEvent_t* end) override {
         if (!on || phase < 0) return false;
+        // a stream under capture records the launch untimed
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+            return false;
         if (pairs_used >= pair_phase.size()) {
             hipEvent_t a, b;
             if (hipEventCreate(&a) != hipSuccess) return false;

@@ -400,6 +400,21 @@ def main():
         if tavg:
             out["roofline"]["rocprof_avg_us"] = tavg
             out["roofline"]["achieved_at_rocprof_avg"] = kern[dom]["bytes_per_launch"] / (tavg * 1e-6) / 1e9
+        # the launch with the most time: the compact append (side appends with the
+        # H W adjoint beside them, then the stacked step) is bound by its chain of
+        # dependent one-workgroup phases, not by HBM; its time and share are shown
+        # with the HBM bytes its counters measured
+        ap = phase.get("qr_append_solve")
+        tuning = acc.get("tuning") or {}
+        if ap and tuning.get("append_groups") == 1 and ap["launches"]:
+            exp_ms = sum(v["ms_total"] for v in phase.values())
+            name = "k_ap1_side_hw" if args.gradient == "maintained" else "k_ap1_side"
+            tr = load_traffic(name, P.name, shash)
+            out["append_launch"] = {
+                "kernel": name, "bound": "latency", "avg_launch_us": ap["us_avg"],
+                "share_of_kernel_time": ap["ms_total"] / exp_ms if exp_ms > 0 else None,
+                "hbm_bytes_per_launch": tr,
+                "GBps_at_hbm_bytes": tr / (ap["us_avg"] * 1e-6) / 1e9 if tr else None}
         sk = ["kb_forward", "kb_adjoint", "kb_scatter"]
         tb = sum(kern[k]["bytes_per_launch"] * kern[k]["launches"] for k in sk if k in kern)
         tt = sum(kern[k]["ms_total"] for k in sk if k in kern) * 1e-3

@@ -7,8 +7,9 @@ k = 100): sgks_create (transposes, sketch of b, initial Krylov basis, QR
 factors), k expansions, and x_k = W y written to device memory.  The inputs
 (A, L, b) are resident in device memory before the timed region starts.
 
-The timed region replays the captured graphs of the expansion (the production
-path; --eager launches kernel by kernel).  A second, profiled pass runs the same
+The timed region runs the production path, kernel-by-kernel launches on one
+stream (--graph replays captured graphs of the expansion instead, which measured
+slower).  A second, profiled pass runs the same
 steps kernel by kernel, every launch carrying HIP events bound to the kernel
 itself (its begin and end of execution, as a kernel trace reports them); kernel
 durations from it give the roofline of the dominant kernel
@@ -158,7 +159,7 @@ def bench_batch(G, torch, np, make):
     # launch shapes autotuned per operator shape (the warm-up create tunes and
     # caches them; the timed batched and plain solves reuse the same choices)
     opts = dict(ell=Ps[0].ell, max_iters=k, zeta=Ps[0].zeta, autotune=True)
-    # warm-up (module load, graph capture paths)
+    # warm-up (module load, autotuning)
     B = G.SGKSBatch(data, **opts)
     B.iterate(2)
     B.close()
@@ -261,8 +262,8 @@ def main():
     ap.add_argument("--cpu-reps", type=int, default=8)
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the profiled pass (no per-phase times, no roofline)")
-    ap.add_argument("--eager", action="store_true",
-                    help="time kernel-by-kernel launches instead of graph replays")
+    ap.add_argument("--graph", action="store_true",
+                    help="time replays of captured graphs instead of kernel-by-kernel launches")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched and adjoint comparisons")
     ap.add_argument("--gradient", choices=["maintained", "direct"], default="maintained",
@@ -290,7 +291,7 @@ def main():
     def step(acc, prof):
         t0 = time.perf_counter()
         S = G.SGKS(A, L, b, P.mu, P.s, P.seed, ell=P.ell, max_iters=P.k, zeta=P.zeta,
-                   refine_steps=P.refine_steps, graph=not args.eager, autotune=args.autotune,
+                   refine_steps=P.refine_steps, graph=args.graph, autotune=args.autotune,
                    gradient=args.gradient)
         acc["tuning"] = S.tuning()
         t1 = time.perf_counter()
@@ -348,7 +349,7 @@ def main():
             "operator_storage": P.dtype,
             "vectors": "f64",
             "k": P.k, "n": P.n, "s": P.s,
-            "launch": "kernel by kernel" if args.eager else "graph replay (8 expansions per graph)",
+            "launch": "graph replay (8 expansions per graph)" if args.graph else "kernel by kernel",
             "gradient_form": args.gradient,
         },
         "paper_context": PAPER_CONTEXT,

@@ -106,9 +106,10 @@ typedef struct {
                                 side; the second to finish also updates the stacked factor),
                                 2..32 = chain of kernels on that many workgroups (slabs of
                                 <= 64 sketch rows); 0 = choose by s * dmax                     */
-    int32_t graph;           /* 1 = sgks_iterate / sgks_batch_iterate replay a captured HIP
-                                graph of the expansion (default), 0 = launch kernel by kernel.
-                                Profiling (sgks_profile_enable) always launches kernel by kernel */
+    int32_t graph;           /* 0 = sgks_iterate / sgks_batch_iterate launch kernel by kernel
+                                (default: the faster of the two on MI355X), 1 = replay captured
+                                HIP graphs of 1 and 8 expansions.  Profiling
+                                (sgks_profile_enable) always launches kernel by kernel          */
     int32_t gradient_form;   /* SGKS_GRADIENT_MAINTAINED (default) or SGKS_GRADIENT_DIRECT:
                                 how the gradient r = A^T (A x - b) + mu L^T L x is evaluated
                                 each expansion (see below)                                      */

@@ -563,7 +563,7 @@ void sgks_default_options(sgks_options* o) {
     o->lanes_A = 0;
     o->lanes_At = 0;
     o->append_groups = 0;
-    o->graph = 1;
+    o->graph = 0;
     o->autotune = 0;
     o->gradient_form = SGKS_GRADIENT_MAINTAINED;
     o->workspace = nullptr;

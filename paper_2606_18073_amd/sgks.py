@@ -180,7 +180,7 @@ def _check(code, where):
 
 
 def make_options(lib, vdt, stream, *, ell=3, max_iters=200, zeta=8, refine_steps=0, qr_passes=2,
-                 sketch="sparse_sign", lanes_A=0, lanes_At=0, append_groups=0, graph=True,
+                 sketch="sparse_sign", lanes_A=0, lanes_At=0, append_groups=0, graph=False,
                  autotune=False, gradient="maintained"):
     o = Options()
     lib.sgks_default_options(ctypes.byref(o))

@@ -26,7 +26,7 @@ def test_default_options(lib):
     o = G.default_options()
     assert (o.ell, o.max_iters, o.zeta, o.qr_passes, o.value_dtype) == (3, 200, 8, 2, G.F64)
     assert o.sketch_mode == G.SKETCH_SPARSE_SIGN and o.refine_steps == 0
-    assert (o.graph, o.autotune, o.lanes_A, o.lanes_At, o.append_groups) == (1, 0, 0, 0, 0)
+    assert (o.graph, o.autotune, o.lanes_A, o.lanes_At, o.append_groups) == (0, 0, 0, 0, 0)
     assert o.gradient_form == G.GRADIENT_MAINTAINED
 
 

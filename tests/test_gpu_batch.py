@@ -77,12 +77,13 @@ def test_batch_small_matches_plain_and_oracle():
 
 
 def test_batch_resume_profile_and_views():
-    """Iterate in pieces with profiling (kernel by kernel) then graphs; a problem
-    iterated alone through its view keeps its own basis size."""
+    """Iterate in pieces with profiling (kernel by kernel) then graph replays, against
+    a batch launched kernel by kernel; a problem iterated alone through its view keeps
+    its own basis size."""
     Ps = problem("batch", "small")
     say("case batch resume/profile")
     data = G.upload_batch(Ps)
-    B1 = G.SGKSBatch(data, max_iters=Ps[0].k)
+    B1 = G.SGKSBatch(data, max_iters=Ps[0].k, graph=True)
     B1.profile(True).iterate(3)
     ms, cnt = B1.profile_read()
     na = cnt[G.PHASE_NAMES.index("qr_append_solve")]
@@ -283,11 +284,12 @@ def test_caller_workspace():
     assert e.value.code == -1
 
 
-def test_two_contexts_on_two_streams_concurrently():
+@pytest.mark.parametrize("graph", [False, True])
+def test_two_contexts_on_two_streams_concurrently(graph):
     """Two solves enqueued on two streams at once (each context owns its memory,
     counters and graphs) reproduce their one-at-a-time results bit for bit."""
     Ps = [problem("deblur2d", "small"), problem("ct2d", "small")]
-    say("case two streams")
+    say("case two streams, graph", graph)
     ref = []
     for P in Ps:
         A, L, b = G.upload_problem(P)
@@ -300,7 +302,7 @@ def test_two_contexts_on_two_streams_concurrently():
     data = [G.upload_problem(P) for P in Ps]
     torch.cuda.synchronize()
     Ss = [G.SGKS(A, L, b, P.mu, P.s, P.seed, max_iters=P.k, refine_steps=P.refine_steps,
-                 stream=st) for (A, L, b), P, st in zip(data, Ps, streams)]
+                 stream=st, graph=graph) for (A, L, b), P, st in zip(data, Ps, streams)]
     for step in range(0, max(P.k for P in Ps), 4):   # interleaved enqueues
         for S, P in zip(Ss, Ps):
             n = min(4, P.k - step)

@@ -228,7 +228,7 @@ def test_profiling_times_kernels_and_keeps_results(groups, refine, form):
     S1.profile(True).iterate(k)
     x1 = S1.solution().cpu().numpy()
     ms, cnt = S1.profile_read()
-    S2 = G.SGKS(A, L, b, P.mu, P.s, P.seed, **kw)
+    S2 = G.SGKS(A, L, b, P.mu, P.s, P.seed, graph=True, **kw)
     S2.iterate(k)
     x2 = S2.solution().cpu().numpy()
     assert np.array_equal(x1, x2)

@@ -145,8 +145,11 @@ int enqueue_iteration(const sgks::Plan& P, int refine_steps, Profiler* pr, hipSt
 // basis size d is read on the device), so one graph serves every expansion.
 constexpr int kGraphChunk = 8;
 
-// default 64-entry tiles per wave of the sketch scatter
-constexpr int kScatterTilesPerWave = 8;
+// default 64-entry tiles per wave of the sketch scatter: fewer tiles give more
+// workgroups (the scatter is bound by each compute unit's LDS atomics) but more
+// partial bins for the append to reduce; 4 balances the two at the 2D
+// deblurring sizes (m = 65,536, p = 131,072, s = 400)
+constexpr int kScatterTilesPerWave = 4;
 
 struct GraphCache {
     hipStream_t cap = nullptr;

@@ -275,8 +275,9 @@ int tune_one(const State& S, int kind, hipStream_t st) {
 }
 
 // tiles per wave of the sketch scatter: each count is timed as the scatter of
-// both images plus the reduction of its partial bins (fewer, fuller workgroups
-// leave fewer partial bins to reduce)
+// both images plus the reduction of its partial bins as the append does it (one
+// workgroup per side, both sides at once: the side with more partial bins sets
+// the time).  Fewer, fuller workgroups leave fewer partial bins to reduce.
 int tune_scatter(const State& S, hipStream_t st) {
     const auto key = std::make_tuple(3, S.m, S.p, (int64_t)S.s, (int64_t)S.zeta, S.vdt);
     {
@@ -290,13 +291,12 @@ int tune_scatter(const State& S, hipStream_t st) {
         State T = S;
         T.nbA = sgks::scatter_blocks(S.m, tpw);
         T.nbL = sgks::scatter_blocks(S.p, tpw);
-        State TL = T;
-        TL.binA = T.binL;
-        TL.nbA = T.nbL;
         const float ms = time_launches(st, [&] {
             sgks::launch_scatter(T, S.u, S.t, st);
-            sgks::launch_cb(T, st);
-            sgks::launch_cb(TL, st);
+            if (T.nbA >= T.nbL)
+                sgks::launch_reduce_bins_probe(T.binA, T.nbA, S.s, S.cb, st);
+            else
+                sgks::launch_reduce_bins_probe(T.binL, T.nbL, S.s, S.cb, st);
         }, 5);
         if (ms < tbest) {
             tbest = ms;

@@ -1588,6 +1588,15 @@ __device__ void reduce_bins(const double* __restrict__ bins, int nb, int s, doub
     __syncthreads();
 }
 
+// Autotuning probe: one workgroup of the side-append size reduces nb partial
+// bins of s entries as a side append does, into out (s entries).
+__global__ __launch_bounds__(kAp1Threads) void k_reduce_bins_probe(const double* __restrict__ bins,
+                                                                  int nb, int s, double* out) {
+    __shared__ double a[kMaxS];
+    reduce_bins(bins, nb, s, 1.0, a);
+    for (int i = threadIdx.x; i < s; i += blockDim.x) out[i] = a[i];
+}
+
 // One CGS projection of the s-vector a against the d columns of Q:
 // p = Q^T a, a -= Q p.  With Q32 the coefficients p come from the FP32 copy
 // (the first of two projections); the update always uses the FP64 Q, so a
@@ -2207,6 +2216,10 @@ void launch_cb(const State& S, hipStream_t st) {
     const double scale = S.sketch_mode == 1 ? 1.0 : 1.0 / sqrt((double)S.zeta);
     hipLaunchKernelGGL(k_cb, dim3(1), dim3(kBlock), 0, st, S.binA, S.nbA, S.s, scale, S.cb,
                        S.scal);
+}
+
+void launch_reduce_bins_probe(const double* bins, int nb, int s, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce_bins_probe, dim3(1), dim3(kAp1Threads), 0, st, bins, nb, s, out);
 }
 
 void launch_residual_small(const State& S, double* out2, hipStream_t st) {

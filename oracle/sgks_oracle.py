@@ -182,13 +182,6 @@ def gram_solve(G, g):
     return sla.solve_triangular(G, t, lower=False)
 
 
-def cgs2_normalize(V, v):
-    """Orthonormalise v against the orthonormal columns of V by two projections."""
-    for _ in range(2):
-        v = v - V @ (V.T @ v)
-    return v / np.linalg.norm(v)
-
-
 class DegenerateInitialSpace(ValueError):
     """K_ell(A^T A, A^T b) has dimension below ell."""
 
@@ -418,9 +411,9 @@ def tikhonov_residual(A, L, b, mu, x):
     return math.sqrt(float(np.linalg.norm(A @ x - b) ** 2 + mu * np.linalg.norm(L @ x) ** 2))
 
 
-def sketched_residual(A, L, b, mu, x, s, seed, zeta=8):
+def sketched_residual(A, L, b, mu, x, s, seed, zeta=8, kind="sparse_sign"):
     """sqrt(||S_A(A x - b)||^2 + mu ||S_L L x||^2) (the functional of eq:tik_new_sketched)."""
-    S_A, S_L = make_sketches(A.shape[0], L.shape[0], s, seed, zeta)
+    S_A, S_L = make_sketches(A.shape[0], L.shape[0], s, seed, zeta, kind)
     return math.sqrt(float(np.linalg.norm(S_A @ (A @ x - b)) ** 2
                            + mu * np.linalg.norm(S_L @ (L @ x)) ** 2))
 

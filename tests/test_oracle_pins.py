@@ -466,3 +466,149 @@ def test_pins_catch_planted_mistakes(monkeypatch):
     y2 = np.linalg.lstsq(M, np.concatenate([S_A @ b, np.zeros(60)]), rcond=None)[0]
     assert np.linalg.norm(bad.y - y2) > 1e-6 * np.linalg.norm(y2)
     assert good.status == O.STATUS_OK
+
+
+# ----------------------------------------------------------------------------
+# residual norms (eq:tik, eq:tik_new_sketched) and the small-factor formula
+# ----------------------------------------------------------------------------
+
+def _dense_sparse_sign(h, s, zeta, seed, stream):
+    """The s x h sparse-sign embedding built column by column from the scalar
+    definition (no call into the oracle's vectorised pattern)."""
+    S = np.zeros((s, h))
+    for j in range(h):
+        rows, signs = _bruteforce_column(j, s, zeta, seed, stream)
+        for r, g in zip(rows, signs):
+            S[r, j] = g / math.sqrt(zeta)
+    return S
+
+
+def test_tikhonov_residual_is_stacked_least_squares_norm():
+    """sqrt(||Ax-b||^2 + mu||Lx||^2) is the norm of [A; sqrt(mu) L] x - [b; 0] (eq:tik);
+    at the Tikhonov minimiser it equals sqrt(||b||^2 - b^T A x) (normal equations)."""
+    A, L, b, mu = tiny2d(N=7)
+    Ad, Ld = A.toarray(), L.toarray()
+    M = np.vstack([Ad, math.sqrt(mu) * Ld])
+    f = np.concatenate([b, np.zeros(Ld.shape[0])])
+    rng = np.random.default_rng(5)
+    for x in [rng.standard_normal(A.shape[1]) for _ in range(3)]:
+        assert abs(O.tikhonov_residual(A, L, b, mu, x) - np.linalg.norm(M @ x - f)) <= \
+            1e-13 * np.linalg.norm(M @ x - f)
+    x_star = np.linalg.lstsq(M, f, rcond=None)[0]
+    closed = math.sqrt(b @ b - b @ (Ad @ x_star))
+    assert abs(O.tikhonov_residual(A, L, b, mu, x_star) - closed) <= 1e-10 * closed
+
+
+def test_sketched_residual_is_stacked_sketched_norm():
+    """eq:tik_new_sketched: sqrt(||S_A(Ax-b)||^2 + mu||S_L L x||^2) equals the norm of
+    [S_A A; sqrt(mu) S_L L] x - [S_A b; 0] with S_A, S_L built from the scalar
+    definition; with identity sketches it is the Tikhonov residual."""
+    A, L, b, mu = tiny2d(N=7)
+    s, seed, zeta = 30, 9, 8
+    SA = _dense_sparse_sign(A.shape[0], s, zeta, seed, 0)
+    SL = _dense_sparse_sign(L.shape[0], s, zeta, seed, 1)
+    M = np.vstack([SA @ A.toarray(), math.sqrt(mu) * SL @ L.toarray()])
+    f = np.concatenate([SA @ b, np.zeros(s)])
+    rng = np.random.default_rng(6)
+    for x in [rng.standard_normal(A.shape[1]) for _ in range(3)]:
+        ref = np.linalg.norm(M @ x - f)
+        assert abs(O.sketched_residual(A, L, b, mu, x, s, seed, zeta) - ref) <= 1e-13 * ref
+        ident = O.sketched_residual(A, L, b, mu, x, s, seed, zeta, kind="identity")
+        assert abs(ident - O.tikhonov_residual(A, L, b, mu, x)) <= 1e-13 * ident
+
+
+def test_small_factor_sketched_residual_equals_sketched_residual():
+    """At x = W y the sketched residual follows from the small factors alone:
+    ||R_A y - d_A||^2 + (||S_A b||^2 - ||d_A||^2) + mu ||R_L y||^2, since
+    S_A A W = Q_A R_A, S_L L W = Q_L R_L and d_A = Q_A^T S_A b (eq:updqr,
+    eq:dA_update); checked for the sGKS y and for other y."""
+    A, L, b, mu = tiny2d(N=10)
+    s, seed = 90, 2
+    res = O.sgks(A, L, b, mu, 9, s, seed)
+    rng = np.random.default_rng(7)
+    for y in [res.y] + [rng.standard_normal(res.y.size) for _ in range(3)]:
+        small2 = (np.linalg.norm(res.R_A @ y - res.d_A) ** 2
+                  + (res.c_b @ res.c_b - res.d_A @ res.d_A)
+                  + mu * np.linalg.norm(res.R_L @ y) ** 2)
+        ref = O.sketched_residual(A, L, b, mu, res.W @ y, s, seed)
+        assert abs(math.sqrt(small2) - ref) <= 1e-11 * ref
+
+
+# ----------------------------------------------------------------------------
+# heavy-ball refinement weights
+# ----------------------------------------------------------------------------
+
+def test_refinement_two_steps_worked_by_hand():
+    """Two heavy-ball steps on a 1 x 1 problem, values worked out by hand:
+    A = 2, L = 1, b = 4, mu = 1, W = 1, G = 2, d / s = 1 / 4 so eta^2 = 1/4,
+    alpha = (1 - 1/4)^2 = 9/16, beta = 1/4.  r(y) = A^T(Ay - b) + mu L^T L y
+    = 5y - 8, delta = r / G^2 = (5y - 8) / 4.
+      y0 = 1:        delta0 = -3/4,        y1 = 1 + (9/16)(3/4)            = 1.421875
+      y1:            delta1 = -57/256,     y2 = y1 + (9/16)(57/256) + (1/4)(y1 - y0)
+                                               = 1.652587890625
+    (fixed point 8/5)."""
+    A = sp.csr_matrix(np.array([[2.0]]))
+    L = sp.csr_matrix(np.array([[1.0]]))
+    b = np.array([4.0])
+    W = np.array([[1.0]])
+    G = np.array([[2.0]])
+    y1 = O.refine(A, L, b, 1.0, W, np.array([1.0]), G, 4, 1)
+    y2 = O.refine(A, L, b, 1.0, W, np.array([1.0]), G, 4, 2)
+    assert y1[0] == 1.421875
+    assert y2[0] == 1.652587890625
+    assert O.refinement_weights(1, 4) == (0.5625, 0.25)
+
+
+def test_refinement_weights_give_the_optimal_heavy_ball_rate():
+    """With the preconditioned spectrum in [1/(1+eta)^2, 1/(1-eta)^2] (singular values
+    of the sketched basis in [1-eta, 1+eta]), Polyak's optimal step and momentum are
+    alpha = 4/(sqrt(l_max) + sqrt(l_min))^2 = (1-eta^2)^2 and
+    beta = ((sqrt(l_max) - sqrt(l_min))/(sqrt(l_max) + sqrt(l_min)))^2 = eta^2, and the
+    error contracts like eta^k; a diagonal system with both extremes shows it."""
+    d, s = 4, 25
+    eta = math.sqrt(d / s)
+    lam = np.array([1 / (1 + eta) ** 2, 1 / (1 - eta) ** 2, 1.0, 0.9])
+    lmin, lmax = lam.min(), lam.max()
+    a_opt = 4 / (math.sqrt(lmax) + math.sqrt(lmin)) ** 2
+    b_opt = ((math.sqrt(lmax) - math.sqrt(lmin)) / (math.sqrt(lmax) + math.sqrt(lmin))) ** 2
+    alpha, beta = O.refinement_weights(d, s)
+    assert abs(alpha - a_opt) <= 1e-15 and abs(beta - b_opt) <= 1e-15
+    # the oracle's refine() on this system: A = diag(sqrt(lam)), L = 0, W = I, G = I,
+    # so W^T r(y) = lam * y - sqrt(lam) * b and the solution is b / sqrt(lam)
+    A = sp.diags(np.sqrt(lam)).tocsr()
+    L = sp.csr_matrix((1, d))
+    b = np.ones(d)
+    y_star = b / np.sqrt(lam)
+    e0 = np.linalg.norm(np.zeros(d) - y_star)
+    k = 40
+    y = O.refine(A, L, b, 1.0, np.eye(d), np.zeros(d), np.eye(d), s, k)
+    rate = (np.linalg.norm(y - y_star) / e0) ** (1.0 / k)
+    assert rate <= 1.1 * eta
+    # a wrong momentum (beta = 0, plain preconditioned Richardson) is slower
+    with pytest.MonkeyPatch().context() as mp:
+        mp.setattr(O, "refinement_weights", lambda d_, s_: (alpha, 0.0))
+        y_r = O.refine(A, L, b, 1.0, np.eye(d), np.zeros(d), np.eye(d), s, k)
+    assert np.linalg.norm(y_r - y_star) > 10 * np.linalg.norm(y - y_star)
+
+
+# ----------------------------------------------------------------------------
+# sketch size: sGKS approaches GKS as s grows (Sec. 4.1)
+# ----------------------------------------------------------------------------
+
+def test_sgks_approaches_gks_as_sketch_grows():
+    """Sec. 4.1: the reconstruction of sGKS approaches that of GKS as the sketch size
+    grows; over s in {2d, 4d, 16d} (d = ell + k) and three sketch seeds the mean
+    distance ||x_sGKS - x_GKS|| / ||x_GKS|| and the mean |RRE_sGKS - RRE_GKS| fall."""
+    from workloads import make
+    P = make("deblur1d", 0, "small")
+    d = P.ell + P.k
+    g = O.gks(P.A, P.L, P.b, P.mu, P.k)
+    rre = lambda x: np.linalg.norm(x - P.x_true) / np.linalg.norm(P.x_true)
+    dist, gap = [], []
+    for s in (2 * d, 4 * d, 16 * d):
+        xs = [O.sgks(P.A, P.L, P.b, P.mu, P.k, s, seed).x for seed in (0, 1, 2)]
+        dist.append(np.mean([np.linalg.norm(x - g.x) / np.linalg.norm(g.x) for x in xs]))
+        gap.append(np.mean([abs(rre(x) - rre(g.x)) for x in xs]))
+    assert dist[0] > dist[1] > dist[2]
+    assert gap[0] > gap[2]
+    assert dist[2] < 0.5 * dist[0]

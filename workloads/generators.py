@@ -410,25 +410,36 @@ def dynamic_ct(seed=0, nt=30, N=128, n_angles=60, n_det=182, k=200, s=800, mu=1e
                    meta=dict(nt=nt, N=N, n_angles=n_angles, n_det=n_det))
 
 
-def batch_problems(seed=0, count=32, k=80, s=320, sides=(64, 256), dtype="f32"):
-    """Uneven batch: types cycle deblur / CT / travel time; sides log-uniform; mu log-uniform."""
+def batch_specs(seed=0, count=32, sides=(64, 256)):
+    """(kind, N, mu) of every problem of the uneven batch: types cycle deblur / CT /
+    travel time; sides and mu log-uniform."""
     rng = np.random.default_rng(seed)
-    probs = []
+    out = []
     for i in range(count):
         N = int(round(math.exp(rng.uniform(math.log(sides[0]), math.log(sides[1])))))
         mu = float(math.exp(rng.uniform(math.log(1e-3), math.log(1e-1))))
-        kind = i % 3
-        if kind == 0:
-            P = deblur2d(seed=seed + i, N=N, k=k, s=s, mu=mu, dtype=dtype)
-        elif kind == 1:
-            n_det = int(math.ceil(N * math.sqrt(2.0)))
-            P = ct2d(seed=seed + i, N=N, n_angles=max(8, (180 * N) // 256), n_det=n_det,
-                     k=k, s=s, mu=mu, refine_steps=0, dtype=dtype)
-        else:
-            P = traveltime2d(seed=seed + i, N=N, k=k, s=s, mu=mu, dtype=dtype)
-        P.seed = seed + i
-        probs.append(P)
-    return probs
+        out.append((("deblur2d", "ct2d", "traveltime2d")[i % 3], N, mu))
+    return out
+
+
+def batch_problem(i, seed=0, count=32, k=80, s=320, sides=(64, 256), dtype="f32"):
+    """Problem i of the uneven batch (as batch_problems builds it)."""
+    kind, N, mu = batch_specs(seed, count, sides)[i]
+    if kind == "deblur2d":
+        P = deblur2d(seed=seed + i, N=N, k=k, s=s, mu=mu, dtype=dtype)
+    elif kind == "ct2d":
+        n_det = int(math.ceil(N * math.sqrt(2.0)))
+        P = ct2d(seed=seed + i, N=N, n_angles=max(8, (180 * N) // 256), n_det=n_det,
+                 k=k, s=s, mu=mu, refine_steps=0, dtype=dtype)
+    else:
+        P = traveltime2d(seed=seed + i, N=N, k=k, s=s, mu=mu, dtype=dtype)
+    P.seed = seed + i
+    return P
+
+
+def batch_problems(seed=0, count=32, k=80, s=320, sides=(64, 256), dtype="f32"):
+    """Uneven batch: types cycle deblur / CT / travel time; sides log-uniform; mu log-uniform."""
+    return [batch_problem(i, seed, count, k, s, sides, dtype) for i in range(count)]
 
 
 def make(config, seed=0, scale="full"):

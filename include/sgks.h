@@ -57,7 +57,7 @@ extern "C" {
 #define SGKS_ERR_ZERO_RHS (-6)        /* b = 0 or A^T b = 0                        */
 #define SGKS_ERR_NONFINITE (-7)       /* NaN/Inf in b or in a computed vector      */
 #define SGKS_ERR_HIP (-8)             /* a HIP runtime call failed                 */
-#define SGKS_ERR_DEVICE (-9)          /* device-side failure (grid barrier)        */
+#define SGKS_ERR_DEVICE (-9)          /* device-side failure reported by a kernel  */
 #define SGKS_ERR_INITIAL_SPACE (-10)  /* K_ell(A^T A, A^T b) has dimension < ell,
                                          or its sketched columns are dependent     */
 
@@ -124,7 +124,8 @@ typedef struct {
                                 owned by the caller and used for every array of the context
                                 (no device allocation in sgks_create or afterwards, except the
                                 temporary of sgks_copy_state(W)); keep it alive until
-                                sgks_destroy.  Not accepted by sgks_batch_create.              */
+                                sgks_destroy.  sgks_batch_create takes one workspace for the
+                                whole batch (sgks_batch_workspace_bytes).                      */
     size_t workspace_bytes;
 } sgks_options;
 
@@ -160,13 +161,20 @@ int sgks_create(const sgks_csr *A, const sgks_csr *L, const void *b, double mu,
  * basis would exceed ell + max_iters columns. */
 int sgks_iterate(sgks_ctx *ctx, int32_t k);
 
-/* x = W y (n FP64 values) into the device buffer x_dev.  Asynchronous. */
+/* The iterate x_k = W_k y_k that Alg. 2 returns (its last line, with the basis
+ * of the expansions done so far): n FP64 values into the device buffer x_dev
+ * (caller-owned, n doubles).  Asynchronous on the context's stream; returns
+ * SGKS_ERR_INVALID_ARG for a null pointer. */
 int sgks_solution(sgks_ctx *ctx, double *x_dev);
 
-/* Synchronising.  true_norm = sqrt(||A x - b||^2 + mu ||L x||^2) at the
- * current x; sketched_norm = sqrt(||S_A(A x - b)||^2 + mu ||S_L L x||^2)
- * computed from the small factors: ||R_A y - d_A||^2 + ||S_A b||^2 - ||d_A||^2
- * + mu ||R_L y||^2.  Either pointer may be NULL. */
+/* Residual norms at the current iterate x = W y.  true_norm is the square root
+ * of the Tikhonov functional of eq:tik, sqrt(||A x - b||^2 + mu ||L x||^2),
+ * from one pass of A and L over x.  sketched_norm is the square root of the
+ * sketched functional of eq:tik_new_sketched, sqrt(||S_A(A x - b)||^2 +
+ * mu ||S_L L x||^2), computed in O(d^2) from the small factors alone
+ * (S_A A W = Q_A R_A, S_L L W = Q_L R_L, d_A = Q_A^T S_A b, eq:updqr and
+ * eq:dA_update): ||R_A y - d_A||^2 + ||S_A b||^2 - ||d_A||^2 + mu ||R_L y||^2.
+ * Host doubles; either pointer may be NULL.  Synchronises the stream. */
 int sgks_residual_norm(sgks_ctx *ctx, double *true_norm, double *sketched_norm);
 
 /* Synchronising.  *iters_done = expansions done so far; returns the status
@@ -177,7 +185,10 @@ int sgks_status(sgks_ctx *ctx, int32_t *iters_done);
  * W, Q_A, R_A, R_L held fixed, x = W H^{-1} R_A^T Q_A^T S_A b where
  * H = R_A^T R_A + mu R_L^T R_L.  Given grad_x (device, n FP64) writes
  * grad_b = S_A^T Q_A R_A z with z = H^{-1} W^T grad_x (device, m FP64) and
- * *grad_mu = -(R_L z).(R_L y) (host).  Synchronising. */
+ * *grad_mu = -(R_L z).(R_L y) (host).  Synchronising.  Returns
+ * SGKS_ERR_INVALID_ARG, before any device work, for a context created with
+ * refine_steps > 0: its x is the refined solve, whose derivative this adjoint
+ * is not. */
 int sgks_backward(sgks_ctx *ctx, const double *grad_x, double *grad_b, double *grad_mu);
 
 /* Copy one piece of the solver state to host memory (synchronising), for
@@ -244,11 +255,22 @@ typedef struct {
 
 typedef struct sgks_batch sgks_batch;
 
+/* Device bytes of a batch of these problems and options (host only, no device
+ * work): the contexts' arenas, each 256-byte aligned, then the device array of
+ * the problems' States.  0 if an argument is invalid. */
+size_t sgks_batch_workspace_bytes(int32_t count, const sgks_problem *problems,
+                                  const sgks_options *opt);
+
 /* Set up count (1..SGKS_MAX_BATCH) problems that share opt (value dtype,
  * zeta, ell, max_iters, refinement, QR passes, sketch kind, stream, graph and
  * autotune choices; lanes and append_groups must be 0).  Each problem is set
  * up as by sgks_create; the first failing problem's code is returned and
- * nothing is kept.  Synchronises the stream. */
+ * nothing is kept.  Device memory: with opt->workspace NULL the batch
+ * allocates each context's arena and its States array; otherwise
+ * opt->workspace (256-byte aligned, opt->workspace_bytes >=
+ * sgks_batch_workspace_bytes) holds all of them, carved in problem order, and
+ * nothing is allocated (SGKS_ERR_INVALID_ARG if it is too small or
+ * misaligned).  Synchronises the stream. */
 int sgks_batch_create(int32_t count, const sgks_problem *problems, const sgks_options *opt,
                       sgks_batch **out);
 

@@ -869,6 +869,9 @@ int sgks_status(sgks_ctx* c, int32_t* iters_done) {
 
 int sgks_backward(sgks_ctx* c, const double* grad_x, double* grad_b, double* grad_mu) {
     if (!c || !grad_x || !grad_b) return SGKS_ERR_INVALID_ARG;
+    // the adjoint is that of the unrefined projected solve (y = G^{-1} h); a
+    // refined y is another function of b and mu
+    if (c->opt.refine_steps > 0) return SGKS_ERR_INVALID_ARG;
     State& S = c->S;
     hipStream_t st = c->st;
     sgks::launch_gemvt(S, grad_x, -1, st);
@@ -985,6 +988,7 @@ void sgks_destroy(sgks_ctx* c) {
 struct sgks_batch {
     std::vector<sgks_ctx*> ctx;
     State* Sdev = nullptr;      // device array of the problems' States
+    bool own_sdev = false;      // allocated here (not in a caller's workspace)
     sgks::Plan plan;
     sgks_options opt;
     hipStream_t st = nullptr;
@@ -992,7 +996,42 @@ struct sgks_batch {
     GraphCache graphs;
 };
 
+namespace {
+
+size_t round256(size_t v) { return (v + 255) / 256 * 256; }
+
+// arena bytes of each problem of a batch (0 if one is invalid)
+bool batch_sizes(int32_t count, const sgks_problem* probs, const sgks_options& o,
+                 std::vector<size_t>& sizes) {
+    sizes.assign(count, 0);
+    for (int i = 0; i < count; ++i) {
+        sgks_options oi = o;
+        oi.workspace = nullptr;
+        oi.workspace_bytes = 0;
+        sizes[i] = sgks_workspace_bytes(&probs[i].A, &probs[i].L, probs[i].sketch_rows, &oi);
+        if (!sizes[i]) return false;
+    }
+    return true;
+}
+
+}  // namespace
+
 extern "C" {
+
+size_t sgks_batch_workspace_bytes(int32_t count, const sgks_problem* probs,
+                                  const sgks_options* opt) {
+    if (count < 1 || count > sgks::kMaxBatch || !probs) return 0;
+    sgks_options o;
+    if (opt)
+        o = *opt;
+    else
+        sgks_default_options(&o);
+    std::vector<size_t> sizes;
+    if (!batch_sizes(count, probs, o, sizes)) return 0;
+    size_t total = 0;
+    for (size_t v : sizes) total += round256(v);
+    return total + round256(sizeof(State) * count);
+}
 
 int sgks_batch_create(int32_t count, const sgks_problem* probs, const sgks_options* opt,
                       sgks_batch** out) {
@@ -1004,11 +1043,26 @@ int sgks_batch_create(int32_t count, const sgks_problem* probs, const sgks_optio
         o = *opt;
     else
         sgks_default_options(&o);
-    if (o.lanes_A || o.lanes_At || o.append_groups || o.workspace) return SGKS_ERR_INVALID_ARG;
+    if (o.lanes_A || o.lanes_At || o.append_groups) return SGKS_ERR_INVALID_ARG;
     for (int i = 0; i < count; ++i) {
         const int rc = sgks_validate(&probs[i].A, &probs[i].L, probs[i].b, probs[i].mu,
                                      probs[i].sketch_rows, &o);
         if (rc) return rc;
+    }
+    // a caller's workspace: the contexts' arenas in problem order, then the States
+    std::vector<size_t> offs(count, 0), sizes;
+    char* ws = (char*)o.workspace;
+    size_t states_off = 0;
+    if (ws) {
+        if (((uintptr_t)ws & 255) || !batch_sizes(count, probs, o, sizes))
+            return SGKS_ERR_INVALID_ARG;
+        size_t off = 0;
+        for (int i = 0; i < count; ++i) {
+            offs[i] = off;
+            off += round256(sizes[i]);
+        }
+        states_off = off;
+        if (o.workspace_bytes < off + round256(sizeof(State) * count)) return SGKS_ERR_INVALID_ARG;
     }
     sgks_batch* B = new (std::nothrow) sgks_batch();
     if (!B) return SGKS_ERR_HIP;
@@ -1023,17 +1077,27 @@ int sgks_batch_create(int32_t count, const sgks_problem* probs, const sgks_optio
     std::vector<int> groups(count);
     for (int i = 0; i < count; ++i) {
         sgks_ctx* c = nullptr;
+        sgks_options oi = o;
+        if (ws) {
+            oi.workspace = ws + offs[i];
+            oi.workspace_bytes = round256(sizes[i]);
+        }
         const int rc = sgks_create(&probs[i].A, &probs[i].L, probs[i].b, probs[i].mu,
-                                   probs[i].sketch_rows, probs[i].seed, &o, &c);
+                                   probs[i].sketch_rows, probs[i].seed, &oi, &c);
         if (rc) return fail(rc);
         c->borrowed = true;
         B->ctx.push_back(c);
         host[i] = c->S;
         groups[i] = c->groups;
     }
-    if (hipMalloc((void**)&B->Sdev, sizeof(State) * count) != hipSuccess) {
-        B->Sdev = nullptr;
-        return fail(SGKS_ERR_HIP);
+    if (ws) {
+        B->Sdev = (State*)(ws + states_off);
+    } else {
+        if (hipMalloc((void**)&B->Sdev, sizeof(State) * count) != hipSuccess) {
+            B->Sdev = nullptr;
+            return fail(SGKS_ERR_HIP);
+        }
+        B->own_sdev = true;
     }
     if (hipMemcpyAsync(B->Sdev, host.data(), sizeof(State) * count, hipMemcpyHostToDevice,
                        B->st) != hipSuccess ||
@@ -1078,7 +1142,7 @@ void sgks_batch_destroy(sgks_batch* B) {
     if (!B) return;
     (void)hipStreamSynchronize(B->st);
     for (sgks_ctx* c : B->ctx) destroy_ctx(c);
-    if (B->Sdev) (void)hipFree(B->Sdev);
+    if (B->Sdev && B->own_sdev) (void)hipFree(B->Sdev);
     delete B;
 }
 

@@ -110,6 +110,8 @@ def load_library(path=LIB_PATH):
     L.sgks_dim.restype = ctypes.c_int32
     L.sgks_get_tuning.argtypes = [ctypes.c_void_p, P(ctypes.c_int32)]
     L.sgks_get_tuning.restype = ctypes.c_int
+    L.sgks_batch_workspace_bytes.argtypes = [ctypes.c_int32, P(ProblemStruct), P(Options)]
+    L.sgks_batch_workspace_bytes.restype = ctypes.c_size_t
     L.sgks_batch_create.argtypes = [ctypes.c_int32, P(ProblemStruct), P(Options),
                                     P(ctypes.c_void_p)]
     L.sgks_batch_create.restype = ctypes.c_int
@@ -349,16 +351,14 @@ class SGKSBatch:
             stream = torch.cuda.current_stream(b0.device)
         self.stream = stream
         self.options = make_options(self._lib, vdt, stream, ell=ell, **opts)
-        if workspace is not None:   # not supported for batches: the library says so
+        if workspace is not None:
+            # caller-owned device memory for every context and the States array
+            self._workspace = workspace
             self.options.workspace = ctypes.c_void_p(workspace.data_ptr())
             self.options.workspace_bytes = workspace.numel() * workspace.element_size()
         self.problems = problems
         self.ell = int(ell)
-        arr = (ProblemStruct * len(problems))()
-        for i, (A, L, b, mu, s, seed) in enumerate(problems):
-            arr[i].A, arr[i].L = A.struct(), L.struct()
-            arr[i].b = b.data_ptr()
-            arr[i].mu, arr[i].sketch_rows, arr[i].seed = float(mu), int(s), int(seed)
+        arr = _problem_array(problems)
         h = ctypes.c_void_p()
         _check(self._lib.sgks_batch_create(len(problems), arr, ctypes.byref(self.options),
                                            ctypes.byref(h)), "sgks_batch_create")
@@ -409,6 +409,27 @@ class SGKSBatch:
             self.close()
         except Exception:
             pass
+
+
+def _problem_array(problems):
+    arr = (ProblemStruct * len(problems))()
+    for i, (A, L, b, mu, s, seed) in enumerate(problems):
+        arr[i].A, arr[i].L = A.struct(), L.struct()
+        arr[i].b = b.data_ptr()
+        arr[i].mu, arr[i].sketch_rows, arr[i].seed = float(mu), int(s), int(seed)
+    return arr
+
+
+def batch_workspace_bytes(problems, *, ell=3, value_dtype="f32", **opts):
+    """Device bytes of a batch of (A, L, b, mu, s, seed) problems (sgks_batch_workspace_bytes)."""
+    lib = load_library()
+
+    class _S:
+        cuda_stream = 0
+    o = make_options(lib, F32 if value_dtype == "f32" else F64, _S(), ell=ell, **opts)
+    problems = list(problems)
+    return int(lib.sgks_batch_workspace_bytes(len(problems), _problem_array(problems),
+                                              ctypes.byref(o)))
 
 
 def workspace_bytes(A: DeviceCsr, L: DeviceCsr, s, *, ell=3, value_dtype="f32", **opts):
@@ -482,6 +503,9 @@ def _function_class():
 
         @staticmethod
         def forward(ctx, b, mu, A, L, s, seed, k, opts):
+            if opts.get("refine_steps", 0) and (ctx.needs_input_grad[0] or ctx.needs_input_grad[1]):
+                raise ValueError("sgks_solve: no backward with refine_steps > 0 (the adjoint "
+                                 "is that of the unrefined projected solve)")
             S = SGKS(A, L, b.detach().contiguous(), float(mu), s, seed, **opts)
             S.iterate(k)
             ctx.solver = S

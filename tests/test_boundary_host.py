@@ -168,3 +168,32 @@ def test_workspace_bytes_host_only(lib):
     assert ws(gradient_form=G.GRADIENT_DIRECT) < base       # no HW
     assert ws(s=50) == 0                                     # invalid: s < ell + max_iters
     assert ws(zeta=3) == 0
+
+
+def test_batch_workspace_bytes_and_checks_before_device_work(lib):
+    """The batch workspace holds each context's arena (256-byte aligned) and the States
+    array; too small or misaligned workspaces are refused before any device work."""
+    probs = (G.ProblemStruct * 2)()
+    sizes = []
+    o = G.default_options()
+    o.max_iters = 100
+    for i, p in enumerate(probs):
+        p.A, p.L = _csr(100 + 20 * i, 80, 500), _csr(160, 80, 320)
+        p.b, p.mu, p.sketch_rows, p.seed = 0x4000, 1e-2, 400, i
+        sizes.append(lib.sgks_workspace_bytes(ctypes.byref(p.A), ctypes.byref(p.L), 400,
+                                              ctypes.byref(o)))
+    total = lib.sgks_batch_workspace_bytes(2, probs, ctypes.byref(o))
+    up = lambda v: (v + 255) // 256 * 256
+    assert all(v > 0 for v in sizes)
+    assert total > sum(up(v) for v in sizes)
+    assert total - sum(up(v) for v in sizes) <= up(2 * 4096)     # the States array
+    assert lib.sgks_batch_workspace_bytes(0, probs, ctypes.byref(o)) == 0
+    probs[1].sketch_rows = 50
+    assert lib.sgks_batch_workspace_bytes(2, probs, ctypes.byref(o)) == 0
+    probs[1].sketch_rows = 400
+    out = ctypes.c_void_p()
+    o.workspace, o.workspace_bytes = 0x10000, total - 1      # too small
+    assert lib.sgks_batch_create(2, probs, ctypes.byref(o), ctypes.byref(out)) == -1
+    o.workspace, o.workspace_bytes = 0x10008, total + 256    # misaligned
+    assert lib.sgks_batch_create(2, probs, ctypes.byref(o), ctypes.byref(out)) == -1
+    assert out.value is None

@@ -279,8 +279,32 @@ def test_caller_workspace():
     with pytest.raises(G.SgksError) as e:
         G.SGKS(A, L, b, P.mu, P.s, P.seed, workspace=ws[8:nbytes + 8], **kw)
     assert e.value.code == -1
+
+
+def test_batch_in_caller_workspace():
+    """A whole batch (every context and the States array) in one caller-owned torch
+    uint8 tensor (sgks_batch_workspace_bytes): bitwise the batch that allocates its
+    own memory; too small a workspace is refused."""
+    Ps = problem("batch", "small")
+    say("case batch workspace", len(Ps))
+    data = G.upload_batch(Ps)
+    kw = dict(ell=Ps[0].ell, max_iters=Ps[0].k, zeta=Ps[0].zeta)
+    nbytes = G.batch_workspace_bytes(data, value_dtype=Ps[0].dtype, **kw)
+    say("  batch workspace bytes", nbytes)
+    assert nbytes > 0
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    B1 = G.SGKSBatch(data, workspace=ws, **kw)
+    B1.iterate(Ps[0].k)
+    B2 = G.SGKSBatch(data, **kw)
+    B2.iterate(Ps[0].k)
+    for i in range(len(Ps)):
+        assert np.array_equal(B1.problem(i).solution().cpu().numpy(),
+                              B2.problem(i).solution().cpu().numpy()), i
+        assert B1.problem(i).status() == B2.problem(i).status() == (0, Ps[0].k)
+    B1.close()
+    B2.close()
     with pytest.raises(G.SgksError) as e:
-        G.SGKSBatch([(A, L, b, P.mu, P.s, P.seed)], workspace=ws, **kw)
+        G.SGKSBatch(data, workspace=ws[:nbytes - 256], **kw)
     assert e.value.code == -1
 
 

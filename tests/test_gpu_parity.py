@@ -389,6 +389,23 @@ def test_refinement_small():
     S.close()
 
 
+def test_backward_with_refinement_is_refused():
+    """The adjoint is that of the unrefined projected solve: a context with refinement
+    steps refuses sgks_backward, and the autograd function refuses to record."""
+    P = problem("ct2d", "small")
+    assert P.refine_steps > 0
+    say("case backward with refinement")
+    S, x = G.solve_problem(P, k=3)
+    with pytest.raises(G.SgksError) as e:
+        S.backward(torch.zeros_like(x))
+    assert e.value.code == -1
+    S.close()
+    A, L, b = G.upload_problem(P)
+    bg = b.clone().requires_grad_(True)
+    with pytest.raises(ValueError):
+        G.sgks_solve(A, L, bg, P.mu, P.s, 3, P.seed, refine_steps=P.refine_steps)
+
+
 def test_backward_small_matches_oracle_adjoint():
     P = problem("dynamic_ct", "small")
     say("case backward")

@@ -118,7 +118,35 @@ void enqueue_refine(const sgks::Plan& P, Profiler* pr, hipStream_t st) {
 // columns of H W = (A^T A + mu L^T L) W, whose new column is A^T (A w) +
 // mu L^T (L w) from the images the sketch needs anyway.  Direct form:
 // x = W y, u = A x - b, t = L x, r = A^T u + mu L^T t.
-int enqueue_iteration(const sgks::Plan& P, int refine_steps, Profiler* pr, hipStream_t st) {
+// A second stream of the caller's device (default priority) that takes the
+// H W column's adjoint products while the caller's stream runs the sketch
+// scatter and the QR appends of the same expansion: the two read the same
+// images (A w, L w) and write disjoint memory, and the appends are latency
+// bound (a few workgroups), so the bandwidth-bound adjoint fills the GPU
+// beside them.  The caller's stream waits for it before the expansion ends.
+struct SideStream {
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    ~SideStream() {
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
+        if (side) (void)hipStreamDestroy(side);
+    }
+    bool ready() {
+        if (side) return true;
+        if (hipStreamCreateWithFlags(&side, hipStreamNonBlocking) != hipSuccess) {
+            side = nullptr;
+            return false;
+        }
+        if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess)
+            return false;
+        return true;
+    }
+};
+
+int enqueue_iteration(const sgks::Plan& P, int refine_steps, Profiler* pr, hipStream_t st,
+                      SideStream* ss = nullptr) {
     const bool maintained = P.gradient_form == SGKS_GRADIENT_MAINTAINED;
     if (maintained) {
         Phase ph(pr, 0);
@@ -129,13 +157,27 @@ int enqueue_iteration(const sgks::Plan& P, int refine_steps, Profiler* pr, hipSt
         { Phase ph(pr, 2); sgks::plan_adjoint(P, 0, st); }
     }
     { Phase ph(pr, 3); sgks::plan_forward(P, true, st); }
+    // maintained form: column d of H W from (A w, L w), in the compact append's
+    // launch (beside the side appends, its column index recorded by the SpMV
+    // above) or in a launch of its own, on the side stream when there is one
+    const bool hw_sep = maintained && sgks::plan_has_hw_separate(P);
+    const bool fork = hw_sep && ss;
+    if (fork) {
+        if (hipEventRecord(ss->fork, st) != hipSuccess ||
+            hipStreamWaitEvent(ss->side, ss->fork, 0) != hipSuccess)
+            return SGKS_ERR_HIP;
+        { Phase ph(pr, 2); sgks::plan_hw_separate(P, ss->side); }
+        if (hipEventRecord(ss->join, ss->side) != hipSuccess) return SGKS_ERR_HIP;
+    } else if (hw_sep) {
+        Phase ph(pr, 2);
+        sgks::plan_hw_separate(P, st);
+    }
     { Phase ph(pr, 7); sgks::plan_scatter(P, st); }
     {
-        // maintained form: column d of H W is added in the append's launch,
-        // beside the side appends (its column index recorded by the SpMV above)
         Phase ph(pr, 4);
         if (sgks::plan_append(P, true, maintained, st)) return SGKS_ERR_HIP;
     }
+    if (fork && hipStreamWaitEvent(st, ss->join, 0) != hipSuccess) return SGKS_ERR_HIP;
     for (int r = 0; r < refine_steps; ++r) enqueue_refine(P, pr, st);
     return SGKS_OK;
 }
@@ -183,10 +225,17 @@ struct GraphCache {
 // k expansions of every problem of the plan: graph replays, or kernel by
 // kernel while profiling or when graphs are off.
 int run_iterations(const sgks::Plan& P, int refine_steps, Profiler* pr, GraphCache* gc,
-                   bool use_graph, hipStream_t st, int k) {
+                   bool use_graph, hipStream_t st, int k, SideStream* ss) {
     if (!use_graph || (pr && pr->on)) {
+        // no second stream while the caller's stream is being captured
+        hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(st, &cst) != hipSuccess) return SGKS_ERR_HIP;
+        SideStream* use = nullptr;
+        if (cst == hipStreamCaptureStatusNone && sgks::plan_has_hw_separate(P) && ss &&
+            ss->ready())
+            use = ss;
         for (int it = 0; it < k; ++it) {
-            const int rc = enqueue_iteration(P, refine_steps, pr, st);
+            const int rc = enqueue_iteration(P, refine_steps, pr, st, use);
             if (rc) return rc;
         }
         return hipGetLastError() == hipSuccess ? SGKS_OK : SGKS_ERR_HIP;
@@ -320,6 +369,7 @@ struct sgks_ctx {
     int groups;          // workgroups of the append kernels
     bool borrowed = false;   // owned by a batch
     GraphCache graphs;
+    SideStream side;
     std::vector<void*> allocs;
     double* upart;       // partial sums of ||A x - b||^2
     double* tpart;       // partial sums of ||L x||^2
@@ -826,7 +876,7 @@ int sgks_iterate(sgks_ctx* c, int32_t k) {
     if (!c || k < 0) return SGKS_ERR_INVALID_ARG;
     if (c->d_host + k > c->S.dmax) return SGKS_ERR_CAPACITY;
     const int rc = run_iterations(c->plan, c->opt.refine_steps, &c->prof, &c->graphs,
-                                  c->opt.graph != 0, c->st, k);
+                                  c->opt.graph != 0, c->st, k, &c->side);
     if (rc) return rc;
     c->d_host += k;
     return SGKS_OK;
@@ -994,6 +1044,7 @@ struct sgks_batch {
     hipStream_t st = nullptr;
     Profiler prof;
     GraphCache graphs;
+    SideStream side;
 };
 
 namespace {
@@ -1114,7 +1165,7 @@ int sgks_batch_iterate(sgks_batch* B, int32_t k) {
     for (sgks_ctx* c : B->ctx)
         if (c->d_host + k > c->S.dmax) return SGKS_ERR_CAPACITY;
     const int rc = run_iterations(B->plan, B->opt.refine_steps, &B->prof, &B->graphs,
-                                  B->opt.graph != 0, B->st, k);
+                                  B->opt.graph != 0, B->st, k, &B->side);
     if (rc) return rc;
     for (sgks_ctx* c : B->ctx) c->d_host += k;
     return SGKS_OK;

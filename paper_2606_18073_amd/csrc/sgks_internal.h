@@ -214,8 +214,13 @@ void plan_forward(const Plan& P, bool newcol, hipStream_t st); // u = A x - b, t
 void plan_adjoint(const Plan& P, int dst_kind, hipStream_t st);
 void plan_gradient(const Plan& P, bool to_rtmp, hipStream_t st);  // r from H W
 void plan_scatter(const Plan& P, hipStream_t st);              // sketch bins of (u, t)
-// with_hw (maintained gradient form): also add column d of H W from (u, t)
+// with_hw (maintained gradient form): also add column d of H W from (u, t) in
+// the compact side launch (when the plan fuses it there)
 int plan_append(const Plan& P, bool scale_from_norm, bool with_hw, hipStream_t st);
+// column d of H W from (u, t) = (A w, L w) in a launch of its own, for the
+// problems whose H W column is not fused into the compact side launch
+bool plan_has_hw_separate(const Plan& P);
+void plan_hw_separate(const Plan& P, hipStream_t st);
 void plan_gemvt(const Plan& P, hipStream_t st);                // W^T rtmp partials
 void plan_refine(const Plan& P, hipStream_t st);
 

@@ -2367,17 +2367,21 @@ void plan_scatter(const Plan& P, hipStream_t st) {
 #undef SGKS_SC
 }
 
+bool plan_has_hw_separate(const Plan& P) {
+    return P.gradient_form == 0 && tab_total(P.adj_hw_sep) > 0;
+}
+
+void plan_hw_separate(const Plan& P, hipStream_t st) {
+    if (!plan_has_hw_separate(P)) return;
+    const dim3 grid(tab_total(P.adj_hw_sep));
+    if (P.vdt == 0)
+        SGKS_LAUNCH(kb_adjoint<float>, grid, dim3(kBlock), 0, st, P.SS, P.adj_hw_sep, kDstHW);
+    else
+        SGKS_LAUNCH(kb_adjoint<double>, grid, dim3(kBlock), 0, st, P.SS, P.adj_hw_sep, kDstHW);
+}
+
 int plan_append(const Plan& P, bool scale_from_norm, bool with_hw, hipStream_t st) {
     with_hw = with_hw && P.gradient_form == 0;
-    if (with_hw && tab_total(P.adj_hw_sep) > 0) {
-        const dim3 grid(tab_total(P.adj_hw_sep));
-        if (P.vdt == 0)
-            SGKS_LAUNCH(kb_adjoint<float>, grid, dim3(kBlock), 0, st, P.SS, P.adj_hw_sep,
-                               kDstHW);
-        else
-            SGKS_LAUNCH(kb_adjoint<double>, grid, dim3(kBlock), 0, st, P.SS, P.adj_hw_sep,
-                               kDstHW);
-    }
     if (tab_total(P.ap1_side) > 0) {
         const int sfn = scale_from_norm ? 1 : 0;
         if (!with_hw || !P.fuse_hw)

@@ -33,6 +33,22 @@ def oracle_run(P, k=None, **kw):
                   refine_steps=P.refine_steps, **kw)
 
 
+def backward_error(RA, RL, dA, mu, y):
+    """Normwise backward error of y as a least-squares solution of the projected problem
+    min || [R_A; sqrt(mu) R_L] y - [d_A; 0] || (eq:projected_sketched_bis):
+    ||M^T (M y - f)|| / (||M|| (||M|| ||y|| + 2 ||f||)).  A backward-stable solver keeps it
+    at a modest multiple of d * eps whatever the condition number of M."""
+    M = np.vstack([RA, math.sqrt(mu) * RL])
+    f = np.concatenate([dA, np.zeros(RL.shape[0])])
+    nM = np.linalg.norm(M, 2)
+    return float(np.linalg.norm(M.T @ (M @ y - f)) /
+                 (nM * (nM * np.linalg.norm(y) + 2 * np.linalg.norm(f))))
+
+
+# backward error allowed for the GPU's projected solve, in units of d * eps
+BACKWARD_ERROR_UNITS = 50.0
+
+
 def check_state_consistency(S, P, tol=1e-9):
     """Relations that hold at any k: the GPU's factors are factors of the GPU's basis."""
     W = S.state("W")
@@ -58,12 +74,19 @@ def check_state_consistency(S, P, tol=1e-9):
     y_ref, Gf = O.projected_solve(RA, RL, dA, P.mu)
     kap = np.linalg.cond(np.vstack([RA, math.sqrt(P.mu) * RL]))
     if P.refine_steps == 0:
-        assert rel(y, y_ref) <= max(1e-10, 1e-15 * kap * 10), (rel(y, y_ref), kap)
+        # for any kappa: y is a backward-stable solution of the GPU's own projected problem
+        eta = backward_error(RA, RL, dA, P.mu, y)
+        eta_ref = backward_error(RA, RL, dA, P.mu, y_ref)
+        say(f"  projected solve: kappa {kap:.2e}, backward error {eta:.2e} "
+            f"(Householder on the same factors {eta_ref:.2e}, bound "
+            f"{BACKWARD_ERROR_UNITS * d * 2.2e-16:.2e})")
+        assert eta <= BACKWARD_ERROR_UNITS * d * 2.2e-16, (eta, kap)
+        if kap <= KAPPA_TRUSTED:
+            assert rel(y, y_ref) <= max(1e-10, 1e-15 * kap * 10), (rel(y, y_ref), kap)
     else:
         # refined y: the oracle's heavy-ball steps from y_ref on the GPU basis
         y_ir = O.refine(P.A, P.L, P.b, P.mu, W, y_ref, Gf, P.s, P.refine_steps)
         assert rel(y, y_ir) <= max(1e-9, 1e-15 * kap * 100), (rel(y, y_ir), kap)
-    # last column is the normalised gradient at the previous iterate (if any expansion done)
     return W, y
 
 
@@ -81,3 +104,58 @@ def cond_at(ref, P, k):
 # it the projected problem is numerically singular in FP64 and only the
 # relations that hold for any rounding are checked.
 KAPPA_TRUSTED = 1e10
+
+
+# ----------------------------------------------------------------------------
+# oracle runs in worker processes (started before the GPU is touched, see
+# conftest.py), so that the long full-size references run beside the GPU tests
+# ----------------------------------------------------------------------------
+
+_pool = None
+
+
+def start_oracle_pool(workers=6):
+    global _pool
+    if _pool is None:
+        import multiprocessing as mp
+        _pool = mp.get_context("spawn").Pool(processes=workers)
+    return _pool
+
+
+def _build(spec):
+    kind = spec[0]
+    if kind == "batch_problem":
+        from workloads import generators as gen
+        return gen.batch_problem(spec[1])
+    return make(kind, spec[2], spec[1])
+
+
+def _oracle_history(spec, k, checkpoints):
+    """x after each checkpoint expansion count and kappa(G_k) there."""
+    from threadpoolctl import threadpool_limits
+    P = _build(spec)
+    with threadpool_limits(1):
+        ref = O.sgks(P.A, P.L, P.b, P.mu, k, P.s, P.seed, zeta=P.zeta, ell=P.ell,
+                     refine_steps=P.refine_steps, keep_history=True)
+    hist = {kk: ref.x_hist[kk] for kk in checkpoints if kk <= ref.iters}
+    kap = {kk: cond_at(ref, P, kk) for kk in checkpoints if kk <= ref.iters}
+    return hist, kap, ref.iters, ref.status
+
+
+class _Now:
+    def __init__(self, fn, args):
+        self.fn, self.args, self.val = fn, args, None
+
+    def get(self, timeout=None):
+        if self.val is None:
+            self.val = self.fn(*self.args)
+        return self.val
+
+
+def oracle_history_async(spec, k, checkpoints):
+    """Oracle trajectory of a workload ((name, scale, seed) or ("batch_problem", i)) at the
+    checkpoints: computed in a worker process when the pool runs, else on .get()."""
+    args = (spec, k, tuple(checkpoints))
+    if _pool is not None:
+        return _pool.apply_async(_oracle_history, args)
+    return _Now(_oracle_history, args)

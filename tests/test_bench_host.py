@@ -30,17 +30,40 @@ def test_algorithmic_bytes_of_the_deblurring_workload():
       SpMV of the new column: 8 (nnz(A) + nnz(L)) = 43,822,208 for values and columns,
         4 (m + 1) + 4 (p + 1) = 786,440 for row pointers, 8 n = 524,288 for w,
         8 m + 8 p = 1,572,864 for A w and L w: 46,705,800;
-      scatter: (8 + 2 zeta)(m + p) = 4,718,592 for the images and the int16 pattern,
-        16 s = 6,400 for the bins: 4,724,992;
+      adjoint: 43,822,208 + 8 (n + 1) = 524,296 for the two transposed row-pointer
+        arrays, 8 m + 8 p = 1,572,864 for (u, t), 8 n = 524,288 for the result: 46,443,656;
+      scatter: 8 (m + p) = 1,572,864 for the images (the pattern is hashable: no bytes),
+        16 s = 6,400 for the two bin vectors: 1,579,264;
       gradient at d = 50: 8 n d = 26,214,400 for the columns of H W,
         16 n = 1,048,576 for A^T b and r: 27,262,976."""
     P = make("deblur2d", 0, "full")
     assert (P.m, P.n, P.p, P.A.nnz, P.L.nnz, P.s, P.zeta, P.dtype) == \
         (65536, 65536, 131072, 5216656, 261120, 400, 8, "f32")
-    ab = bench.algorithmic_bytes(P, 50, "maintained")
-    assert ab["spmv_new_column"] == 46_705_800
-    assert ab["sketch_scatter"] == 4_724_992
-    assert ab["gemv"] == 27_262_976
+    assert bench.launch_bytes(P, "spmv_new_column") == 46_705_800
+    assert bench.launch_bytes(P, "adjoint") == 46_443_656
+    assert bench.launch_bytes(P, "sketch_scatter") == 1_579_264
+    assert bench.launch_bytes(P, "gradient", 50) == 27_262_976
+
+
+def test_expected_launches_of_one_step():
+    """One expansion per k: gradient, new-column SpMV, H W adjoint (own launch unless fused
+    into the append), scatter, append; refinement steps add a gradient, W^T r and the
+    update each; the solution adds one GEMV over ell + k columns."""
+    P = make("deblur2d", 0, "small")
+    ex = bench.expected_launches(P, "maintained", fused_hw=True)
+    assert len(ex["gemv"]) == P.k + 1
+    assert "adjoint" not in ex
+    assert ex["qr_append_solve"] == [bench.launch_bytes(P, "adjoint")] * P.k
+    ex = bench.expected_launches(P, "maintained", fused_hw=False)
+    assert len(ex["adjoint"]) == P.k and ex["qr_append_solve"] == [0] * P.k
+    Q = make("ct2d", 0, "small")
+    ex = bench.expected_launches(Q, "maintained", fused_hw=False)
+    assert len(ex["gemv"]) == Q.k * (1 + Q.refine_steps) + 1
+    assert len(ex["gemvt_WTr"]) == Q.k * Q.refine_steps
+    d0 = Q.ell
+    assert ex["gemv"][0] == bench.launch_bytes(Q, "gradient", d0)
+    assert ex["gemv"][1] == bench.launch_bytes(Q, "gradient", d0 + 1)   # refinement after the append
+    assert ex["gemv"][-1] == bench.launch_bytes(Q, "gemv", Q.ell + Q.k)
 
 
 def _profile_commands():
@@ -73,11 +96,14 @@ def test_profiles_name_commands_that_run_committed_files():
 
 def test_stale_profiles_are_not_used():
     """Traffic and trace figures are taken only from summaries of the current sources."""
-    assert bench.load_traffic("kb_forward", "deblur2d", "0" * 16) is None
-    assert bench.load_trace_avg("kb_forward", "deblur2d", "0" * 16) is None
+    d = os.path.join(ROOT, "profiles")
+    traffic = sorted(f for f in os.listdir(d) if f.startswith("traffic_") and f.endswith(".json"))
+    assert traffic
+    t = json.load(open(os.path.join(d, traffic[0])))
+    assert bench.load_traffic(t["kernel"], t["workload"], "0" * 16) is None
+    assert bench.load_trace_avg(t["kernel"], t["workload"], "0" * 16) is None
     h = bench.source_hash()
-    t = json.load(open(os.path.join(ROOT, "profiles", "traffic_kb_forward_deblur2d.json")))
     if t["source_hash"] != h:
         pytest.skip("committed profiles predate the current sources")
-    assert bench.load_traffic("kb_forward", "deblur2d", h) == t["bytes_per_launch"]
-    assert bench.load_trace_avg("kb_forward", "deblur2d", h) > 0
+    assert bench.load_traffic(t["kernel"], t["workload"], h) == t["bytes_per_launch"]
+    assert bench.load_trace_avg(t["kernel"], t["workload"], h) > 0

@@ -26,8 +26,15 @@ from workloads import generators as gen  # noqa: E402
 from workloads import make  # noqa: E402
 
 
-from gpu_common import (KAPPA_TRUSTED, check_state_consistency, cond_at, oracle_run,  # noqa: E402
-                        problem, rel, say)
+from gpu_common import (KAPPA_TRUSTED, check_state_consistency, cond_at,  # noqa: E402
+                        oracle_history_async, oracle_run, problem, rel, say)
+
+# full-size oracle trajectories, computed in worker processes while the other
+# tests run (about 30 s and 140 s of one host core)
+CT_CHECK = (40, 80, 120, 149, 150)
+DYN_CHECK = (20, 50, 100, 150, 199, 200)
+_REF_CT = oracle_history_async(("ct2d", "full", 0), 150, CT_CHECK)
+_REF_DYN = oracle_history_async(("dynamic_ct", "full", 0), 200, DYN_CHECK)
 
 
 # ----------------------------------------------------------------------------
@@ -478,45 +485,55 @@ def test_deblur2d_full_trajectory_and_consistency():
     S.close()
 
 
-def test_ct2d_full_refined():
-    """CT 256^2, 180 x 362 rays, FP32 operators, 2 refinement steps per solve."""
-    P = problem("ct2d", "full")
-    k_traj = 40
-    say("case ct2d full", P.n, P.m, P.k, "trajectory to", k_traj)
-    ref = oracle_run(P, k=k_traj)
-    A, L, b = G.upload_problem(P)
-    S = G.SGKS(A, L, b, P.mu, P.s, P.seed, max_iters=P.k, refine_steps=P.refine_steps)
-    S.iterate(k_traj)
-    e = rel(S.solution().cpu().numpy(), ref.x)
-    say(f"  k={k_traj} rel err {e:.3e}")
-    assert e <= 1e-6
-    S.iterate(P.k - k_traj - 1)
-    check_new_column_is_gradient(S, P)
+def _trajectory_against(S, P, ref_async, checkpoints, tol, final_column=True):
+    """Iterate S to each checkpoint and compare x_k with the oracle's x_k; the last
+    expansion goes through check_new_column_is_gradient."""
+    hist, kap, iters, status = ref_async.get()
+    assert iters == P.k and status == O.STATUS_OK
+    done = 0
+    for k in checkpoints:
+        if final_column and k == P.k:
+            check_new_column_is_gradient(S, P)
+        else:
+            S.iterate(k - done)
+        done = k
+        e = rel(S.solution().cpu().numpy(), hist[k])
+        say(f"  k={k} kappa {kap[k]:.2e} rel err {e:.3e}")
+        assert e <= tol, (k, e, kap[k])
     rc, it = S.status()
     assert rc == 0 and it == P.k
+
+
+@pytest.mark.timeout(900)
+def test_ct2d_full_refined():
+    """CT 256^2, 180 x 362 rays, FP32 operators, 2 refinement steps per solve: x_k against
+    the oracle along the whole run, k = 40 ... 150 (the configured output)."""
+    P = problem("ct2d", "full")
+    say("case ct2d full", P.n, P.m, P.k)
+    A, L, b = G.upload_problem(P)
+    S = G.SGKS(A, L, b, P.mu, P.s, P.seed, max_iters=P.k, refine_steps=P.refine_steps)
+    _trajectory_against(S, P, _REF_CT, CT_CHECK, 1e-6)
     check_state_consistency(S, P)
     x = S.solution().cpu().numpy()
-    say(f"  k={P.k} RRE gpu {rel(x, P.x_true):.6f}")
+    hist, *_ = _REF_CT.get()
+    say(f"  k={P.k} RRE gpu {rel(x, P.x_true):.7f} oracle {rel(hist[P.k], P.x_true):.7f} "
+        f"(grows with k on this workload: the oracle's own RRE rises from k = 20 on)")
     S.close()
 
 
+@pytest.mark.timeout(900)
 def test_dynamic_ct_full():
-    """Dynamic CT 30 x 128^2 frames, block-diagonal A, space-time L, k = 200."""
+    """Dynamic CT 30 x 128^2 frames, block-diagonal A, space-time L, k = 200: x_k against
+    the oracle along the whole run, k = 20 ... 200 (the configured output)."""
     P = problem("dynamic_ct", "full")
-    k_traj = 20
-    say("case dynamic_ct full", P.n, P.m, P.p, "trajectory to", k_traj)
-    ref = oracle_run(P, k=k_traj)
+    say("case dynamic_ct full", P.n, P.m, P.p, P.k)
     A, L, b = G.upload_problem(P)
     S = G.SGKS(A, L, b, P.mu, P.s, P.seed, max_iters=P.k)
-    S.iterate(k_traj)
-    e = rel(S.solution().cpu().numpy(), ref.x)
-    say(f"  k={k_traj} rel err {e:.3e}")
-    assert e <= 1e-8
-    S.iterate(P.k - k_traj - 1)
-    check_new_column_is_gradient(S, P)
+    _trajectory_against(S, P, _REF_DYN, DYN_CHECK, 1e-5)
     check_state_consistency(S, P)
     x = S.solution().cpu().numpy()
-    say(f"  k={P.k} RRE gpu {rel(x, P.x_true):.6f}")
+    hist, *_ = _REF_DYN.get()
+    say(f"  k={P.k} RRE gpu {rel(x, P.x_true):.7f} oracle {rel(hist[P.k], P.x_true):.7f}")
     S.close()
 
 

@@ -142,6 +142,18 @@ def _oracle_history(spec, k, checkpoints):
     return hist, kap, ref.iters, ref.status
 
 
+def wait_ref(res, what=""):
+    """The result of an oracle run, printing a line every 20 s while it is still running."""
+    import time
+    t0 = time.time()
+    if hasattr(res, "ready"):
+        while not res.ready():
+            res.wait(20)
+            if not res.ready():
+                say(f"  waiting for the oracle {what} ({time.time() - t0:.0f} s)")
+    return res.get()
+
+
 class _Now:
     def __init__(self, fn, args):
         self.fn, self.args, self.val = fn, args, None

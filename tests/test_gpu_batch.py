@@ -17,7 +17,7 @@ if not torch.cuda.is_available():
 
 from gpu_common import (BACKWARD_ERROR_UNITS, KAPPA_TRUSTED, backward_error,  # noqa: E402
                         check_state_consistency, oracle_history_async, oracle_run, problem,
-                        rel, say)
+                        rel, say, wait_ref)
 from oracle import sgks_oracle as O  # noqa: E402
 from paper_2606_18073_amd import sgks as G  # noqa: E402
 from workloads import generators as gen  # noqa: E402
@@ -213,7 +213,7 @@ def test_batch_full_size_32_problems():
     sample = BATCH_SAMPLE
     Bs = G.SGKSBatch(G.upload_batch([Ps[i] for i in sample]), ell=Ps[0].ell,
                      max_iters=Ps[0].k, zeta=Ps[0].zeta)
-    refs = {i: _REF_BATCH[i].get() for i in sample}
+    refs = {i: wait_ref(_REF_BATCH[i], f"batch problem {i}") for i in sample}
     done = 0
     checked = 0
     for k in BATCH_CHECK:

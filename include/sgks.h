@@ -199,6 +199,19 @@ int sgks_backward(sgks_ctx *ctx, const double *grad_x, double *grad_b, double *g
  * or an error code. */
 int64_t sgks_copy_state(sgks_ctx *ctx, int32_t which, double *dst, int64_t count);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): sgks_copy_state
+ * without its device temporary.  which, dst, count and the return value are as
+ * for sgks_copy_state (same values, bit for bit).  For W (which = 0) the scaled
+ * columns are staged through a static device array of
+ * SGKS_NOALLOC_SCRATCH_BYTES held by the library on each GPU it runs on (until
+ * the process ends), as many columns at a time as fit; returns
+ * SGKS_ERR_CAPACITY if one column (8 n bytes) exceeds it.  The array is shared
+ * by every call on that GPU: calls that overlap on one GPU (several threads or
+ * contexts at once) race.  Allocates nothing; synchronises the stream. */
+#define SGKS_NOALLOC_SCRATCH_BYTES (16u << 20)
+int64_t sgks_copy_state_noalloc(sgks_ctx *ctx, int32_t which, double *dst, int64_t count);
+
 /* Per-phase device timing (the per-component breakdown of Sec. 4): while
  * enabled, every kernel launch of sgks_iterate / sgks_solution is issued with
  * a pair of HIP events bound to that kernel, which hold the begin and end of

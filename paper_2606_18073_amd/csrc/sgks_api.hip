@@ -19,6 +19,35 @@ using sgks::State;
 
 thread_local sgks::LaunchTimer* sgks::tl_launch_timer = nullptr;
 
+// Staging memory of sgks_copy_state_noalloc: a file-scope device array, one copy
+// per GPU, held until the process ends.  Host code never passes its name to a
+// kernel or a copy; it uses the device address hipGetSymbolAddress returns for
+// the current device (kept per device below).
+static __device__ __align__(256) double scratch[SGKS_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of this device's copy of `scratch`, looked up once per device
+// with that device current.
+int scratch_address(void** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return SGKS_ERR_HIP;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SGKS_ERR_HIP;
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return SGKS_OK;
+}
+
+}  // namespace
+
 namespace {
 
 // Per-phase kernel timing: every launch made inside a phase gets an event
@@ -365,6 +394,7 @@ struct sgks_ctx {
     sgks::Plan plan;     // the iteration as a batch of one
     sgks_options opt;
     hipStream_t st;
+    int device = 0;      // the device current at sgks_create
     int d_host;          // basis columns expected on the device (no breakdown)
     int groups;          // workgroups of the append kernels
     bool borrowed = false;   // owned by a batch
@@ -700,6 +730,15 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
         sgks_destroy(c);
         return rc;
     }
+    {
+        // the device of the context, and (once per device) the address of its
+        // copy of the static staging array
+        void* sp = nullptr;
+        if (hipGetDevice(&c->device) != hipSuccess || scratch_address(&sp) != SGKS_OK) {
+            sgks_destroy(c);
+            return SGKS_ERR_HIP;
+        }
+    }
 #define SGKS_TRY(expr)                      \
     do {                                    \
         if ((expr) != hipSuccess) {         \
@@ -992,6 +1031,43 @@ int64_t sgks_copy_state(sgks_ctx* c, int32_t which, double* dst, int64_t count) 
         case 8: return copy(S.cb, S.s);
         default: return SGKS_ERR_INVALID_ARG;
     }
+}
+
+int64_t sgks_copy_state_noalloc(sgks_ctx* c, int32_t which, double* dst, int64_t count) {
+    if (!c || !dst) return SGKS_ERR_INVALID_ARG;
+    if (which != 0) return sgks_copy_state(c, which, dst, count);   // no temporary there
+    State& S = c->S;
+    hipStream_t st = c->st;
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return SGKS_ERR_HIP;
+    if (cur != c->device && hipSetDevice(c->device) != hipSuccess) return SGKS_ERR_HIP;
+    int64_t rc = 0;
+    void* sp = nullptr;
+    int d = 0;
+    const size_t colbytes = (size_t)S.n * sizeof(double);
+    if (colbytes > SGKS_NOALLOC_SCRATCH_BYTES) {
+        rc = SGKS_ERR_CAPACITY;   // one column of W does not fit the staging array
+    } else if (scratch_address(&sp) != SGKS_OK || hipStreamSynchronize(st) != hipSuccess ||
+               hipMemcpy(&d, S.d, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) {
+        rc = SGKS_ERR_HIP;
+    } else if ((int64_t)S.n * d > count) {
+        rc = SGKS_ERR_INVALID_ARG;
+    } else {
+        // W scaled to unit columns, as many columns at a time as the array holds
+        const int per = (int)(SGKS_NOALLOC_SCRATCH_BYTES / colbytes);
+        for (int j0 = 0; j0 < d && rc == 0; j0 += per) {
+            const int nc = std::min(per, d - j0);
+            sgks::launch_scaled_W_cols(S, j0, nc, (double*)sp, st);
+            if (hipGetLastError() != hipSuccess ||
+                hipMemcpyAsync(dst + (int64_t)j0 * S.n, sp, (size_t)nc * colbytes,
+                               hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                rc = SGKS_ERR_HIP;
+        }
+        if (rc == 0) rc = (int64_t)S.n * d;
+    }
+    if (cur != c->device) (void)hipSetDevice(cur);
+    return rc;
 }
 
 int sgks_profile_enable(sgks_ctx* c, int32_t on) {

@@ -192,6 +192,8 @@ void launch_residual_small(const State& S, double* out2, hipStream_t st);
 void launch_backward_small(const State& S, double* v_out, double* gmu_out, hipStream_t st);
 void launch_sketch_transpose(const State& S, const double* v, double* out, hipStream_t st);
 int launch_copy_scaled_W(const State& S, double* dst, hipStream_t st);  // 0 or -1
+// columns [col0, col0 + ncols) of W scaled by cs into dst (n x ncols, column-major)
+void launch_scaled_W_cols(const State& S, int col0, int ncols, double* dst, hipStream_t st);
 // one workgroup reducing nb x s partial bins as a side append does (autotuning)
 void launch_reduce_bins_probe(const double* bins, int nb, int s, double* out, hipStream_t st);
 void launch_make_pattern(int16_t* pat, int64_t rows, int s, int zeta, uint64_t seed, int stream,

@@ -2247,6 +2247,13 @@ void launch_sketch_transpose(const State& S, const double* v, double* out, hipSt
 #undef SGKS_ST
 }
 
+void launch_scaled_W_cols(const State& S, int col0, int ncols, double* dst, hipStream_t st) {
+    if (ncols <= 0) return;
+    const int nb = grid_for(S.n * (int64_t)ncols, kBlock, 8192);
+    hipLaunchKernelGGL(k_scaled_W, dim3(nb), dim3(kBlock), 0, st, S.W + (int64_t)col0 * S.n,
+                       S.cs + col0, S.n, ncols, dst);
+}
+
 int launch_copy_scaled_W(const State& S, double* dst, hipStream_t st) {
     int dh = 0;
     if (hipMemcpyAsync(&dh, S.d, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||

@@ -102,6 +102,9 @@ def load_library(path=LIB_PATH):
     L.sgks_copy_state.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                   ctypes.c_int64]
     L.sgks_copy_state.restype = ctypes.c_int64
+    L.sgks_copy_state_noalloc.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                          ctypes.c_int64]
+    L.sgks_copy_state_noalloc.restype = ctypes.c_int64
     L.sgks_profile_enable.argtypes = [ctypes.c_void_p, ctypes.c_int32]
     L.sgks_profile_enable.restype = ctypes.c_int
     L.sgks_profile_read.argtypes = [ctypes.c_void_p, P(ctypes.c_double), P(ctypes.c_int64)]

@@ -582,7 +582,10 @@ def main():
             "forward_plus_backward_over_forward": res["ms_per_step"] / fwd,
             "forward_iters_per_s": P.k / (fwd * 1e-3),
         }
-        out["adjoint_vs_plain"].update(adjoint_rel_err(G, np, P, res))
+        try:
+            out["adjoint_vs_plain"].update(adjoint_rel_err(G, np, P, res))
+        except Exception as e:      # reported, never fatal to the measurement
+            out["adjoint_vs_plain"]["rel_err_error"] = repr(e)
     if not args.no_extras:
         sec = {}
         for name in ("deblur2d", "ct2d"):

@@ -418,6 +418,13 @@ def sketched_residual(A, L, b, mu, x, s, seed, zeta=8, kind="sparse_sign"):
                            + mu * np.linalg.norm(S_L @ (L @ x)) ** 2))
 
 
+def _stacked_r(res: Result, mu):
+    """G, the R factor (Householder) of [R_A; sqrt(mu) R_L], so that
+    H = R_A^T R_A + mu R_L^T R_L = G^T G."""
+    _, G = np.linalg.qr(np.vstack([res.R_A, math.sqrt(mu) * res.R_L]), mode="reduced")
+    return G
+
+
 def frozen_adjoint(res: Result, mu, g_x):
     """Gradients of loss(x_k) w.r.t. b and mu with W, Q_A, R_A, R_L held fixed.
 
@@ -425,9 +432,10 @@ def frozen_adjoint(res: Result, mu, g_x):
     for g_x = d loss / d x:  z = H^{-1} W^T g_x,
     d loss / d b  = S_A^T Q_A R_A z   (returned as the s-vector v = Q_A R_A z,
                                         and applied to S_A^T by the caller),
-    d loss / d mu = -(R_L z) . (R_L y)."""
-    H = res.R_A.T @ res.R_A + mu * res.R_L.T @ res.R_L
-    z = np.linalg.solve(H, res.W.T @ g_x)
+    d loss / d mu = -(R_L z) . (R_L y).
+    H^{-1} is applied as G^{-1} G^{-T} with G the R factor of the stacked matrix
+    (H = G^T G), which does not square the condition number as forming H would."""
+    z = gram_solve(_stacked_r(res, mu), res.W.T @ g_x)
     v = res.Q_A @ (res.R_A @ z)
     gmu = -float((res.R_L @ z) @ (res.R_L @ res.y))
     return v, gmu
@@ -442,8 +450,7 @@ def frozen_adjoint_b(res: Result, mu, g_x, A, L, s, seed, zeta=8, sketch="sparse
 
 def frozen_map(res: Result, b, mu, S_A):
     """x(b, mu) = W H(mu)^{-1} R_A^T Q_A^T S_A b with the basis and factors held fixed."""
-    H = res.R_A.T @ res.R_A + mu * res.R_L.T @ res.R_L
-    return res.W @ np.linalg.solve(H, res.R_A.T @ (res.Q_A.T @ (S_A @ b)))
+    return res.W @ gram_solve(_stacked_r(res, mu), res.R_A.T @ (res.Q_A.T @ (S_A @ b)))
 
 
 def dense_tikhonov(A, L, b, mu):

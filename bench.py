@@ -406,6 +406,41 @@ def describe(P):
     return P.name
 
 
+def bench_gks(G, torch, np, P, steps=2):
+    """GKS (Alg. 1) against sGKS on the same GPU and workload: whole solves and the
+    expansions alone (Sec. 4.2.1 and Sec. 4.3 compare the two per iteration)."""
+    A, L, b = G.upload_problem(P)
+    out = {}
+    for method in ("gks", "sgks"):
+        opts = dict(ell=P.ell, max_iters=P.k, zeta=P.zeta, method=method,
+                    refine_steps=P.refine_steps if method == "sgks" else 0)
+        S = G.SGKS(A, L, b, P.mu, P.s, P.seed, **opts)   # warm-up
+        S.iterate(2)
+        S.close()
+        setup = it = 0.0
+        for _ in range(steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            S = G.SGKS(A, L, b, P.mu, P.s, P.seed, **opts)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            S.iterate(P.k)
+            x = S.solution()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            setup += t1 - t0
+            it += t2 - t1
+            rc, n = S.status()
+            S.close()
+        out[method] = {"iters_per_s": steps * P.k / (setup + it),
+                       "iterate_only_iters_per_s": steps * P.k / it,
+                       "ms_per_expansion": 1e3 * it / (steps * P.k), "status": [rc, n],
+                       "rre": float(np.linalg.norm(x.cpu().numpy() - P.x_true) /
+                                    np.linalg.norm(P.x_true))}
+    out["sgks_speedup_per_expansion"] = out["gks"]["ms_per_expansion"] / out["sgks"]["ms_per_expansion"]
+    return out
+
+
 def bench_batch(G, torch, np, make, oracle_refs):
     """The 32-problem uneven batch: one batched solve against the 32 plain solves."""
     Ps = make("batch", 0, "full")
@@ -606,6 +641,12 @@ def main():
             sec[name] = ent
             log(f"secondary {name}: {r['value']:.1f} iters/s")
         out["secondary"] = sec
+        gk = {}
+        for name in ("deblur2d", HEADLINE):
+            Q = P if name == args.workload else make(name, 0, "full")
+            gk[name] = bench_gks(G, torch, np, Q)
+            log(f"gks vs sgks {name}: {gk[name]['sgks_speedup_per_expansion']:.2f}x per expansion")
+        out["gks_vs_sgks"] = gk
         out["batched_vs_plain"] = bench_batch(G, torch, np, make, batch_refs)
         log("batched comparison done")
     if pool is not None:

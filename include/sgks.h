@@ -52,7 +52,8 @@ extern "C" {
 #define SGKS_ERR_INVALID_ARG (-1)     /* null pointer, bad option value            */
 #define SGKS_ERR_SHAPE (-2)           /* A.cols != L.cols, bad CSR sizes           */
 #define SGKS_ERR_BAD_MU (-3)          /* mu <= 0 or not finite                     */
-#define SGKS_ERR_SKETCH_SIZE (-4)     /* s < ell + max_iters, zeta > s, s > 1024   */
+#define SGKS_ERR_SKETCH_SIZE (-4)     /* s < ell + max_iters, zeta > s, s > 16384,
+                                         or s doubles beyond one workgroup's LDS     */
 #define SGKS_ERR_CAPACITY (-5)        /* iterate would exceed ell + max_iters      */
 #define SGKS_ERR_ZERO_RHS (-6)        /* b = 0 or A^T b = 0                        */
 #define SGKS_ERR_NONFINITE (-7)       /* NaN/Inf in b or in a computed vector      */
@@ -81,6 +82,19 @@ extern "C" {
  * refinement step, for n * (ell + max_iters) more doubles of device memory. */
 #define SGKS_GRADIENT_MAINTAINED 0
 #define SGKS_GRADIENT_DIRECT 1
+
+/* Methods.  SGKS (default): sketched GKS, Alg. 2 -- the basis W is not
+ * reorthogonalised and the projected problem is the sketched one of
+ * eq:projected_sketched_bis.  GKS: Alg. 1, the baseline sGKS is measured against
+ * -- each new direction is projected on the orthonormal basis V by the projector
+ * of eq:single_mgs, a second time when the loss ratio of eq:loss_criterion is at
+ * least 1e-10, and normalised; the QR factors are those of the unsketched A V
+ * (m x d) and L V (p x d), extended by eq:updqr with d_A = Q_A^T b
+ * (eq:dA_update), and y solves eq:projected_withQR.  With GKS sketch_rows,
+ * seed, zeta and sketch_mode are not used, refine_steps must be 0, and
+ * sgks_backward and batches are not available (SGKS_ERR_INVALID_ARG). */
+#define SGKS_METHOD_SGKS 0
+#define SGKS_METHOD_GKS 1
 
 /* CSR matrix with int32 indices; column indices sorted within each row.  All
  * three arrays are device pointers; val holds nnz values of the options'
@@ -117,6 +131,7 @@ typedef struct {
                                 per wave of the sketch scatter at create and keep the fastest
                                 (cached per operator shape in the process); 0 = choose from
                                 nnz/row and a fixed tile count (default)                        */
+    int32_t method;          /* SGKS_METHOD_SGKS (default) or SGKS_METHOD_GKS (see above)      */
     void *stream;            /* hipStream_t the work is enqueued on (NULL = default stream)   */
     void *workspace;         /* NULL: the context allocates its device memory (one hipMalloc in
                                 sgks_create, freed by sgks_destroy).  Else device memory of
@@ -193,8 +208,9 @@ int sgks_backward(sgks_ctx *ctx, const double *grad_x, double *grad_b, double *g
 
 /* Copy one piece of the solver state to host memory (synchronising), for
  * checks.  which: 0 W (n x d, column-major, columns scaled to unit norm),
- * 1 y (d), 2 Q_A (s x d), 3 R_A (d x d), 4 Q_L (s x d), 5 R_L (d x d),
- * 6 d_A (d), 7 G (d x d, R factor of [R_A; sqrt(mu) R_L]), 8 S_A b (s).
+ * 1 y (d), 2 Q_A (s x d; m x d with GKS), 3 R_A (d x d), 4 Q_L (s x d; p x d
+ * with GKS), 5 R_L (d x d), 6 d_A (d), 7 G (d x d, R factor of
+ * [R_A; sqrt(mu) R_L]), 8 S_A b (s; not with GKS).
  * count = number of doubles dst can take; returns the number written (>= 0)
  * or an error code. */
 int64_t sgks_copy_state(sgks_ctx *ctx, int32_t which, double *dst, int64_t count);

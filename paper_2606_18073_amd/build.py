@@ -8,7 +8,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libsgks.so")
-SOURCES = ["sgks_kernels.hip", "sgks_api.hip"]
+SOURCES = ["sgks_kernels.hip", "sgks_gks.hip", "sgks_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -20,7 +20,7 @@ FLAGS = [
 ]
 
 
-def build(verbose=False, jobs=2):
+def build(verbose=False, jobs=3):
     os.makedirs(OUT_DIR, exist_ok=True)
     objs = []
     procs = []

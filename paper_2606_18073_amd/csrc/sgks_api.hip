@@ -174,8 +174,37 @@ struct SideStream {
     }
 };
 
+// One expansion of GKS (Alg. 1; one problem): the gradient into W column d,
+// its projection on the orthonormal columns before it (the loss-ratio test of
+// the second pass, the column scale), A v and L v, the H W column, the
+// unsketched QR appends and the stacked step.
+int enqueue_gks_iteration(const sgks::Plan& P, Profiler* pr, hipStream_t st) {
+    const bool maintained = P.gradient_form == SGKS_GRADIENT_MAINTAINED;
+    if (maintained) {
+        Phase ph(pr, 0);
+        sgks::plan_gradient(P, false, st);
+    } else {
+        { Phase ph(pr, 0); sgks::plan_gemv(P, st); }
+        { Phase ph(pr, 1); sgks::plan_forward(P, false, st); }
+        { Phase ph(pr, 2); sgks::plan_adjoint(P, 0, st); }
+    }
+    { Phase ph(pr, 5); sgks::gks_project(*P.host, P.SS, st); }
+    { Phase ph(pr, 3); sgks::plan_forward(P, true, st); }
+    if (maintained) {
+        Phase ph(pr, 2);
+        sgks::plan_adjoint(P, 2, st);   // column d of H W
+    }
+    {
+        Phase ph(pr, 4);
+        sgks::gks_append(*P.host, P.SS, st);
+        sgks::plan_stack_only(P, st);
+    }
+    return hipGetLastError() == hipSuccess ? SGKS_OK : SGKS_ERR_HIP;
+}
+
 int enqueue_iteration(const sgks::Plan& P, int refine_steps, Profiler* pr, hipStream_t st,
                       SideStream* ss = nullptr) {
+    if (P.method == SGKS_METHOD_GKS) return enqueue_gks_iteration(P, pr, st);
     const bool maintained = P.gradient_form == SGKS_GRADIENT_MAINTAINED;
     if (maintained) {
         Phase ph(pr, 0);
@@ -497,11 +526,14 @@ int plan_context(sgks_ctx* c, const sgks_csr* A, const sgks_csr* L, double mu, i
     S.m = A->rows;
     S.n = A->cols;
     S.p = L->rows;
+    S.method = c->opt.method;
+    const bool gks = S.method == SGKS_METHOD_GKS;
+    if (gks) s = 1;   // no sketch: the small sketch-sized arrays shrink to one row
     S.s = s;
     S.dmax = c->opt.ell + c->opt.max_iters;
     S.zeta = c->opt.zeta;
     S.passes = c->opt.qr_passes;
-    S.sketch_mode = c->opt.sketch_mode;
+    S.sketch_mode = gks ? 2 : c->opt.sketch_mode;   // 2: no sketch
     S.vdt = c->opt.value_dtype;
     S.gradient_form = c->opt.gradient_form;
     S.seed = seed;
@@ -536,6 +568,10 @@ int plan_context(sgks_ctx* c, const sgks_csr* A, const sgks_csr* L, double mu, i
         if (rpb > 4096) rpb = 4096;   // staged in LDS (32 KiB)
         S.gt_rows = (int)rpb;
         S.ngt = (int)((S.n + rpb - 1) / rpb);
+    }
+    if (gks) {
+        S.ntA = sgks::gks_tall_blocks(S.m, &S.trA);
+        S.ntL = sgks::gks_tall_blocks(S.p, &S.trL);
     }
     // cooperative append workgroups
     {
@@ -616,6 +652,17 @@ void layout_context(sgks_ctx* c, Arena& ar) {
     ar.add(&c->sbuf, s * 8);
     ar.add(&c->init_norms, (16 + 2 * dmax) * 8);
     ar.add(&c->Sdev, sizeof(State));
+    if (S.method == SGKS_METHOD_GKS) {
+        ar.add(&S.QAt, (size_t)S.m * dmax * 8);
+        ar.add(&S.QLt, (size_t)S.p * dmax * 8);
+        ar.add(&S.wat, S.m * 8);
+        ar.add(&S.wlt, S.p * 8);
+        ar.add(&S.tpA, (size_t)S.ntA * dmax * 8);
+        ar.add(&S.tpL, (size_t)S.ntL * dmax * 8);
+        ar.add(&S.tsq, 5 * 4096 * 8);
+        ar.add(&S.gco, 6 * dmax * 8);
+        ar.add(&S.vsq, 2 * 2048 * 8);
+    }
     const size_t wbytes = (size_t)S.n * dmax * 8 * (S.gradient_form == SGKS_GRADIENT_MAINTAINED ? 2 : 1);
     const size_t sort = std::max(sgks::transpose_scratch_bytes(S.A), sgks::transpose_scratch_bytes(S.L));
     c->sort_bytes = sort > wbytes ? sort : 0;
@@ -649,6 +696,7 @@ void sgks_default_options(sgks_options* o) {
     o->graph = 0;
     o->autotune = 0;
     o->gradient_form = SGKS_GRADIENT_MAINTAINED;
+    o->method = SGKS_METHOD_SGKS;
     o->workspace = nullptr;
     o->workspace_bytes = 0;
     o->stream = nullptr;
@@ -683,7 +731,9 @@ int sgks_validate(const sgks_csr* A, const sgks_csr* L, const void* b, double mu
         return SGKS_ERR_INVALID_ARG;
     if (o.gradient_form != SGKS_GRADIENT_MAINTAINED && o.gradient_form != SGKS_GRADIENT_DIRECT)
         return SGKS_ERR_INVALID_ARG;
-    if (s > sgks::kMaxS || s < 1) return SGKS_ERR_SKETCH_SIZE;
+    if (o.method != SGKS_METHOD_SGKS && o.method != SGKS_METHOD_GKS) return SGKS_ERR_INVALID_ARG;
+    if (o.method == SGKS_METHOD_GKS) return o.refine_steps == 0 ? 0 : SGKS_ERR_INVALID_ARG;
+    if (s > sgks::kMaxSketch || s < 1) return SGKS_ERR_SKETCH_SIZE;
     if (o.sketch_mode == SGKS_SKETCH_SPARSE_SIGN) {
         if (s < o.ell + o.max_iters) return SGKS_ERR_SKETCH_SIZE;
         if (o.zeta > s) return SGKS_ERR_SKETCH_SIZE;
@@ -737,6 +787,17 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
         if (hipGetDevice(&c->device) != hipSuccess || scratch_address(&sp) != SGKS_OK) {
             sgks_destroy(c);
             return SGKS_ERR_HIP;
+        }
+        // the sketch scatter holds at least one copy of the s bins in one workgroup's LDS
+        int lds = 0;
+        if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) !=
+            hipSuccess) {
+            sgks_destroy(c);
+            return SGKS_ERR_HIP;
+        }
+        if (c->S.method == SGKS_METHOD_SGKS && sgks::scatter_lds_bytes(c->S.s) > (size_t)lds) {
+            sgks_destroy(c);
+            return SGKS_ERR_SKETCH_SIZE;
         }
     }
 #define SGKS_TRY(expr)                      \
@@ -795,7 +856,7 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
         S.L.lanes = tune_one(S, 1, st);
         if (!c->opt.lanes_At) S.At.lanes = tune_one(S, 2, st);
         S.Lt.lanes = S.At.lanes;
-        if (sparse) {
+        if (sparse && S.s <= sgks::kMaxS) {   // the probe reduces bins as the compact append does
             const int tpw = tune_scatter(S, st);
             S.nbA = sgks::scatter_blocks(S.m, tpw);
             S.nbL = sgks::scatter_blocks(S.p, tpw);
@@ -836,9 +897,15 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
     sgks::launch_to_f64(b, S.vdt, (double*)S.b, S.m, S.norm_part, S.n_norm_part, st);
     sgks::launch_sum_parts(S.norm_part, S.n_norm_part, S.scal + 2, st);
 
-    // c_b = S_A b
-    sgks::launch_scatter(S, S.b, nullptr, st);
-    sgks::launch_cb(S, st);
+    const bool gks = S.method == SGKS_METHOD_GKS;
+    if (gks) {
+        // no sketch: scal[1] (the ||S_A b||^2 of the small-factor residual) is ||b||^2
+        sgks::launch_sum_parts(S.norm_part, S.n_norm_part, S.scal + 1, st);
+    } else {
+        // c_b = S_A b
+        sgks::launch_scatter(S, S.b, nullptr, st);
+        sgks::launch_cb(S, st);
+    }
 
     // initial basis: orthonormal basis of K_ell(A^T A, A^T b), CGS2 (stored
     // unnormalised with cs[j] = 1 / ||column||)
@@ -863,13 +930,20 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
     SGKS_TRY(hipMemcpyAsync(c->init_norms, S.scal, (16 + 2 * dmax) * 8, hipMemcpyDeviceToDevice,
                             st));
 
-    // sketch and QR-append the initial columns, then y_0
+    // sketch (sGKS) and QR-append the initial columns, then y_0
     for (int j = 0; j < c->opt.ell; ++j) {
-        sgks::launch_sketch_column(S, j, st);
+        if (gks)
+            sgks::launch_forward(S, S.W + (size_t)j * S.n, nullptr, S.u, S.t, true, nullptr,
+                                 nullptr, st);
+        else
+            sgks::launch_sketch_column(S, j, st);
         if (S.HW)   // H W[:, j] = A^T (A w) + mu L^T (L w) from the images just formed
             sgks::launch_adjoint(S, S.u, S.t, true, S.mu, S.HW + (size_t)j * S.n, S.norm_part,
                                  st);
-        if (sgks::plan_append(c->plan, false, false, st)) {
+        if (gks) {
+            sgks::gks_append(S, c->Sdev, st);
+            sgks::plan_stack_only(c->plan, st);
+        } else if (sgks::plan_append(c->plan, false, false, st)) {
             sgks_destroy(c);
             return SGKS_ERR_HIP;
         }
@@ -960,7 +1034,7 @@ int sgks_backward(sgks_ctx* c, const double* grad_x, double* grad_b, double* gra
     if (!c || !grad_x || !grad_b) return SGKS_ERR_INVALID_ARG;
     // the adjoint is that of the unrefined projected solve (y = G^{-1} h); a
     // refined y is another function of b and mu
-    if (c->opt.refine_steps > 0) return SGKS_ERR_INVALID_ARG;
+    if (c->opt.refine_steps > 0 || c->S.method == SGKS_METHOD_GKS) return SGKS_ERR_INVALID_ARG;
     State& S = c->S;
     hipStream_t st = c->st;
     sgks::launch_gemvt(S, grad_x, -1, st);
@@ -1012,9 +1086,13 @@ int64_t sgks_copy_state(sgks_ctx* c, int32_t which, double* dst, int64_t count) 
             return r;
         }
         case 1: return copy(S.y, d);
-        case 2: return copy2d(S.QA, S.s, d, S.s);
+        case 2:
+            return S.method == SGKS_METHOD_GKS ? copy2d(S.QAt, S.m, d, S.m)
+                                               : copy2d(S.QA, S.s, d, S.s);
         case 3: return copy2d(S.RA, d, d, dmax);
-        case 4: return copy2d(S.QL, S.s, d, S.s);
+        case 4:
+            return S.method == SGKS_METHOD_GKS ? copy2d(S.QLt, S.p, d, S.p)
+                                               : copy2d(S.QL, S.s, d, S.s);
         case 5: return copy2d(S.RL, d, d, dmax);
         case 6: return copy(S.dA, d);
         case 7: {   // G is stored row-major: copy then transpose on the host
@@ -1028,7 +1106,7 @@ int64_t sgks_copy_state(sgks_ctx* c, int32_t which, double* dst, int64_t count) 
                 }
             return r;
         }
-        case 8: return copy(S.cb, S.s);
+        case 8: return S.method == SGKS_METHOD_GKS ? SGKS_ERR_INVALID_ARG : copy(S.cb, S.s);
         default: return SGKS_ERR_INVALID_ARG;
     }
 }
@@ -1170,7 +1248,8 @@ int sgks_batch_create(int32_t count, const sgks_problem* probs, const sgks_optio
         o = *opt;
     else
         sgks_default_options(&o);
-    if (o.lanes_A || o.lanes_At || o.append_groups) return SGKS_ERR_INVALID_ARG;
+    if (o.lanes_A || o.lanes_At || o.append_groups || o.method != SGKS_METHOD_SGKS)
+        return SGKS_ERR_INVALID_ARG;
     for (int i = 0; i < count; ++i) {
         const int rc = sgks_validate(&probs[i].A, &probs[i].L, probs[i].b, probs[i].mu,
                                      probs[i].sketch_rows, &o);

@@ -32,10 +32,15 @@ extern thread_local LaunchTimer* tl_launch_timer;
 
 constexpr int kBlock = 256;         // threads per block of the bulk kernels
 constexpr int kWaves = kBlock / 64; // waves per block
-constexpr int kMaxS = 1024;         // largest sketch size (8 wave-private LDS bin copies: 64 KiB)
+constexpr int kMaxS = 1024;         // largest sketch size of the one-workgroup append (LDS vectors)
+constexpr int kMaxSketch = 16384;   // largest sketch size (the multi-workgroup append)
+// LDS of the sketch scatter: wave-private copies of the s bins while they fit in
+// 64 KiB (8 copies up to s = 1024), fewer, shared by several waves, beyond; one
+// copy of s doubles needs s * 8 bytes of one workgroup's LDS
+constexpr int kScatterLdsBytes = 64 * 1024;
 constexpr int kMaxD = 512;          // largest basis dimension
 constexpr int kAppendThreads = 256; // threads per workgroup of the append chain kernels
-constexpr int kMaxAppendGroups = 32;  // workgroups of the append kernels
+constexpr int kMaxAppendGroups = 256; // workgroups of the append kernels
 constexpr int kAppendMaxSlab = 64;    // sketch rows per append workgroup
 constexpr int kSketchBlock = 512;   // threads per block of the sketch kernel
 constexpr int kSketchWaves = kSketchBlock / 64;
@@ -132,6 +137,21 @@ struct State {
     int* status;       // device status word
     int* degenerate;   // count of numerically absent QR columns
     unsigned* sync;    // side appends finished this expansion (0 between launches)
+
+    // GKS (Alg. 1) only: the basis W is orthonormal (columns scaled by cs), the
+    // QR factors are of the unsketched A W and L W
+    int method;        // 0 sGKS, 1 GKS
+    double* QAt;       // m x dmax, Q of A W
+    double* QLt;       // p x dmax, Q of L W
+    double* wat;       // m: working column of the A-side append
+    double* wlt;       // p: working column of the L-side append
+    double* tpA;       // ntA x dmax partial column dots over the A-side row slabs
+    double* tpL;       // ntL x dmax partial column dots over the L-side row slabs
+    double* tsq;       // 8 x (ntA + ntL) partial sums of the appends (norms, w . b)
+    double* gco;       // 6 dmax: projection coefficients (V pass 0, 1; A, L pass 0, 1 ...)
+    double* vsq;       // 2 x 2048 partial sums of ||v||^2 after each V projection pass
+    int ntA, ntL;      // row slabs of the A-side and L-side appends
+    int trA, trL;      // rows per slab
 };
 
 // Block table of one batched launch: problem q owns the workgroups
@@ -146,7 +166,9 @@ struct BTab {
 // dtype, zeta, projection passes) are common to the set.
 struct Plan {
     const State* SS;
+    const State* host;   // host copy of problem 0's State (the GKS launchers read its shapes)
     int np;
+    int method;         // 0 sGKS, 1 GKS (one problem)
     int vdt, zeta, passes, sketch_mode, gradient_form;
     int max_s;          // largest sketch size (LDS bins of the scatter)
     int max_gt_rows;    // largest row slab of the W^T v kernel
@@ -199,6 +221,7 @@ void launch_reduce_bins_probe(const double* bins, int nb, int s, double* out, hi
 void launch_make_pattern(int16_t* pat, int64_t rows, int s, int zeta, uint64_t seed, int stream,
                          hipStream_t st);
 int scatter_blocks(int64_t rows, int tiles_per_wave);
+size_t scatter_lds_bytes(int s);
 size_t transpose_scratch_bytes(const Csr& M);
 // scratch (device, scratch_bytes) serves the sort when large enough; else the
 // scratch is allocated and freed around the sort
@@ -224,6 +247,19 @@ int plan_append(const Plan& P, bool scale_from_norm, bool with_hw, hipStream_t s
 bool plan_has_hw_separate(const Plan& P);
 void plan_hw_separate(const Plan& P, hipStream_t st);
 void plan_gemvt(const Plan& P, hipStream_t st);                // W^T rtmp partials
+// the stacked step alone, after the unsketched QR appends of GKS
+void plan_stack_only(const Plan& P, hipStream_t st);
+
+// ----- GKS (Alg. 1, sgks_gks.hip), one problem -----------------------------
+// projection of the new basis column (the gradient, in W column d) on the
+// orthonormal columns before it: pass 0, then pass 1 when the loss ratio
+// ||V^T v|| / ||v|| is at least kGksTau; then the column scale and breakdown test
+constexpr double kGksTau = 1e-10;
+void gks_project(const State& S, const State* Sdev, hipStream_t st);
+// rank-one appends of A v and L v (in u, t, unnormalised) to the QR factors of
+// A V and L V, d_A gains q^T b; then the stacked step (plan_stack_only)
+void gks_append(const State& S, const State* Sdev, hipStream_t st);
+int gks_tall_blocks(int64_t rows, int* rows_per_block);
 void plan_refine(const Plan& P, hipStream_t st);
 
 }  // namespace sgks

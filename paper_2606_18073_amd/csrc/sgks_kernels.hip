@@ -16,19 +16,13 @@
 // workgroup ranges, so a batch of problems shares each launch.
 #include <hipcub/hipcub.hpp>
 
-#include "sgks_internal.h"
+#include "sgks_device.h"
 
 namespace sgks {
 
 // ---------------------------------------------------------------------------
 // reductions
 // ---------------------------------------------------------------------------
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
-}
 
 // Totals of N = 2^m values per lane over the 64 lanes of a wave, transposed:
 // each of the first m butterfly steps sends half of the lane's values to its
@@ -68,39 +62,6 @@ __device__ __forceinline__ double group_sum(double v) {
     return v;
 }
 
-// Sum over a block of blockDim.x (multiple of 64) threads; every thread gets
-// the same total (the per-wave sums are added in wave order).
-__device__ double block_sum(double v, double* red) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    v = wave_sum(v);
-    if (lane == 0) red[wave] = v;
-    __syncthreads();
-    double t = 0.0;
-    for (int w = 0; w < nw; ++w) t += red[w];
-    __syncthreads();
-    return t;
-}
-
-// Sum of p[0], p[stride], ..., p[(n-1) stride] in that order, sixteen
-// independent loads in flight at a time (the small kernels are latency
-// bound: a load-then-add loop would pay one memory latency per term).
-__device__ __forceinline__ double strided_sum(const double* __restrict__ p, int64_t stride,
-                                              int n) {
-    // loads are unconditional from clamped (valid) addresses so that all
-    // sixteen are issued before the first wait; the mask applies to values
-    double acc = 0.0;
-    for (int k = 0; k < n; k += 16) {
-        double v[16];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) v[u] = p[(int64_t)min(k + u, n - 1) * stride];
-#pragma unroll
-        for (int u = 0; u < 16; ++u)
-            if (k + u < n) acc += v[u];
-    }
-    return acc;
-}
-
-// sum_k p[k stride] v[k], k < n, in order, sixteen loads in flight
 template <int B = 16>
 __device__ __forceinline__ double strided_dot(const double* __restrict__ p, int64_t stride,
                                               const double* v, int n) {
@@ -302,14 +263,6 @@ __device__ void tri_apply2(const double* __restrict__ Ma, const double* __restri
     tri_apply2_t(GTri{Ma, rs, cs}, GTri{Mb, rs, cs}, d, v, outa, outb, blockDim.x);
 }
 
-// Thread-strided sum of p[i], i = threadIdx.x, threadIdx.x + T, ... < n,
-// eight loads in flight (per-thread order fixed).
-__device__ __forceinline__ double thread_strided_sum(const double* __restrict__ p, int n, int T) {
-    const int tid = threadIdx.x;
-    const int cnt = tid < n ? (n - tid + T - 1) / T : 0;
-    return strided_sum(p + tid, T, cnt);
-}
-
 // Dot product of one CSR row with x by the V lanes of a group (lane g of V).
 // acc += sum_u va[k + u V] x[ci[k + u V]], u < U, in u order: all U index and
 // value loads are issued before the gathers
@@ -431,30 +384,8 @@ __global__ __launch_bounds__(kBlock) void k_sum_parts(const double* part, int nb
 }
 
 // ---------------------------------------------------------------------------
-// batched launches: workgroup -> (problem, local workgroup)
+// XCD-aware workgroup order
 // ---------------------------------------------------------------------------
-
-struct Slot {
-    int p;      // problem
-    int blk;    // workgroup within the problem
-    int nblk;   // workgroups of the problem
-};
-
-// One problem: the grid is the problem's.  Several: binary search of the
-// prefix table in the kernel-argument segment (a few scalar loads).
-__device__ __forceinline__ Slot find_slot(const BTab& t) {
-    const int b = blockIdx.x;
-    if (t.np == 1) return Slot{0, b, t.pref[1]};
-    int lo = 0, hi = t.np;   // pref[lo] <= b < pref[hi]
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (b >= t.pref[mid])
-            lo = mid;
-        else
-            hi = mid;
-    }
-    return Slot{lo, b - t.pref[lo], t.pref[lo + 1] - t.pref[lo]};
-}
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
 // L2).  Logical index of workgroup j of n: the workgroups of one XCD get
@@ -469,19 +400,6 @@ __device__ __forceinline__ int xcd_order(int j, int n) {
 __device__ __forceinline__ int rows_blocks_of(const Csr& M) {
     const uint32_t per = (uint32_t)(kBlock / M.lanes);   // rows < 2^31: 32-bit arithmetic
     return (int)(((uint32_t)M.rows + per - 1u) / per);
-}
-
-// The States are read-only while any kernel runs, so they are read through the
-// constant address space: the fields become scalar loads and every pointer
-// loaded from them is known to address global memory (global, not flat,
-// memory instructions in the loops that use it).
-__device__ __forceinline__ State load_state(const State* SS, int p) {
-#if defined(__HIP_DEVICE_COMPILE__)
-    typedef __attribute__((address_space(4))) const State ConstState;
-    return ((ConstState*)SS)[p];
-#else
-    return SS[p];   // the host pass never runs device functions
-#endif
 }
 
 // ---------------------------------------------------------------------------
@@ -718,11 +636,13 @@ __device__ __forceinline__ void scatter_body(const double* __restrict__ zA, int6
                                              int nbL, int s, uint64_t seed, int identity,
                                              const int16_t* patA, const int16_t* patL,
                                              double* partA, double* partL, int blk_all,
-                                             double* sm) {
+                                             double* sm, int lds_doubles) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int i = threadIdx.x; i < kSketchWaves * s; i += kSketchBlock) sm[i] = 0.0;
+    // copies of the bins in LDS: one per wave while they fit, else shared by waves
+    const int copies = max(1, min(kSketchWaves, lds_doubles / s));
+    for (int i = threadIdx.x; i < copies * s; i += kSketchBlock) sm[i] = 0.0;
     __syncthreads();
-    double* bins = sm + wave * s;
+    double* bins = sm + (wave % copies) * s;
     const bool isA = blk_all < nbA;
     const double* __restrict__ z = isA ? zA : zL;
     const int16_t* pat = isA ? patA : patL;
@@ -774,7 +694,7 @@ __device__ __forceinline__ void scatter_body(const double* __restrict__ zA, int6
     double* out = (isA ? partA : partL) + (int64_t)blk * s;
     for (int j = threadIdx.x; j < s; j += kSketchBlock) {
         double a = 0.0;
-        for (int w = 0; w < kSketchWaves; ++w) a += sm[w * s + j];
+        for (int w = 0; w < copies; ++w) a += sm[w * s + j];
         out[j] = a;
     }
 }
@@ -787,23 +707,23 @@ __global__ __launch_bounds__(kSketchBlock) void k_scatter(const double* __restri
                                                          uint64_t seed, int identity,
                                                          const int16_t* patA,
                                                          const int16_t* patL, double* partA,
-                                                         double* partL) {
+                                                         double* partL, int lds_doubles) {
     extern __shared__ double sm[];
     scatter_body<Z>(zA, m, zL, p, nbA, nbL, s, seed, identity, patA, patL, partA, partL,
-                    (int)blockIdx.x, sm);
+                    (int)blockIdx.x, sm, lds_doubles);
 }
 
 // Iteration form: the sketch of the new column's images (u, t); skipped on a
 // set status.
 template <int Z>
 __global__ __launch_bounds__(kSketchBlock) void kb_scatter(const State* __restrict__ SS,
-                                                          BTab tab) {
+                                                          BTab tab, int lds_doubles) {
     extern __shared__ double sm[];
     const Slot sl = find_slot(tab);
     const State S = load_state(SS, sl.p);
     if (*S.status != 0) return;
     scatter_body<Z>(S.u, S.m, S.t, S.p, S.nbA, S.nbL, S.s, S.seed, S.sketch_mode, S.patA, S.patL,
-                    S.binA, S.binL, sl.blk, sm);
+                    S.binA, S.binL, sl.blk, sm, lds_doubles);
 }
 
 // ---------------------------------------------------------------------------
@@ -989,13 +909,15 @@ __device__ __forceinline__ double* ap_region(const State& S, const ApDims& D, in
 
 // sum over workgroups of one slot: G consecutive values, one batch of loads
 __device__ __forceinline__ double sum_g(const double* __restrict__ slot, int G) {
-    double v[kMaxAppendGroups];
-#pragma unroll
-    for (int u = 0; u < kMaxAppendGroups; ++u) v[u] = slot[min(u, G - 1)];
     double a = 0.0;
+    for (int g0 = 0; g0 < G; g0 += 32) {
+        double v[32];
 #pragma unroll
-    for (int u = 0; u < kMaxAppendGroups; ++u)
-        if (u < G) a += v[u];
+        for (int u = 0; u < 32; ++u) v[u] = slot[min(g0 + u, G - 1)];
+#pragma unroll
+        for (int u = 0; u < 32; ++u)
+            if (g0 + u < G) a += v[u];
+    }
     return a;
 }
 
@@ -1836,6 +1758,17 @@ __device__ void side_then_stack(const State& S, int side, int scale_from_norm, A
     if (sh.last) ap1_stack_body(S, sh.u.stack);
 }
 
+// The stacked step alone (one workgroup per problem): the appends of the QR
+// factors ran before (the unsketched appends of GKS), their R columns in
+// pacc[2 dmax ...), pacc[3 dmax ...), rho_A, rho_L in scal[12], scal[13] and d_A[d].
+__global__ __launch_bounds__(kAp1Threads) void k_stack_only(const State* __restrict__ SS,
+                                                           BTab tab) {
+    __shared__ Ap1Stack sh;
+    const State S = load_state(SS, find_slot(tab).p);
+    if (*S.status != 0) return;
+    ap1_stack_body(S, sh);
+}
+
 __global__ __launch_bounds__(kAp1Threads) void k_ap1_side(const State* __restrict__ SS, BTab tab,
                                                          int scale_from_norm) {
     __shared__ AppendLds sh;
@@ -1966,10 +1899,14 @@ template <int Z>
 __global__ __launch_bounds__(kBlock) void k_sketch_transpose(const double* __restrict__ v, int s,
                                                             int64_t m, uint64_t seed,
                                                             int identity, double scale,
-                                                            double* __restrict__ out) {
-    extern __shared__ double vs[];
-    for (int i = threadIdx.x; i < s; i += kBlock) vs[i] = v[i];
+                                                            double* __restrict__ out,
+                                                            int staged) {
+    // v staged in LDS when it fits (staged), else read through the caches
+    extern __shared__ double lds[];
+    if (staged)
+        for (int i = threadIdx.x; i < s; i += kBlock) lds[i] = v[i];
     __syncthreads();
+    const double* vs = staged ? lds : v;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m;
          i += (int64_t)gridDim.x * kBlock) {
         double a;
@@ -2047,13 +1984,6 @@ __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
 // launchers
 // ===========================================================================
 
-static int grid_for(int64_t work, int per_block, int cap) {
-    int64_t g = (work + per_block - 1) / per_block;
-    if (g < 1) g = 1;
-    if (g > cap) g = cap;
-    return (int)g;
-}
-
 void launch_to_f64(const void* src, int vdt, double* dst, int64_t n, double* part, int nb,
                    hipStream_t st) {
     if (vdt == 0)
@@ -2109,13 +2039,23 @@ void launch_adjoint(const State& S, const double* u, const double* t, bool with_
                            with_L ? 1 : 0, mu, u, t, dst, S.n, part);
 }
 
+// LDS bytes of the scatter for sketch size s: as many copies of the bins as fit
+// in kScatterLdsBytes (at most one per wave), at least one
+size_t scatter_lds_bytes(int s) {
+    int copies = kScatterLdsBytes / (8 * s);
+    if (copies > kSketchWaves) copies = kSketchWaves;
+    if (copies < 1) copies = 1;
+    return (size_t)copies * s * sizeof(double);
+}
+
 void launch_scatter(const State& S, const double* zA, const double* zL, hipStream_t st) {
-    const size_t shm = (size_t)kSketchWaves * S.s * sizeof(double);
+    const size_t shm = scatter_lds_bytes(S.s);
     const int nbL = zL ? S.nbL : 0;
     const int nb = S.nbA + nbL;
 #define SGKS_SC(Zv)                                                                             \
     hipLaunchKernelGGL((k_scatter<Zv>), dim3(nb), dim3(kSketchBlock), shm, st, zA, S.m, zL, S.p, \
-                       S.nbA, nbL, S.s, S.seed, S.sketch_mode, S.patA, S.patL, S.binA, S.binL)
+                       S.nbA, nbL, S.s, S.seed, S.sketch_mode, S.patA, S.patL, S.binA, S.binL, \
+                       (int)(shm / sizeof(double)))
     switch (S.zeta) {
         case 2: SGKS_SC(2); break;
         case 4: SGKS_SC(4); break;
@@ -2203,7 +2143,7 @@ bool append_groups_ok(int s, int dmax, int G) {
 }
 
 int choose_append_groups(int s, int dmax, int cap) {
-    if ((int64_t)s * dmax <= kCompactAppendMax) return 1;
+    if ((int64_t)s * dmax <= kCompactAppendMax && s <= kMaxS) return 1;
     int G = (s + 31) / 32;
     if (G < 4) G = 4;
     while ((s + G - 1) / G > kAppendMaxSlab || (dmax + G - 1) / G > kAppendMaxSlab) ++G;
@@ -2232,12 +2172,13 @@ void launch_backward_small(const State& S, double* v_out, double* gmu_out, hipSt
 
 void launch_sketch_transpose(const State& S, const double* v, double* out, hipStream_t st) {
     const int nb = grid_for(S.m, kBlock, 4096);
-    const size_t shm = (size_t)S.s * sizeof(double);
+    const int staged = (size_t)S.s * sizeof(double) <= (size_t)kScatterLdsBytes ? 1 : 0;
+    const size_t shm = staged ? (size_t)S.s * sizeof(double) : 0;
     const double scale = 1.0 / sqrt((double)S.zeta);
     const int ident = S.sketch_mode == 1 ? 1 : 0;
 #define SGKS_ST(Zv)                                                                        \
     hipLaunchKernelGGL((k_sketch_transpose<Zv>), dim3(nb), dim3(kBlock), shm, st, v, S.s, \
-                       S.m, S.seed, ident, scale, out)
+                       S.m, S.seed, ident, scale, out, staged)
     switch (S.zeta) {
         case 2: SGKS_ST(2); break;
         case 4: SGKS_ST(4); break;
@@ -2281,7 +2222,9 @@ static int tab_total(const BTab& t) { return t.pref[t.np]; }
 int plan_build(Plan& P, const State* host, const State* dev, int np, const int* groups) {
     if (np < 1 || np > kMaxBatch) return -1;
     P.SS = dev;
+    P.host = host;
     P.np = np;
+    P.method = host[0].method;
     P.vdt = host[0].vdt;
     P.zeta = host[0].zeta;
     P.passes = host[0].passes;
@@ -2298,7 +2241,8 @@ int plan_build(Plan& P, const State* host, const State* dev, int np, const int* 
     for (int q = 0; q < np; ++q) {
         const State& S = host[q];
         if (S.vdt != P.vdt || S.zeta != P.zeta || S.passes != P.passes ||
-            S.sketch_mode != P.sketch_mode || S.gradient_form != P.gradient_form)
+            S.sketch_mode != P.sketch_mode || S.gradient_form != P.gradient_form ||
+            S.method != P.method || (S.method != 0 && np != 1))
             return -1;
         if (!append_groups_ok(S.s, S.dmax, groups[q])) return -1;
         fwd[q] = forward_blocks(S, true, nullptr);
@@ -2361,10 +2305,11 @@ void plan_gradient(const Plan& P, bool to_rtmp, hipStream_t st) {
 }
 
 void plan_scatter(const Plan& P, hipStream_t st) {
-    const size_t shm = (size_t)kSketchWaves * P.max_s * sizeof(double);
+    const size_t shm = scatter_lds_bytes(P.max_s);
     const dim3 grid(tab_total(P.sc));
 #define SGKS_SC(Zv) \
-    SGKS_LAUNCH((kb_scatter<Zv>), grid, dim3(kSketchBlock), shm, st, P.SS, P.sc)
+    SGKS_LAUNCH((kb_scatter<Zv>), grid, dim3(kSketchBlock), shm, st, P.SS, P.sc, \
+                (int)(shm / sizeof(double)))
     switch (P.zeta) {
         case 2: SGKS_SC(2); break;
         case 4: SGKS_SC(4); break;
@@ -2415,6 +2360,10 @@ int plan_append(const Plan& P, bool scale_from_norm, bool with_hw, hipStream_t s
                            P.ap_fix);
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+void plan_stack_only(const Plan& P, hipStream_t st) {
+    SGKS_LAUNCH(k_stack_only, dim3(P.np), dim3(kAp1Threads), 0, st, P.SS, P.one);
 }
 
 void plan_gemvt(const Plan& P, hipStream_t st) {

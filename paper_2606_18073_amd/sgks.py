@@ -25,6 +25,7 @@ ERRORS = {
 }
 F32, F64 = 0, 1
 GRADIENT_MAINTAINED, GRADIENT_DIRECT = 0, 1
+METHOD_SGKS, METHOD_GKS = 0, 1
 SKETCH_SPARSE_SIGN, SKETCH_IDENTITY = 0, 1
 PHASES = 8
 # phase 0: x = W y (direct gradient form) or r = (H W) y - A^T b (maintained);
@@ -52,7 +53,7 @@ class Options(ctypes.Structure):
                 ("sketch_mode", ctypes.c_int32), ("lanes_A", ctypes.c_int32),
                 ("lanes_At", ctypes.c_int32), ("append_groups", ctypes.c_int32),
                 ("graph", ctypes.c_int32), ("gradient_form", ctypes.c_int32),
-                ("autotune", ctypes.c_int32),
+                ("autotune", ctypes.c_int32), ("method", ctypes.c_int32),
                 ("stream", ctypes.c_void_p),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
 
@@ -186,7 +187,7 @@ def _check(code, where):
 
 def make_options(lib, vdt, stream, *, ell=3, max_iters=200, zeta=8, refine_steps=0, qr_passes=2,
                  sketch="sparse_sign", lanes_A=0, lanes_At=0, append_groups=0, graph=False,
-                 autotune=False, gradient="maintained"):
+                 autotune=False, gradient="maintained", method="sgks"):
     o = Options()
     lib.sgks_default_options(ctypes.byref(o))
     o.ell, o.max_iters, o.zeta, o.value_dtype = ell, max_iters, zeta, vdt
@@ -195,6 +196,9 @@ def make_options(lib, vdt, stream, *, ell=3, max_iters=200, zeta=8, refine_steps
     o.lanes_A, o.lanes_At, o.append_groups = lanes_A, lanes_At, append_groups
     o.graph, o.autotune = int(bool(graph)), int(bool(autotune))
     o.gradient_form = GRADIENT_DIRECT if gradient == "direct" else GRADIENT_MAINTAINED
+    if method not in ("sgks", "gks"):
+        raise ValueError(method)
+    o.method = METHOD_GKS if method == "gks" else METHOD_SGKS
     o.stream = ctypes.c_void_p(stream.cuda_stream)
     return o
 
@@ -309,8 +313,11 @@ class SGKS:
         """Copy one state array to host (numpy, column-major shapes as in sgks.h)."""
         rc, it = self.status()
         d = self.ell + it
-        shapes = {"W": (self.n, d), "y": (d,), "Q_A": (self.s, d), "R_A": (d, d),
-                  "Q_L": (self.s, d), "R_L": (d, d), "d_A": (d,), "G": (d, d), "c_b": (self.s,)}
+        gks = self.options.method == METHOD_GKS
+        qa = (self.m if gks else self.s, d)
+        ql = (self.L.shape[0] if gks else self.s, d)
+        shapes = {"W": (self.n, d), "y": (d,), "Q_A": qa, "R_A": (d, d),
+                  "Q_L": ql, "R_L": (d, d), "d_A": (d,), "G": (d, d), "c_b": (self.s,)}
         shp = shapes[which]
         buf = np.zeros(int(np.prod(shp)), dtype=np.float64)
         got = self._lib.sgks_copy_state(self._h, STATE[which],

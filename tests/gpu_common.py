@@ -130,14 +130,27 @@ def _build(spec):
     return make(kind, spec[2], spec[1])
 
 
-def _oracle_history(spec, k, checkpoints):
-    """x after each checkpoint expansion count and kappa(G_k) there."""
+def _oracle_history(spec, k, checkpoints, permute=None):
+    """x after each checkpoint expansion count and kappa(G_k) there.  With permute (a
+    seed), the oracle runs on the problem with its unknowns permuted (the columns of A
+    and L): the same iteration in exact arithmetic, another rounding order of its sparse
+    products; x is mapped back to the original order."""
+    import scipy.sparse as sp
     from threadpoolctl import threadpool_limits
     P = _build(spec)
+    A, L, Pm = P.A, P.L, None
+    if permute is not None:
+        perm = np.random.default_rng(permute).permutation(P.n)
+        Pm = sp.identity(P.n, format="csr")[:, perm]          # x = Pm x'
+        A = (P.A @ Pm).tocsr()
+        L = (P.L @ Pm).tocsr()
+        A.sort_indices()
+        L.sort_indices()
     with threadpool_limits(1):
-        ref = O.sgks(P.A, P.L, P.b, P.mu, k, P.s, P.seed, zeta=P.zeta, ell=P.ell,
+        ref = O.sgks(A, L, P.b, P.mu, k, P.s, P.seed, zeta=P.zeta, ell=P.ell,
                      refine_steps=P.refine_steps, keep_history=True)
-    hist = {kk: ref.x_hist[kk] for kk in checkpoints if kk <= ref.iters}
+    back = (lambda v: Pm @ v) if Pm is not None else (lambda v: v)
+    hist = {kk: back(ref.x_hist[kk]) for kk in checkpoints if kk <= ref.iters}
     kap = {kk: cond_at(ref, P, kk) for kk in checkpoints if kk <= ref.iters}
     return hist, kap, ref.iters, ref.status
 
@@ -164,10 +177,10 @@ class _Now:
         return self.val
 
 
-def oracle_history_async(spec, k, checkpoints):
+def oracle_history_async(spec, k, checkpoints, permute=None):
     """Oracle trajectory of a workload ((name, scale, seed) or ("batch_problem", i)) at the
     checkpoints: computed in a worker process when the pool runs, else on .get()."""
-    args = (spec, k, tuple(checkpoints))
+    args = (spec, k, tuple(checkpoints), permute)
     if _pool is not None:
         return _pool.apply_async(_oracle_history, args)
     return _Now(_oracle_history, args)

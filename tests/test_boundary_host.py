@@ -53,9 +53,12 @@ def test_validation_codes(lib):
     assert _v(lib, A, L, mu=float("nan")) == -3
     assert _v(lib, A, L, mu=float("inf")) == -3
     assert _v(lib, A, L, s=50) == -4                            # s < ell + max_iters
-    assert _v(lib, A, L, s=4096) == -4                          # above the LDS bin limit
-    assert _v(lib, A, L, s=1025) == -4
-    assert _v(lib, A, L, s=1024) == 0
+    assert _v(lib, A, L, s=16385) == -4                         # above the largest sketch
+    assert _v(lib, A, L, s=16384) == 0
+    assert _v(lib, A, L, s=1025) == 0                           # the multi-workgroup append
+    assert _v(lib, A, L, method=2) == -1
+    assert _v(lib, A, L, method=G.METHOD_GKS) == 0               # no sketch: s not used
+    assert _v(lib, A, L, method=G.METHOD_GKS, refine_steps=1) == -1
     assert _v(lib, A, L, s=6, max_iters=0, zeta=8) == -4        # zeta > s
     assert _v(lib, A, L, zeta=3) == -1
     assert _v(lib, A, L, qr_passes=3) == -1
@@ -130,6 +133,7 @@ int main(void) {
            offsetof(sgks_problem, seed));
     printf("%zu %zu\n", sizeof(sgks_csr), offsetof(sgks_problem, sketch_rows));
     printf("%zu %zu\n", offsetof(sgks_options, workspace), offsetof(sgks_options, workspace_bytes));
+    printf("%zu\n", offsetof(sgks_options, method));
     return 0;
 }
 """
@@ -147,7 +151,7 @@ def test_struct_layouts_match_the_header(tmp_path):
     O, P = G.Options, G.ProblemStruct
     assert got == [ctypes.sizeof(O), O.graph.offset, O.stream.offset, ctypes.sizeof(P),
                    P.b.offset, P.seed.offset, ctypes.sizeof(G.CsrStruct), P.sketch_rows.offset,
-                   O.workspace.offset, O.workspace_bytes.offset]
+                   O.workspace.offset, O.workspace_bytes.offset, O.method.offset]
 
 
 def test_workspace_bytes_host_only(lib):

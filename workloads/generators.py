@@ -268,6 +268,43 @@ def travel_time(N, m, rng):
     return _csr(np.concatenate(rows), np.concatenate(cols), np.concatenate(vals), (m, N * N))
 
 
+def perimeter_points(N, count, offset=0.0, inset=0.25):
+    """count points equally spaced along the boundary of [-N/2, N/2]^2 (counter-clockwise
+    from the bottom-left corner, arc-length parameter (j + offset) 4N / count), moved
+    inset pixels into the square so that no ray runs along its edge."""
+    u = (np.arange(count) + offset) * (4.0 * N / count)
+    side = np.minimum((u // N).astype(np.int64), 3)
+    h = N / 2.0 - inset
+    pos = -h + (u - side * N) / N * (2 * h)
+    x = np.select([side == 0, side == 1, side == 2, side == 3], [pos, np.full_like(u, h), -pos, np.full_like(u, -h)])
+    y = np.select([side == 0, side == 1, side == 2, side == 3], [np.full_like(u, -h), pos, np.full_like(u, h), -pos])
+    return np.stack([x, y], axis=1)
+
+
+def travel_time_pairs(N, n_src, n_rec):
+    """Straight-ray travel-time matrix between every source and every receiver (one row per
+    pair, source-major): n_src sources and n_rec receivers equally spaced along the
+    boundary, receivers offset by half a spacing."""
+    S = perimeter_points(N, n_src, 0.0)
+    R = perimeter_points(N, n_rec, 0.5)
+    P = np.repeat(S, n_rec, axis=0)
+    Q = np.tile(R, (n_src, 1))
+    d = Q - P
+    ln = np.linalg.norm(d, axis=1)
+    d = d / ln[:, None]
+    d[np.abs(d) < 1e-15] = 0.0
+    m = P.shape[0]
+    rows, cols, vals = [], [], []
+    chunk = 4096
+    for c0 in range(0, m, chunk):
+        sl = slice(c0, min(m, c0 + chunk))
+        r, q, v = _siddon(N, P[sl], d[sl], np.zeros(sl.stop - sl.start), ln[sl])
+        rows.append(r + c0)
+        cols.append(q)
+        vals.append(v)
+    return _csr(np.concatenate(rows), np.concatenate(cols), np.concatenate(vals), (m, N * N))
+
+
 # ----------------------------------------------------------------------------
 # images
 # ----------------------------------------------------------------------------
@@ -410,6 +447,61 @@ def dynamic_ct(seed=0, nt=30, N=128, n_angles=60, n_det=182, k=200, s=800, mu=1e
                    meta=dict(nt=nt, N=N, n_angles=n_angles, n_det=n_det))
 
 
+# ----------------------------------------------------------------------------
+# the paper's experiment shapes (Sec. 4.2.1, Sec. 4.2.2, Sec. 4.3) on synthetic data
+# ----------------------------------------------------------------------------
+
+def ct_exp2(seed=0, N=500, n_angles=120, n_det=500, k=300, s=606, mu=35.9, noise=0.01,
+            dtype="f32"):
+    """Exp. 2 shape: N x N parallel-beam CT, n_angles angles equally spaced over
+    [0, 179] degrees, n_det unit-spaced detectors (m = 60,000 at the paper's size),
+    first-difference L, 1% noise, the paper's lambda* = 35.9, s = 606, k = 300."""
+    rng = np.random.default_rng(seed)
+    angles = np.linspace(0.0, 179.0, n_angles) * math.pi / 180.0
+    A = parallel_beam_ct(N, angles, n_det)
+    L = grad2d(N)
+    x = phantom_ct(N, rng)
+    b = add_noise(A @ x, noise, rng)
+    if dtype == "f32":
+        A, L, b = _round32(A), _round32(L), b.astype(np.float32).astype(np.float64)
+    return Problem("ct_exp2", A, L, b, x, mu, k, s, seed, dtype=dtype,
+                   meta=dict(N=N, n_angles=n_angles, n_det=n_det))
+
+
+def traveltime_exp3(seed=0, N=256, k=300, s=1000, mu=37.3, noise=0.01, dtype="f32"):
+    """Exp. 3 shape: N x N travel-time tomography, 3N sources and 2N receivers along the
+    boundary, every pair a ray (m = 6 N^2 = 393,216 at N = 256), first-difference L, 1%
+    noise, the paper's lambda* ~ 37.3, k = 300, s one of the paper's sketch sizes."""
+    rng = np.random.default_rng(seed)
+    A = travel_time_pairs(N, 3 * N, 2 * N)
+    L = grad2d(N)
+    x = random_ellipses(N, rng)
+    b = add_noise(A @ x, noise, rng)
+    if dtype == "f32":
+        A, L, b = _round32(A), _round32(L), b.astype(np.float32).astype(np.float64)
+    return Problem("traveltime_exp3", A, L, b, x, mu, k, s, seed, dtype=dtype, meta=dict(N=N))
+
+
+def dynamic_ct_exp4(seed=0, nt=10, N=256, n_angles=30, n_det=512, k=400, s=806, mu=6.81,
+                    noise=0.001, dtype="f32"):
+    """Exp. 4 shape: nt frames of N x N; frame t sees n_angles angles equally spaced in the
+    t-th of nt equal sectors of [0, pi) (18 degrees each at nt = 10), n_det detectors
+    (m = 153,600 at the paper's size), block-diagonal A, space-time L, 0.1% noise, the
+    paper's lambda*_sGKS = 6.81, s = 806, k = 400."""
+    rng = np.random.default_rng(seed)
+    sector = math.pi / nt
+    blocks = [parallel_beam_ct(N, t * sector + np.arange(n_angles) * sector / n_angles, n_det)
+              for t in range(nt)]
+    A = _fix_csr(sp.block_diag(blocks, format="csr"))
+    L = _fix_csr(grad_spacetime(nt, N))
+    x = moving_ellipses(nt, N, rng)
+    b = add_noise(A @ x, noise, rng)
+    if dtype == "f32":
+        A, L, b = _round32(A), _round32(L), b.astype(np.float32).astype(np.float64)
+    return Problem("dynamic_ct_exp4", A, L, b, x, mu, k, s, seed, dtype=dtype,
+                   meta=dict(nt=nt, N=N, n_angles=n_angles, n_det=n_det))
+
+
 def batch_specs(seed=0, count=32, sides=(64, 256)):
     """(kind, N, mu) of every problem of the uneven batch: types cycle deblur / CT /
     travel time; sides and mu log-uniform."""
@@ -454,6 +546,15 @@ def make(config, seed=0, scale="full"):
     if config == "dynamic_ct":
         return dynamic_ct(seed) if not small else dynamic_ct(seed, nt=4, N=24, n_angles=12,
                                                               n_det=35, k=20, s=100)
+    if config == "ct_exp2":
+        return ct_exp2(seed) if not small else ct_exp2(seed, N=40, n_angles=24, n_det=40, k=20,
+                                                       s=60)
+    if config == "traveltime_exp3":
+        return (traveltime_exp3(seed) if not small else
+                traveltime_exp3(seed, N=24, k=20, s=1500))
+    if config == "dynamic_ct_exp4":
+        return (dynamic_ct_exp4(seed) if not small else
+                dynamic_ct_exp4(seed, nt=4, N=24, n_angles=8, n_det=48, k=20, s=100))
     if config == "batch":
         return batch_problems(seed) if not small else batch_problems(seed, count=5, k=12, s=60,
                                                                      sides=(16, 40))
@@ -461,3 +562,5 @@ def make(config, seed=0, scale="full"):
 
 
 CONFIGS = ("deblur1d", "deblur2d", "ct2d", "batch", "dynamic_ct")
+# the paper's experiment shapes (NEXT beyond the configs above)
+PAPER_SCALE = ("ct_exp2", "traveltime_exp3", "dynamic_ct_exp4")

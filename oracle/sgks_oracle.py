@@ -125,6 +125,82 @@ def sparse_sign_matrix(h, s, zeta, seed, stream):
 
 
 # ----------------------------------------------------------------------------
+# Subsampled randomised trigonometric transform (SRTT, eq:sketching_trig):
+#   S = sqrt(h / s) D F E  (s x h)
+# E: diagonal of Rademacher signs, F: the orthonormal DCT-II of length h,
+#   F[k, i] = c_k cos(pi k (2 i + 1) / (2 h)),  c_0 = sqrt(1/h), c_k = sqrt(2/h),
+# D: s distinct rows of the identity.  The paper does not fix how E and D are
+# drawn; here both come from SplitMix64 (same finaliser and gamma as above):
+#   sign key  ks = mix64(seed + gamma (stream + 3)),  E_i = -1 if mix64(ks + gamma (i + 1)) is odd
+#   row key   kr = mix64(seed + gamma (stream + 1)),  draw c: z_c = mix64(kr + gamma (c + 1)),
+#             row = ((z_c >> 32) h) >> 32, a row already drawn is skipped, until s rows;
+#   output j of S is frequency rows[j] (draw order).
+# ----------------------------------------------------------------------------
+
+def srtt_signs(h, seed, stream):
+    """The h Rademacher signs of E (+1 / -1)."""
+    with np.errstate(over="ignore"):
+        ks = mix64(np.uint64(seed) + GAMMA * np.uint64(stream + 3))
+        z = mix64(ks + GAMMA * (np.arange(h, dtype=np.uint64) + np.uint64(1)))
+    return np.where((z & np.uint64(1)) == 1, -1.0, 1.0)
+
+
+def srtt_rows(h, s, seed, stream):
+    """The s distinct frequencies D selects, in draw order."""
+    if s > h:
+        raise ValueError("an SRTT selects at most h rows")
+    with np.errstate(over="ignore"):
+        kr = mix64(np.uint64(seed) + GAMMA * np.uint64(stream + 1))
+    rows, seen, c = [], set(), 0
+    while len(rows) < s:
+        with np.errstate(over="ignore"):
+            z = int(mix64(kr + GAMMA * np.uint64(c + 1)))
+        c += 1
+        r = ((z >> 32) * h) >> 32
+        if r not in seen:
+            seen.add(r)
+            rows.append(r)
+    return np.array(rows, dtype=np.int64)
+
+
+class SRTT:
+    """S = sqrt(h/s) D F E applied with the fast DCT-II (scipy.fft, orthonormal) as one
+    step; S @ v for a vector or the columns of a matrix, S.T @ w for its transpose."""
+
+    def __init__(self, h, s, seed, stream):
+        self.h, self.s = h, s
+        self.E = srtt_signs(h, seed, stream)
+        self.rows = srtt_rows(h, s, seed, stream)
+        self.scale = math.sqrt(h / s)
+        self.shape = (s, h)
+
+    def __matmul__(self, v):
+        import scipy.fft as fft
+        v = np.asarray(v, dtype=np.float64)
+        ev = self.E[:, None] * v if v.ndim == 2 else self.E * v
+        return self.scale * fft.dct(ev, type=2, norm="ortho", axis=0)[self.rows]
+
+    @property
+    def T(self):
+        return _SRTTTranspose(self)
+
+
+class _SRTTTranspose:
+    def __init__(self, S):
+        self.S = S
+        self.shape = (S.h, S.s)
+
+    def __matmul__(self, w):
+        import scipy.fft as fft
+        S = self.S
+        w = np.asarray(w, dtype=np.float64)
+        full = np.zeros((S.h,) + w.shape[1:])
+        full[S.rows] = w
+        out = fft.idct(full, type=2, norm="ortho", axis=0)     # F^T, F orthonormal
+        return S.scale * (S.E[:, None] * out if w.ndim == 2 else S.E * out)
+
+
+# ----------------------------------------------------------------------------
 # Building blocks
 # ----------------------------------------------------------------------------
 
@@ -240,9 +316,12 @@ class Result:
 # ----------------------------------------------------------------------------
 
 def make_sketches(m, p, s, seed, zeta=8, kind="sparse_sign"):
-    """(S_A, S_L): s x m and s x p sparse-sign embeddings, or identities for kind="identity"."""
+    """(S_A, S_L): s x m and s x p sparse-sign embeddings, SRTTs for kind="srtt"
+    (eq:sketching_trig), or identities for kind="identity"."""
     if kind == "identity":
         return sp.identity(m, format="csr"), sp.identity(p, format="csr")
+    if kind == "srtt":
+        return SRTT(m, s, seed, 0), SRTT(p, s, seed, 1)
     if kind != "sparse_sign":
         raise ValueError(kind)
     return (sparse_sign_matrix(m, s, zeta, seed, 0), sparse_sign_matrix(p, s, zeta, seed, 1))

@@ -38,6 +38,10 @@ constexpr int kMaxSketch = 16384;   // largest sketch size (the multi-workgroup 
 // 64 KiB (8 copies up to s = 1024), fewer, shared by several waves, beyond; one
 // copy of s doubles needs s * 8 bytes of one workgroup's LDS
 constexpr int kScatterLdsBytes = 64 * 1024;
+// sketch rows of one scatter range: beyond, the rows are split into ranges, each
+// scatter workgroup taking one range of its tiles' bins (the tiles are read once
+// per range)
+constexpr int kScatterRange = kScatterLdsBytes / 8;
 constexpr int kMaxD = 512;          // largest basis dimension
 constexpr int kAppendThreads = 256; // threads per workgroup of the append chain kernels
 constexpr int kMaxAppendGroups = 256; // workgroups of the append kernels
@@ -222,6 +226,7 @@ void launch_make_pattern(int16_t* pat, int64_t rows, int s, int zeta, uint64_t s
                          hipStream_t st);
 int scatter_blocks(int64_t rows, int tiles_per_wave);
 size_t scatter_lds_bytes(int s);
+int scatter_ranges(int s);
 size_t transpose_scratch_bytes(const Csr& M);
 // scratch (device, scratch_bytes) serves the sort when large enough; else the
 // scratch is allocated and freed around the sort

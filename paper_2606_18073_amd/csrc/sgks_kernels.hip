@@ -638,11 +638,18 @@ __device__ __forceinline__ void scatter_body(const double* __restrict__ zA, int6
                                              double* partA, double* partL, int blk_all,
                                              double* sm, int lds_doubles) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    // copies of the bins in LDS: one per wave while they fit, else shared by waves
-    const int copies = max(1, min(kSketchWaves, lds_doubles / s));
-    for (int i = threadIdx.x; i < copies * s; i += kSketchBlock) sm[i] = 0.0;
+    // sketch rows in ranges of at most kScatterRange (one LDS copy each): workgroup
+    // blk_all of the problem takes range blk_all / (nbA + nbL) of its tiles' bins
+    const int R = (s + kScatterRange - 1) / kScatterRange;
+    const int len = (s + R - 1) / R;
+    const int rg = blk_all / (nbA + nbL);
+    blk_all -= rg * (nbA + nbL);
+    const int r0 = rg * len, r1 = min(s, r0 + len);
+    // copies of the range's bins in LDS: one per wave while they fit, else shared
+    const int copies = max(1, min(kSketchWaves, lds_doubles / len));
+    for (int i = threadIdx.x; i < copies * len; i += kSketchBlock) sm[i] = 0.0;
     __syncthreads();
-    double* bins = sm + (wave % copies) * s;
+    double* bins = sm + (wave % copies) * len - r0;   // indexed by the sketch row
     const bool isA = blk_all < nbA;
     const double* __restrict__ z = isA ? zA : zL;
     const int16_t* pat = isA ? patA : patL;
@@ -669,7 +676,9 @@ __device__ __forceinline__ void scatter_body(const double* __restrict__ zA, int6
             for (int u = 0; u < TB; ++u) {
                 if ((t0 + u * tstride) * 64 + lane < rows) {
 #pragma unroll
-                    for (int q = 0; q < Z; ++q) atomicAdd(&bins[bin[u][q]], sg[u][q] * v[u]);
+                    for (int q = 0; q < Z; ++q)
+                        if (R == 1 || (bin[u][q] >= r0 && bin[u][q] < r1))
+                            atomicAdd(&bins[bin[u][q]], sg[u][q] * v[u]);
                 }
             }
         }
@@ -679,22 +688,23 @@ __device__ __forceinline__ void scatter_body(const double* __restrict__ zA, int6
             if (i < rows) {
                 const double v = z[i];
                 if (identity) {
-                    atomicAdd(&bins[i], v);
+                    if (i >= r0 && i < r1) atomicAdd(&bins[i], v);
                 } else {
                     int bin[Z];
                     double sg[Z];
                     sketch_column<Z>(seed, stream, i, s, bin, sg);
 #pragma unroll
-                    for (int q = 0; q < Z; ++q) atomicAdd(&bins[bin[q]], sg[q] * v);
+                    for (int q = 0; q < Z; ++q)
+                        if (bin[q] >= r0 && bin[q] < r1) atomicAdd(&bins[bin[q]], sg[q] * v);
                 }
             }
         }
     }
     __syncthreads();
-    double* out = (isA ? partA : partL) + (int64_t)blk * s;
-    for (int j = threadIdx.x; j < s; j += kSketchBlock) {
+    double* out = (isA ? partA : partL) + (int64_t)blk * s + r0;
+    for (int j = threadIdx.x; j < r1 - r0; j += kSketchBlock) {
         double a = 0.0;
-        for (int w = 0; w < copies; ++w) a += sm[w * s + j];
+        for (int w = 0; w < copies; ++w) a += sm[w * len + j];
         out[j] = a;
     }
 }
@@ -2041,7 +2051,11 @@ void launch_adjoint(const State& S, const double* u, const double* t, bool with_
 
 // LDS bytes of the scatter for sketch size s: as many copies of the bins as fit
 // in kScatterLdsBytes (at most one per wave), at least one
+int scatter_ranges(int s) { return (s + kScatterRange - 1) / kScatterRange; }
+
 size_t scatter_lds_bytes(int s) {
+    const int R = scatter_ranges(s);
+    s = (s + R - 1) / R;   // the sketch rows of one range
     int copies = kScatterLdsBytes / (8 * s);
     if (copies > kSketchWaves) copies = kSketchWaves;
     if (copies < 1) copies = 1;
@@ -2051,7 +2065,7 @@ size_t scatter_lds_bytes(int s) {
 void launch_scatter(const State& S, const double* zA, const double* zL, hipStream_t st) {
     const size_t shm = scatter_lds_bytes(S.s);
     const int nbL = zL ? S.nbL : 0;
-    const int nb = S.nbA + nbL;
+    const int nb = (S.nbA + nbL) * scatter_ranges(S.s);
 #define SGKS_SC(Zv)                                                                             \
     hipLaunchKernelGGL((k_scatter<Zv>), dim3(nb), dim3(kSketchBlock), shm, st, zA, S.m, zL, S.p, \
                        S.nbA, nbL, S.s, S.seed, S.sketch_mode, S.patA, S.patL, S.binA, S.binL, \
@@ -2247,7 +2261,7 @@ int plan_build(Plan& P, const State* host, const State* dev, int np, const int* 
         if (!append_groups_ok(S.s, S.dmax, groups[q])) return -1;
         fwd[q] = forward_blocks(S, true, nullptr);
         adj[q] = adjoint_blocks(S);
-        sc[q] = S.nbA + S.nbL;
+        sc[q] = (S.nbA + S.nbL) * scatter_ranges(S.s);
         gv[q] = gemv_blocks(S);
         gr[q] = gradient_blocks(S);
         gt[q] = S.ngt;

@@ -612,3 +612,80 @@ def test_sgks_approaches_gks_as_sketch_grows():
     assert dist[0] > dist[1] > dist[2]
     assert gap[0] > gap[2]
     assert dist[2] < 0.5 * dist[0]
+
+
+# ----------------------------------------------------------------------------
+# SRTT (eq:sketching_trig)
+# ----------------------------------------------------------------------------
+
+def _srtt_dense_by_definition(h, s, seed, stream):
+    """S = sqrt(h/s) D F E written out entry by entry: DCT-II cosines from their formula,
+    signs and rows from scalar SplitMix64 loops (Python integers mod 2^64)."""
+    mask = (1 << 64) - 1
+    g = 0x9E3779B97F4A7C15
+    mix = lambda z: int(O.mix64(np.uint64(z & mask)))
+    ks = mix(seed + g * (stream + 3))
+    E = [(-1.0 if mix(ks + g * (i + 1)) & 1 else 1.0) for i in range(h)]
+    kr = mix(seed + g * (stream + 1))
+    rows, c = [], 0
+    while len(rows) < s:
+        z = mix(kr + g * (c + 1))
+        c += 1
+        r = ((z >> 32) * h) >> 32
+        if r not in rows:
+            rows.append(r)
+    S = np.zeros((s, h))
+    for j, k in enumerate(rows):
+        ck = math.sqrt((1.0 if k == 0 else 2.0) / h)
+        for i in range(h):
+            S[j, i] = math.sqrt(h / s) * ck * math.cos(math.pi * k * (2 * i + 1) / (2 * h)) * E[i]
+    return S
+
+
+@pytest.mark.parametrize("h,s,seed,stream", [(24, 10, 0, 0), (37, 37, 5, 1), (64, 9, 3, 0)])
+def test_srtt_matches_its_definition(h, s, seed, stream):
+    """The oracle's SRTT (fast DCT) equals the matrix written from eq:sketching_trig."""
+    S = O.SRTT(h, s, seed, stream)
+    M = _srtt_dense_by_definition(h, s, seed, stream)
+    rng = np.random.default_rng(0)
+    v = rng.standard_normal(h)
+    V = rng.standard_normal((h, 3))
+    w = rng.standard_normal(s)
+    assert np.allclose(S @ v, M @ v, rtol=0, atol=1e-12 * np.linalg.norm(M @ v))
+    assert np.allclose(S @ V, M @ V, rtol=0, atol=1e-12 * np.linalg.norm(M @ V))
+    assert np.allclose(S.T @ w, M.T @ w, rtol=0, atol=1e-12 * np.linalg.norm(M.T @ w))
+
+
+def test_srtt_full_selection_is_orthogonal():
+    """With s = h every frequency is kept and S = D F E is orthogonal (F and E are)."""
+    h = 50
+    S = O.SRTT(h, h, 7, 0)
+    M = S @ np.eye(h)
+    assert np.allclose(M.T @ M, np.eye(h), atol=1e-13)
+
+
+def test_srtt_is_isometric_in_expectation_and_embeds():
+    """E ||S x||^2 = ||x||^2 over the random signs and rows; for s well above a subspace's
+    dimension the embedding distortion of Def. 1 is below one."""
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(400)
+    ratios = [np.linalg.norm(O.SRTT(400, 40, sd, 0) @ x) ** 2 / (x @ x) for sd in range(300)]
+    assert abs(np.mean(ratios) - 1.0) < 0.03
+    Q, _ = np.linalg.qr(rng.standard_normal((400, 5)))
+    assert O.embedding_epsilon(O.SRTT(400, 200, 2, 0), Q) < 0.9
+
+
+def test_sgks_with_srtt_satisfies_prop2():
+    """Prop. 2 (max form) with SRTT sketches, eps measured on range([A W, b]), range(L W)."""
+    A, L, b, mu = tiny2d(N=10)
+    s, seed = 60, 4
+    res = O.sgks(A, L, b, mu, 8, s, seed, sketch="srtt")
+    S_A, S_L = O.make_sketches(A.shape[0], L.shape[0], s, seed, kind="srtt")
+    W = res.W
+    eps = max(_eps(S_A, np.column_stack([A @ W, b])), _eps(S_L, L @ W))
+    assert eps < 1
+    phi = lambda y: np.linalg.norm(A @ W @ y - b) ** 2 + mu * np.linalg.norm(L @ W @ y) ** 2
+    y0 = O.unsketched_projected_solution(A, L, b, mu, W)
+    assert phi(res.y) <= (1 + eps) / (1 - eps) * phi(y0) * (1 + 1e-12)
+    # Q_A R_A = S_A A W with the SRTT
+    assert np.allclose(res.Q_A @ res.R_A, S_A @ (A @ W), atol=1e-10)

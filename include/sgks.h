@@ -66,11 +66,19 @@ extern "C" {
 #define SGKS_F32 0
 #define SGKS_F64 1
 
-/* sketch kinds: the sparse-sign embedding, or identities (sGKS_0 of Prop. 1,
+/* sketch kinds: the sparse-sign embedding; identities (sGKS_0 of Prop. 1,
  * meant for small checks: then s must equal max(m, p) and both sketches are
- * the identity on the first m (resp. p) rows). */
+ * the identity on the first m (resp. p) rows); or the subsampled randomised
+ * trigonometric transform of eq:sketching_trig, S = sqrt(h/s) D F E with F the
+ * orthonormal DCT-II of length h (h = m for S_A, p for S_L), E Rademacher signs
+ * (sign i = -1 if mix64(mix64(seed + g (stream + 3)) + g (i + 1)) is odd) and
+ * D s distinct rows (draws mix64(mix64(seed + g (stream + 1)) + g (c + 1)),
+ * row ((draw >> 32) h) >> 32, repeats skipped, outputs in draw order); needs
+ * s <= min(m, p); zeta is not used.  Its s outputs are evaluated directly, h s
+ * FP64 terms per image. */
 #define SGKS_SKETCH_SPARSE_SIGN 0
 #define SGKS_SKETCH_IDENTITY 1
+#define SGKS_SKETCH_SRTT 2
 
 /* Gradient forms (the same vector, two associations; eq: gradient).  DIRECT:
  * x = W y, u = A x - b, t = L x, r = A^T u + mu L^T t (two SpMVs and a GEMV per

@@ -438,6 +438,7 @@ struct sgks_ctx {
     double* init_norms;  // copy of the scalars after the initial basis (checked at the end of create)
     int16_t* patA = nullptr;
     int16_t* patL = nullptr;
+    std::vector<int32_t> srtt_rows;   // the SRTT frequencies of both sides (host copy)
     void* sort_scratch = nullptr;   // transpose sort scratch when W (and HW) are too small
     size_t sort_bytes = 0;
     int32_t* At_rowptr;
@@ -533,7 +534,7 @@ int plan_context(sgks_ctx* c, const sgks_csr* A, const sgks_csr* L, double mu, i
     S.dmax = c->opt.ell + c->opt.max_iters;
     S.zeta = c->opt.zeta;
     S.passes = c->opt.qr_passes;
-    S.sketch_mode = gks ? 2 : c->opt.sketch_mode;   // 2: no sketch
+    S.sketch_mode = gks ? sgks::kSketchNone : c->opt.sketch_mode;
     S.vdt = c->opt.value_dtype;
     S.gradient_form = c->opt.gradient_form;
     S.seed = seed;
@@ -552,9 +553,15 @@ int plan_context(sgks_ctx* c, const sgks_csr* A, const sgks_csr* L, double mu, i
     S.Lt = Csr{S.n, S.p, S.L.nnz, nullptr, nullptr, nullptr, choose_lanes(S.L.nnz, S.n)};
 
     // scatter workgroups: kScatterTilesPerWave 64-entry tiles per wave (the
-    // autotuner may choose another count; the partial bins are sized for one)
-    S.nbA = sgks::scatter_blocks(S.m, kScatterTilesPerWave);
-    S.nbL = sgks::scatter_blocks(S.p, kScatterTilesPerWave);
+    // autotuner may choose another count; the partial bins are sized for one);
+    // SRTT: chunks of rows
+    if (S.sketch_mode == SGKS_SKETCH_SRTT) {
+        S.nbA = sgks::srtt_chunks(S.m, &S.srA);
+        S.nbL = sgks::srtt_chunks(S.p, &S.srL);
+    } else {
+        S.nbA = sgks::scatter_blocks(S.m, kScatterTilesPerWave);
+        S.nbL = sgks::scatter_blocks(S.p, kScatterTilesPerWave);
+    }
     S.n_norm_part = norm_parts(S);
     int nbFA = 0;
     const int nbF = sgks::forward_blocks(S, true, &nbFA);
@@ -577,7 +584,7 @@ int plan_context(sgks_ctx* c, const sgks_csr* A, const sgks_csr* L, double mu, i
     {
         const int cap = sgks::max_append_groups();
         int G = c->opt.append_groups;
-        if (G == 0) G = sgks::choose_append_groups(s, dmax, cap < 64 ? cap : 64);
+        if (G == 0) G = sgks::choose_append_groups(s, dmax, cap);
         if (G > cap) G = cap;
         if (!sgks::append_groups_ok(s, dmax, G)) return SGKS_ERR_SKETCH_SIZE;
         c->groups = G;
@@ -632,6 +639,10 @@ void layout_context(sgks_ctx* c, Arena& ar) {
     if (sparse) {
         ar.add(&c->patA, (size_t)S.m * S.zeta * 2);
         ar.add(&c->patL, (size_t)S.p * S.zeta * 2);
+    }
+    if (S.sketch_mode == SGKS_SKETCH_SRTT) {
+        ar.add((int32_t**)&S.rowsA, (size_t)s * 4);
+        ar.add((int32_t**)&S.rowsL, (size_t)s * 4);
     }
     ar.add(&S.wa, s * 8);
     ar.add(&S.wl, s * 8);
@@ -723,7 +734,8 @@ int sgks_validate(const sgks_csr* A, const sgks_csr* L, const void* b, double mu
     if (o.value_dtype != SGKS_F32 && o.value_dtype != SGKS_F64) return SGKS_ERR_INVALID_ARG;
     if (o.qr_passes != 1 && o.qr_passes != 2) return SGKS_ERR_INVALID_ARG;
     if (o.refine_steps < 0) return SGKS_ERR_INVALID_ARG;
-    if (o.sketch_mode != SGKS_SKETCH_SPARSE_SIGN && o.sketch_mode != SGKS_SKETCH_IDENTITY)
+    if (o.sketch_mode != SGKS_SKETCH_SPARSE_SIGN && o.sketch_mode != SGKS_SKETCH_IDENTITY &&
+        o.sketch_mode != SGKS_SKETCH_SRTT)
         return SGKS_ERR_INVALID_ARG;
     if (!pow2_lanes(o.lanes_A) || !pow2_lanes(o.lanes_At)) return SGKS_ERR_INVALID_ARG;
     if (o.append_groups < 0) return SGKS_ERR_INVALID_ARG;
@@ -737,6 +749,10 @@ int sgks_validate(const sgks_csr* A, const sgks_csr* L, const void* b, double mu
     if (o.sketch_mode == SGKS_SKETCH_SPARSE_SIGN) {
         if (s < o.ell + o.max_iters) return SGKS_ERR_SKETCH_SIZE;
         if (o.zeta > s) return SGKS_ERR_SKETCH_SIZE;
+    } else if (o.sketch_mode == SGKS_SKETCH_SRTT) {
+        // D keeps s distinct rows of each image
+        if (s < o.ell + o.max_iters || (int64_t)s > A->rows || (int64_t)s > L->rows)
+            return SGKS_ERR_SKETCH_SIZE;
     } else {
         if ((int64_t)s < A->rows || (int64_t)s < L->rows) return SGKS_ERR_SKETCH_SIZE;
     }
@@ -848,6 +864,16 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
         S.patA = c->patA;
         S.patL = c->patL;
     }
+    if (S.sketch_mode == SGKS_SKETCH_SRTT) {
+        // the frequencies D selects, drawn on the host
+        c->srtt_rows.resize((size_t)2 * s);
+        sgks::srtt_rows_host(S.m, s, seed, 0, c->srtt_rows.data());
+        sgks::srtt_rows_host(S.p, s, seed, 1, c->srtt_rows.data() + s);
+        SGKS_TRY(hipMemcpyAsync((void*)S.rowsA, c->srtt_rows.data(), (size_t)s * 4,
+                                hipMemcpyHostToDevice, st));
+        SGKS_TRY(hipMemcpyAsync((void*)S.rowsL, c->srtt_rows.data() + s, (size_t)s * 4,
+                                hipMemcpyHostToDevice, st));
+    }
     if (c->opt.autotune) {
         SGKS_TRY(hipMemsetAsync(S.x, 0, S.n * 8, st));
         SGKS_TRY(hipMemsetAsync(S.u, 0, S.m * 8, st));
@@ -903,7 +929,10 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
         sgks::launch_sum_parts(S.norm_part, S.n_norm_part, S.scal + 1, st);
     } else {
         // c_b = S_A b
-        sgks::launch_scatter(S, S.b, nullptr, st);
+        if (S.sketch_mode == SGKS_SKETCH_SRTT)
+            sgks::launch_srtt(S, S.b, nullptr, st);
+        else
+            sgks::launch_scatter(S, S.b, nullptr, st);
         sgks::launch_cb(S, st);
     }
 

@@ -59,6 +59,12 @@ constexpr int64_t kFuseHWMaxNnz = 12000000;
 // beyond, the bandwidth of one compute unit makes the multi-workgroup chain faster
 constexpr int64_t kCompactAppendMax = 120000;
 
+// sketch kinds inside the library: the public ones, and none (GKS)
+constexpr int kSketchSparseSign = 0, kSketchIdentity = 1, kSketchSrtt = 2, kSketchNone = 3;
+// SRTT sketch: output frequencies per workgroup (one per thread), rows per chunk
+constexpr int kSrttThreads = 256;
+constexpr int kSrttMaxChunks = 128;
+
 // Device status word values (mirrors the public codes).
 constexpr int kStatusOk = 0;
 constexpr int kStatusBreakdown = 1;
@@ -83,7 +89,7 @@ struct State {
     int dmax;        // capacity of the basis
     int zeta;
     int passes;      // projections per QR append (1 or 2)
-    int sketch_mode; // 0 sparse-sign, 1 identity
+    int sketch_mode; // kSketchSparseSign, kSketchIdentity, kSketchSrtt or kSketchNone
     int vdt;         // value dtype of A, L
     int gradient_form; // 0: r from the maintained H W; 1: r = A^T (A x - b) + mu L^T L x directly
     uint64_t seed;
@@ -127,6 +133,11 @@ struct State {
     // from the hash: entry i*zeta + q = +-(row + 1) (sign of the entry), 0 if none
     const int16_t* patA;
     const int16_t* patL;
+    // SRTT: the s frequencies D selects on each side (draw order), rows per chunk
+    // of the images (the partial bins are per chunk: nbA = chunks of m, nbL of p)
+    const int32_t* rowsA;
+    const int32_t* rowsL;
+    int srA, srL;
     double* wa;        // s: working sketched A column of the append
     double* wl;        // s: working sketched L column
     double* wu;        // 2 dmax: working column of the stacked factor
@@ -226,6 +237,13 @@ void launch_make_pattern(int16_t* pat, int64_t rows, int s, int zeta, uint64_t s
                          hipStream_t st);
 int scatter_blocks(int64_t rows, int tiles_per_wave);
 size_t scatter_lds_bytes(int s);
+// SRTT: chunks of h rows (at most kSrttMaxChunks), rows per chunk into *rows_per
+int srtt_chunks(int64_t h, int* rows_per);
+// partial SRTT sketches of zA (m rows, S_A) and, if zL, zL (p rows, S_L) into the
+// partial bins, scaled by sqrt(h/s) c_k (the append adds the chunks)
+void launch_srtt(const State& S, const double* zA, const double* zL, hipStream_t st);
+// the s frequencies an SRTT selects among h rows (host, draw order)
+void srtt_rows_host(int64_t h, int s, uint64_t seed, int stream, int32_t* rows);
 int scatter_ranges(int s);
 size_t transpose_scratch_bytes(const Csr& M);
 // scratch (device, scratch_bytes) serves the sort when large enough; else the

@@ -16,6 +16,8 @@
 // workgroup ranges, so a batch of problems shares each launch.
 #include <hipcub/hipcub.hpp>
 
+#include <vector>
+
 #include "sgks_device.h"
 
 namespace sgks {
@@ -737,6 +739,127 @@ __global__ __launch_bounds__(kSketchBlock) void kb_scatter(const State* __restri
 }
 
 // ---------------------------------------------------------------------------
+// SRTT sketch (eq:sketching_trig): S = sqrt(h/s) D F E with F the orthonormal
+// DCT-II of length h, E Rademacher signs, D s selected frequencies, so
+//   (S z)_j = sqrt(h/s) c_k sum_i E_i z_i cos(pi k (2 i + 1) / (2 h)),  k = rows[j],
+// c_0 = sqrt(1/h), c_k = sqrt(2/h).  Only the s selected outputs are formed,
+// directly: workgroup (chunk, group) stages E z over its chunk of rows in LDS
+// and each thread accumulates one frequency over the chunk, its cosines from a
+// rotation by pi k / h (exact sincospi every kSrttAnchor rows, from the
+// argument reduced in integers).  FP64 ALU work of h s terms per image; the
+// chunks' sums are partial bins added by the append like the scatter's.
+// ---------------------------------------------------------------------------
+
+constexpr int kSrttStage = 2048;   // rows of a chunk staged in LDS at a time
+constexpr int kSrttAnchor = 256;   // rotation steps between exact cosines
+
+__device__ void srtt_body(const double* __restrict__ z, int64_t h, int s,
+                          const int32_t* __restrict__ rows, uint64_t seed, int stream,
+                          int rows_per, int blk, int nkg, double* __restrict__ part,
+                          double* ez) {
+    const uint64_t gam = 0x9E3779B97F4A7C15ull;
+    const uint64_t ks = mix64(seed + gam * (uint64_t)(stream + 3));
+    const int c = blk / nkg, g = blk - (blk / nkg) * nkg;
+    const int64_t i0 = (int64_t)c * rows_per;
+    const int nr = (int)min((int64_t)rows_per, h - i0);
+    const int j = g * kSrttThreads + threadIdx.x;
+    const bool active = j < s;
+    const int64_t k = active ? rows[j] : 0;
+    double Sn, C;
+    sincospi((double)k / (double)h, &Sn, &C);
+    double acc = 0.0;
+    for (int b0 = 0; b0 < nr; b0 += kSrttStage) {
+        const int nb = min(kSrttStage, nr - b0);
+        __syncthreads();   // the previous stage was read by every thread
+        for (int i = threadIdx.x; i < nb; i += kSrttThreads) {
+            const int64_t gi = i0 + b0 + i;
+            const double sg = (mix64(ks + gam * (uint64_t)(gi + 1)) & 1ull) ? -1.0 : 1.0;
+            ez[i] = sg * z[gi];
+        }
+        __syncthreads();
+        if (active) {
+            for (int a0 = 0; a0 < nb; a0 += kSrttAnchor) {
+                const int64_t gi = i0 + b0 + a0;
+                const int64_t r = (k * (2 * gi + 1)) % (4 * h);
+                double sn, cs;
+                sincospi((double)r / (double)(2 * h), &sn, &cs);
+                const int ne = min(kSrttAnchor, nb - a0);
+                for (int q = 0; q < ne; ++q) {
+                    acc += cs * ez[a0 + q];
+                    const double cn = cs * C - sn * Sn;
+                    sn = sn * C + cs * Sn;
+                    cs = cn;
+                }
+            }
+        }
+    }
+    if (active) {
+        const double ck = k == 0 ? sqrt(1.0 / (double)h) : sqrt(2.0 / (double)h);
+        part[(int64_t)c * s + j] = sqrt((double)h / (double)s) * ck * acc;
+    }
+}
+
+// workgroups [0, nbA nkg) sketch zA (S_A, m rows), the rest zL (S_L, p rows)
+__device__ __forceinline__ void srtt_pair(const State& S, const double* zA, const double* zL,
+                                          int nbL, int blk, double* ez) {
+    const int nkg = (S.s + kSrttThreads - 1) / kSrttThreads;
+    if (blk < S.nbA * nkg)
+        srtt_body(zA, S.m, S.s, S.rowsA, S.seed, 0, S.srA, blk, nkg, S.binA, ez);
+    else if (blk < (S.nbA + nbL) * nkg)
+        srtt_body(zL, S.p, S.s, S.rowsL, S.seed, 1, S.srL, blk - S.nbA * nkg, nkg, S.binL, ez);
+}
+
+__global__ __launch_bounds__(kSrttThreads) void k_srtt(const State S, const double* zA,
+                                                      const double* zL, int nbL) {
+    __shared__ double ez[kSrttStage];
+    srtt_pair(S, zA, zL, nbL, blockIdx.x, ez);
+}
+
+// Iteration form: the SRTT sketches of the new column's images (u, t); skipped on
+// a set status.
+__global__ __launch_bounds__(kSrttThreads) void kb_srtt(const State* __restrict__ SS, BTab tab) {
+    __shared__ double ez[kSrttStage];
+    const Slot sl = find_slot(tab);
+    const State S = load_state(SS, sl.p);
+    if (*S.status != 0) return;
+    srtt_pair(S, S.u, S.t, S.nbL, sl.blk, ez);
+}
+
+// out_i = sqrt(m/s) E_i sum_j c_{k_j} cos(pi k_j (2 i + 1) / (2 m)) v_j  (S_A^T v)
+__global__ __launch_bounds__(kBlock) void k_srtt_transpose(const double* __restrict__ v, int s,
+                                                          int64_t m, const int32_t* __restrict__ rows,
+                                                          uint64_t seed, double* __restrict__ out) {
+    __shared__ double vs[kSrttStage];
+    __shared__ int32_t ks_[kSrttStage];
+    const uint64_t gam = 0x9E3779B97F4A7C15ull;
+    const uint64_t ksg = mix64(seed + gam * 3ull);
+    const double sc = sqrt((double)m / (double)s);
+    for (int64_t i0 = (int64_t)blockIdx.x * kBlock; i0 < m; i0 += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = i0 + threadIdx.x;
+        double acc = 0.0;
+        for (int j0 = 0; j0 < s; j0 += kSrttStage) {
+            const int nj = min(kSrttStage, s - j0);
+            __syncthreads();
+            for (int q = threadIdx.x; q < nj; q += kBlock) {
+                const int k = rows[j0 + q];
+                ks_[q] = k;
+                vs[q] = v[j0 + q] * (k == 0 ? sqrt(1.0 / (double)m) : sqrt(2.0 / (double)m));
+            }
+            __syncthreads();
+            if (i < m)
+                for (int q = 0; q < nj; ++q) {
+                    const int64_t r = ((int64_t)ks_[q] * (2 * i + 1)) % (4 * m);
+                    acc += cospi((double)r / (double)(2 * m)) * vs[q];
+                }
+        }
+        if (i < m) {
+            const double sg = (mix64(ksg + gam * (uint64_t)(i + 1)) & 1ull) ? -1.0 : 1.0;
+            out[i] = sc * sg * acc;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // dense basis products
 // ---------------------------------------------------------------------------
 
@@ -1055,7 +1178,7 @@ __global__ __launch_bounds__(kAppendThreads) void k_ap_q0(const State* __restric
         scale = S.cs[d];
     }
     // bins of this slab: thread (row i, chunk q) sums a contiguous range of blocks
-    const double bscale = S.sketch_mode == 1 ? scale : scale / sqrt((double)S.zeta);
+    const double bscale = S.sketch_mode == kSketchSparseSign ? scale / sqrt((double)S.zeta) : scale;
     const int nq = D.ns > 0 ? T / D.ns : 1;
     double* scrA = sh.cA;   // free until the coefficients arrive
     double* scrL = sh.cL;
@@ -1577,7 +1700,7 @@ __device__ void ap1_side_body(const State& S, int side, int scale_from_norm, Ap1
     } else {
         scale = S.cs[d];
     }
-    const double bscale = S.sketch_mode == 1 ? scale : scale / sqrt((double)S.zeta);
+    const double bscale = S.sketch_mode == kSketchSparseSign ? scale / sqrt((double)S.zeta) : scale;
     double* Q = side ? S.QL : S.QA;
     double* R = side ? S.RL : S.RA;
     reduce_bins(side ? S.binL : S.binA, side ? S.nbL : S.nbA, s, bscale, sh.a);
@@ -2079,6 +2202,44 @@ void launch_scatter(const State& S, const double* zA, const double* zL, hipStrea
 #undef SGKS_SC
 }
 
+int srtt_chunks(int64_t h, int* rows_per) {
+    int64_t rp = (h + kSrttMaxChunks - 1) / kSrttMaxChunks;
+    if (rp < 512) rp = 512;
+    *rows_per = (int)rp;
+    return (int)((h + rp - 1) / rp);
+}
+
+void launch_srtt(const State& S, const double* zA, const double* zL, hipStream_t st) {
+    const int nkg = (S.s + kSrttThreads - 1) / kSrttThreads;
+    const int nbL = zL ? S.nbL : 0;
+    hipLaunchKernelGGL(k_srtt, dim3((S.nbA + nbL) * nkg), dim3(kSrttThreads), 0, st, S, zA, zL,
+                       nbL);
+}
+
+void srtt_rows_host(int64_t h, int s, uint64_t seed, int stream, int32_t* rows) {
+    auto mix = [](uint64_t z) {
+        z ^= z >> 30;
+        z *= 0xBF58476D1CE4E5B9ull;
+        z ^= z >> 27;
+        z *= 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        return z;
+    };
+    const uint64_t gam = 0x9E3779B97F4A7C15ull;
+    const uint64_t kr = mix(seed + gam * (uint64_t)(stream + 1));
+    std::vector<char> seen((size_t)h, 0);
+    uint64_t c = 0;
+    for (int j = 0; j < s;) {
+        const uint64_t z = mix(kr + gam * (c + 1));
+        ++c;
+        const int64_t r = (int64_t)(((z >> 32) * (uint64_t)h) >> 32);
+        if (!seen[r]) {
+            seen[r] = 1;
+            rows[j++] = (int32_t)r;
+        }
+    }
+}
+
 int scatter_blocks(int64_t rows, int tiles_per_wave) {
     const int64_t tiles = (rows + 63) / 64;
     const int64_t per = (int64_t)tiles_per_wave * kSketchWaves;
@@ -2105,7 +2266,10 @@ void launch_make_pattern(int16_t* pat, int64_t rows, int s, int zeta, uint64_t s
 // z = A w, L w of basis column col into the u, t buffers, then their sketch bins
 void launch_sketch_column(const State& S, int col, hipStream_t st) {
     launch_forward(S, S.W + (int64_t)col * S.n, nullptr, S.u, S.t, true, nullptr, nullptr, st);
-    launch_scatter(S, S.u, S.t, st);
+    if (S.sketch_mode == kSketchSrtt)
+        launch_srtt(S, S.u, S.t, st);
+    else
+        launch_scatter(S, S.u, S.t, st);
 }
 
 int gemv_blocks(const State& S) { return grid_for(S.n, kBlock, 4096); }
@@ -2144,7 +2308,7 @@ int max_append_groups() {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        return 1;
+        return kMaxAppendGroups;   // no device (a size query on the host): the largest choice
     return cus > 0 ? cus : 1;
 }
 
@@ -2167,7 +2331,7 @@ int choose_append_groups(int s, int dmax, int cap) {
 }
 
 void launch_cb(const State& S, hipStream_t st) {
-    const double scale = S.sketch_mode == 1 ? 1.0 : 1.0 / sqrt((double)S.zeta);
+    const double scale = S.sketch_mode == kSketchSparseSign ? 1.0 / sqrt((double)S.zeta) : 1.0;
     hipLaunchKernelGGL(k_cb, dim3(1), dim3(kBlock), 0, st, S.binA, S.nbA, S.s, scale, S.cb,
                        S.scal);
 }
@@ -2185,6 +2349,11 @@ void launch_backward_small(const State& S, double* v_out, double* gmu_out, hipSt
 }
 
 void launch_sketch_transpose(const State& S, const double* v, double* out, hipStream_t st) {
+    if (S.sketch_mode == kSketchSrtt) {
+        hipLaunchKernelGGL(k_srtt_transpose, dim3(grid_for(S.m, kBlock, 2048)), dim3(kBlock), 0,
+                           st, v, S.s, S.m, S.rowsA, S.seed, out);
+        return;
+    }
     const int nb = grid_for(S.m, kBlock, 4096);
     const int staged = (size_t)S.s * sizeof(double) <= (size_t)kScatterLdsBytes ? 1 : 0;
     const size_t shm = staged ? (size_t)S.s * sizeof(double) : 0;
@@ -2261,7 +2430,9 @@ int plan_build(Plan& P, const State* host, const State* dev, int np, const int* 
         if (!append_groups_ok(S.s, S.dmax, groups[q])) return -1;
         fwd[q] = forward_blocks(S, true, nullptr);
         adj[q] = adjoint_blocks(S);
-        sc[q] = (S.nbA + S.nbL) * scatter_ranges(S.s);
+        sc[q] = S.sketch_mode == kSketchSrtt
+                    ? (S.nbA + S.nbL) * ((S.s + kSrttThreads - 1) / kSrttThreads)
+                    : (S.nbA + S.nbL) * scatter_ranges(S.s);
         gv[q] = gemv_blocks(S);
         gr[q] = gradient_blocks(S);
         gt[q] = S.ngt;
@@ -2319,6 +2490,10 @@ void plan_gradient(const Plan& P, bool to_rtmp, hipStream_t st) {
 }
 
 void plan_scatter(const Plan& P, hipStream_t st) {
+    if (P.sketch_mode == kSketchSrtt) {
+        SGKS_LAUNCH(kb_srtt, dim3(tab_total(P.sc)), dim3(kSrttThreads), 0, st, P.SS, P.sc);
+        return;
+    }
     const size_t shm = scatter_lds_bytes(P.max_s);
     const dim3 grid(tab_total(P.sc));
 #define SGKS_SC(Zv) \

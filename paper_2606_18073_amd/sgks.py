@@ -26,7 +26,7 @@ ERRORS = {
 F32, F64 = 0, 1
 GRADIENT_MAINTAINED, GRADIENT_DIRECT = 0, 1
 METHOD_SGKS, METHOD_GKS = 0, 1
-SKETCH_SPARSE_SIGN, SKETCH_IDENTITY = 0, 1
+SKETCH_SPARSE_SIGN, SKETCH_IDENTITY, SKETCH_SRTT = 0, 1, 2
 PHASES = 8
 # phase 0: x = W y (direct gradient form) or r = (H W) y - A^T b (maintained);
 # phase 2: r = A^T u + mu L^T t (direct) or the new column of H W (maintained)
@@ -192,7 +192,8 @@ def make_options(lib, vdt, stream, *, ell=3, max_iters=200, zeta=8, refine_steps
     lib.sgks_default_options(ctypes.byref(o))
     o.ell, o.max_iters, o.zeta, o.value_dtype = ell, max_iters, zeta, vdt
     o.refine_steps, o.qr_passes = refine_steps, qr_passes
-    o.sketch_mode = SKETCH_IDENTITY if sketch == "identity" else SKETCH_SPARSE_SIGN
+    o.sketch_mode = {"sparse_sign": SKETCH_SPARSE_SIGN, "identity": SKETCH_IDENTITY,
+                     "srtt": SKETCH_SRTT}[sketch]
     o.lanes_A, o.lanes_At, o.append_groups = lanes_A, lanes_At, append_groups
     o.graph, o.autotune = int(bool(graph)), int(bool(autotune))
     o.gradient_form = GRADIENT_DIRECT if gradient == "direct" else GRADIENT_MAINTAINED

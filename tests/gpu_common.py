@@ -49,19 +49,19 @@ def backward_error(RA, RL, dA, mu, y):
 BACKWARD_ERROR_UNITS = 50.0
 
 
-def check_state_consistency(S, P, tol=1e-9):
+def check_state_consistency(S, P, tol=1e-9, sketch="sparse_sign"):
     """Relations that hold at any k: the GPU's factors are factors of the GPU's basis."""
     W = S.state("W")
     y = S.state("y")
     QA, RA, QL, RL = S.state("Q_A"), S.state("R_A"), S.state("Q_L"), S.state("R_L")
     dA, cb = S.state("d_A"), S.state("c_b")
-    S_A, S_L = O.make_sketches(P.m, P.p, P.s, P.seed, P.zeta)
+    S_A, S_L = O.make_sketches(P.m, P.p, P.s, P.seed, P.zeta, kind=sketch)
     d = W.shape[1]
     # unit columns (normalised basis)
     assert np.allclose(np.linalg.norm(W, axis=0), 1.0, atol=1e-12)
-    # c_b = S_A b (integer-exact pattern, FP64 sums)
+    # c_b = S_A b (integer-exact pattern or selection, FP64 sums)
     cb_ref = S_A @ P.b
-    assert rel(cb, cb_ref) < 1e-13
+    assert rel(cb, cb_ref) < (1e-13 if sketch != "srtt" else 1e-12)
     SAW = S_A @ (P.A @ W)
     SLW = S_L @ (P.L @ W)
     assert np.linalg.norm(QA @ RA - SAW) <= tol * np.linalg.norm(SAW)

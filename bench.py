@@ -255,14 +255,19 @@ def host_cores():
 # ----------------------------------------------------------------------------
 
 def measure(G, torch, P, steps, warmup, *, backward, profile, graph=False, autotune=False,
-            gradient="maintained"):
-    """Time `steps` complete solves of P (create + k expansions + x_k [+ backward])."""
+            gradient="maintained", order=True):
+    """Time `steps` complete solves of P (create + k expansions + x_k [+ backward]).
+    order: work in the Morton order of the image's unknowns (the library's order option)."""
+    from workloads.generators import image_order
     dev = torch.device("cuda:0")
     A, L, b = G.upload_problem(P)
     x = torch.empty(P.n, dtype=torch.float64, device=dev)
     xt = torch.as_tensor(P.x_true, device=dev)
     opts = dict(ell=P.ell, max_iters=P.k, zeta=P.zeta, refine_steps=P.refine_steps,
                 graph=graph, autotune=autotune, gradient=gradient)
+    io = image_order(P) if order else None
+    if io is not None:
+        opts["order"] = torch.as_tensor(io, dtype=torch.int32, device=dev)
 
     def step(acc, prof):
         t0 = time.perf_counter()
@@ -406,14 +411,18 @@ def describe(P):
     return P.name
 
 
-def bench_gks(G, torch, np, P, steps=2):
+def bench_gks(G, torch, np, P, steps=2, order=True):
     """GKS (Alg. 1) against sGKS on the same GPU and workload: whole solves and the
     expansions alone (Sec. 4.2.1 and Sec. 4.3 compare the two per iteration)."""
+    from workloads.generators import image_order
     A, L, b = G.upload_problem(P)
+    io = image_order(P) if order else None
     out = {}
     for method in ("gks", "sgks"):
         opts = dict(ell=P.ell, max_iters=P.k, zeta=P.zeta, method=method,
                     refine_steps=P.refine_steps if method == "sgks" else 0)
+        if io is not None:
+            opts["order"] = torch.as_tensor(io, dtype=torch.int32, device="cuda")
         S = G.SGKS(A, L, b, P.mu, P.s, P.seed, **opts)   # warm-up
         S.iterate(2)
         S.close()
@@ -441,10 +450,11 @@ def bench_gks(G, torch, np, P, steps=2):
     return out
 
 
-def bench_batch(G, torch, np, make, oracle_refs):
+def bench_batch(G, torch, np, make, oracle_refs, order=True):
     """The 32-problem uneven batch: one batched solve against the 32 plain solves."""
+    from workloads.generators import image_order
     Ps = make("batch", 0, "full")
-    data = G.upload_batch(Ps)
+    data = G.upload_batch(Ps, orders=[image_order(P) for P in Ps] if order else None)
     k = Ps[0].k
     opts = dict(ell=Ps[0].ell, max_iters=k, zeta=Ps[0].zeta, autotune=True)
     B = G.SGKSBatch(data, **opts)      # warm-up (module load, autotuning cached per shape)
@@ -463,10 +473,11 @@ def bench_batch(G, torch, np, make, oracle_refs):
     B.close()
     setup_p = iter_p = 0.0
     same = True
-    for i, (A, L, b, mu, s, seed) in enumerate(data):
+    for i, pr in enumerate(data):
+        A, L, b, mu, s, seed = pr[:6]
         torch.cuda.synchronize()
         u0 = time.perf_counter()
-        S = G.SGKS(A, L, b, mu, s, seed, **opts)
+        S = G.SGKS(A, L, b, mu, s, seed, order=pr[6] if len(pr) > 6 else None, **opts)
         torch.cuda.synchronize()
         u1 = time.perf_counter()
         S.iterate(k)
@@ -548,6 +559,9 @@ def main():
     ap.add_argument("--gradient", choices=["maintained", "direct"], default="maintained")
     ap.add_argument("--autotune", action="store_true",
                     help="let the library time its launch shapes at create (cached per shape)")
+    ap.add_argument("--no-order", action="store_true",
+                    help="work in the caller's row-major order of the unknowns instead of "
+                         "the Morton order of each image frame")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -579,9 +593,10 @@ def main():
     P = make(args.workload, 0, "full")
     backward = args.workload == HEADLINE
     log(f"{P.name}: n={P.n} m={P.m} p={P.p} nnz(A)={P.A.nnz} k={P.k}")
+    order = not args.no_order
     res = measure(G, torch, P, args.steps, args.warmup, backward=backward,
                   profile=not args.no_profile, graph=args.graph, autotune=args.autotune,
-                  gradient=args.gradient)
+                  gradient=args.gradient, order=order)
     log(f"timed: {res['value']:.1f} iters/s, {res['ms_per_step']:.2f} ms per step")
     out = {
         "metric": "sGKS iters/s + SpMV/sketch HBM GB/s; batched & adjoint vs plain at equal rel err",
@@ -602,6 +617,7 @@ def main():
             "k": P.k, "n": P.n, "m": P.m, "p": P.p, "s": P.s,
             "launch": "graph replay" if args.graph else "kernel by kernel",
             "gradient_form": args.gradient,
+            "unknowns_order": "Morton curve per frame" if order else "row-major",
         },
         "paper_context": PAPER_CONTEXT,
     }
@@ -628,7 +644,7 @@ def main():
                 continue
             Q = make(name, 0, "full")
             r = measure(G, torch, Q, max(5, args.steps // 2), 1, backward=False,
-                        profile=not args.no_profile)
+                        profile=not args.no_profile, order=order)
             ent = {"workload": describe(Q), "value": r["value"], "unit": "iters/s",
                    "ms_per_step": r["ms_per_step"], "setup_ms_per_step": r["setup_ms_per_step"],
                    "iterate_only_iters_per_s": r["iterate_only_iters_per_s"]}
@@ -644,10 +660,10 @@ def main():
         gk = {}
         for name in ("deblur2d", HEADLINE):
             Q = P if name == args.workload else make(name, 0, "full")
-            gk[name] = bench_gks(G, torch, np, Q)
+            gk[name] = bench_gks(G, torch, np, Q, order=order)
             log(f"gks vs sgks {name}: {gk[name]['sgks_speedup_per_expansion']:.2f}x per expansion")
         out["gks_vs_sgks"] = gk
-        out["batched_vs_plain"] = bench_batch(G, torch, np, make, batch_refs)
+        out["batched_vs_plain"] = bench_batch(G, torch, np, make, batch_refs, order=order)
         log("batched comparison done")
     if pool is not None:
         log("oracle on the host ...")

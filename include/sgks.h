@@ -140,6 +140,16 @@ typedef struct {
                                 (cached per operator shape in the process); 0 = choose from
                                 nnz/row and a fixed tile count (default)                        */
     int32_t method;          /* SGKS_METHOD_SGKS (default) or SGKS_METHOD_GKS (see above)      */
+    const int32_t *order;    /* NULL (default) or device array of n int32: a permutation of the
+                                unknowns the context works in internally, order[i] = the
+                                caller's unknown at internal position i (e.g. pixels along a
+                                space-filling curve, so that the rows of A and L gather nearby
+                                entries).  The columns of A and L are relabelled once at create
+                                (4 (nnz(A) + nnz(L)) more bytes of device memory; the values
+                                stay the caller's); results are unchanged up to rounding order,
+                                and every output (x_k, W) and input (grad_x) is in the caller's
+                                order.  SGKS_ERR_INVALID_ARG at create if it is not a
+                                permutation of [0, n).  Borrowed until sgks_destroy.          */
     void *stream;            /* hipStream_t the work is enqueued on (NULL = default stream)   */
     void *workspace;         /* NULL: the context allocates its device memory (one hipMalloc in
                                 sgks_create, freed by sgks_destroy).  Else device memory of
@@ -280,14 +290,16 @@ const char *sgks_strerror(int code);
 #define SGKS_MAX_BATCH 64
 
 /* One problem of a batch: operators, right-hand side (device, value_dtype of
- * the options), mu > 0, sketch size s and seed, as the arguments of
- * sgks_create. */
+ * the options), mu > 0, sketch size s, seed and order of unknowns, as the
+ * arguments and the order option of sgks_create (the options' order is not
+ * used by batches). */
 typedef struct {
     sgks_csr A, L;
     const void *b;
     double mu;
     int32_t sketch_rows;
     uint64_t seed;
+    const int32_t *order;    /* the problem's internal order of unknowns, as sgks_options.order */
 } sgks_problem;
 
 typedef struct sgks_batch sgks_batch;

@@ -438,6 +438,9 @@ struct sgks_ctx {
     double* init_norms;  // copy of the scalars after the initial basis (checked at the end of create)
     int16_t* patA = nullptr;
     int16_t* patL = nullptr;
+    int32_t* colA2 = nullptr;   // columns of A and L in the internal order of the unknowns
+    int32_t* colL2 = nullptr;
+    int* order_flag = nullptr;  // set on the device if the order is not a permutation
     std::vector<int32_t> srtt_rows;   // the SRTT frequencies of both sides (host copy)
     void* sort_scratch = nullptr;   // transpose sort scratch when W (and HW) are too small
     size_t sort_bytes = 0;
@@ -605,6 +608,11 @@ void layout_context(sgks_ctx* c, Arena& ar) {
     const bool sparse = S.sketch_mode == SGKS_SKETCH_SPARSE_SIGN;
     const int regions = 2 * S.passes + 2;
     const int CW = 2 * dmax + 8;
+    if (c->opt.order) {
+        ar.add(&c->colA2, S.A.nnz * 4);
+        ar.add(&c->colL2, S.L.nnz * 4);
+        ar.add(&c->order_flag, 64);
+    }
     ar.add(&c->At_rowptr, (S.n + 1) * 4);
     ar.add(&c->At_col, S.A.nnz * 4);
     ar.add((char**)&c->At_val, S.A.nnz * vsz);
@@ -708,6 +716,7 @@ void sgks_default_options(sgks_options* o) {
     o->autotune = 0;
     o->gradient_form = SGKS_GRADIENT_MAINTAINED;
     o->method = SGKS_METHOD_SGKS;
+    o->order = nullptr;
     o->workspace = nullptr;
     o->workspace_bytes = 0;
     o->stream = nullptr;
@@ -837,6 +846,19 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
         ar.place((char*)c->opt.workspace);
     } else {
         SGKS_TRY(ar.commit(c));
+    }
+    if (c->opt.order) {
+        // internal order of the unknowns: relabel the columns of A and L (the
+        // inverse permutation lives in x until the first iterate)
+        SGKS_TRY(hipMemsetAsync(c->order_flag, 0, 64, c->st));
+        if (sgks::order_setup(c->opt.order, S.n, (int32_t*)S.x, c->order_flag, S.A, c->colA2,
+                              S.L, c->colL2, c->st)) {
+            sgks_destroy(c);
+            return SGKS_ERR_HIP;
+        }
+        S.A.col = c->colA2;
+        S.L.col = c->colL2;
+        S.perm = c->opt.order;
     }
     // sort scratch: W (and HW) before they are used, or its own piece
     void* sbase = c->sort_bytes ? c->sort_scratch : (void*)S.W;
@@ -985,7 +1007,14 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
     int stw = 0;
     SGKS_TRY(hipMemcpyAsync(sc.data(), c->init_norms, sc.size() * 8, hipMemcpyDeviceToHost, st));
     SGKS_TRY(hipMemcpyAsync(&stw, S.status, sizeof(int), hipMemcpyDeviceToHost, st));
+    int bad_order = 0;
+    if (c->order_flag)
+        SGKS_TRY(hipMemcpyAsync(&bad_order, c->order_flag, sizeof(int), hipMemcpyDeviceToHost, st));
     SGKS_TRY(hipStreamSynchronize(st));
+    if (bad_order) {
+        sgks_destroy(c);
+        return SGKS_ERR_INVALID_ARG;
+    }
     int err = SGKS_OK;
     const double bn2 = sc[2], r0 = sc[0];
     if (!(bn2 < INFINITY))
@@ -1027,7 +1056,7 @@ int sgks_iterate(sgks_ctx* c, int32_t k) {
 int sgks_solution(sgks_ctx* c, double* x_dev) {
     if (!c || !x_dev) return SGKS_ERR_INVALID_ARG;
     Phase ph(&c->prof, 0);
-    sgks::launch_gemv(c->S, c->S.y, x_dev, nullptr, -1, c->st);
+    sgks::launch_solution(c->S, x_dev, c->st);
     return hipGetLastError() == hipSuccess ? SGKS_OK : SGKS_ERR_HIP;
 }
 
@@ -1066,6 +1095,10 @@ int sgks_backward(sgks_ctx* c, const double* grad_x, double* grad_b, double* gra
     if (c->opt.refine_steps > 0 || c->S.method == SGKS_METHOD_GKS) return SGKS_ERR_INVALID_ARG;
     State& S = c->S;
     hipStream_t st = c->st;
+    if (S.perm) {
+        sgks::launch_gather_perm(grad_x, S.perm, S.n, S.rtmp, st);
+        grad_x = S.rtmp;
+    }
     sgks::launch_gemvt(S, grad_x, -1, st);
     sgks::launch_backward_small(S, c->sbuf, S.scal + 11, st);
     sgks::launch_sketch_transpose(S, c->sbuf, grad_b, st);
@@ -1242,6 +1275,7 @@ bool batch_sizes(int32_t count, const sgks_problem* probs, const sgks_options& o
         sgks_options oi = o;
         oi.workspace = nullptr;
         oi.workspace_bytes = 0;
+        oi.order = probs[i].order;
         sizes[i] = sgks_workspace_bytes(&probs[i].A, &probs[i].L, probs[i].sketch_rows, &oi);
         if (!sizes[i]) return false;
     }
@@ -1313,6 +1347,7 @@ int sgks_batch_create(int32_t count, const sgks_problem* probs, const sgks_optio
     for (int i = 0; i < count; ++i) {
         sgks_ctx* c = nullptr;
         sgks_options oi = o;
+        oi.order = probs[i].order;
         if (ws) {
             oi.workspace = ws + offs[i];
             oi.workspace_bytes = round256(sizes[i]);

@@ -98,6 +98,7 @@ struct State {
 
     Csr A, At, L, Lt;
 
+    const int32_t* perm; // internal order of the unknowns: perm[i] = caller's index (null: same)
     const double* b;   // m
     double* x;         // n
     double* u;         // m
@@ -229,6 +230,15 @@ void launch_residual_small(const State& S, double* out2, hipStream_t st);
 void launch_backward_small(const State& S, double* v_out, double* gmu_out, hipStream_t st);
 void launch_sketch_transpose(const State& S, const double* v, double* out, hipStream_t st);
 int launch_copy_scaled_W(const State& S, double* dst, hipStream_t st);  // 0 or -1
+// x_k = W y into out in the caller's order of the unknowns
+void launch_solution(const State& S, double* out, hipStream_t st);
+// inverse of a caller's order (flag: 1 if it is not a permutation) and the
+// relabelled column indices of A and L
+int order_setup(const int32_t* order, int64_t n, int32_t* inv, int* flag, const Csr& A,
+                int32_t* colA, const Csr& L, int32_t* colL, hipStream_t st);
+// out[i] = in[perm[i]]
+void launch_gather_perm(const double* in, const int32_t* perm, int64_t n, double* out,
+                        hipStream_t st);
 // columns [col0, col0 + ncols) of W scaled by cs into dst (n x ncols, column-major)
 void launch_scaled_W_cols(const State& S, int col0, int ncols, double* dst, hipStream_t st);
 // one workgroup reducing nb x s partial bins as a side append does (autotuning)

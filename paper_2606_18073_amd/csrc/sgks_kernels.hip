@@ -863,13 +863,14 @@ __global__ __launch_bounds__(kBlock) void k_srtt_transpose(const double* __restr
 // dense basis products
 // ---------------------------------------------------------------------------
 
-// out = [base -] sum_j W[:, j] * cs[j] * coef[j], j < d (grid-stride rows)
+// out[perm[i]] = [base[i] -] sum_j W[i, j] * cs[j] * coef[j], j < d (grid-stride
+// rows; perm null: the identity)
 __device__ __forceinline__ void gemv_body(const double* __restrict__ W,
                                           const double* __restrict__ cs,
                                           const double* __restrict__ coef, int d, int64_t n,
                                           const double* __restrict__ base,
                                           double* __restrict__ out, int blk, int nblk,
-                                          double* yt) {
+                                          double* yt, const int32_t* __restrict__ perm = nullptr) {
     for (int j = threadIdx.x; j < d; j += kBlock) yt[j] = cs[j] * coef[j];
     __syncthreads();
     for (int64_t i = (int64_t)blk * kBlock + threadIdx.x; i < n; i += (int64_t)nblk * kBlock) {
@@ -884,7 +885,7 @@ __device__ __forceinline__ void gemv_body(const double* __restrict__ W,
             for (int u = 0; u < 8; ++u) acc += v[u] * yt[j + u];
         }
         for (; j < d; ++j) acc += w[(int64_t)j * n] * yt[j];
-        out[i] = base ? base[i] - acc : acc;
+        out[perm ? (int64_t)perm[i] : i] = base ? base[i] - acc : acc;
     }
 }
 
@@ -893,10 +894,11 @@ __global__ __launch_bounds__(kBlock) void k_gemv(const double* __restrict__ W,
                                                 const double* __restrict__ coef, const int* dptr,
                                                 int ncols_fixed, int64_t n,
                                                 const double* __restrict__ base,
-                                                double* __restrict__ out) {
+                                                double* __restrict__ out,
+                                                const int32_t* __restrict__ perm) {
     __shared__ double yt[kMaxD];
     const int d = ncols_fixed >= 0 ? ncols_fixed : *dptr;
-    gemv_body(W, cs, coef, d, n, base, out, (int)blockIdx.x, (int)gridDim.x, yt);
+    gemv_body(W, cs, coef, d, n, base, out, (int)blockIdx.x, (int)gridDim.x, yt, perm);
 }
 
 // Iteration form: x = W y on the current d columns.
@@ -2058,14 +2060,56 @@ __global__ __launch_bounds__(kBlock) void k_sketch_transpose(const double* __res
     }
 }
 
-// dst[i + j n] = W[i + j n] * cs[j]
+// dst[perm[i] + j n] = W[i + j n] * cs[j] (perm null: the identity)
 __global__ __launch_bounds__(kBlock) void k_scaled_W(const double* __restrict__ W,
                                                     const double* __restrict__ cs, int64_t n,
-                                                    int d, double* __restrict__ dst) {
+                                                    int d, double* __restrict__ dst,
+                                                    const int32_t* __restrict__ perm) {
     const int64_t total = n * (int64_t)d;
     for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < total;
+         k += (int64_t)gridDim.x * kBlock) {
+        const int64_t j = k / n, i = k - j * n;
+        dst[(perm ? (int64_t)perm[i] : i) + j * n] = W[k] * cs[j];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// internal order of the unknowns (a caller's permutation, e.g. along a
+// space-filling curve of the image): order[i] = the caller's unknown at
+// internal position i.  The columns of A and L are relabelled once at create
+// (the values stay the caller's), so the transposes, W, H W and x are kept in
+// the internal order; only the outputs (x_k, W) and the backward's input map
+// back.
+// ---------------------------------------------------------------------------
+
+// inv[order[i]] = i; flag gets 1 if order is not a permutation of [0, n)
+__global__ __launch_bounds__(kBlock) void k_invert_order(const int32_t* __restrict__ order,
+                                                        int64_t n, int32_t* __restrict__ inv,
+                                                        int* flag) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        const int32_t o = order[i];
+        if (o < 0 || (int64_t)o >= n || atomicCAS(&inv[o], -1, (int32_t)i) != -1)
+            atomicOr(flag, 1);
+    }
+}
+
+// col2[k] = inv[col[k]]
+__global__ __launch_bounds__(kBlock) void k_relabel(const int32_t* __restrict__ col, int64_t nnz,
+                                                   const int32_t* __restrict__ inv,
+                                                   int32_t* __restrict__ col2) {
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < nnz;
          k += (int64_t)gridDim.x * kBlock)
-        dst[k] = W[k] * cs[k / n];
+        col2[k] = inv[col[k]];
+}
+
+// out[i] = in[perm[i]] (the caller's order into the internal one)
+__global__ __launch_bounds__(kBlock) void k_gather_perm(const double* __restrict__ in,
+                                                       const int32_t* __restrict__ perm,
+                                                       int64_t n, double* __restrict__ out) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        out[i] = in[perm[i]];
 }
 
 // ---------------------------------------------------------------------------
@@ -2285,7 +2329,33 @@ int hw_blocks(const State& S) {
 void launch_gemv(const State& S, const double* coef, double* out, const double* base,
                  int ncols_fixed, hipStream_t st) {
     SGKS_LAUNCH(k_gemv, dim3(gemv_blocks(S)), dim3(kBlock), 0, st, S.W, S.cs, coef, S.d,
-                       ncols_fixed, S.n, base, out);
+                       ncols_fixed, S.n, base, out, (const int32_t*)nullptr);
+}
+
+void launch_solution(const State& S, double* out, hipStream_t st) {
+    SGKS_LAUNCH(k_gemv, dim3(gemv_blocks(S)), dim3(kBlock), 0, st, S.W, S.cs, S.y, S.d, -1, S.n,
+                (const double*)nullptr, out, S.perm);
+}
+
+int order_setup(const int32_t* order, int64_t n, int32_t* inv, int* flag, const Csr& A,
+                int32_t* colA, const Csr& L, int32_t* colL, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, st, inv, n,
+                       -1);
+    hipLaunchKernelGGL(k_invert_order, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, st,
+                       order, n, inv, flag);
+    if (A.nnz > 0)
+        hipLaunchKernelGGL(k_relabel, dim3(grid_for(A.nnz, kBlock, 16384)), dim3(kBlock), 0, st,
+                           A.col, A.nnz, (const int32_t*)inv, colA);
+    if (L.nnz > 0)
+        hipLaunchKernelGGL(k_relabel, dim3(grid_for(L.nnz, kBlock, 16384)), dim3(kBlock), 0, st,
+                           L.col, L.nnz, (const int32_t*)inv, colL);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+void launch_gather_perm(const double* in, const int32_t* perm, int64_t n, double* out,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_gather_perm, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, st, in,
+                       perm, n, out);
 }
 
 void launch_gemvt(const State& S, const double* v, int ncols_fixed, hipStream_t st) {
@@ -2375,7 +2445,7 @@ void launch_scaled_W_cols(const State& S, int col0, int ncols, double* dst, hipS
     if (ncols <= 0) return;
     const int nb = grid_for(S.n * (int64_t)ncols, kBlock, 8192);
     hipLaunchKernelGGL(k_scaled_W, dim3(nb), dim3(kBlock), 0, st, S.W + (int64_t)col0 * S.n,
-                       S.cs + col0, S.n, ncols, dst);
+                       S.cs + col0, S.n, ncols, dst, S.perm);
 }
 
 int launch_copy_scaled_W(const State& S, double* dst, hipStream_t st) {
@@ -2385,7 +2455,7 @@ int launch_copy_scaled_W(const State& S, double* dst, hipStream_t st) {
         return -1;
     if (dh <= 0) return 0;
     const int nb = grid_for(S.n * (int64_t)dh, kBlock, 8192);
-    hipLaunchKernelGGL(k_scaled_W, dim3(nb), dim3(kBlock), 0, st, S.W, S.cs, S.n, dh, dst);
+    hipLaunchKernelGGL(k_scaled_W, dim3(nb), dim3(kBlock), 0, st, S.W, S.cs, S.n, dh, dst, S.perm);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

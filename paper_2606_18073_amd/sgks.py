@@ -54,6 +54,7 @@ class Options(ctypes.Structure):
                 ("lanes_At", ctypes.c_int32), ("append_groups", ctypes.c_int32),
                 ("graph", ctypes.c_int32), ("gradient_form", ctypes.c_int32),
                 ("autotune", ctypes.c_int32), ("method", ctypes.c_int32),
+                ("order", ctypes.c_void_p),
                 ("stream", ctypes.c_void_p),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
 
@@ -61,7 +62,7 @@ class Options(ctypes.Structure):
 class ProblemStruct(ctypes.Structure):
     _fields_ = [("A", CsrStruct), ("L", CsrStruct), ("b", ctypes.c_void_p),
                 ("mu", ctypes.c_double), ("sketch_rows", ctypes.c_int32),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("order", ctypes.c_void_p)]
 
 
 MAX_BATCH = 64
@@ -208,7 +209,7 @@ class SGKS:
     """One sGKS solve on the GPU: sgks_create / sgks_iterate / sgks_solution / ..."""
 
     def __init__(self, A: DeviceCsr, L: DeviceCsr, b, mu, s, seed=0, *, ell=3, stream=None,
-                 workspace=None, **opts):
+                 workspace=None, order=None, **opts):
         import torch
         self._lib = load_library()
         self.A, self.L, self.b = A, L, b
@@ -224,6 +225,10 @@ class SGKS:
             self._workspace = workspace
             o.workspace = ctypes.c_void_p(workspace.data_ptr())
             o.workspace_bytes = workspace.numel() * workspace.element_size()
+        if order is not None:
+            # the internal order of the unknowns (device int32, kept alive with the context)
+            self._order = order.to(device=b.device, dtype=torch.int32).contiguous()
+            o.order = ctypes.c_void_p(self._order.data_ptr())
         self.options = o
         self._owner = None
         self.mu, self.s, self.seed, self.ell = float(mu), int(s), int(seed), int(ell)
@@ -388,7 +393,7 @@ class SGKSBatch:
             hdl = self._lib.sgks_batch_get(self._h, int(i))
             if not hdl:
                 raise IndexError(i)
-            A, L, b, mu, s, seed = self.problems[i]
+            A, L, b, mu, s, seed = self.problems[i][:6]
             self._views[i] = SGKS._borrowed(self, hdl, A, L, b, mu, s, seed, self.ell,
                                             self.stream)
         return self._views[i]
@@ -423,11 +428,15 @@ class SGKSBatch:
 
 
 def _problem_array(problems):
+    """problems: (A, L, b, mu, s, seed[, order]) tuples; order a device int32 tensor."""
     arr = (ProblemStruct * len(problems))()
-    for i, (A, L, b, mu, s, seed) in enumerate(problems):
+    for i, pr in enumerate(problems):
+        A, L, b, mu, s, seed = pr[:6]
         arr[i].A, arr[i].L = A.struct(), L.struct()
         arr[i].b = b.data_ptr()
         arr[i].mu, arr[i].sketch_rows, arr[i].seed = float(mu), int(s), int(seed)
+        if len(pr) > 6 and pr[6] is not None:
+            arr[i].order = pr[6].data_ptr()
     return arr
 
 
@@ -465,12 +474,19 @@ def upload_problem(P, device="cuda"):
     return A, L, b
 
 
-def upload_batch(Ps, device="cuda"):
-    """(A, L, b, mu, s, seed) tuples of device data for a list of workloads.Problem."""
+def upload_batch(Ps, device="cuda", orders=None):
+    """(A, L, b, mu, s, seed[, order]) tuples of device data for a list of
+    workloads.Problem; orders: host int32 arrays (or None) of the unknowns' order."""
+    import torch
     out = []
-    for P in Ps:
+    for i, P in enumerate(Ps):
         A, L, b = upload_problem(P, device)
-        out.append((A, L, b, P.mu, P.s, P.seed))
+        o = orders[i] if orders is not None else None
+        if o is None:
+            out.append((A, L, b, P.mu, P.s, P.seed))
+        else:
+            out.append((A, L, b, P.mu, P.s, P.seed,
+                        torch.as_tensor(o, dtype=torch.int32, device=device)))
     return out
 
 

@@ -133,7 +133,8 @@ int main(void) {
            offsetof(sgks_problem, seed));
     printf("%zu %zu\n", sizeof(sgks_csr), offsetof(sgks_problem, sketch_rows));
     printf("%zu %zu\n", offsetof(sgks_options, workspace), offsetof(sgks_options, workspace_bytes));
-    printf("%zu\n", offsetof(sgks_options, method));
+    printf("%zu %zu\n", offsetof(sgks_options, method), offsetof(sgks_options, order));
+    printf("%zu\n", offsetof(sgks_problem, order));
     return 0;
 }
 """
@@ -151,7 +152,8 @@ def test_struct_layouts_match_the_header(tmp_path):
     O, P = G.Options, G.ProblemStruct
     assert got == [ctypes.sizeof(O), O.graph.offset, O.stream.offset, ctypes.sizeof(P),
                    P.b.offset, P.seed.offset, ctypes.sizeof(G.CsrStruct), P.sketch_rows.offset,
-                   O.workspace.offset, O.workspace_bytes.offset, O.method.offset]
+                   O.workspace.offset, O.workspace_bytes.offset, O.method.offset,
+                   O.order.offset, P.order.offset]
 
 
 def test_workspace_bytes_host_only(lib):

@@ -122,3 +122,16 @@ def test_small_configs_are_seeded(name):
     if P1.dtype == "f32":
         assert np.array_equal(P1.A.data, P1.A.data.astype(np.float32).astype(np.float64))
         assert np.array_equal(P1.b, P1.b.astype(np.float32).astype(np.float64))
+
+
+def test_morton_order_is_a_local_permutation():
+    """The Morton order is a permutation; each 4 x 4 block of a frame takes 16 consecutive
+    positions (the curve's locality), frames stay outermost."""
+    from workloads.generators import morton_order
+    N, nt = 16, 3
+    o = morton_order(N, nt)
+    assert sorted(o.tolist()) == list(range(N * N * nt))
+    first = o[:16]
+    ys, xs = first // N, first % N
+    assert set(zip(ys.tolist(), xs.tolist())) == {(y, x) for y in range(4) for x in range(4)}
+    assert set((o[N * N:2 * N * N] // (N * N)).tolist()) == {1}

@@ -448,6 +448,34 @@ def dynamic_ct(seed=0, nt=30, N=128, n_angles=60, n_det=182, k=200, s=800, mu=1e
 
 
 # ----------------------------------------------------------------------------
+# an order of the unknowns along a space-filling curve (Morton, per frame):
+# neighbouring pixels get neighbouring positions, so the rows of A and L gather
+# entries that share cache lines
+# ----------------------------------------------------------------------------
+
+def morton_order(N, nt=1):
+    """order[i] = the row-major unknown (frame-major, then y, then x) at position i when
+    each N x N frame is traversed along the Morton (Z) curve."""
+    idx = np.arange(N * N, dtype=np.int64)
+    y, x = idx // N, idx % N
+    key = np.zeros(N * N, dtype=np.int64)
+    for bit in range(16):
+        key |= ((x >> bit) & 1) << (2 * bit)
+        key |= ((y >> bit) & 1) << (2 * bit + 1)
+    frame = np.argsort(key, kind="stable")
+    return np.concatenate([t * N * N + frame for t in range(nt)]).astype(np.int32)
+
+
+def image_order(P):
+    """The Morton order of the unknowns of an image problem (None for the 1D deblurring)."""
+    N = P.meta.get("N")
+    if N is None:
+        return None
+    nt = P.meta.get("nt", 1)
+    return morton_order(N, nt) if N * N * nt == P.n else None
+
+
+# ----------------------------------------------------------------------------
 # the paper's experiment shapes (Sec. 4.2.1, Sec. 4.2.2, Sec. 4.3) on synthetic data
 # ----------------------------------------------------------------------------
 

@@ -117,13 +117,15 @@ def expected_launches(P, form="maintained", fused_hw=False, backward=False):
         add("sketch_scatter", launch_bytes(P, "sketch_scatter"))
         # the append launch: with the H W adjoint inside it, that adjoint's bytes
         add("qr_append_solve", launch_bytes(P, "adjoint") if fused_hw else 0)
-        for _ in range(ir):
-            if form == "maintained":
-                add("gemv", launch_bytes(P, "gradient", d + 1))
-            else:
-                add("gemv", launch_bytes(P, "gemv", d + 1))
-                add("forward_Ax_Lx", launch_bytes(P, "forward_Ax_Lx"))
-                add("adjoint", launch_bytes(P, "adjoint"))
+        if form == "maintained" and ir:
+            # the new column of W^T H W (the d + 1 columns of W against the new H W
+            # column), then every refinement step on the small matrix in one launch
+            add("gemvt_WTr", launch_bytes(P, "gemvt", d + 1))
+            add("refine_step", 0)
+        for _ in range(ir if form != "maintained" else 0):
+            add("gemv", launch_bytes(P, "gemv", d + 1))
+            add("forward_Ax_Lx", launch_bytes(P, "forward_Ax_Lx"))
+            add("adjoint", launch_bytes(P, "adjoint"))
             add("gemvt_WTr", launch_bytes(P, "gemvt", d + 1))
             add("refine_step", 0)
     add("gemv", launch_bytes(P, "gemv", ell + k))       # x_k = W y
@@ -141,9 +143,9 @@ def phase_kernel(phase, tuning, fused_hw, form="maintained"):
     if phase == "sketch_scatter":
         return "kb_scatter"
     if phase == "gemvt_WTr":
-        return "kb_gemvt"
+        return "kb_mcol" if form == "maintained" else "kb_gemvt"
     if phase == "refine_step":
-        return "k_refine"
+        return "k_mrefine" if form == "maintained" else "k_refine"
     if phase == "qr_append_solve":
         if (tuning or {}).get("append_groups", 1) == 1:
             return "k_ap1_side_hw" if fused_hw else "k_ap1_side"
@@ -408,7 +410,50 @@ def describe(P):
                 f"{m['n_det']} detectors (m={P.m}), Siddon CSR nnz={P.A.nnz} ({P.dtype} values), "
                 f"L=[Dx;Dy] nnz={P.L.nnz}, s={P.s}, k={P.k}, {P.refine_steps} refinement steps "
                 f"per projected solve; one step = create + {P.k} expansions + x_k")
+    if P.name == "ct_exp2":
+        return (f"Exp. 2 shape: {m['N']}x{m['N']} parallel-beam CT (n={P.n}), {m['n_angles']} "
+                f"angles x {m['n_det']} detectors (m={P.m}), nnz={P.A.nnz}, L {P.p}x{P.n}, "
+                f"s={P.s}, k={P.k}, mu={P.mu}; one step = create + {P.k} expansions + x_k")
+    if P.name == "traveltime_exp3":
+        return (f"Exp. 3 shape: {m['N']}x{m['N']} travel-time tomography (n={P.n}), every "
+                f"source-receiver pair a straight ray (m={P.m}), nnz={P.A.nnz}, L {P.p}x{P.n}, "
+                f"s={P.s}, k={P.k}, mu={P.mu}; one step = create + {P.k} expansions + x_k")
+    if P.name == "dynamic_ct_exp4":
+        return (f"Exp. 4 shape: {m['nt']} frames of {m['N']}x{m['N']} (n={P.n}), "
+                f"{m['n_angles']} angles per frame in its own sector x {m['n_det']} detectors "
+                f"(m={P.m}), nnz={P.A.nnz}, space-time L {P.p}x{P.n} nnz={P.L.nnz}, s={P.s}, "
+                f"k={P.k}, mu={P.mu}; one step = create + {P.k} expansions + x_k")
     return P.name
+
+
+# the paper's sGKS totals for its Exp. 3 and Exp. 4 (context only, see PAPER_CONTEXT)
+PAPER_TOTALS = {"traveltime_exp3": PAPER_CONTEXT["exp3_travel_time_n65536"],
+                "dynamic_ct_exp4": PAPER_CONTEXT["exp4_dynamic_ct_n655360"]}
+
+
+def bench_paper_scale(G, torch, make, order=True):
+    """The paper's experiment shapes at full size (synthetic data): whole solves."""
+    from workloads.generators import PAPER_SCALE
+    out = {}
+    for name in PAPER_SCALE:
+        Q = make(name, 0, "full")
+        try:
+            r = measure(G, torch, Q, 2, 1, backward=False, profile=False, order=order)
+        except Exception as e:      # reported, never fatal to the measurement
+            out[name] = {"workload": describe(Q), "error": repr(e)}
+            continue
+        if "solver" in r:
+            r["solver"].close()
+        ent = {"workload": describe(Q), "value": r["value"], "unit": "iters/s",
+               "ms_per_solve": r["ms_per_step"], "setup_ms": r["setup_ms_per_step"],
+               "iterate_only_iters_per_s": r["iterate_only_iters_per_s"],
+               "rre_gpu": float(((r["x"] - Q.x_true) ** 2).sum() ** 0.5 /
+                                (Q.x_true ** 2).sum() ** 0.5)}
+        if name in PAPER_TOTALS:
+            ent["paper_context"] = dict(PAPER_TOTALS[name], note=PAPER_CONTEXT["note"])
+        out[name] = ent
+        log(f"paper scale {name}: {r['value']:.1f} iters/s")
+    return out
 
 
 def bench_gks(G, torch, np, P, steps=2, order=True):
@@ -450,8 +495,9 @@ def bench_gks(G, torch, np, P, steps=2, order=True):
     return out
 
 
-def bench_batch(G, torch, np, make, oracle_refs, order=True):
-    """The 32-problem uneven batch: one batched solve against the 32 plain solves."""
+def bench_batch(G, torch, np, make, oracle_refs, order=True, plain=True):
+    """The 32-problem uneven batch: one batched solve against the 32 plain solves
+    (plain=False: the batched solve only)."""
     from workloads.generators import image_order
     Ps = make("batch", 0, "full")
     data = G.upload_batch(Ps, orders=[image_order(P) for P in Ps] if order else None)
@@ -473,7 +519,7 @@ def bench_batch(G, torch, np, make, oracle_refs, order=True):
     B.close()
     setup_p = iter_p = 0.0
     same = True
-    for i, pr in enumerate(data):
+    for i, pr in enumerate(data if plain else []):
         A, L, b, mu, s, seed = pr[:6]
         torch.cuda.synchronize()
         u0 = time.perf_counter()
@@ -498,6 +544,11 @@ def bench_batch(G, torch, np, make, oracle_refs, order=True):
     for P in Ps:
         ex = expected_launches(P, "maintained", False)
         bulk += sum(sum(v) for v in ex.values())
+    if not plain:
+        return {"workload": f"{len(Ps)} problems, batched solve only", "problem_iterations": total,
+                "batched_iters_per_s": total / (t2 - t0),
+                "batched_iterate_only_iters_per_s": total / (t2 - t1),
+                "batched_setup_ms": 1e3 * (t1 - t0), "sample_rel_err_vs_oracle": errs}
     return {
         "workload": (f"{len(Ps)} problems (deblurring / CT / travel time, sides 64..256 "
                      f"log-uniform, own mu), total n={sum(P.n for P in Ps)}, total nnz(A)="
@@ -562,6 +613,8 @@ def main():
     ap.add_argument("--no-order", action="store_true",
                     help="work in the caller's row-major order of the unknowns instead of "
                          "the Morton order of each image frame")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="with --workload batch: time the batched solve only (no plain solves)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -578,7 +631,7 @@ def main():
         pool = mp.get_context("spawn").Pool(processes=max(2, nwork))
         full_ref = pool.apply_async(_oracle_full, (args.workload,))
         batch_refs = {}
-        if not args.no_extras:
+        if not args.no_extras or args.workload == "batch":
             for i in (24, 10, 23):       # the smallest deblurring, CT and travel-time problems
                 batch_refs[i] = pool.apply_async(_oracle_batch_problem, (i, 80))
     else:
@@ -589,6 +642,23 @@ def main():
 
     from paper_2606_18073_amd import sgks as G
     from workloads import make
+
+    if args.workload == "batch":
+        # the uneven batch on its own (for its profiles): one batched solve, then its
+        # 32 plain solves
+        b = bench_batch(G, torch, np, make, batch_refs, order=not args.no_order,
+                        plain=not args.no_plain)
+        if pool is not None:
+            pool.close()
+            pool.join()
+        print(json.dumps({
+            "metric": "sGKS problem-iterations/s of the batched solve", "value":
+            b["batched_iters_per_s"], "unit": "iters/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+            "ms_per_step": b["problem_iterations"] / b["batched_iters_per_s"] * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic", "config": {"workload": b["workload"]}, "batched_vs_plain": b}),
+            flush=True)
+        return
 
     P = make(args.workload, 0, "full")
     backward = args.workload == HEADLINE
@@ -665,6 +735,7 @@ def main():
         out["gks_vs_sgks"] = gk
         out["batched_vs_plain"] = bench_batch(G, torch, np, make, batch_refs, order=order)
         log("batched comparison done")
+        out["paper_scale"] = bench_paper_scale(G, torch, make, order=order)
     if pool is not None:
         log("oracle on the host ...")
         xo, dt_full, it_full = full_ref.get()

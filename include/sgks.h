@@ -126,7 +126,7 @@ typedef struct {
     int32_t lanes_At;        /* lanes per row for A^T rows; 0 = choose                          */
     int32_t append_groups;   /* QR append: 1 = compact (one launch, one workgroup per sketch
                                 side; the second to finish also updates the stacked factor),
-                                2..32 = chain of kernels on that many workgroups (slabs of
+                                2..256 = chain of kernels on that many workgroups (slabs of
                                 <= 64 sketch rows); 0 = choose by s * dmax                     */
     int32_t graph;           /* 0 = sgks_iterate / sgks_batch_iterate launch kernel by kernel
                                 (default: the faster of the two on MI355X), 1 = replay captured

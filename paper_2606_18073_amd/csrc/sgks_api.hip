@@ -127,17 +127,25 @@ struct Phase {
 
 // Refinement step of every problem of the plan: the gradient r(y) into rtmp,
 // W^T r, y update (heavy ball).
-void enqueue_refine(const sgks::Plan& P, Profiler* pr, hipStream_t st) {
+// The refinement steps after an append (Sec. 3.1: the unsketched projected
+// normal equations, preconditioned by the sketched factor).  Maintained form:
+// the new column of W^T H W from the kept H W column, then all the steps on
+// the d x d matrix in one launch (`steps` = 0 only stores the column).  Direct
+// form: per step x = W y, u = A x - b, t = L x, r = A^T u + mu L^T t, W^T r and
+// the heavy-ball update.
+void enqueue_refinement(const sgks::Plan& P, int steps, Profiler* pr, hipStream_t st) {
     if (P.gradient_form == SGKS_GRADIENT_MAINTAINED) {
-        Phase ph(pr, 0);
-        sgks::plan_gradient(P, true, st);
-    } else {
+        { Phase ph(pr, 5); sgks::plan_mcol(P, st); }
+        { Phase ph(pr, 6); sgks::plan_mrefine(P, steps, st); }
+        return;
+    }
+    for (int r = 0; r < steps; ++r) {
         { Phase ph(pr, 0); sgks::plan_gemv(P, st); }
         { Phase ph(pr, 1); sgks::plan_forward(P, false, st); }
         { Phase ph(pr, 2); sgks::plan_adjoint(P, 1, st); }
+        { Phase ph(pr, 5); sgks::plan_gemvt(P, st); }
+        { Phase ph(pr, 6); sgks::plan_refine(P, st); }
     }
-    { Phase ph(pr, 5); sgks::plan_gemvt(P, st); }
-    { Phase ph(pr, 6); sgks::plan_refine(P, st); }
 }
 
 // One expansion of every problem of the plan (the loop body of Alg. 2): the
@@ -236,7 +244,7 @@ int enqueue_iteration(const sgks::Plan& P, int refine_steps, Profiler* pr, hipSt
         if (sgks::plan_append(P, true, maintained, st)) return SGKS_ERR_HIP;
     }
     if (fork && hipStreamWaitEvent(st, ss->join, 0) != hipSuccess) return SGKS_ERR_HIP;
-    for (int r = 0; r < refine_steps; ++r) enqueue_refine(P, pr, st);
+    if (refine_steps > 0) enqueue_refinement(P, refine_steps, pr, st);
     return SGKS_OK;
 }
 
@@ -574,7 +582,7 @@ int plan_context(sgks_ctx* c, const sgks_csr* A, const sgks_csr* L, double mu, i
     {
         int64_t rpb = (S.n + 511) / 512;
         rpb = ((rpb + 63) / 64) * 64;
-        if (rpb < 256) rpb = 256;
+        if (rpb < 128) rpb = 128;
         if (rpb > 4096) rpb = 4096;   // staged in LDS (32 KiB)
         S.gt_rows = (int)rpb;
         S.ngt = (int)((S.n + rpb - 1) / rpb);
@@ -587,7 +595,7 @@ int plan_context(sgks_ctx* c, const sgks_csr* A, const sgks_csr* L, double mu, i
     {
         const int cap = sgks::max_append_groups();
         int G = c->opt.append_groups;
-        if (G == 0) G = sgks::choose_append_groups(s, dmax, cap);
+        if (G == 0) G = sgks::choose_append_groups(s, dmax, cap, S.A.nnz + S.L.nnz);
         if (G > cap) G = cap;
         if (!sgks::append_groups_ok(s, dmax, G)) return SGKS_ERR_SKETCH_SIZE;
         c->groups = G;
@@ -657,7 +665,11 @@ void layout_context(sgks_ctx* c, Arena& ar) {
     ar.add(&S.wu, 2 * dmax * 8);
     ar.add(&S.pacc, 4 * dmax * 8);
     ar.add(&S.gacc, dmax * 8);
-    ar.add(&S.gpart, (size_t)S.ngt * dmax * 8);
+    ar.add(&S.gpart, (size_t)S.ngt * (dmax + 1) * 8);
+    if (S.gradient_form == SGKS_GRADIENT_MAINTAINED && c->opt.refine_steps > 0) {
+        ar.add(&S.Mnt, (size_t)dmax * dmax * 8);
+        ar.add(&S.cnt, dmax * 8);
+    }
     ar.add(&S.coop, (size_t)regions * c->groups * CW * 8);
     ar.add(&S.scal, (16 + 2 * dmax) * 8);
     ar.add(&S.d, 64);
@@ -998,8 +1010,13 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
             sgks_destroy(c);
             return SGKS_ERR_HIP;
         }
+        // maintained form with refinement: column j of W^T H W (the refinement
+        // steps after the last initial column)
+        if (S.Mnt)
+            enqueue_refinement(c->plan, j + 1 == c->opt.ell ? c->opt.refine_steps : 0, nullptr, st);
     }
-    for (int r = 0; r < c->opt.refine_steps; ++r) enqueue_refine(c->plan, nullptr, st);
+    if (!S.Mnt && c->opt.refine_steps > 0)
+        enqueue_refinement(c->plan, c->opt.refine_steps, nullptr, st);
     c->d_host = c->opt.ell;
 
     // the one synchronisation of the set-up: ||b||^2, the initial norms and the status

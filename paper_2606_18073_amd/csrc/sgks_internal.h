@@ -43,7 +43,7 @@ constexpr int kScatterLdsBytes = 64 * 1024;
 // per range)
 constexpr int kScatterRange = kScatterLdsBytes / 8;
 constexpr int kMaxD = 512;          // largest basis dimension
-constexpr int kAppendThreads = 256; // threads per workgroup of the append chain kernels
+constexpr int kAppendThreads = 512; // threads per workgroup of the append chain kernels
 constexpr int kMaxAppendGroups = 256; // workgroups of the append kernels
 constexpr int kAppendMaxSlab = 64;    // sketch rows per append workgroup
 constexpr int kSketchBlock = 512;   // threads per block of the sketch kernel
@@ -56,8 +56,13 @@ constexpr int kMaxBatch = 64;       // problems of one batched launch
 // of their own at full occupancy
 constexpr int64_t kFuseHWMaxNnz = 12000000;
 // s * dmax up to which the compact append (one workgroup per side) is chosen;
-// beyond, the bandwidth of one compute unit makes the multi-workgroup chain faster
+// beyond, the bandwidth of one compute unit makes the multi-workgroup chain
+// faster.  With the H W adjoint in a launch of its own (larger operators) the
+// chain, which overlaps that launch, wins earlier: measured at s * dmax =
+// 91,800 (CT, 256 x 256) the chain is 4% faster per expansion, at 41,200
+// (deblurring, H W inside the compact launch) the compact append 1.5x.
 constexpr int64_t kCompactAppendMax = 120000;
+constexpr int64_t kCompactAppendMaxSep = 60000;
 
 // sketch kinds inside the library: the public ones, and none (GKS)
 constexpr int kSketchSparseSign = 0, kSketchIdentity = 1, kSketchSrtt = 2, kSketchNone = 3;
@@ -144,7 +149,10 @@ struct State {
     double* wu;        // 2 dmax: working column of the stacked factor
     double* pacc;      // 4 dmax: running sums of the Q projection coefficients, final sums
     double* gacc;      // dmax: running sum of the U projection coefficients
-    double* gpart;     // ngt x dmax partial W^T v sums
+    double* gpart;     // ngt x (dmax + 1) partial W^T v sums
+    double* Mnt;       // dmax x dmax row-major W^T H W, raw columns (maintained form with
+                       // refinement; else null)
+    double* cnt;       // dmax: W[:, i]^T A^T b, raw columns (with Mnt)
     int ngt;
     int gt_rows;       // rows per block of the W^T v kernel
     double* coop;      // partial vectors of the append kernels (regions x (2 dmax + 8) x G)
@@ -223,7 +231,7 @@ int hw_blocks(const State& S);
 void launch_gemvt(const State& S, const double* v, int ncols_fixed, hipStream_t st);
 void launch_reduce_gpart(const State& S, int ncols_fixed, double* out, hipStream_t st);
 void launch_set_scale(const State& S, int col, bool store_r0, hipStream_t st);
-int choose_append_groups(int s, int dmax, int cap);
+int choose_append_groups(int s, int dmax, int cap, int64_t nnz);
 bool append_groups_ok(int s, int dmax, int G);
 void launch_cb(const State& S, hipStream_t st);
 void launch_residual_small(const State& S, double* out2, hipStream_t st);
@@ -280,6 +288,8 @@ int plan_append(const Plan& P, bool scale_from_norm, bool with_hw, hipStream_t s
 bool plan_has_hw_separate(const Plan& P);
 void plan_hw_separate(const Plan& P, hipStream_t st);
 void plan_gemvt(const Plan& P, hipStream_t st);                // W^T rtmp partials
+void plan_mcol(const Plan& P, hipStream_t st);                 // new column of W^T H W
+void plan_mrefine(const Plan& P, int steps, hipStream_t st);   // store it, refinement steps
 // the stacked step alone, after the unsketched QR appends of GKS
 void plan_stack_only(const Plan& P, hipStream_t st);
 

@@ -92,8 +92,14 @@ struct GTri {
 // threads of the block (the others return at once):
 //   trans = 0: out[k] = sum_{j >= k} M(k, j) v[j]
 //   trans = 1: out[k] = sum_{i <= k} M(i, k) v[i]
+// Loads in flight per lane in the small triangular products (latency bound:
+// one workgroup, the matrix in L2).  16 and 32 measured slower than 8 (the
+// one-workgroup append launch 48.3 and 56.4 vs 44.8 us on the deblurring
+// workload): more clamped loads past the row ends and fewer waves.
+constexpr int kTriChunk = 8;
+
 // Groups of tpr lanes share one output, each lane taking every tpr-th term
-// with eight loads in flight; the group sums with shuffles (fixed order, the
+// with kTriChunk loads in flight; the group sums with shuffles (fixed order, the
 // same for every accessor).
 template <class Mat>
 __device__ void tri_mv_t(const Mat& M, int d, int trans, const double* v, double* out,
@@ -107,16 +113,18 @@ __device__ void tri_mv_t(const Mat& M, int d, int trans, const double* v, double
         const int k = base + threadIdx.x / tpr;
         double acc = 0.0;
         if (k < d) {
-            const int lo = trans ? 0 : k, hi = trans ? k + 1 : d;
-            for (int q = lo + c; q < hi; q += 8 * tpr) {
-                double w[8];
+            // trans 0: row k from the diagonal on; 1: column k down to the
+            // diagonal; 2: the whole row k
+            const int lo = trans == 0 ? k : 0, hi = trans == 1 ? k + 1 : d;
+            for (int q = lo + c; q < hi; q += kTriChunk * tpr) {
+                double w[kTriChunk];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
+                for (int u = 0; u < kTriChunk; ++u) {
                     const int idx = min(q + u * tpr, hi - 1);   // clamped: loads stay unconditional
-                    w[u] = trans ? M(idx, k) : M(k, idx);
+                    w[u] = trans == 1 ? M(idx, k) : M(k, idx);
                 }
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
+                for (int u = 0; u < kTriChunk; ++u) {
                     const int idx = q + u * tpr;
                     if (idx < hi) acc += w[u] * v[idx];
                 }
@@ -146,12 +154,12 @@ __device__ void tri_mv2_t(const Mat& M, int d, const double* v1, const double* v
         const int k = base + threadIdx.x / tpr;
         double a1 = 0.0, a2 = 0.0;
         if (k < d) {
-            for (int q = k + c; q < d; q += 8 * tpr) {
-                double w[8];
+            for (int q = k + c; q < d; q += kTriChunk * tpr) {
+                double w[kTriChunk];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) w[u] = M(k, min(q + u * tpr, d - 1));
+                for (int u = 0; u < kTriChunk; ++u) w[u] = M(k, min(q + u * tpr, d - 1));
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
+                for (int u = 0; u < kTriChunk; ++u) {
                     const int idx = q + u * tpr;
                     if (idx < d) {
                         a1 += w[u] * v1[idx];
@@ -187,16 +195,16 @@ __device__ void tri_dot2t_t(const Mat& Ma, const Mat& Mb, int d, const double* v
         const int k = base + threadIdx.x / tpr;
         double acc = 0.0;
         if (k < d) {
-            for (int q = c; q <= k; q += 8 * tpr) {
-                double wa[8], wb[8];
+            for (int q = c; q <= k; q += kTriChunk * tpr) {
+                double wa[kTriChunk], wb[kTriChunk];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
+                for (int u = 0; u < kTriChunk; ++u) {
                     const int i = min(q + u * tpr, k);
                     wa[u] = Ma(i, k);
                     wb[u] = Mb(i, k);
                 }
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
+                for (int u = 0; u < kTriChunk; ++u) {
                     const int i = q + u * tpr;
                     if (i <= k) acc += wa[u] * va[i] + wb[u] * vb[i];
                 }
@@ -219,16 +227,16 @@ __device__ void tri_apply2_t(const Mat& Ma, const Mat& Mb, int d, const double* 
         const int i = base + threadIdx.x / tpr;
         double aa = 0.0, ab = 0.0;
         if (i < d) {
-            for (int q = i + c; q < d; q += 8 * tpr) {
-                double wa[8], wb[8];
+            for (int q = i + c; q < d; q += kTriChunk * tpr) {
+                double wa[kTriChunk], wb[kTriChunk];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
+                for (int u = 0; u < kTriChunk; ++u) {
                     const int k = min(q + u * tpr, d - 1);
                     wa[u] = Ma(i, k);
                     wb[u] = Mb(i, k);
                 }
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
+                for (int u = 0; u < kTriChunk; ++u) {
                     const int k = q + u * tpr;
                     if (k < d) {
                         aa += wa[u] * v[k];
@@ -534,10 +542,14 @@ __global__ __launch_bounds__(kBlock) void kb_adjoint(const State* __restrict__ S
     const Slot sl = find_slot(tab);
     const State S = load_state(SS, sl.p);
     if (dst_kind != kDstRefine && *S.status != 0) return;
+    // the H W column is the one the new-column SpMV recorded: beside the append
+    // chain on another stream, the append may advance d while this grid runs
     double* dst = dst_kind == kDstRefine ? S.rtmp
-                  : dst_kind == kDstHW   ? S.HW + (int64_t)(*S.d) * S.n
+                  : dst_kind == kDstHW   ? S.HW + (int64_t)S.scal[15] * S.n
                                          : S.W + (int64_t)(*S.d) * S.n;
-    adjoint_body<T>(S.At, S.Lt, 1, S.mu, S.u, S.t, dst, S.n, S.norm_part, sl.blk, sl.nblk, red);
+    // the H W column's norm is not needed: no partial sums
+    adjoint_body<T>(S.At, S.Lt, 1, S.mu, S.u, S.t, dst, S.n,
+                    dst_kind == kDstHW ? nullptr : S.norm_part, sl.blk, sl.nblk, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -910,6 +922,7 @@ __global__ __launch_bounds__(kBlock) void kb_gemv(const State* __restrict__ SS, 
 }
 
 // part[blk * ld + j] = cs[j] * sum_{i in the workgroup's rows} W[i, j] v[i], j < d
+// (cs null: no column scale)
 __device__ __forceinline__ void gemvt_body(const double* __restrict__ W,
                                            const double* __restrict__ cs,
                                            const double* __restrict__ v, int d, int64_t n,
@@ -919,13 +932,37 @@ __device__ __forceinline__ void gemvt_body(const double* __restrict__ W,
     const int nr = (int)min((int64_t)rows_per_block, n - r0);
     for (int i = threadIdx.x; i < nr; i += kBlock) vs[i] = v[r0 + i];
     __syncthreads();
+    // each wave takes eight columns at a time; a lane loads its rows (lane + 64 t)
+    // of all eight, four rows per column at a time, every load in flight
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int j = wave; j < d; j += kWaves) {
-        const double* wc = W + (int64_t)j * n + r0;
-        double acc = 0.0;
-        for (int i = lane; i < nr; i += 64) acc += wc[i] * vs[i];
-        acc = wave_sum(acc);
-        if (lane == 0) part[(int64_t)blk * ld + j] = acc * cs[j];
+    const int nt = (nr + 63) / 64;
+    for (int j0 = wave * 8; j0 < d; j0 += kWaves * 8) {
+        const double* wc[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) wc[c] = W + (int64_t)min(j0 + c, d - 1) * n + r0;
+        double acc[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+        for (int t0 = 0; t0 < nt; t0 += 4) {
+            double w[8][4], vv[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int i = min(lane + 64 * (t0 + t), nr - 1);   // clamped; masked below
+                vv[t] = (t0 + t < nt && lane + 64 * (t0 + t) < nr) ? vs[i] : 0.0;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) w[c][t] = wc[c][i];
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int c = 0; c < 8; ++c) acc[c] += w[c][t] * vv[t];
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const double a = wave_sum(acc[c]);
+            if (lane == 0 && j0 + c < d)
+                part[(int64_t)blk * ld + j0 + c] = cs ? a * cs[j0 + c] : a;
+        }
     }
 }
 
@@ -946,6 +983,31 @@ __global__ __launch_bounds__(kBlock) void kb_gemvt(const State* __restrict__ SS,
     const State S = load_state(SS, sl.p);
     if (*S.status != 0) return;
     gemvt_body(S.W, S.cs, S.rtmp, *S.d, S.n, S.gt_rows, S.gpart, S.dmax, sl.blk, vs);
+}
+
+// Partials of the newest column c = d - 1 of the projected normal matrix
+// M = W^T H W (raw columns: W[:, i]^T H W[:, c], i <= c, H W[:, c] the kept
+// column) and of W[:, c]^T W[:, 0] (W[:, 0] = A^T b), into gpart with leading
+// dimension dmax + 1 (slot c + 1 for the second).  The new column's images
+// H W[:, c] are complete: the caller's stream has joined the stream that
+// computed them.
+__global__ __launch_bounds__(kBlock) void kb_mcol(const State* __restrict__ SS, BTab tab) {
+    extern __shared__ double vs[];
+    __shared__ double red[kWaves];
+    const Slot sl = find_slot(tab);
+    const State S = load_state(SS, sl.p);
+    if (*S.status != 0) return;
+    const int c = *S.d - 1;
+    const int ld = S.dmax + 1;
+    gemvt_body(S.W, nullptr, S.HW + (int64_t)c * S.n, c + 1, S.n, S.gt_rows, S.gpart, ld, sl.blk,
+               vs);
+    const int64_t r0 = (int64_t)sl.blk * S.gt_rows;
+    const int nr = (int)min((int64_t)S.gt_rows, S.n - r0);
+    const double* wc = S.W + (int64_t)c * S.n + r0;
+    double a = 0.0;
+    for (int i = threadIdx.x; i < nr; i += kBlock) a += wc[i] * S.W[r0 + i];
+    a = block_sum(a, red);
+    if (threadIdx.x == 0) S.gpart[(int64_t)sl.blk * ld + c + 1] = a;
 }
 
 // out[j] = sum_b part[b * ld + j], j < d
@@ -992,7 +1054,7 @@ __global__ __launch_bounds__(kBlock) void k_cb(const double* __restrict__ bins, 
 // update G^{-1} and y = G^{-1} h.
 // ---------------------------------------------------------------------------
 
-// The append runs as a chain of small kernels, each with G <= 32 workgroups.
+// The append runs as a chain of small kernels, each with G <= 256 workgroups.
 // Workgroup g owns sketch rows [lo, hi) of Q_A and Q_L and rows [ulo, uhi)
 // of both halves of U.  Each kernel finishes the previous projection with the
 // coefficients reduced (in workgroup order) from the previous kernel's
@@ -1008,9 +1070,9 @@ __global__ __launch_bounds__(kBlock) void k_cb(const double* __restrict__ bins, 
 // coefficients (S.pacc[0, 2 dmax), the final p in S.pacc[2 dmax, 4 dmax)) and
 // gacc = sum of the U coefficients (S.gacc).  No workgroup writes memory that
 // another workgroup of the same launch reads; kernel boundaries order the
-// phases, and the basis size d advances in the single-workgroup k_yfix.  Memory traffic is small (the slabs
-// stay in L2); what these kernels pay is latency, so every loop issues its
-// loads in batches.
+// phases, and the basis size d advances in the single-workgroup k_yfix.
+// Memory traffic is small (the slabs stay in L2); what these kernels pay is
+// latency, so every loop issues its loads in batches.
 
 constexpr int kSlots = 8;   // scalar slots after the 2 dmax coefficient slots
 
@@ -1056,82 +1118,102 @@ __device__ __forceinline__ double sum_g(const double* __restrict__ slot, int G) 
     return a;
 }
 
-// partial[j * G + g] = sum_{i < nrows} (Ma[j * ld + i] va[i] + Ml[j * ld + i] vl[i])
-// for j < d (Ml may be null), nrows <= 64.  Lane = row; each wave takes 16
-// columns per batch (all their loads in flight), writes the products to an
-// LDS tile and reduces it transposed: lane l sums 16 rows of column l % 16,
-// then two shuffle levels join the four row groups (fixed order).
-// tile: kAppendThreads / 64 * 16 * 64 doubles of LDS.
-__device__ void slab_dots(const double* __restrict__ Ma, const double* __restrict__ Ml,
-                          int64_t ld, int nrows, int d, const double* va, const double* vl,
-                          double* partial, int g, int G, double* tile) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    if (nrows <= 0 || d <= 0) {
-        for (int j = threadIdx.x; j < d; j += blockDim.x) partial[(int64_t)j * G + g] = 0.0;
-        return;
-    }
-    const int rl = min(lane, nrows - 1);   // clamped row: loads stay unconditional
-    const double a_l = lane < nrows ? va[rl] : 0.0;
-    const double l_l = (Ml && lane < nrows) ? vl[rl] : 0.0;
-    double* tw = tile + wave * 16 * 64;
-    for (int jb = 0; jb < d; jb += 16 * nw) {   // uniform trip count: barriers inside
-        const int j0 = jb + wave * 16;
-        double w[16];
-        if (Ml) {
+// Column dots over a slab of rows of two column-major matrices (leading
+// dimension ld, rows [0, nrows) of each column contiguous):
+//   Joint:  pA[j G + g] = sum_i (MA[j ld + i] vA[i] + ML[j ld + i] vL[i])
+//   !Joint: pA[j G + g] = sum_i MA[j ld + i] vA[i], pL[j G + g] = sum_i ML[j ld + i] vL[i]
+// for j < d.  Thread j owns column j (strided over the workgroup) and loads
+// sixteen rows of each side at a time, all in flight; vA, vL are read from
+// LDS (one address per wave).  Rows are added in order: fixed sums.
+template <bool Joint>
+__device__ void slab_dots2(const double* __restrict__ MA, const double* __restrict__ ML,
+                           int64_t ld, int nrows, int d, const double* vA, const double* vL,
+                           double* pA, double* pL, int g, int G) {
+    __syncthreads();   // vA, vL were just written by other threads
+    for (int j = threadIdx.x; j < d; j += blockDim.x) {
+        const double* __restrict__ ca = MA + (int64_t)j * ld;
+        const double* __restrict__ cl = ML + (int64_t)j * ld;
+        double accA = 0.0, accL = 0.0;
+        for (int i0 = 0; i0 < nrows; i0 += 16) {
+            double wa[16], wl[16];
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
-                const int64_t o = (int64_t)min(j0 + u, d - 1) * ld + rl;
-                w[u] = Ma[o] * a_l + Ml[o] * l_l;
+                const int i = min(i0 + u, nrows - 1);   // clamped: loads stay unconditional
+                wa[u] = ca[i];
+                wl[u] = cl[i];
             }
-        } else {
 #pragma unroll
-            for (int u = 0; u < 16; ++u) w[u] = Ma[(int64_t)min(j0 + u, d - 1) * ld + rl] * a_l;
+            for (int u = 0; u < 16; ++u)
+                if (i0 + u < nrows) {
+                    accA += wa[u] * vA[i0 + u];
+                    if (Joint)
+                        accA += wl[u] * vL[i0 + u];
+                    else
+                        accL += wl[u] * vL[i0 + u];
+                }
         }
-#pragma unroll
-        for (int u = 0; u < 16; ++u)
-            if (j0 + u >= d) w[u] = 0.0;
-#pragma unroll
-        for (int u = 0; u < 16; ++u) tw[u * 64 + lane] = w[u];
-        __syncthreads();
-        const int c = lane & 15, rg = lane >> 4;
-        double acc = 0.0;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) acc += tw[c * 64 + rg * 16 + k];
-        acc += __shfl_xor(acc, 16);
-        acc += __shfl_xor(acc, 32);
-        if (lane < 16 && j0 + c < d) partial[(int64_t)(j0 + c) * G + g] = acc;
-        __syncthreads();
+        pA[(int64_t)j * G + g] = accA;
+        if (!Joint) pL[(int64_t)j * G + g] = accL;
     }
 }
 
-// out[i] -= sum_j M[j * ld + i] c[j], i < nrows (M global, column-major slab;
-// c, out in LDS).  Threads split rows and contiguous chunks of j; the chunk
-// sums are added in chunk order.
+// outA[i] -= sum_j MA[j ld + i] cA[j] and outL[i] -= sum_j ML[j ld + i] cL[j]
+// for i < nrows (MA, ML global column-major slabs; cA, cL, outA, outL in LDS).
+// The two sides take the two halves of the workgroup; within a side, threads
+// split the rows and contiguous chunks of j, and the chunk sums are added in
+// chunk order.  scratch: blockDim.x doubles of LDS.
 template <int B = 16>
-__device__ void slab_apply(const double* __restrict__ M, int64_t ld, int nrows, int d,
-                           const double* c, double* out, double* scratch) {
-    const int T = blockDim.x, tid = threadIdx.x;
-    __syncthreads();   // c and out were just written by other threads
+__device__ void slab_apply2(const double* __restrict__ MA, const double* __restrict__ ML,
+                            int64_t ld, int nrows, int d, const double* cA, const double* cL,
+                            double* outA, double* outL, double* scratch) {
+    const int T = blockDim.x / 2, side = threadIdx.x / T, tid = threadIdx.x % T;
+    __syncthreads();   // the coefficients and out were just written by other threads
     if (nrows <= 0 || d <= 0) {
         __syncthreads();
         return;
     }
+    const double* __restrict__ M = side ? ML : MA;
+    const double* c = side ? cL : cA;
+    double* out = side ? outL : outA;
+    double* scr = scratch + side * T;
     const int nq = nrows >= T ? 1 : T / nrows;
     for (int r0 = 0; r0 < nrows; r0 += T) {
-        const int i = r0 + tid % min(nrows - r0, T), q = tid / min(nrows - r0, T);
         const int nr = min(nrows - r0, T);
-        if (q < nq && i < nrows) {
+        const int i = r0 + tid % nr, q = tid / nr;
+        if (q < nq) {
             const int j0 = (int)((int64_t)d * q / nq), j1 = (int)((int64_t)d * (q + 1) / nq);
-            scratch[q * nr + (i - r0)] =
-                strided_dot<B>(M + (int64_t)j0 * ld + i, ld, c + j0, j1 - j0);
+            scr[q * nr + (i - r0)] = strided_dot<B>(M + (int64_t)j0 * ld + i, ld, c + j0, j1 - j0);
         }
         __syncthreads();
         if (tid < nr) {
             double a = 0.0;
-            for (int qq = 0; qq < nq; ++qq) a += scratch[qq * nr + tid];
+            for (int qq = 0; qq < nq; ++qq) a += scr[qq * nr + tid];
             out[r0 + tid] -= a;
         }
         __syncthreads();
+    }
+}
+
+// Two strided sums, pA[0] + pA[stride] + ... (nA terms) and likewise pL (nL
+// terms), each in order, with the loads of both in flight together.
+__device__ __forceinline__ void strided_sum_pair(const double* __restrict__ pA, int nA,
+                                                 const double* __restrict__ pL, int nL,
+                                                 int64_t stride, double& a, double& l) {
+    a = 0.0;
+    l = 0.0;
+    const int n = max(nA, nL);
+    for (int k = 0; k < n; k += 16) {
+        double va[16], vl[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            va[u] = nA > 0 ? pA[(int64_t)min(k + u, nA - 1) * stride] : 0.0;
+            vl[u] = nL > 0 ? pL[(int64_t)min(k + u, nL - 1) * stride] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            if (k + u < nA) a += va[u];
+            if (k + u < nL) l += vl[u];
+        }
     }
 }
 
@@ -1147,7 +1229,6 @@ struct ApShared {
     double cuL[kMaxD];
     double scr[kAppendThreads];
     double sc[kSlots];
-    double tile[kAppendThreads / 64 * 16 * 64];
 };
 
 // Q pass 0: column scale (breakdown test), reduce the sketch bins of this
@@ -1189,8 +1270,9 @@ __global__ __launch_bounds__(kAppendThreads) void k_ap_q0(const State* __restric
         if (q < nq) {
             const int a0 = (int)((int64_t)S.nbA * q / nq), a1 = (int)((int64_t)S.nbA * (q + 1) / nq);
             const int l0 = (int)((int64_t)S.nbL * q / nq), l1 = (int)((int64_t)S.nbL * (q + 1) / nq);
-            scrA[q * D.ns + i] = strided_sum(S.binA + (int64_t)a0 * D.s + D.lo + i, D.s, a1 - a0);
-            scrL[q * D.ns + i] = strided_sum(S.binL + (int64_t)l0 * D.s + D.lo + i, D.s, l1 - l0);
+            strided_sum_pair(S.binA + (int64_t)a0 * D.s + D.lo + i, a1 - a0,
+                             S.binL + (int64_t)l0 * D.s + D.lo + i, l1 - l0, D.s,
+                             scrA[q * D.ns + i], scrL[q * D.ns + i]);
         }
     }
     __syncthreads();
@@ -1213,9 +1295,8 @@ __global__ __launch_bounds__(kAppendThreads) void k_ap_q0(const State* __restric
     na2 = block_sum(na2, sh.red);
     nl2 = block_sum(nl2, sh.red);
     double* reg = ap_region(S, D, G, 0);
-    slab_dots(S.QA + D.lo, nullptr, D.s, D.ns, d, sh.av, nullptr, reg, D.g, G, sh.tile);
-    slab_dots(S.QL + D.lo, nullptr, D.s, D.ns, d, sh.lv, nullptr, reg + (int64_t)S.dmax * G, D.g, G,
-              sh.tile);
+    slab_dots2<false>(S.QA + D.lo, S.QL + D.lo, D.s, D.ns, d, sh.av, sh.lv, reg,
+                      reg + (int64_t)S.dmax * G, D.g, G);
     if (tid == 0) {
         reg[(int64_t)(2 * S.dmax) * G + g] = na2;
         reg[(int64_t)(2 * S.dmax + 1) * G + g] = nl2;
@@ -1253,16 +1334,14 @@ __global__ __launch_bounds__(kAppendThreads) void k_ap_qp(const State* __restric
         sh.lv[i] = S.wl[D.lo + i];
     }
     ap_take_q(S, D, G, pass - 1, sh);
-    slab_apply(S.QA + D.lo, D.s, D.ns, d, sh.cA, sh.av, sh.scr);
-    slab_apply(S.QL + D.lo, D.s, D.ns, d, sh.cL, sh.lv, sh.scr);
+    slab_apply2(S.QA + D.lo, S.QL + D.lo, D.s, D.ns, d, sh.cA, sh.cL, sh.av, sh.lv, sh.scr);
     for (int i = tid; i < D.ns; i += kAppendThreads) {
         S.wa[D.lo + i] = sh.av[i];
         S.wl[D.lo + i] = sh.lv[i];
     }
     double* reg = ap_region(S, D, G, pass);
-    slab_dots(S.QA + D.lo, nullptr, D.s, D.ns, d, sh.av, nullptr, reg, D.g, G, sh.tile);
-    slab_dots(S.QL + D.lo, nullptr, D.s, D.ns, d, sh.lv, nullptr, reg + (int64_t)S.dmax * G, D.g, G,
-              sh.tile);
+    slab_dots2<false>(S.QA + D.lo, S.QL + D.lo, D.s, D.ns, d, sh.av, sh.lv, reg,
+                      reg + (int64_t)S.dmax * G, D.g, G);
 }
 
 // Q finish: last projection, norms and d_A numerator, U pass 0 on
@@ -1298,8 +1377,7 @@ __global__ __launch_bounds__(kAppendThreads) void k_ap_qf(const State* __restric
             if (g == 0) S.pacc[2 * S.dmax + slot] = p;   // the running sums stay intact
         }
     }
-    slab_apply(S.QA + D.lo, D.s, D.ns, d, sh.cA, sh.av, sh.scr);
-    slab_apply(S.QL + D.lo, D.s, D.ns, d, sh.cL, sh.lv, sh.scr);
+    slab_apply2(S.QA + D.lo, S.QL + D.lo, D.s, D.ns, d, sh.cA, sh.cL, sh.av, sh.lv, sh.scr);
     double ra = 0.0, rl = 0.0, dl = 0.0;
     for (int i = tid; i < D.ns; i += kAppendThreads) {
         S.wa[D.lo + i] = sh.av[i];
@@ -1319,7 +1397,8 @@ __global__ __launch_bounds__(kAppendThreads) void k_ap_qf(const State* __restric
     rl = block_sum(rl, sh.red);
     dl = block_sum(dl, sh.red);
     double* reg = ap_region(S, D, G, P);
-    slab_dots(S.U + D.ulo, S.U + S.dmax + D.ulo, D.ld2, D.nua, d, sh.cuA, sh.cuL, reg, D.g, G, sh.tile);
+    slab_dots2<true>(S.U + D.ulo, S.U + S.dmax + D.ulo, D.ld2, D.nua, d, sh.cuA, sh.cuL, reg,
+                     nullptr, D.g, G);
     if (tid == 0) {
         reg[(int64_t)(2 * S.dmax) * G + g] = ra;
         reg[(int64_t)(2 * S.dmax + 1) * G + g] = rl;
@@ -1350,15 +1429,15 @@ __global__ __launch_bounds__(kAppendThreads) void k_ap_u(const State* __restrict
             if (g == 0) S.gacc[j] = (upass == 1 ? 0.0 : S.gacc[j]) + c;
         }
     }
-    slab_apply(S.U + D.ulo, D.ld2, D.nua, d, sh.cA, sh.cuA, sh.scr);
-    slab_apply(S.U + S.dmax + D.ulo, D.ld2, D.nua, d, sh.cA, sh.cuL, sh.scr);
+    slab_apply2(S.U + D.ulo, S.U + S.dmax + D.ulo, D.ld2, D.nua, d, sh.cA, sh.cA, sh.cuA, sh.cuL,
+                sh.scr);
     for (int i = tid; i < D.nua; i += kAppendThreads) {
         S.wu[D.ulo + i] = sh.cuA[i];
         S.wu[S.dmax + D.ulo + i] = sh.cuL[i];
     }
     if (!last) {
-        slab_dots(S.U + D.ulo, S.U + S.dmax + D.ulo, D.ld2, D.nua, d, sh.cuA, sh.cuL,
-                  ap_region(S, D, G, P + upass), D.g, G, sh.tile);
+        slab_dots2<true>(S.U + D.ulo, S.U + S.dmax + D.ulo, D.ld2, D.nua, d, sh.cuA, sh.cuL,
+                         ap_region(S, D, G, P + upass), nullptr, D.g, G);
         return;
     }
     double gam2 = 0.0, hnum = 0.0;
@@ -1940,7 +2019,9 @@ __global__ __launch_bounds__(kAp1Threads) void k_ap1_side_hw(const State* __rest
 // delta = G^{-1} G^{-T} g, y <- y - alpha delta + beta (y - y_prev)
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kBlock) void k_refine(const State* __restrict__ SS, BTab tab) {
+constexpr int kRefineThreads = 1024;
+
+__global__ __launch_bounds__(kRefineThreads) void k_refine(const State* __restrict__ SS, BTab tab) {
     __shared__ double gv[kMaxD];
     __shared__ double tv[kMaxD];
     __shared__ double dv[kMaxD];
@@ -1949,7 +2030,34 @@ __global__ __launch_bounds__(kBlock) void k_refine(const State* __restrict__ SS,
     const int d = *S.d;
     const int dmax = S.dmax;
     const double* Gi = S.G + (int64_t)dmax * dmax;   // row-major G^{-1}
-    for (int j = threadIdx.x; j < d; j += kBlock) gv[j] = strided_sum(S.gpart + j, dmax, S.ngt);
+    // g = W^T r from the per-workgroup partials: a wave sums four columns at a
+    // time, its lanes over the partial rows (sixteen loads in flight)
+    {
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+        const int nb = S.ngt;
+        for (int j0 = wave * 4; j0 < d; j0 += nw * 4) {
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int b0 = 0; b0 < nb; b0 += 256) {
+                double w[4][4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int b = b0 + lane + 64 * t;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        w[c][t] = b < nb ? S.gpart[(int64_t)b * dmax + min(j0 + c, d - 1)] : 0.0;
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc[c] += w[c][t];
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double a = wave_sum(acc[c]);
+                if (lane == 0 && j0 + c < d) gv[j0 + c] = a;
+            }
+        }
+    }
     __syncthreads();
     tri_mv(Gi, dmax, 1, d, 1, gv, tv);   // t = G^{-T} g
     __syncthreads();
@@ -1957,10 +2065,92 @@ __global__ __launch_bounds__(kBlock) void k_refine(const State* __restrict__ SS,
     __syncthreads();
     const double eta2 = fmin((double)d / (double)S.s, 0.999);
     const double alpha = (1.0 - eta2) * (1.0 - eta2), beta = eta2;
-    for (int i = threadIdx.x; i < d; i += kBlock) {
+    for (int i = threadIdx.x; i < d; i += blockDim.x) {
         const double yi = S.y[i], yp = S.yprev[i];
         S.y[i] = yi - alpha * dv[i] + beta * (yi - yp);
         S.yprev[i] = yi;
+    }
+}
+
+// Refinement from the projected normal matrix M = W^T H W kept column by
+// column.  The gradient of a refinement step, W^T r(y) for unit columns with
+// r(y) = H W y - A^T b, is C (M C y - c) with C = diag(cs) and c_i =
+// W[:, i]^T A^T b, an O(d^2) product instead of two passes over n x d data.
+// First the newest column c = d - 1 of M and c_c from kb_mcol's partials
+// (stored symmetric, row-major), then `steps` heavy-ball steps as k_refine's.
+__global__ __launch_bounds__(kRefineThreads) void k_mrefine(const State* __restrict__ SS, BTab tab,
+                                                           int steps) {
+    __shared__ double gv[kMaxD + 1];
+    __shared__ double yv[kMaxD];
+    __shared__ double ypv[kMaxD];
+    __shared__ double zv[kMaxD];
+    __shared__ double tv[kMaxD];
+    const State S = load_state(SS, find_slot(tab).p);
+    if (*S.status != 0) return;
+    const int d = *S.d, c = d - 1, dmax = S.dmax, ld = dmax + 1;
+    {
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+        const int nb = S.ngt, ns = c + 2;
+        for (int j0 = wave * 4; j0 < ns; j0 += nw * 4) {
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int b0 = 0; b0 < nb; b0 += 256) {
+                double w[4][4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int b = b0 + lane + 64 * t;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        w[q][t] = b < nb ? S.gpart[(int64_t)b * ld + min(j0 + q, ns - 1)] : 0.0;
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) acc[q] += w[q][t];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double a = wave_sum(acc[q]);
+                if (lane == 0 && j0 + q < ns) gv[j0 + q] = a;
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= c; i += blockDim.x) {
+        S.Mnt[(int64_t)i * dmax + c] = gv[i];
+        S.Mnt[(int64_t)c * dmax + i] = gv[i];
+    }
+    if (threadIdx.x == 0) S.cnt[c] = gv[c + 1];
+    __syncthreads();   // the new row and column are read by the whole workgroup below
+    if (steps <= 0) return;
+    const double* Gi = S.G + (int64_t)dmax * dmax;   // row-major G^{-1}
+    const double eta2 = fmin((double)d / (double)S.s, 0.999);
+    const double alpha = (1.0 - eta2) * (1.0 - eta2), beta = eta2;
+    for (int i = threadIdx.x; i < d; i += blockDim.x) {
+        yv[i] = S.y[i];
+        ypv[i] = S.yprev[i];
+    }
+    for (int st = 0; st < steps; ++st) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < d; i += blockDim.x) zv[i] = S.cs[i] * yv[i];
+        __syncthreads();
+        tri_mv_t(GTri{S.Mnt, dmax, 1}, d, 2, zv, tv, blockDim.x);   // t = M C y
+        __syncthreads();
+        for (int i = threadIdx.x; i < d; i += blockDim.x) gv[i] = S.cs[i] * (tv[i] - S.cnt[i]);
+        __syncthreads();
+        tri_mv(Gi, dmax, 1, d, 1, gv, tv);   // G^{-T} g
+        __syncthreads();
+        tri_mv(Gi, dmax, 1, d, 0, tv, zv);   // delta = G^{-1} G^{-T} g
+        __syncthreads();
+        for (int i = threadIdx.x; i < d; i += blockDim.x) {
+            const double yi = yv[i];
+            yv[i] = yi - alpha * zv[i] + beta * (yi - ypv[i]);
+            ypv[i] = yi;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < d; i += blockDim.x) {
+        S.y[i] = yv[i];
+        S.yprev[i] = ypv[i];
     }
 }
 
@@ -2199,6 +2389,31 @@ void launch_forward(const State& S, const double* x, const double* b, double* u,
                            u, t, upart, tpart);
 }
 
+// Workgroups of the H W adjoint of a single problem when it runs beside the
+// append chain: the chain's small launches find free wave slots only while the
+// adjoint holds fewer than all of them, so its grid is a few workgroups per
+// compute unit (grid-stride over the rows; 3 measured best on the dynamic CT
+// workload among 2 to 8, 16% more expansions per second than 8).  A batch keeps
+// the full grid: there the adjoint products of all problems are most of an
+// expansion and the appends are one-workgroup launches.
+constexpr int kSideAdjoint_WgPerCu = 3;
+
+static int device_cus() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+        return 256;
+    return cus;
+}
+
+static int side_adjoint_blocks(const State& S, int cus) {
+    const int per = kBlock / S.At.lanes;
+    const int64_t groups = (S.n + per - 1) / per;
+    const int64_t cap = (int64_t)kSideAdjoint_WgPerCu * cus;
+    return (int)(groups < cap ? groups : cap);
+}
+
 int adjoint_blocks(const State& S) {
     const int per = kBlock / S.At.lanes;
     const int64_t nb = (S.n + per - 1) / per;
@@ -2390,8 +2605,9 @@ bool append_groups_ok(int s, int dmax, int G) {
            (dmax + G - 1) / G <= kAppendMaxSlab;
 }
 
-int choose_append_groups(int s, int dmax, int cap) {
-    if ((int64_t)s * dmax <= kCompactAppendMax && s <= kMaxS) return 1;
+int choose_append_groups(int s, int dmax, int cap, int64_t nnz) {
+    const int64_t compact_max = nnz <= kFuseHWMaxNnz ? kCompactAppendMax : kCompactAppendMaxSep;
+    if ((int64_t)s * dmax <= compact_max && s <= kMaxS) return 1;
     int G = (s + 31) / 32;
     if (G < 4) G = 4;
     while ((s + G - 1) / G > kAppendMaxSlab || (dmax + G - 1) / G > kAppendMaxSlab) ++G;
@@ -2490,6 +2706,7 @@ int plan_build(Plan& P, const State* host, const State* dev, int np, const int* 
         gr[kMaxBatch], ap1h[kMaxBatch], ahs[kMaxBatch];
     int64_t nnz_total = 0;
     for (int q = 0; q < np; ++q) nnz_total += host[q].A.nnz + host[q].L.nnz;
+    const int cus = np == 1 ? device_cus() : 0;
     P.fuse_hw = nnz_total <= kFuseHWMaxNnz ? 1 : 0;
     for (int q = 0; q < np; ++q) {
         const State& S = host[q];
@@ -2512,7 +2729,9 @@ int plan_build(Plan& P, const State* host, const State* dev, int np, const int* 
         ap1s[q] = compact ? 2 : 0;
         const bool hw = S.gradient_form == 0;
         ap1h[q] = compact ? 2 + (hw && P.fuse_hw ? hw_blocks(S) : 0) : 0;
-        ahs[q] = (hw && !(compact && P.fuse_hw)) ? adjoint_blocks(S) : 0;
+        ahs[q] = (hw && !(compact && P.fuse_hw))
+                     ? (np == 1 ? side_adjoint_blocks(S, cus) : adjoint_blocks(S))
+                     : 0;
         one[q] = 1;
         P.max_s = S.s > P.max_s ? S.s : P.max_s;
         P.max_gt_rows = S.gt_rows > P.max_gt_rows ? S.gt_rows : P.max_gt_rows;
@@ -2631,7 +2850,16 @@ void plan_gemvt(const Plan& P, hipStream_t st) {
 }
 
 void plan_refine(const Plan& P, hipStream_t st) {
-    SGKS_LAUNCH(k_refine, dim3(P.np), dim3(kBlock), 0, st, P.SS, P.one);
+    SGKS_LAUNCH(k_refine, dim3(P.np), dim3(kRefineThreads), 0, st, P.SS, P.one);
+}
+
+void plan_mcol(const Plan& P, hipStream_t st) {
+    const size_t shm = (size_t)P.max_gt_rows * sizeof(double);
+    SGKS_LAUNCH(kb_mcol, dim3(tab_total(P.gemvt)), dim3(kBlock), shm, st, P.SS, P.gemvt);
+}
+
+void plan_mrefine(const Plan& P, int steps, hipStream_t st) {
+    SGKS_LAUNCH(k_mrefine, dim3(P.np), dim3(kRefineThreads), 0, st, P.SS, P.one, steps);
 }
 
 // bytes of scratch the transpose of M needs (four nnz-long int32 arrays and the

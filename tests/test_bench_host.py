@@ -47,8 +47,9 @@ def test_algorithmic_bytes_of_the_deblurring_workload():
 
 def test_expected_launches_of_one_step():
     """One expansion per k: gradient, new-column SpMV, H W adjoint (own launch unless fused
-    into the append), scatter, append; refinement steps add a gradient, W^T r and the
-    update each; the solution adds one GEMV over ell + k columns."""
+    into the append), scatter, append; with refinement the maintained form adds the new
+    column of W^T H W and one launch for all the steps, the direct form a gradient, W^T r
+    and the update per step; the solution adds one GEMV over ell + k columns."""
     P = make("deblur2d", 0, "small")
     ex = bench.expected_launches(P, "maintained", fused_hw=True)
     assert len(ex["gemv"]) == P.k + 1
@@ -57,13 +58,19 @@ def test_expected_launches_of_one_step():
     ex = bench.expected_launches(P, "maintained", fused_hw=False)
     assert len(ex["adjoint"]) == P.k and ex["qr_append_solve"] == [0] * P.k
     Q = make("ct2d", 0, "small")
+    assert Q.refine_steps == 2
     ex = bench.expected_launches(Q, "maintained", fused_hw=False)
-    assert len(ex["gemv"]) == Q.k * (1 + Q.refine_steps) + 1
-    assert len(ex["gemvt_WTr"]) == Q.k * Q.refine_steps
+    # maintained form: the steps run on W^T H W, whose new column is one W^T v pass
+    assert len(ex["gemv"]) == Q.k + 1
+    assert len(ex["gemvt_WTr"]) == Q.k and len(ex["refine_step"]) == Q.k
     d0 = Q.ell
     assert ex["gemv"][0] == bench.launch_bytes(Q, "gradient", d0)
-    assert ex["gemv"][1] == bench.launch_bytes(Q, "gradient", d0 + 1)   # refinement after the append
+    assert ex["gemv"][1] == bench.launch_bytes(Q, "gradient", d0 + 1)   # the next expansion
+    assert ex["gemvt_WTr"][0] == bench.launch_bytes(Q, "gemvt", d0 + 1)
     assert ex["gemv"][-1] == bench.launch_bytes(Q, "gemv", Q.ell + Q.k)
+    ex = bench.expected_launches(Q, "direct", fused_hw=False)
+    assert len(ex["gemv"]) == Q.k * (1 + Q.refine_steps) + 1
+    assert len(ex["gemvt_WTr"]) == Q.k * Q.refine_steps
 
 
 def _profile_commands():

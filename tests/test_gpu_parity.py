@@ -246,14 +246,17 @@ def test_profiling_times_kernels_and_keeps_results(groups, refine, form):
     n = {name: cnt[i] for i, name in enumerate(G.PHASE_NAMES)}
     say("  launches", n)
     assert n["spmv_new_column"] == k and n["sketch_scatter"] == k
-    assert n["gemvt_WTr"] == k * refine and n["refine_step"] == k * refine
     if form == "maintained":
-        # one gradient launch per expansion and refinement step, plus x = W y; the H W
-        # column inside the compact append's launch, else in an adjoint launch of its own
-        assert n["gemv"] == k * (1 + refine) + 1
+        # one gradient launch per expansion, plus x = W y; the H W column inside the
+        # compact append's launch, else in an adjoint launch of its own; with
+        # refinement one launch for the new column of W^T H W and one for all the
+        # steps of an expansion
+        assert n["gemv"] == k + 1
+        assert n["gemvt_WTr"] == k * min(refine, 1) and n["refine_step"] == k * min(refine, 1)
         assert n["forward_Ax_Lx"] == 0
         assert n["adjoint"] == (0 if groups == 1 else k)
     else:
+        assert n["gemvt_WTr"] == k * refine and n["refine_step"] == k * refine
         assert n["gemv"] == k * (1 + refine) + 1
         assert n["forward_Ax_Lx"] == k * (1 + refine) and n["adjoint"] == k * (1 + refine)
     if groups == 1 and form == "maintained":

@@ -293,13 +293,45 @@ __device__ __forceinline__ void row_chunk(const int32_t* __restrict__ ci, const 
     for (int u = 0; u < U; ++u) acc += (double)w[u] * xv[u];
 }
 
-template <int V, typename T>
+// In the masked form, rows split over at least this many lanes take masked
+// chunks (below).
+constexpr int kMaskedRowMinLanes = 8;
+
+template <int V, typename T, bool Masked = false>
 __device__ __forceinline__ double row_dot(const Csr& M, const double* __restrict__ x, int64_t row,
                                           int g) {
     const int32_t* __restrict__ ci = M.col;
     const T* __restrict__ va = (const T*)M.val;
     const int beg = M.rowptr[row], end = M.rowptr[row + 1];
     double acc = 0.0;
+    if constexpr (Masked && V >= kMaskedRowMinLanes) {
+        // wide groups: a lane's share of a row is short, so every chunk is eight
+        // (index, value) loads from clamped addresses (all in flight, then the
+        // eight gathers) and the terms past the row's end are masked: one
+        // dependent round trip per eight entries of a lane instead of separate
+        // chunks of eight, four, two and one.  Same terms in the same order.
+        // Faster for the batch (its long ray rows on 16 to 64 lanes: 27,900 vs
+        // 25,000 problem-expansions/s); slower for a single problem, whose
+        // adjoint then takes wave slots and issue cycles from the append chain
+        // beside it (CT 3,914 vs 4,080 iterations/s), so only batched plans use it.
+        for (int k = beg + g; k < end; k += 8 * V) {
+            int c[8];
+            T w[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int q = min(k + u * V, end - 1);
+                c[u] = ci[q];
+                w[u] = va[q];
+            }
+            double xv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) xv[u] = x[c[u]];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (k + u * V < end) acc += (double)w[u] * xv[u];
+        }
+        return group_sum<V>(acc);
+    }
     int k = beg + g;
     // eight (then four, two) entries per lane in flight before the gathers of x
     for (; k + 7 * V < end; k += 8 * V) row_chunk<8, V>(ci, va, x, k, acc);
@@ -417,7 +449,7 @@ __device__ __forceinline__ int rows_blocks_of(const Csr& M) {
 // workgroups [0, nbA) take rows of A, the rest rows of L
 // ---------------------------------------------------------------------------
 
-template <typename T>
+template <typename T, bool Masked = false>
 __device__ __forceinline__ void forward_body(const Csr& A, const Csr& L, int nbA, int nb_all,
                                              const double* __restrict__ x,
                                              const double* __restrict__ b,
@@ -435,7 +467,7 @@ __device__ __forceinline__ void forward_body(const Csr& A, const Csr& L, int nbA
         const int64_t row = (int64_t)blk * (kBlock / V) + threadIdx.x / V;
         const int g = threadIdx.x % V;
         if (row < M.rows) {
-            double v = row_dot<V, T>(M, x, row, g);
+            double v = row_dot<V, T, Masked>(M, x, row, g);
             if (sub) v -= sub[row];
             if (g == 0) {
                 out[row] = v;
@@ -462,7 +494,7 @@ __global__ __launch_bounds__(kBlock) void k_forward(Csr A, Csr L, int nbA,
 // Iteration form: newcol = 0: u = A x - b, t = L x from the state's x;
 // newcol = 1: u = A w, t = L w for the basis column d (skipped on a set status),
 // and workgroup 0 also sums ||w||^2 into scal[14].
-template <typename T>
+template <typename T, bool Masked>
 __global__ __launch_bounds__(kBlock) void kb_forward(const State* __restrict__ SS, BTab tab,
                                                     int newcol) {
     __shared__ double red[kWaves];
@@ -471,8 +503,8 @@ __global__ __launch_bounds__(kBlock) void kb_forward(const State* __restrict__ S
     if (newcol && *S.status != 0) return;
     const double* x = newcol ? S.W + (int64_t)(*S.d) * S.n : S.x;
     if (newcol && sl.blk == 0 && threadIdx.x == 0) S.scal[15] = (double)(*S.d);   // H W column
-    forward_body<T>(S.A, S.L, rows_blocks_of(S.A), sl.nblk, x, newcol ? nullptr : S.b, S.u, S.t,
-                    nullptr, nullptr, sl.blk, red);
+    forward_body<T, Masked>(S.A, S.L, rows_blocks_of(S.A), sl.nblk, x, newcol ? nullptr : S.b, S.u,
+                            S.t, nullptr, nullptr, sl.blk, red);
     if (newcol && sl.blk == 0) {
         // ||r||^2 of the new (unnormalised) column from the adjoint's partial sums,
         // for the column scale of the append
@@ -486,7 +518,7 @@ __global__ __launch_bounds__(kBlock) void kb_forward(const State* __restrict__ S
 // partial sums of r^2 (grid-stride over the n rows)
 // ---------------------------------------------------------------------------
 
-template <typename T, int NT = kBlock>
+template <typename T, int NT = kBlock, bool Masked = false>
 __device__ __forceinline__ void adjoint_body(const Csr& At, const Csr& Lt, int withL, double mu,
                                              const double* __restrict__ u,
                                              const double* __restrict__ t,
@@ -503,8 +535,8 @@ __device__ __forceinline__ void adjoint_body(const Csr& At, const Csr& Lt, int w
         for (int64_t grp = g0; grp < g1; ++grp) {
             const int64_t row = grp * rpg + threadIdx.x / V;
             if (row < n) {
-                double v = row_dot<V, T>(At, u, row, g);
-                if (withL) v += mu * row_dot<V, T>(Lt, t, row, g);
+                double v = row_dot<V, T, Masked>(At, u, row, g);
+                if (withL) v += mu * row_dot<V, T, Masked>(Lt, t, row, g);
                 if (g == 0) {
                     dst[row] = v;
                     sq += v * v;
@@ -535,7 +567,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(Csr At, Csr Lt, int withL, d
 //                 of the new column (skipped on a set status)
 constexpr int kDstBasis = 0, kDstRefine = 1, kDstHW = 2;
 
-template <typename T>
+template <typename T, bool Masked>
 __global__ __launch_bounds__(kBlock) void kb_adjoint(const State* __restrict__ SS, BTab tab,
                                                     int dst_kind) {
     __shared__ double red[kWaves];
@@ -548,8 +580,9 @@ __global__ __launch_bounds__(kBlock) void kb_adjoint(const State* __restrict__ S
                   : dst_kind == kDstHW   ? S.HW + (int64_t)S.scal[15] * S.n
                                          : S.W + (int64_t)(*S.d) * S.n;
     // the H W column's norm is not needed: no partial sums
-    adjoint_body<T>(S.At, S.Lt, 1, S.mu, S.u, S.t, dst, S.n,
-                    dst_kind == kDstHW ? nullptr : S.norm_part, sl.blk, sl.nblk, red);
+    adjoint_body<T, kBlock, Masked>(S.At, S.Lt, 1, S.mu, S.u, S.t, dst, S.n,
+                                    dst_kind == kDstHW ? nullptr : S.norm_part, sl.blk, sl.nblk,
+                                    red);
 }
 
 // ---------------------------------------------------------------------------
@@ -2755,22 +2788,29 @@ void plan_gemv(const Plan& P, hipStream_t st) {
     SGKS_LAUNCH(kb_gemv, dim3(tab_total(P.gemv)), dim3(kBlock), 0, st, P.SS, P.gemv);
 }
 
+// Batched plans take the masked row form (see row_dot).
 void plan_forward(const Plan& P, bool newcol, hipStream_t st) {
     const dim3 grid(tab_total(P.fwd));
-    if (P.vdt == 0)
-        SGKS_LAUNCH(kb_forward<float>, grid, dim3(kBlock), 0, st, P.SS, P.fwd,
-                           newcol ? 1 : 0);
-    else
-        SGKS_LAUNCH(kb_forward<double>, grid, dim3(kBlock), 0, st, P.SS, P.fwd,
-                           newcol ? 1 : 0);
+    const bool m = P.np > 1;
+    if (P.vdt == 0) {
+        auto* k = m ? &kb_forward<float, true> : &kb_forward<float, false>;
+        SGKS_LAUNCH(k, grid, dim3(kBlock), 0, st, P.SS, P.fwd, newcol ? 1 : 0);
+    } else {
+        auto* k = m ? &kb_forward<double, true> : &kb_forward<double, false>;
+        SGKS_LAUNCH(k, grid, dim3(kBlock), 0, st, P.SS, P.fwd, newcol ? 1 : 0);
+    }
 }
 
 void plan_adjoint(const Plan& P, int dst_kind, hipStream_t st) {
     const dim3 grid(tab_total(P.adj));
-    if (P.vdt == 0)
-        SGKS_LAUNCH(kb_adjoint<float>, grid, dim3(kBlock), 0, st, P.SS, P.adj, dst_kind);
-    else
-        SGKS_LAUNCH(kb_adjoint<double>, grid, dim3(kBlock), 0, st, P.SS, P.adj, dst_kind);
+    const bool m = P.np > 1;
+    if (P.vdt == 0) {
+        auto* k = m ? &kb_adjoint<float, true> : &kb_adjoint<float, false>;
+        SGKS_LAUNCH(k, grid, dim3(kBlock), 0, st, P.SS, P.adj, dst_kind);
+    } else {
+        auto* k = m ? &kb_adjoint<double, true> : &kb_adjoint<double, false>;
+        SGKS_LAUNCH(k, grid, dim3(kBlock), 0, st, P.SS, P.adj, dst_kind);
+    }
 }
 
 void plan_gradient(const Plan& P, bool to_rtmp, hipStream_t st) {
@@ -2804,10 +2844,14 @@ bool plan_has_hw_separate(const Plan& P) {
 void plan_hw_separate(const Plan& P, hipStream_t st) {
     if (!plan_has_hw_separate(P)) return;
     const dim3 grid(tab_total(P.adj_hw_sep));
-    if (P.vdt == 0)
-        SGKS_LAUNCH(kb_adjoint<float>, grid, dim3(kBlock), 0, st, P.SS, P.adj_hw_sep, kDstHW);
-    else
-        SGKS_LAUNCH(kb_adjoint<double>, grid, dim3(kBlock), 0, st, P.SS, P.adj_hw_sep, kDstHW);
+    const bool m = P.np > 1;
+    if (P.vdt == 0) {
+        auto* k = m ? &kb_adjoint<float, true> : &kb_adjoint<float, false>;
+        SGKS_LAUNCH(k, grid, dim3(kBlock), 0, st, P.SS, P.adj_hw_sep, kDstHW);
+    } else {
+        auto* k = m ? &kb_adjoint<double, true> : &kb_adjoint<double, false>;
+        SGKS_LAUNCH(k, grid, dim3(kBlock), 0, st, P.SS, P.adj_hw_sep, kDstHW);
+    }
 }
 
 int plan_append(const Plan& P, bool scale_from_norm, bool with_hw, hipStream_t st) {

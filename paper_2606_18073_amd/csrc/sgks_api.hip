@@ -565,7 +565,7 @@ int plan_context(sgks_ctx* c, const sgks_csr* A, const sgks_csr* L, double mu, i
 
     // scatter workgroups: kScatterTilesPerWave 64-entry tiles per wave (the
     // autotuner may choose another count; the partial bins are sized for one);
-    // SRTT: chunks of rows
+    // SRTT: blocks of 4096 rows in at most 128 ranges (the partial bins)
     if (S.sketch_mode == SGKS_SKETCH_SRTT) {
         S.nbA = sgks::srtt_chunks(S.m, &S.srA);
         S.nbL = sgks::srtt_chunks(S.p, &S.srL);
@@ -659,6 +659,8 @@ void layout_context(sgks_ctx* c, Arena& ar) {
     if (S.sketch_mode == SGKS_SKETCH_SRTT) {
         ar.add((int32_t**)&S.rowsA, (size_t)s * 4);
         ar.add((int32_t**)&S.rowsL, (size_t)s * 4);
+        ar.add((double**)&S.srtTA, (size_t)2 * sgks::srtt_pad(s) * 256 * 8);
+        ar.add((double**)&S.srtTL, (size_t)2 * sgks::srtt_pad(s) * 256 * 8);
     }
     ar.add(&S.wa, s * 8);
     ar.add(&S.wl, s * 8);
@@ -907,6 +909,7 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
                                 hipMemcpyHostToDevice, st));
         SGKS_TRY(hipMemcpyAsync((void*)S.rowsL, c->srtt_rows.data() + s, (size_t)s * 4,
                                 hipMemcpyHostToDevice, st));
+        sgks::launch_srtt_tables(S, st);   // the cosines and sines of the chunk rows
     }
     if (c->opt.autotune) {
         SGKS_TRY(hipMemsetAsync(S.x, 0, S.n * 8, st));

@@ -139,10 +139,14 @@ struct State {
     // from the hash: entry i*zeta + q = +-(row + 1) (sign of the entry), 0 if none
     const int16_t* patA;
     const int16_t* patL;
-    // SRTT: the s frequencies D selects on each side (draw order), rows per chunk
-    // of the images (the partial bins are per chunk: nbA = chunks of m, nbL of p)
+    // SRTT: the s frequencies D selects on each side (draw order); the cosine and
+    // sine tables of each side (2 x spad x 256, spad = s rounded up to 16); the
+    // blocks of 4096 image rows (srA of m, srL of p), split into the nbA, nbL
+    // ranges whose partial sums are the partial bins
     const int32_t* rowsA;
     const int32_t* rowsL;
+    const double* srtTA;
+    const double* srtTL;
     int srA, srL;
     double* wa;        // s: working sketched A column of the append
     double* wl;        // s: working sketched L column
@@ -255,8 +259,11 @@ void launch_make_pattern(int16_t* pat, int64_t rows, int s, int zeta, uint64_t s
                          hipStream_t st);
 int scatter_blocks(int64_t rows, int tiles_per_wave);
 size_t scatter_lds_bytes(int s);
-// SRTT: chunks of h rows (at most kSrttMaxChunks), rows per chunk into *rows_per
-int srtt_chunks(int64_t h, int* rows_per);
+// SRTT: the blocks of 4096 of h rows (into *blocks) and the ranges of blocks
+// (at most kSrttMaxChunks) whose sums are the partial bins
+int srtt_chunks(int64_t h, int* blocks);
+int srtt_pad(int s);
+void launch_srtt_tables(const State& S, hipStream_t st);
 // partial SRTT sketches of zA (m rows, S_A) and, if zL, zL (p rows, S_L) into the
 // partial bins, scaled by sqrt(h/s) c_k (the append adds the chunks)
 void launch_srtt(const State& S, const double* zA, const double* zL, hipStream_t st);

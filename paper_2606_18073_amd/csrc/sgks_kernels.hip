@@ -787,88 +787,169 @@ __global__ __launch_bounds__(kSketchBlock) void kb_scatter(const State* __restri
 // SRTT sketch (eq:sketching_trig): S = sqrt(h/s) D F E with F the orthonormal
 // DCT-II of length h, E Rademacher signs, D s selected frequencies, so
 //   (S z)_j = sqrt(h/s) c_k sum_i E_i z_i cos(pi k (2 i + 1) / (2 h)),  k = rows[j],
-// c_0 = sqrt(1/h), c_k = sqrt(2/h).  Only the s selected outputs are formed,
-// directly: workgroup (chunk, group) stages E z over its chunk of rows in LDS
-// and each thread accumulates one frequency over the chunk, its cosines from a
-// rotation by pi k / h (exact sincospi every kSrttAnchor rows, from the
-// argument reduced in integers).  FP64 ALU work of h s terms per image; the
-// chunks' sums are partial bins added by the append like the scatter's.
+// c_0 = sqrt(1/h), c_k = sqrt(2/h).  Only the s selected outputs are formed.
+// With i = 256 Q + r (chunk Q, row r) and theta = pi k / (2 h) the angle is
+// phi_Q + psi_r, phi_Q = theta (512 Q + 1), psi_r = 2 theta r, so
+//   sum_i y_i cos(.) = sum_Q [cos phi_Q (C Y)_Q - sin phi_Q (S Y)_Q],  y = E z,
+// with C[k][r] = cos(psi_r), S[k][r] = sin(psi_r) the same s x 256 matrices for
+// every chunk and Y the 256 x (chunks) matrix of y: two dense FP64 products, on
+// MFMA (16 x 16 x 4 FP64 tiles).  A workgroup takes 16 frequencies and a range
+// of chunk blocks (16 chunks, 4096 rows each): its four waves split the 256
+// rows of the contraction, their tiles are added in LDS, and each (frequency,
+// chunk) pair is rotated by phi_Q (exact sincospi from the argument reduced in
+// integers) and summed over the chunks.  The range sums are partial bins added
+// by the append like the scatter's.
 // ---------------------------------------------------------------------------
 
-constexpr int kSrttStage = 2048;   // rows of a chunk staged in LDS at a time
-constexpr int kSrttAnchor = 256;   // rotation steps between exact cosines
+typedef double sgks_double4 __attribute__((ext_vector_type(4)));
 
-__device__ void srtt_body(const double* __restrict__ z, int64_t h, int s,
-                          const int32_t* __restrict__ rows, uint64_t seed, int stream,
-                          int rows_per, int blk, int nkg, double* __restrict__ part,
-                          double* ez) {
+constexpr int kSrttB = 256;                   // rows of a chunk (the contraction)
+constexpr int kSrttNB = 16;                   // chunks of a block (the MFMA N)
+constexpr int kSrttBlockRows = kSrttB * kSrttNB;
+constexpr int kSrttFT = 16;                   // frequencies of a workgroup (the MFMA M)
+constexpr int kSrttYs = 17;                   // LDS row stride of the staged block (banks)
+
+// C and S tables of one side: T[j * 256 + r] = cos(pi k_j r / h), then at
+// offset spad * 256 the sines (rows j >= s are zero)
+__global__ __launch_bounds__(kBlock) void k_srtt_tables(const int32_t* __restrict__ rows,
+                                                       int64_t h, int s, int spad,
+                                                       double* __restrict__ T) {
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= (int64_t)spad * kSrttB) return;
+    const int j = (int)(e / kSrttB), r = (int)(e % kSrttB);
+    double sn = 0.0, cs = 0.0;
+    if (j < s) {
+        const int64_t k = rows[j];
+        const int64_t q = (k * r) % (2 * h);   // angle pi k r / h, reduced mod 2 pi
+        sincospi((double)q / (double)h, &sn, &cs);
+    }
+    T[e] = cs;
+    T[(int64_t)spad * kSrttB + e] = sn;
+}
+
+__device__ __forceinline__ void srtt_body(const double* __restrict__ z, int64_t h, int s,
+                          const int32_t* __restrict__ rows, const double* __restrict__ T,
+                          uint64_t seed, int stream, int ncb, int nr, int ft, int qr,
+                          double* __restrict__ part, double* ys, double* red) {
     const uint64_t gam = 0x9E3779B97F4A7C15ull;
     const uint64_t ks = mix64(seed + gam * (uint64_t)(stream + 3));
-    const int c = blk / nkg, g = blk - (blk / nkg) * nkg;
-    const int64_t i0 = (int64_t)c * rows_per;
-    const int nr = (int)min((int64_t)rows_per, h - i0);
-    const int j = g * kSrttThreads + threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int spad = ((s + kSrttFT - 1) / kSrttFT) * kSrttFT;
+    // MFMA operands: lane holds A[i = lane % 16][kk = lane / 16] of each 16 x 4
+    // step; wave w takes rows [64 w, 64 w + 64) of the contraction (read from L2
+    // for every block: held across the loop they would halve the occupancy)
+    const double* Tc = T + (int64_t)(ft * kSrttFT + (lane & 15)) * kSrttB + 64 * w + (lane >> 4);
+    const double* Tsn = Tc + (int64_t)spad * kSrttB;
+    // combine role: thread (frequency fi, chunk qq of the block)
+    const int fi = tid >> 4, qq = tid & 15;
+    const int j = ft * kSrttFT + fi;
     const bool active = j < s;
-    const int64_t k = active ? rows[j] : 0;
-    double Sn, C;
-    sincospi((double)k / (double)h, &Sn, &C);
-    double acc = 0.0;
-    for (int b0 = 0; b0 < nr; b0 += kSrttStage) {
-        const int nb = min(kSrttStage, nr - b0);
-        __syncthreads();   // the previous stage was read by every thread
-        for (int i = threadIdx.x; i < nb; i += kSrttThreads) {
-            const int64_t gi = i0 + b0 + i;
-            const double sg = (mix64(ks + gam * (uint64_t)(gi + 1)) & 1ull) ? -1.0 : 1.0;
-            ez[i] = sg * z[gi];
-        }
-        __syncthreads();
-        if (active) {
-            for (int a0 = 0; a0 < nb; a0 += kSrttAnchor) {
-                const int64_t gi = i0 + b0 + a0;
-                const int64_t r = (k * (2 * gi + 1)) % (4 * h);
-                double sn, cs;
-                sincospi((double)r / (double)(2 * h), &sn, &cs);
-                const int ne = min(kSrttAnchor, nb - a0);
-                for (int q = 0; q < ne; ++q) {
-                    acc += cs * ez[a0 + q];
-                    const double cn = cs * C - sn * Sn;
-                    sn = sn * C + cs * Sn;
-                    cs = cn;
-                }
+    const int64_t kf = active ? rows[j] : 0;
+    double accj = 0.0;
+    const int cb0 = (int)((int64_t)ncb * qr / nr), cb1 = (int)((int64_t)ncb * (qr + 1) / nr);
+    for (int cb = cb0; cb < cb1; ++cb) {
+        __syncthreads();   // the previous block's ys and red were read by every thread
+        const int64_t i0 = (int64_t)cb * kSrttBlockRows;
+        {
+            // the block's 16 entries of this thread: every load in flight first
+            constexpr int U = kSrttBlockRows / kBlock;
+            double zv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) zv[u] = z[min(i0 + tid + u * kBlock, h - 1)];
+#pragma unroll 2
+            for (int u = 0; u < U; ++u) {
+                const int e = tid + u * kBlock;
+                const int64_t gi = i0 + e;
+                const double sg = (mix64(ks + gam * (uint64_t)(gi + 1)) & 1ull) ? -1.0 : 1.0;
+                ys[(e & (kSrttB - 1)) * kSrttYs + (e >> 8)] = gi < h ? sg * zv[u] : 0.0;   // [row][chunk]
             }
         }
+        __syncthreads();
+        double ac[16], as_[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            ac[q] = Tc[4 * q];
+            as_[q] = Tsn[4 * q];
+        }
+        sgks_double4 dc = {0.0, 0.0, 0.0, 0.0}, ds = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            // B[kk = lane / 16][chunk = lane % 16] of step q
+            const double b = ys[(64 * w + 4 * q + (lane >> 4)) * kSrttYs + (lane & 15)];
+            dc = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[q], b, dc, 0, 0, 0);
+            ds = __builtin_amdgcn_mfma_f64_16x16x4f64(as_[q], b, ds, 0, 0, 0);
+        }
+        // element t of lane l holds D[i = 4 t + l / 16][chunk = l % 16] (measured
+        // on gfx950 with a probe of known operands)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int i = 4 * t + (lane >> 4);
+            red[((w * 2 + 0) * kSrttFT + i) * kSrttNB + (lane & 15)] = dc[t];
+            red[((w * 2 + 1) * kSrttFT + i) * kSrttNB + (lane & 15)] = ds[t];
+        }
+        __syncthreads();
+        double pc = 0.0, ps = 0.0;
+#pragma unroll
+        for (int ww = 0; ww < 4; ++ww) {
+            pc += red[((ww * 2 + 0) * kSrttFT + fi) * kSrttNB + qq];
+            ps += red[((ww * 2 + 1) * kSrttFT + fi) * kSrttNB + qq];
+        }
+        const int64_t Q = (int64_t)cb * kSrttNB + qq;
+        double val = 0.0;
+        if (active && Q * kSrttB < h) {
+            // phi = pi k (512 Q + 1) / (2 h), reduced mod 2 pi in integers
+            const int64_t a = (kf * (2 * kSrttB * Q + 1)) % (4 * h);
+            double sn, cs;
+            sincospi((double)a / (double)(2 * h), &sn, &cs);
+            val = cs * pc - sn * ps;
+        }
+        val += __shfl_xor(val, 8);
+        val += __shfl_xor(val, 4);
+        val += __shfl_xor(val, 2);
+        val += __shfl_xor(val, 1);
+        accj += val;
     }
-    if (active) {
-        const double ck = k == 0 ? sqrt(1.0 / (double)h) : sqrt(2.0 / (double)h);
-        part[(int64_t)c * s + j] = sqrt((double)h / (double)s) * ck * acc;
+    if (active && qq == 0) {
+        const double ck = kf == 0 ? sqrt(1.0 / (double)h) : sqrt(2.0 / (double)h);
+        part[(int64_t)qr * s + j] = sqrt((double)h / (double)s) * ck * accj;
     }
 }
 
-// workgroups [0, nbA nkg) sketch zA (S_A, m rows), the rest zL (S_L, p rows)
+struct SrttLds {
+    double ys[kSrttB * kSrttYs];
+    double red[4 * 2 * kSrttFT * kSrttNB];
+};
+
+// workgroups [0, nbA nft) sketch zA (S_A, m rows), the rest zL (S_L, p rows);
+// within a side, workgroup b takes range b / nft and frequency tile b % nft
 __device__ __forceinline__ void srtt_pair(const State& S, const double* zA, const double* zL,
-                                          int nbL, int blk, double* ez) {
-    const int nkg = (S.s + kSrttThreads - 1) / kSrttThreads;
-    if (blk < S.nbA * nkg)
-        srtt_body(zA, S.m, S.s, S.rowsA, S.seed, 0, S.srA, blk, nkg, S.binA, ez);
-    else if (blk < (S.nbA + nbL) * nkg)
-        srtt_body(zL, S.p, S.s, S.rowsL, S.seed, 1, S.srL, blk - S.nbA * nkg, nkg, S.binL, ez);
+                                          int nbL, int blk, SrttLds& sh) {
+    const int nft = (S.s + kSrttFT - 1) / kSrttFT;
+    if (blk >= (S.nbA + nbL) * nft) return;
+    const bool a = blk < S.nbA * nft;   // one call site: the body is inlined once
+    const int b = a ? blk : blk - S.nbA * nft;
+    srtt_body(a ? zA : zL, a ? S.m : S.p, S.s, a ? S.rowsA : S.rowsL, a ? S.srtTA : S.srtTL,
+              S.seed, a ? 0 : 1, a ? S.srA : S.srL, a ? S.nbA : S.nbL, b % nft, b / nft,
+              a ? S.binA : S.binL, sh.ys, sh.red);
 }
 
-__global__ __launch_bounds__(kSrttThreads) void k_srtt(const State S, const double* zA,
-                                                      const double* zL, int nbL) {
-    __shared__ double ez[kSrttStage];
-    srtt_pair(S, zA, zL, nbL, blockIdx.x, ez);
+__global__ __launch_bounds__(kBlock) void k_srtt(const State S, const double* zA,
+                                                const double* zL, int nbL) {
+    __shared__ SrttLds sh;
+    srtt_pair(S, zA, zL, nbL, blockIdx.x, sh);
 }
 
 // Iteration form: the SRTT sketches of the new column's images (u, t); skipped on
 // a set status.
-__global__ __launch_bounds__(kSrttThreads) void kb_srtt(const State* __restrict__ SS, BTab tab) {
-    __shared__ double ez[kSrttStage];
+__global__ __launch_bounds__(kBlock) void kb_srtt(const State* __restrict__ SS, BTab tab) {
+    __shared__ SrttLds sh;
     const Slot sl = find_slot(tab);
     const State S = load_state(SS, sl.p);
     if (*S.status != 0) return;
-    srtt_pair(S, S.u, S.t, S.nbL, sl.blk, ez);
+    srtt_pair(S, S.u, S.t, S.nbL, sl.blk, sh);
 }
+
+constexpr int kSrttStage = 2048;   // frequencies staged in LDS at a time (transpose)
 
 // out_i = sqrt(m/s) E_i sum_j c_{k_j} cos(pi k_j (2 i + 1) / (2 m)) v_j  (S_A^T v)
 __global__ __launch_bounds__(kBlock) void k_srtt_transpose(const double* __restrict__ v, int s,
@@ -2494,18 +2575,28 @@ void launch_scatter(const State& S, const double* zA, const double* zL, hipStrea
 #undef SGKS_SC
 }
 
-int srtt_chunks(int64_t h, int* rows_per) {
-    int64_t rp = (h + kSrttMaxChunks - 1) / kSrttMaxChunks;
-    if (rp < 512) rp = 512;
-    *rows_per = (int)rp;
-    return (int)((h + rp - 1) / rp);
+int srtt_chunks(int64_t h, int* blocks) {
+    const int64_t nb = (h + kSrttBlockRows - 1) / kSrttBlockRows;
+    *blocks = (int)nb;
+    return (int)(nb < kSrttMaxChunks ? nb : kSrttMaxChunks);
+}
+
+int srtt_pad(int s) { return ((s + kSrttFT - 1) / kSrttFT) * kSrttFT; }
+
+void launch_srtt_tables(const State& S, hipStream_t st) {
+    const int spad = srtt_pad(S.s);
+    const int64_t ne = (int64_t)spad * kSrttB;
+    const dim3 grid((unsigned)((ne + kBlock - 1) / kBlock));
+    hipLaunchKernelGGL(k_srtt_tables, grid, dim3(kBlock), 0, st, S.rowsA, S.m, S.s, spad,
+                       (double*)S.srtTA);
+    hipLaunchKernelGGL(k_srtt_tables, grid, dim3(kBlock), 0, st, S.rowsL, S.p, S.s, spad,
+                       (double*)S.srtTL);
 }
 
 void launch_srtt(const State& S, const double* zA, const double* zL, hipStream_t st) {
-    const int nkg = (S.s + kSrttThreads - 1) / kSrttThreads;
+    const int nft = (S.s + kSrttFT - 1) / kSrttFT;
     const int nbL = zL ? S.nbL : 0;
-    hipLaunchKernelGGL(k_srtt, dim3((S.nbA + nbL) * nkg), dim3(kSrttThreads), 0, st, S, zA, zL,
-                       nbL);
+    hipLaunchKernelGGL(k_srtt, dim3((S.nbA + nbL) * nft), dim3(kBlock), 0, st, S, zA, zL, nbL);
 }
 
 void srtt_rows_host(int64_t h, int s, uint64_t seed, int stream, int32_t* rows) {
@@ -2751,7 +2842,7 @@ int plan_build(Plan& P, const State* host, const State* dev, int np, const int* 
         fwd[q] = forward_blocks(S, true, nullptr);
         adj[q] = adjoint_blocks(S);
         sc[q] = S.sketch_mode == kSketchSrtt
-                    ? (S.nbA + S.nbL) * ((S.s + kSrttThreads - 1) / kSrttThreads)
+                    ? (S.nbA + S.nbL) * ((S.s + kSrttFT - 1) / kSrttFT)
                     : (S.nbA + S.nbL) * scatter_ranges(S.s);
         gv[q] = gemv_blocks(S);
         gr[q] = gradient_blocks(S);
@@ -2820,7 +2911,7 @@ void plan_gradient(const Plan& P, bool to_rtmp, hipStream_t st) {
 
 void plan_scatter(const Plan& P, hipStream_t st) {
     if (P.sketch_mode == kSketchSrtt) {
-        SGKS_LAUNCH(kb_srtt, dim3(tab_total(P.sc)), dim3(kSrttThreads), 0, st, P.SS, P.sc);
+        SGKS_LAUNCH(kb_srtt, dim3(tab_total(P.sc)), dim3(kBlock), 0, st, P.SS, P.sc);
         return;
     }
     const size_t shm = scatter_lds_bytes(P.max_s);

@@ -72,6 +72,23 @@ def test_srtt_deblur2d_full_and_sketch_independence():
     S2.close()
 
 
+def test_srtt_dynamic_ct_full_size_factors():
+    """The dynamic CT workload at full size with the SRTT (m = 327,600: 80 blocks of 4,096
+    rows; p = 1,474,560: 360 blocks in 128 ranges of two or three): ten expansions against
+    the oracle's SRTT run, and the GPU's factors against the oracle's SRTT applied to the
+    GPU's own basis (Q_A R_A = S_A A W, Q_L R_L = S_L L W)."""
+    P = dataclasses.replace(problem("dynamic_ct", "full"), k=10)
+    say("case srtt dynamic_ct full, k = 10")
+    ref = _oracle(P)
+    S, x = G.solve_problem(P, sketch="srtt")
+    e = rel(x.cpu().numpy(), ref.x)
+    say(f"  rel err vs oracle {e:.3e}")
+    assert e <= 1e-8
+    assert S.status() == (0, P.k)
+    check_state_consistency(S, P, sketch="srtt")
+    S.close()
+
+
 def test_srtt_backward():
     P = problem("dynamic_ct", "small")
     say("case srtt backward")

@@ -16,7 +16,9 @@ Large-Scale Regularization"):
   * sGKS, Alg. 2 (Sec. 3): no reorthogonalisation, sketch-and-solve projected
     problem eq:projected_sketched_bis with two independent sketches S_A, S_L
   * iterative refinement of the projected solve (end of Sec. 3.1; Sec. 4.3)
-  * a frozen-basis adjoint of the final projected solve (not in the paper)
+  * a frozen-basis adjoint of the final projected solve, and the total
+    derivative of x_k through every expansion and the initial basis (reverse
+    sweep); neither is in the paper
   * the sparse-sign embedding (the paper uses an SRTT, eq:sketching_trig, and
     states the method is independent of the embedding, Sec. 2.2)
 
@@ -530,6 +532,88 @@ def frozen_adjoint_b(res: Result, mu, g_x, A, L, s, seed, zeta=8, sketch="sparse
 def frozen_map(res: Result, b, mu, S_A):
     """x(b, mu) = W H(mu)^{-1} R_A^T Q_A^T S_A b with the basis and factors held fixed."""
     return res.W @ gram_solve(_stacked_r(res, mu), res.R_A.T @ (res.Q_A.T @ (S_A @ b)))
+
+
+def total_adjoint(A, L, b, mu, k, s, seed, g_x, zeta=8, ell=3, sketch="sparse_sign"):
+    """(d loss / d b, d loss / d mu) of the whole sGKS map b, mu -> x_k (Alg. 2, k
+    expansions, no refinement), given g_x = d loss / d x_k.  Not in the paper.
+
+    Differentiated map (the exact-arithmetic form of every step of Alg. 2):
+      * W_0 = Gram-Schmidt of the Krylov chain v_1 = A^T b / ||A^T b||,
+        p_i = (I - V_i V_i^T) A^T A v_i, v_{i+1} = p_i / ||p_i|| (Sec. 2.1);
+      * with B_A = S_A A W_j, B_L = S_L L W_j and c_b = S_A b, the projected
+        solve eq:projected_sketched_bis is y_j = N_j^{-1} B_A^T c_b with
+        N_j = B_A^T B_A + mu B_L^T B_L (Q_A R_A = B_A, Q_L R_L = B_L by
+        eq:updqr, d_A = Q_A^T c_b by eq:dA_update);
+      * x_j = W_j y_j; r_j = A^T (A x_j - b) + mu L^T L x_j (eq: gradient);
+        the next column is r_j / ||r_j||.
+    The reverse sweep runs j = k, ..., 0 and keeps the adjoint of every basis
+    column as an explicit n x d matrix; N_j^{-1} is applied through the R factor
+    of [B_A; sqrt(mu) B_L] (no squared condition number)."""
+    A = sp.csr_matrix(A, dtype=np.float64)
+    L = sp.csr_matrix(L, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    res = sgks(A, L, b, mu, k, s, seed, zeta, ell, sketch=sketch, keep_history=True)
+    if res.status != STATUS_OK or res.iters != k:
+        raise ValueError("the total adjoint needs k expansions without breakdown")
+    S_A, S_L = make_sketches(A.shape[0], L.shape[0], s, seed, zeta, sketch)
+    W = res.W
+    n, d = W.shape
+    c_b = S_A @ b
+    BA = S_A @ (A @ W)
+    BL = S_L @ (L @ W)
+
+    def hess(v):
+        return A.T @ (A @ v) + mu * (L.T @ (L @ v))
+
+    Wbar = np.zeros((n, d))
+    gb = np.zeros(A.shape[0])
+    gmu = 0.0
+    cbar = np.zeros(c_b.shape[0])
+    for j in range(k, -1, -1):
+        dj = ell + j
+        y = res.y_hist[j]
+        if j == k:
+            xbar = np.asarray(g_x, dtype=np.float64)
+        else:
+            # column dj was r_j / ||r_j||
+            x_j = res.x_hist[j]
+            r = gradient(A, L, b, mu, x_j)
+            w = W[:, dj]
+            wbar = Wbar[:, dj]
+            rbar = (wbar - w * (w @ wbar)) / np.linalg.norm(r)
+            xbar = hess(rbar)
+            gb -= A @ rbar
+            gmu += float((L @ rbar) @ (L @ x_j))
+        # x_j = W_j y_j
+        Wbar[:, :dj] += np.outer(xbar, y)
+        ybar = W[:, :dj].T @ xbar
+        # y_j = N_j^{-1} B_A^T c_b
+        Bj, Lj = BA[:, :dj], BL[:, :dj]
+        _, G = np.linalg.qr(np.vstack([Bj, math.sqrt(mu) * Lj]), mode="reduced")
+        u = gram_solve(G, ybar)
+        cbar += Bj @ u
+        sym = np.outer(y, u) + np.outer(u, y)
+        BAbar = np.outer(c_b, u) - Bj @ sym
+        BLbar = -mu * (Lj @ sym)
+        gmu -= float((Lj @ u) @ (Lj @ y))
+        Wbar[:, :dj] += A.T @ (S_A.T @ BAbar) + L.T @ (S_L.T @ BLbar)
+    # W_0: reverse of the Krylov Gram-Schmidt chain
+    V = W[:, :ell]
+    Vbar = Wbar[:, :ell].copy()
+    for i in range(ell - 1, 0, -1):
+        z = A.T @ (A @ V[:, i - 1])
+        Vi = V[:, :i]
+        p = z - Vi @ (Vi.T @ z)
+        pbar = (Vbar[:, i] - V[:, i] * (V[:, i] @ Vbar[:, i])) / np.linalg.norm(p)
+        zbar = pbar - Vi @ (Vi.T @ pbar)
+        Vbar[:, :i] -= np.outer(pbar, Vi.T @ z) + np.outer(z, Vi.T @ pbar)
+        Vbar[:, i - 1] += A.T @ (A @ zbar)
+    g = A.T @ b
+    v1 = V[:, 0]
+    gb += A @ ((Vbar[:, 0] - v1 * (v1 @ Vbar[:, 0])) / np.linalg.norm(g))
+    gb += S_A.T @ cbar
+    return gb, gmu
 
 
 def dense_tikhonov(A, L, b, mu):

@@ -416,6 +416,81 @@ def test_frozen_adjoint_equals_dense_adjoint_at_full_space():
 
 
 # ----------------------------------------------------------------------------
+# total-derivative adjoint (through every expansion and the initial basis)
+# ----------------------------------------------------------------------------
+
+def _total_fd_errors(A, L, b, mu, k, s, seed, sketch, g_x, gb, gmu, rng, ndir=3):
+    """Relative errors of the adjoint against central differences of
+    g_x . x_k(b, mu), x_k from k expansions of the oracle's Alg. 2."""
+    f = lambda bb, mm: float(g_x @ O.sgks(A, L, bb, mm, k, s, seed, sketch=sketch).x)
+    errs = []
+    for _ in range(ndir):
+        db = rng.standard_normal(b.size)
+        h = 1e-5 * np.linalg.norm(b) / np.linalg.norm(db)
+        fd = (f(b + h * db, mu) - f(b - h * db, mu)) / (2 * h)
+        errs.append(abs(fd - gb @ db) / max(abs(fd), 1e-3))
+    hm = 1e-5 * mu
+    fd = (f(b, mu + hm) - f(b, mu - hm)) / (2 * hm)
+    errs.append(abs(fd - gmu) / max(abs(fd), 1e-3))
+    return errs
+
+
+@pytest.mark.parametrize("k,sketch", [(0, "sparse_sign"), (4, "sparse_sign"), (6, "srtt")])
+def test_total_adjoint_matches_central_differences(k, sketch):
+    """The reverse sweep is the derivative of the composed map of Alg. 2: directional
+    derivatives in b and mu from central differences of x_k itself.  k = 0 leaves
+    only the initial Krylov basis and the first projected solve."""
+    A, L, b, mu = tiny2d(N=6 if sketch == "sparse_sign" else 8)
+    s, seed = 60, 3
+    rng = np.random.default_rng(7)
+    g_x = rng.standard_normal(A.shape[1])
+    gb, gmu = O.total_adjoint(A, L, b, mu, k, s, seed, g_x, sketch=sketch)
+    assert max(_total_fd_errors(A, L, b, mu, k, s, seed, sketch, g_x, gb, gmu, rng)) < 1e-6
+
+
+def test_total_adjoint_at_full_space_is_dense_adjoint():
+    """At d = n, x_k is the dense sketched Tikhonov solution whatever the basis, so every
+    contribution through the basis cancels and the adjoint is the closed form
+    S_A^T S_A A Hs^{-1} g_x, -(Hs^{-1} g_x)^T L^T S_L^T S_L L x."""
+    A, L, b, mu = tiny(n=8, sigma=0.8)
+    s, seed = 100, 5
+    S_A, S_L = O.make_sketches(A.shape[0], L.shape[0], s, seed)
+    Ad, Ld = A.toarray(), L.toarray()
+    SA, SL = S_A.toarray(), S_L.toarray()
+    H = Ad.T @ SA.T @ SA @ Ad + mu * Ld.T @ SL.T @ SL @ Ld
+    x = np.linalg.solve(H, Ad.T @ SA.T @ SA @ b)
+    g_x = np.random.default_rng(2).standard_normal(A.shape[1])
+    z = np.linalg.solve(H, g_x)
+    gb_dense = SA.T @ SA @ Ad @ z
+    gmu_dense = -float(z @ (Ld.T @ SL.T @ SL @ Ld @ x))
+    res = O.sgks(A, L, b, mu, 5, s, seed)
+    gb, gmu = O.total_adjoint(A, L, b, mu, 5, s, seed, g_x)
+    tol = 1e-13 * np.linalg.cond(res.W) ** 2
+    assert np.linalg.norm(gb - gb_dense) <= tol * np.linalg.norm(gb_dense)
+    assert abs(gmu - gmu_dense) <= tol * abs(gmu_dense)
+
+
+def test_total_adjoint_pins_reject_a_wrong_solve_and_the_frozen_adjoint(monkeypatch):
+    """The difference pin separates the total derivative from plausible slips: the
+    frozen-basis adjoint (no path through W) and a projected solve applied with one
+    triangular factor only both miss it by far more than the tolerance."""
+    A, L, b, mu = tiny2d(N=6)
+    k, s, seed = 4, 60, 3
+    rng = np.random.default_rng(7)
+    g_x = rng.standard_normal(A.shape[1])
+    res = O.sgks(A, L, b, mu, k, s, seed)
+    gb_f, gmu_f = O.frozen_adjoint_b(res, mu, g_x, A, L, s, seed)
+    assert max(_total_fd_errors(A, L, b, mu, k, s, seed, "sparse_sign", g_x, gb_f, gmu_f,
+                                np.random.default_rng(7))) > 1e-3
+    import scipy.linalg as sla
+    with monkeypatch.context() as mp:
+        mp.setattr(O, "gram_solve", lambda G, g: sla.solve_triangular(G, g, lower=False))
+        gb_w, gmu_w = O.total_adjoint(A, L, b, mu, k, s, seed, g_x)
+    assert max(_total_fd_errors(A, L, b, mu, k, s, seed, "sparse_sign", g_x, gb_w, gmu_w,
+                                np.random.default_rng(7))) > 1e-3
+
+
+# ----------------------------------------------------------------------------
 # planted mistakes: the pins above must catch plausible slips in the oracle
 # ----------------------------------------------------------------------------
 

@@ -140,6 +140,12 @@ typedef struct {
                                 (cached per operator shape in the process); 0 = choose from
                                 nnz/row and a fixed tile count (default)                        */
     int32_t method;          /* SGKS_METHOD_SGKS (default) or SGKS_METHOD_GKS (see above)      */
+    int32_t keep_history;    /* 1 = record y after every projected solve, and hold the buffers
+                                of sgks_backward_total (about 2 dmax^2 + n (max_iters + ell + 4)
+                                + m + p + 2 s doubles more); needs method SGKS, the
+                                maintained gradient form and refine_steps = 0, else
+                                SGKS_ERR_INVALID_ARG at create; not for batches.  0 = off
+                                (default)                                                      */
     const int32_t *order;    /* NULL (default) or device array of n int32: a permutation of the
                                 unknowns the context works in internally, order[i] = the
                                 caller's unknown at internal position i (e.g. pixels along a
@@ -223,6 +229,31 @@ int sgks_status(sgks_ctx *ctx, int32_t *iters_done);
  * refine_steps > 0: its x is the refined solve, whose derivative this adjoint
  * is not. */
 int sgks_backward(sgks_ctx *ctx, const double *grad_x, double *grad_b, double *grad_mu);
+
+/* Total-derivative adjoint (not in the paper): the gradient of loss(x_k) with
+ * respect to b and mu through the whole sGKS map of Alg. 2 -- the initial
+ * Krylov basis K_ell(A^T A, A^T b) (Sec. 2.1), every gradient column of
+ * eq: gradient appended since, the sketched products S_A A W and S_L L W
+ * (eq:updqr) and every projected solve (eq:projected_sketched_bis, with
+ * d_A = Q_A^T S_A b of eq:dA_update) -- in exact arithmetic, where the solve
+ * with d columns is y = N^{-1} (S_A A W)^T S_A b, N = (S_A A W)^T S_A A W +
+ * mu (S_L L W)^T S_L L W.  Reverse sweep over the expansions done so far
+ * (a breakdown ends them early), with W, H W and the factors resident on the
+ * device: per basis column one product of A, A^T, L and L^T, two sketch
+ * transposes and two dense passes over at most d stored n-vectors.  Given
+ * grad_x (device, n FP64, the caller's order) writes grad_b (device, m FP64)
+ * and *grad_mu (host, may be NULL).  Needs a context created with
+ * keep_history = 1 (else SGKS_ERR_INVALID_ARG, before any device work).
+ * Accuracy: every solve is inverted through N = G^T G, so rounding errors grow
+ * like eps kappa(G)^2 (G the final stacked factor [R_A; sqrt(mu) R_L] = U G,
+ * whose leading blocks are the G_j); *err_est (host, may be NULL) receives
+ * d eps kappa(G)^2, kappa from power iterations on G and G^{-1}.  Where it is
+ * near 1 or above (the basis of Alg. 2 is never reorthogonalised, so kappa
+ * grows with k) the result is not to be trusted; the frozen adjoint
+ * (sgks_backward) loses accuracy far later.
+ * Synchronising; the context can iterate further afterwards. */
+int sgks_backward_total(sgks_ctx *ctx, const double *grad_x, double *grad_b, double *grad_mu,
+                        double *err_est);
 
 /* Copy one piece of the solver state to host memory (synchronising), for
  * checks.  which: 0 W (n x d, column-major, columns scaled to unit norm),

@@ -245,6 +245,8 @@ int enqueue_iteration(const sgks::Plan& P, int refine_steps, Profiler* pr, hipSt
     }
     if (fork && hipStreamWaitEvent(st, ss->join, 0) != hipSuccess) return SGKS_ERR_HIP;
     if (refine_steps > 0) enqueue_refinement(P, refine_steps, pr, st);
+    // y of this solve, for the total-derivative adjoint (one problem)
+    if (P.np == 1 && P.host[0].yh) sgks::launch_record_y(P.SS, st);
     return SGKS_OK;
 }
 
@@ -459,6 +461,7 @@ struct sgks_ctx {
     int32_t* Lt_col;
     void* Lt_val;
     Profiler prof;
+    sgks::Rev rv{};      // buffers of the total-derivative adjoint (keep_history)
 };
 
 namespace {
@@ -672,6 +675,7 @@ void layout_context(sgks_ctx* c, Arena& ar) {
         ar.add(&S.Mnt, (size_t)dmax * dmax * 8);
         ar.add(&S.cnt, dmax * 8);
     }
+    if (c->opt.keep_history) ar.add(&S.yh, (size_t)(dmax + 1) * dmax * 8);
     ar.add(&S.coop, (size_t)regions * c->groups * CW * 8);
     ar.add(&S.scal, (16 + 2 * dmax) * 8);
     ar.add(&S.d, 64);
@@ -685,6 +689,32 @@ void layout_context(sgks_ctx* c, Arena& ar) {
     ar.add(&c->sbuf, s * 8);
     ar.add(&c->init_norms, (16 + 2 * dmax) * 8);
     ar.add(&c->Sdev, sizeof(State));
+    if (c->opt.keep_history) {
+        sgks::Rev& R = c->rv;
+        const int K = c->opt.max_iters;
+        ar.add(&R.uh, (size_t)(dmax + 1) * dmax * 8);
+        ar.add(&R.E, (size_t)S.n * (K > 0 ? K : 1) * 8);
+        ar.add(&R.vbar, (size_t)S.n * c->opt.ell * 8);
+        ar.add(&R.tv, S.n * 8);
+        ar.add(&R.zb, S.n * 8);
+        ar.add(&R.pb, S.n * 8);
+        ar.add(&R.zh, S.n * 8);
+        ar.add(&R.bA, S.m * 8);
+        ar.add(&R.bL, S.p * 8);
+        ar.add(&R.zA, (size_t)s * 8);
+        ar.add(&R.zL, (size_t)s * 8);
+        // L-row workgroups of the forward products for any lanes choice (the
+        // autotuner may change them after the layout)
+        ar.add(&R.ldot, (size_t)((S.p + 3) / 4 + 1) * 8);
+        ar.add(&R.ubar, dmax * 8);
+        ar.add(&R.vA, dmax * 8);
+        ar.add(&R.vL, dmax * 8);
+        ar.add(&R.dz, dmax * 8);
+        ar.add(&R.dp, dmax * 8);
+        ar.add(&R.kap, (size_t)(K + 1) * 8);
+        ar.add(&R.ones, (size_t)(K > 0 ? K : 1) * 8);
+        ar.add(&R.rs, 16 * 8);
+    }
     if (S.method == SGKS_METHOD_GKS) {
         ar.add(&S.QAt, (size_t)S.m * dmax * 8);
         ar.add(&S.QLt, (size_t)S.p * dmax * 8);
@@ -728,6 +758,7 @@ void sgks_default_options(sgks_options* o) {
     o->append_groups = 0;
     o->graph = 0;
     o->autotune = 0;
+    o->keep_history = 0;
     o->gradient_form = SGKS_GRADIENT_MAINTAINED;
     o->method = SGKS_METHOD_SGKS;
     o->order = nullptr;
@@ -767,6 +798,11 @@ int sgks_validate(const sgks_csr* A, const sgks_csr* L, const void* b, double mu
     if (o.gradient_form != SGKS_GRADIENT_MAINTAINED && o.gradient_form != SGKS_GRADIENT_DIRECT)
         return SGKS_ERR_INVALID_ARG;
     if (o.method != SGKS_METHOD_SGKS && o.method != SGKS_METHOD_GKS) return SGKS_ERR_INVALID_ARG;
+    if (o.keep_history != 0 && o.keep_history != 1) return SGKS_ERR_INVALID_ARG;
+    // the total-derivative adjoint differentiates the unrefined sGKS map and reads H W
+    if (o.keep_history && (o.method != SGKS_METHOD_SGKS || o.refine_steps != 0 ||
+                           o.gradient_form != SGKS_GRADIENT_MAINTAINED))
+        return SGKS_ERR_INVALID_ARG;
     if (o.method == SGKS_METHOD_GKS) return o.refine_steps == 0 ? 0 : SGKS_ERR_INVALID_ARG;
     if (s > sgks::kMaxSketch || s < 1) return SGKS_ERR_SKETCH_SIZE;
     if (o.sketch_mode == SGKS_SKETCH_SPARSE_SIGN) {
@@ -1020,6 +1056,10 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
     }
     if (!S.Mnt && c->opt.refine_steps > 0)
         enqueue_refinement(c->plan, c->opt.refine_steps, nullptr, st);
+    if (S.yh) {
+        sgks::launch_record_y(c->Sdev, st);
+        if (c->opt.max_iters > 0) sgks::launch_fill(c->rv.ones, c->opt.max_iters, 1.0, st);
+    }
     c->d_host = c->opt.ell;
 
     // the one synchronisation of the set-up: ||b||^2, the initial norms and the status
@@ -1128,6 +1168,139 @@ int sgks_backward(sgks_ctx* c, const double* grad_x, double* grad_b, double* gra
     if (hipStreamSynchronize(st) != hipSuccess) return SGKS_ERR_HIP;
     if (grad_mu) *grad_mu = gm;
     return SGKS_OK;
+}
+
+// ||M||_2 of an upper-triangular d x d row-major matrix (leading dimension ld) by
+// power iteration on M^T M from a fixed start (a lower bound that converges to it)
+static double tri_norm2(const std::vector<double>& M, int d, int ld) {
+    std::vector<double> v(d, 1.0 / sqrt((double)d)), w(d), z(d);
+    double lam = 0.0;
+    for (int it = 0; it < 40; ++it) {
+        for (int i = 0; i < d; ++i) {
+            double a = 0.0;
+            for (int j = i; j < d; ++j) a += M[(size_t)i * ld + j] * v[j];
+            w[i] = a;
+        }
+        for (int j = 0; j < d; ++j) z[j] = 0.0;
+        for (int i = 0; i < d; ++i)
+            for (int j = i; j < d; ++j) z[j] += M[(size_t)i * ld + j] * w[i];
+        double nz = 0.0;
+        for (int j = 0; j < d; ++j) nz += z[j] * z[j];
+        nz = sqrt(nz);
+        if (!(nz > 0.0) || !(nz < INFINITY)) return nz;
+        lam = nz;   // ||M^T M v|| with ||v|| = 1
+        for (int j = 0; j < d; ++j) v[j] = z[j] / nz;
+    }
+    return sqrt(lam);
+}
+
+int sgks_backward_total(sgks_ctx* c, const double* grad_x, double* grad_b, double* grad_mu,
+                        double* err_est) {
+#define SGKS_HIP_OK(expr) \
+    do { if ((expr) != hipSuccess) return SGKS_ERR_HIP; } while (0)
+    if (!c || !grad_x || !grad_b) return SGKS_ERR_INVALID_ARG;
+    State& S = c->S;
+    if (!S.yh || c->borrowed) return SGKS_ERR_INVALID_ARG;
+    const int stw = sync_status(c);
+    if (stw < 0) return stw;
+    sgks::Rev R = c->rv;
+    R.nldot = c->nbF_L;   // L-row workgroups of the forward products (final lanes)
+    hipStream_t st = c->st;
+    const int ell = c->opt.ell;
+    int d = 0;
+    SGKS_HIP_OK(hipMemcpyAsync(&d, S.d, sizeof(int), hipMemcpyDeviceToHost, st));
+    SGKS_HIP_OK(hipStreamSynchronize(st));
+    const int k = d - ell;   // expansions done (a breakdown stops them early)
+    if (k < 0 || k > c->opt.max_iters) return SGKS_ERR_DEVICE;
+    const int64_t n = S.n;
+    if (S.perm) {
+        sgks::launch_gather_perm(grad_x, S.perm, n, S.rtmp, st);
+        grad_x = S.rtmp;
+    }
+    const int dmax = S.dmax;
+    SGKS_HIP_OK(hipMemsetAsync(R.uh, 0, (size_t)(dmax + 1) * dmax * 8, st));
+    SGKS_HIP_OK(hipMemsetAsync(R.ubar, 0, (size_t)dmax * 8, st));
+    SGKS_HIP_OK(hipMemsetAsync(R.rs, 0, 16 * 8, st));
+
+    // one column c: its adjoint, scaled by `scale`, into dst
+    auto column = [&](int c_, const double* scale, double* dst) {
+        sgks::launch_rev_svec(S, R, d, st);                    // Q R C[:, c] (- S_A b ubar_c)
+        const int i0 = c_ - ell + 1 > 0 ? c_ - ell + 1 : 0;
+        sgks::launch_rev_tgemv(S, R, i0, k - i0, st);          // sum_i (y_i)_c e_i
+        sgks::launch_rev_forward(S, R, S.W + (size_t)c_ * n, st);   // with S_A^T zA, S_L^T zL
+        sgks::launch_rev_adjoint(S, R, grad_x, scale, dst, st);
+    };
+    // the last solve: W_k^T grad_x, then the columns from the newest down
+    sgks::launch_gemvt(S, grad_x, d, st);
+    sgks::launch_rev_small(S, R, ell, k, k, d - 1, -1, 0, st);
+    for (int j = k - 1; j >= 0; --j) {
+        const int cc = ell + j;   // made from the gradient r_j
+        double* e = R.E + (size_t)j * n;
+        column(cc, S.cs + cc, e);   // e_j = adjoint / ||r_j||
+        sgks::launch_gemvt_mat(S, S.HW, e, cc, st);   // W_j^T H e_j
+        sgks::launch_rev_small(S, R, ell, k, j, cc - 1, cc, 0, st);
+    }
+    for (int cc = ell - 1; cc >= 0; --cc) {
+        column(cc, nullptr, R.vbar + (size_t)cc * n);
+        sgks::launch_rev_small(S, R, ell, k, -1, cc - 1, cc, cc == 0 ? 1 : 0, st);
+    }
+    // the initial basis: v_i = p_i / ||p_i||, p_i = (I - V_i V_i^T) A^T A v_{i-1}
+    // (raw columns: W[:, i] = p_i / cs[i - 1], cs[i] = 1 / ||W[:, i]||)
+    for (int i = ell - 1; i >= 1; --i) {
+        const double* wprev = S.W + (size_t)(i - 1) * n;
+        sgks::launch_forward(S, wprev, nullptr, S.u, S.t, false, nullptr, nullptr, st);
+        sgks::launch_adjoint(S, S.u, nullptr, false, 0.0, R.zb, nullptr, st);   // z (raw)
+        sgks::launch_gemvt(S, R.zb, i, st);
+        sgks::launch_reduce_gpart(S, i, R.dz, st);                             // V_i^T z
+        sgks::LinComb lc{};
+        lc.t[0] = sgks::LinTerm{R.vbar + (size_t)i * n, 1.0, S.cs + i, nullptr, 0};
+        lc.nt = 1;
+        sgks::launch_lincomb(lc, n, R.pb, false, st);                           // p^ (raw)
+        sgks::launch_gemvt(S, R.pb, i, st);
+        sgks::launch_reduce_gpart(S, i, R.dp, st);                             // V_i^T p^
+        sgks::launch_gemv(S, R.dp, R.zh, R.pb, i, st);                         // z^ (raw)
+        for (int l = 0; l < i; ++l) {
+            sgks::LinComb u{};
+            u.t[0] = sgks::LinTerm{R.pb, -1.0, R.dz + l, nullptr, 0};
+            u.t[1] = sgks::LinTerm{R.zb, -1.0, R.dp + l, nullptr, 0};
+            u.nt = 2;
+            sgks::launch_lincomb(u, n, R.vbar + (size_t)l * n, true, st);
+        }
+        sgks::launch_forward(S, R.zh, nullptr, S.u, S.t, false, nullptr, nullptr, st);
+        sgks::launch_adjoint(S, S.u, nullptr, false, 0.0, R.zb, nullptr, st);   // A^T A z^
+        sgks::LinComb a{};
+        a.t[0] = sgks::LinTerm{R.zb, 1.0, S.cs + (i - 1), nullptr, 1};
+        a.nt = 1;
+        sgks::launch_lincomb(a, n, R.vbar + (size_t)(i - 1) * n, true, st);
+    }
+    // d loss / d b = A (cs[0] vbar_0 - sum_j e_j) + S_A^T Q_A R_A ubar
+    {
+        sgks::LinComb v0{};
+        v0.t[0] = sgks::LinTerm{R.vbar, 1.0, S.cs, nullptr, 0};
+        v0.nt = 1;
+        sgks::launch_lincomb(v0, n, R.zb, false, st);
+        sgks::launch_gemv_plain(S, R.E, R.ones, k, R.zb, R.zh, st);
+        sgks::launch_rev_svec(S, R, d, st);   // zA = -Q_A R_A ubar (set by the last small step)
+        sgks::launch_sketch_transpose_side(S, 0, R.zA, R.bA, st);
+        sgks::launch_forward(S, R.zh, R.bA, grad_b, S.t, false, nullptr, nullptr, st);
+    }
+    double gm = 0.0;
+    SGKS_HIP_OK(hipGetLastError());
+    SGKS_HIP_OK(hipMemcpyAsync(&gm, R.rs, 8, hipMemcpyDeviceToHost, st));
+    if (err_est) {
+        // d eps kappa(G)^2: the adjoint solves with N_j = G_j^T G_j
+        std::vector<double> Gh((size_t)d * dmax), Gih((size_t)d * dmax);
+        SGKS_HIP_OK(hipMemcpyAsync(Gh.data(), S.G, Gh.size() * 8, hipMemcpyDeviceToHost, st));
+        SGKS_HIP_OK(hipMemcpyAsync(Gih.data(), S.G + (size_t)dmax * dmax, Gih.size() * 8,
+                                   hipMemcpyDeviceToHost, st));
+        SGKS_HIP_OK(hipStreamSynchronize(st));
+        const double kap = tri_norm2(Gh, d, dmax) * tri_norm2(Gih, d, dmax);
+        *err_est = (double)d * 0x1p-53 * kap * kap;
+    }
+    SGKS_HIP_OK(hipStreamSynchronize(st));
+    if (grad_mu) *grad_mu = gm;
+    return SGKS_OK;
+#undef SGKS_HIP_OK
 }
 
 int64_t sgks_copy_state(sgks_ctx* c, int32_t which, double* dst, int64_t count) {
@@ -1314,6 +1487,7 @@ size_t sgks_batch_workspace_bytes(int32_t count, const sgks_problem* probs,
         o = *opt;
     else
         sgks_default_options(&o);
+    if (o.keep_history) return 0;
     std::vector<size_t> sizes;
     if (!batch_sizes(count, probs, o, sizes)) return 0;
     size_t total = 0;
@@ -1331,7 +1505,8 @@ int sgks_batch_create(int32_t count, const sgks_problem* probs, const sgks_optio
         o = *opt;
     else
         sgks_default_options(&o);
-    if (o.lanes_A || o.lanes_At || o.append_groups || o.method != SGKS_METHOD_SGKS)
+    if (o.lanes_A || o.lanes_At || o.append_groups || o.method != SGKS_METHOD_SGKS ||
+        o.keep_history)
         return SGKS_ERR_INVALID_ARG;
     for (int i = 0; i < count; ++i) {
         const int rc = sgks_validate(&probs[i].A, &probs[i].L, probs[i].b, probs[i].mu,

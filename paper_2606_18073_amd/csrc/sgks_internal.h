@@ -160,6 +160,8 @@ struct State {
     double* cnt;       // dmax: W[:, i]^T A^T b, raw columns (with Mnt)
     int ngt;
     int gt_rows;       // rows per block of the W^T v kernel
+    double* yh;        // (dmax + 1) x dmax: row d = y of the projected solve with d columns
+                       // (recorded for the total-derivative adjoint; else null)
     double* coop;      // partial vectors of the append kernels (regions x (2 dmax + 8) x G)
     double* scal;      // scalars: [0] ||A^T b||, [1] ||S_A b||^2, [2..] scratch
     int* d;            // current number of basis columns
@@ -181,6 +183,32 @@ struct State {
     double* vsq;       // 2 x 2048 partial sums of ||v||^2 after each V projection pass
     int ntA, ntL;      // row slabs of the A-side and L-side appends
     int trA, trL;      // rows per slab
+};
+
+// Buffers of the total-derivative adjoint (reverse sweep over the expansions).
+// Column-major n-vectors; e_j is the adjoint of the gradient r_j.
+struct Rev {
+    double* uh;     // (dmax + 1) x dmax: row d = u of the adjoint solve with d columns
+    double* E;      // n x max_iters: e_j, j < k
+    double* vbar;   // n x ell: adjoints of the (unit) initial columns
+    double* tv;     // n: sum_i (y_i)_c e_i of the current column c
+    double* zb;     // n: scratch of the initial-basis reverse
+    double* pb;     // n
+    double* zh;     // n
+    double* bA;     // m: S_A^T of zA
+    double* bL;     // p: S_L^T of zL
+    double* zA;     // s: Q_A R_A C[:, c] - S_A b ubar_c
+    double* zL;     // s: Q_L R_L C[:, c]
+    double* ldot;   // nldot workgroup partials of (L w_c) . (L t)
+    double* ubar;   // dmax: sum of the u of every solve (zero padded)
+    double* vA;     // dmax: R_A C[:, c]
+    double* vL;     // dmax: R_L C[:, c]
+    double* dz;     // dmax: coefficient vectors of the initial-basis reverse
+    double* dp;     // dmax
+    double* kap;    // max_iters + 1: (y_i)_c, the coefficients of tv
+    double* ones;   // max_iters
+    double* rs;     // 16 scalars: [0] d loss / d mu, [1] (y_k)_c, [2] ubar_c
+    int nldot;
 };
 
 // Block table of one batched launch: problem q owns the workgroups
@@ -242,6 +270,45 @@ void launch_cb(const State& S, hipStream_t st);
 void launch_residual_small(const State& S, double* out2, hipStream_t st);
 void launch_backward_small(const State& S, double* v_out, double* gmu_out, hipStream_t st);
 void launch_sketch_transpose(const State& S, const double* v, double* out, hipStream_t st);
+// S^T v of one side's embedding (0: S_A, m outputs; 1: S_L, p outputs)
+void launch_sketch_transpose_side(const State& S, int side, const double* v, double* out,
+                                  hipStream_t st);
+// ----- total-derivative adjoint (reverse sweep) ----------------------------
+// row d of yh = y (one problem, device State)
+void launch_record_y(const State* Sdev, hipStream_t st);
+// one-workgroup step: j >= 0 the adjoint solve of the projected problem with
+// ell + j columns (from the W^T partials in gpart); c >= 0 the small data of
+// column c; c_done >= 0 adds the L partials of column c_done to d loss / d mu;
+// fin: R_A ubar for the S_A b term
+void launch_rev_small(const State& S, const Rev& R, int ell, int k, int j, int c, int c_done,
+                      int fin, hipStream_t st);
+void launch_rev_svec(const State& S, const Rev& R, int dk, hipStream_t st);
+// tv = E[:, i0 : i0 + ncols] kap[i0 : i0 + ncols]
+void launch_rev_tgemv(const State& S, const Rev& R, int i0, int ncols, hipStream_t st);
+// u = A tv - S_A^T zA, t = L tv - S_L^T zL, partials of (L wc) . (L tv)
+void launch_rev_forward(const State& S, const Rev& R, const double* wc, hipStream_t st);
+// dst = scale (A^T u + mu L^T t + rs[1] gx)   (scale null: 1)
+void launch_rev_adjoint(const State& S, const Rev& R, const double* gx, const double* scale,
+                        double* dst, hipStream_t st);
+// partials of M[:, :ncols]^T v scaled by cs into gpart (ld dmax)
+void launch_gemvt_mat(const State& S, const double* M, const double* v, int ncols, hipStream_t st);
+// out (+)= sum_t h_t f(d1_t) f(d2_t) v_t, f(d) = *d (1 / *d where inv), f(null) = 1
+struct LinTerm {
+    const double* v;
+    double h;
+    const double* d1;
+    const double* d2;
+    int inv1;
+};
+struct LinComb {
+    LinTerm t[4];
+    int nt;
+};
+void launch_lincomb(const LinComb& lc, int64_t n, double* out, bool accumulate, hipStream_t st);
+// out = base - M[:, :ncols] coef (no column scale), M with n rows
+void launch_gemv_plain(const State& S, const double* M, const double* coef, int ncols,
+                       const double* base, double* out, hipStream_t st);
+void launch_fill(double* p, int64_t n, double v, hipStream_t st);
 int launch_copy_scaled_W(const State& S, double* dst, hipStream_t st);  // 0 or -1
 // x_k = W y into out in the caller's order of the unknowns
 void launch_solution(const State& S, double* out, hipStream_t st);

@@ -954,11 +954,12 @@ constexpr int kSrttStage = 2048;   // frequencies staged in LDS at a time (trans
 // out_i = sqrt(m/s) E_i sum_j c_{k_j} cos(pi k_j (2 i + 1) / (2 m)) v_j  (S_A^T v)
 __global__ __launch_bounds__(kBlock) void k_srtt_transpose(const double* __restrict__ v, int s,
                                                           int64_t m, const int32_t* __restrict__ rows,
-                                                          uint64_t seed, double* __restrict__ out) {
+                                                          uint64_t seed, int stream,
+                                                          double* __restrict__ out) {
     __shared__ double vs[kSrttStage];
     __shared__ int32_t ks_[kSrttStage];
     const uint64_t gam = 0x9E3779B97F4A7C15ull;
-    const uint64_t ksg = mix64(seed + gam * 3ull);
+    const uint64_t ksg = mix64(seed + gam * (uint64_t)(stream + 3));
     const double sc = sqrt((double)m / (double)s);
     for (int64_t i0 = (int64_t)blockIdx.x * kBlock; i0 < m; i0 += (int64_t)gridDim.x * kBlock) {
         const int64_t i = i0 + threadIdx.x;
@@ -990,14 +991,14 @@ __global__ __launch_bounds__(kBlock) void k_srtt_transpose(const double* __restr
 // ---------------------------------------------------------------------------
 
 // out[perm[i]] = [base[i] -] sum_j W[i, j] * cs[j] * coef[j], j < d (grid-stride
-// rows; perm null: the identity)
+// rows; perm null: the identity; cs null: no column scale)
 __device__ __forceinline__ void gemv_body(const double* __restrict__ W,
                                           const double* __restrict__ cs,
                                           const double* __restrict__ coef, int d, int64_t n,
                                           const double* __restrict__ base,
                                           double* __restrict__ out, int blk, int nblk,
                                           double* yt, const int32_t* __restrict__ perm = nullptr) {
-    for (int j = threadIdx.x; j < d; j += kBlock) yt[j] = cs[j] * coef[j];
+    for (int j = threadIdx.x; j < d; j += kBlock) yt[j] = cs ? cs[j] * coef[j] : coef[j];
     __syncthreads();
     for (int64_t i = (int64_t)blk * kBlock + threadIdx.x; i < n; i += (int64_t)nblk * kBlock) {
         const double* w = W + i;
@@ -2333,10 +2334,302 @@ __global__ __launch_bounds__(kBlock) void k_backward_small(State S, double* v_ou
     if (threadIdx.x == 0) gmu_out[0] = -prod;
 }
 
-// out[i] = sum_q sign_q(i) v[bin_q(i)] / sqrt(zeta)  (S_A^T v), i < m
+// ---------------------------------------------------------------------------
+// total-derivative adjoint of x_k (reverse sweep over the k expansions and the
+// initial Krylov basis).  In exact arithmetic the projected solve of
+// eq:projected_sketched_bis on the first d_j columns is
+// y_j = N_j^{-1} B_A^T S_A b with B_A = S_A A W_j = Q_A R_A, B_L = S_L L W_j =
+// Q_L R_L and N_j = B_A^T B_A + mu B_L^T B_L = G_j^T G_j, G_j the leading block
+// of the final stacked factor (the appends never change earlier columns).  The
+// adjoint of unit column c collects, over every solve j that uses it,
+//   x^_j (y_j)_c + A^T S_A^T (S_A b ubar_c - B_A C[:, c]) - mu L^T S_L^T B_L C[:, c]
+// with u_j = N_j^{-1} W_j^T x^_j, ubar = sum_j u_j, C = sum_j (u_j y_j^T + y_j u_j^T)
+// (zero padded) and x^_j = H e_j for j < k (x^_k = grad_x).  Column c is final
+// once every solve with more than c columns is processed; then e of the
+// gradient it was made from is its adjoint divided by ||r|| (its component
+// along the column vanishes: x_k depends on the span of W only).
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_record_y(const State* __restrict__ SS) {
+    const State S = load_state(SS, 0);
+    const int d = *S.d;
+    double* row = S.yh + (int64_t)d * S.dmax;
+    for (int i = threadIdx.x; i < d; i += kBlock) row[i] = S.y[i];
+}
+
+// One workgroup of kRevThreads: the triangular products take four lanes per
+// row (d <= 256) and the sum over the solves' histories four thread groups.
+constexpr int kRevThreads = 1024;
+
+__global__ __launch_bounds__(kRevThreads) void k_rev_small(State S, Rev R, int ell, int k, int j,
+                                                          int c, int c_done, int fin) {
+    __shared__ double gv[kMaxD];
+    __shared__ double tvv[kMaxD];
+    __shared__ double uv[kMaxD];
+    __shared__ double yv[kMaxD];
+    __shared__ double l1[kMaxD];
+    __shared__ double l2[kMaxD];
+    __shared__ double sY[kMaxD + 1];
+    __shared__ double sU[kMaxD + 1];
+    __shared__ double part[4][256];
+    __shared__ double red[kRevThreads / 64];
+    const int dmax = S.dmax;
+    const double* Gi = S.G + (int64_t)dmax * dmax;   // row-major G^{-1}
+    const int dk = ell + k;
+    if (c_done >= 0) {
+        // (L w_c) . (L t_c) of the column just finished: its part of d loss / d mu
+        const double a = block_sum(thread_strided_sum(R.ldot, R.nldot, kRevThreads), red);
+        if (threadIdx.x == 0) R.rs[0] += S.cs[c_done] * a;
+        __syncthreads();
+    }
+    if (j >= 0) {
+        const int dj = ell + j;
+        for (int i = threadIdx.x; i < dj; i += kRevThreads) {
+            gv[i] = strided_sum(S.gpart + i, dmax, S.ngt);
+            yv[i] = S.yh[(int64_t)dj * dmax + i];
+        }
+        __syncthreads();
+        tri_mv(Gi, dmax, 1, dj, 1, gv, tvv);   // G_j^{-T} W_j^T x^_j
+        __syncthreads();
+        tri_mv(Gi, dmax, 1, dj, 0, tvv, uv);   // u_j = N_j^{-1} W_j^T x^_j
+        __syncthreads();
+        for (int i = threadIdx.x; i < dj; i += kRevThreads) {
+            R.uh[(int64_t)dj * dmax + i] = uv[i];
+            R.ubar[i] += uv[i];
+        }
+        tri_mv2(S.RL, 1, dmax, dj, uv, yv, l1, l2);   // B_L u_j, B_L y_j (as R_L products)
+        __syncthreads();
+        double pr = 0.0;
+        for (int i = threadIdx.x; i < dj; i += kRevThreads) pr += l1[i] * l2[i];
+        pr = block_sum(pr, red);
+        if (threadIdx.x == 0) R.rs[0] -= pr;   // -(B_L u_j) . (B_L y_j)
+        __syncthreads();
+    }
+    if (c >= 0) {
+        const int i0 = max(0, c - ell + 1);   // solves with more than c columns
+        for (int i = i0 + (int)threadIdx.x; i <= k; i += kRevThreads) {
+            sY[i] = S.yh[(int64_t)(ell + i) * dmax + c];
+            sU[i] = R.uh[(int64_t)(ell + i) * dmax + c];
+        }
+        __syncthreads();
+        for (int i = i0 + (int)threadIdx.x; i < k; i += kRevThreads) R.kap[i] = sY[i];
+        if (threadIdx.x == 0) {
+            R.rs[1] = sY[k];
+            R.rs[2] = R.ubar[c];
+        }
+        // C[:, c] = sum_i u_i (y_i)_c + y_i (u_i)_c, rows r < dk: group g sums the
+        // solves i0 + g, i0 + g + 4, ..., eight in flight; groups added in order
+        const int g = threadIdx.x >> 8, rl = threadIdx.x & 255;
+        for (int r0 = 0; r0 < dk; r0 += 256) {
+            const int r = r0 + rl;
+            const int rr = min(r, dk - 1);
+            double acc = 0.0;
+            for (int i = i0 + g; i <= k; i += 32) {
+                double a[8], b[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int ii = min(i + 4 * q, k);
+                    a[q] = R.uh[(int64_t)(ell + ii) * dmax + rr];
+                    b[q] = S.yh[(int64_t)(ell + ii) * dmax + rr];
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (i + 4 * q <= k) acc += a[q] * sY[i + 4 * q] + b[q] * sU[i + 4 * q];
+            }
+            part[g][rl] = acc;
+            __syncthreads();
+            if (g == 0 && r < dk) gv[r] = ((part[0][rl] + part[1][rl]) + part[2][rl]) + part[3][rl];
+            __syncthreads();
+        }
+        tri_apply2(S.RA, S.RL, 1, dmax, dk, gv, l1, l2);   // R_A C[:, c], R_L C[:, c]
+        __syncthreads();
+        for (int r = threadIdx.x; r < dk; r += kRevThreads) {
+            R.vA[r] = l1[r];
+            R.vL[r] = l2[r];
+        }
+    }
+    if (fin) {
+        // the S_A b term of d loss / d b: S_A^T B_A ubar = S_A^T Q_A R_A ubar (negated
+        // for the forward product's subtraction)
+        for (int i = threadIdx.x; i < dk; i += kRevThreads) gv[i] = R.ubar[i];
+        __syncthreads();
+        tri_mv(S.RA, 1, dmax, dk, 0, gv, l1);
+        __syncthreads();
+        for (int r = threadIdx.x; r < dk; r += kRevThreads) {
+            R.vA[r] = -l1[r];
+            R.vL[r] = 0.0;
+        }
+        if (threadIdx.x == 0) R.rs[2] = 0.0;
+    }
+}
+
+// zA = Q_A vA - S_A b rs[2], zL = Q_L vL: workgroup b < nbs takes 64 rows of
+// the A side, the others of the L side; the four waves split the columns
+// (every fourth), their sums added in wave order
+__global__ __launch_bounds__(kBlock) void k_rev_svec(State S, Rev R, int dk, int nbs) {
+    __shared__ double vv[kMaxD];
+    __shared__ double part[kWaves][64];
+    const bool isA = (int)blockIdx.x < nbs;
+    const int blk = isA ? blockIdx.x : blockIdx.x - nbs;
+    const double* __restrict__ Q = isA ? S.QA : S.QL;
+    const double* __restrict__ v = isA ? R.vA : R.vL;
+    for (int i = threadIdx.x; i < dk; i += kBlock) vv[i] = v[i];
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int s = S.s;
+    const int r = blk * 64 + lane;
+    const int rr = min(r, s - 1);
+    double acc = 0.0;
+    int q = wave;
+    for (; q + 7 * kWaves < dk; q += 8 * kWaves) {
+        double w[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) w[u] = Q[(int64_t)(q + u * kWaves) * s + rr];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += w[u] * vv[q + u * kWaves];
+    }
+    for (; q < dk; q += kWaves) acc += Q[(int64_t)q * s + rr] * vv[q];
+    part[wave][lane] = acc;
+    __syncthreads();
+    if (wave == 0 && r < s) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) t += part[w][lane];
+        if (isA)
+            R.zA[r] = t - S.cb[r] * R.rs[2];
+        else
+            R.zL[r] = t;
+    }
+}
+
+// sum_q sign_q(i) z[bin_q(i)] over the cached pattern of row i (no scale)
+template <int Z>
+__device__ __forceinline__ double pattern_gather(const int16_t* __restrict__ pat, int64_t i,
+                                                 const double* __restrict__ z) {
+    if constexpr (Z == 0) {
+        return 0.0;
+    } else {
+        int bin[Z];
+        double sg[Z];
+        load_pattern<Z>(pat, i, bin, sg);
+        double a = 0.0;
+#pragma unroll
+        for (int q = 0; q < Z; ++q) a += sg[q] * z[bin[q]];
+        return a;
+    }
+}
+
+// u = A x - S_A^T zA, t = L x - S_L^T zL, and per-workgroup partials of
+// (L wc) . (L x).  Z > 0: the sparse-sign transposes formed per row from the
+// cached pattern (zeta entries of the s-vector); Z = 0: taken from bA, bL.
+template <typename T, int Z>
+__global__ __launch_bounds__(kBlock) void k_rev_forward(Csr A, Csr L, int nbA,
+                                                       const double* __restrict__ x,
+                                                       const double* __restrict__ bA,
+                                                       const double* __restrict__ bL,
+                                                       const double* __restrict__ zA,
+                                                       const double* __restrict__ zL,
+                                                       const int16_t* __restrict__ patA,
+                                                       const int16_t* __restrict__ patL,
+                                                       double zscale,
+                                                       const double* __restrict__ wc,
+                                                       double* __restrict__ u,
+                                                       double* __restrict__ t,
+                                                       double* __restrict__ ldot) {
+    __shared__ double red[kWaves];
+    const int blk_all = blockIdx.x;
+    const bool isA = blk_all < nbA;
+    const Csr& M = isA ? A : L;
+    const int nb = isA ? nbA : (int)gridDim.x - nbA;
+    const int lb = isA ? blk_all : blk_all - nbA;
+    const int blk = xcd_order(lb, nb);
+    double dot = 0.0;
+    SGKS_LANES_SWITCH(M.lanes, {
+        const int64_t row = (int64_t)blk * (kBlock / V) + threadIdx.x / V;
+        const int g = threadIdx.x % V;
+        if (row < M.rows) {
+            const double v = row_dot<V, T>(M, x, row, g);
+            const double lw = isA ? 0.0 : row_dot<V, T>(M, wc, row, g);
+            if (g == 0) {
+                const double sub = Z > 0 ? zscale * pattern_gather<Z>(isA ? patA : patL, row,
+                                                                      isA ? zA : zL)
+                                         : (isA ? bA[row] : bL[row]);
+                if (isA) {
+                    u[row] = v - sub;
+                } else {
+                    t[row] = v - sub;
+                    dot = v * lw;
+                }
+            }
+        }
+    })
+    if (!isA) {
+        const double tot = block_sum(dot, red);
+        if (threadIdx.x == 0) ldot[lb] = tot;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_rev_adjoint(Csr At, Csr Lt, double mu,
+                                                       const double* __restrict__ u,
+                                                       const double* __restrict__ t, int64_t n,
+                                                       const double* __restrict__ gx,
+                                                       const double* __restrict__ gcoef,
+                                                       const double* __restrict__ scale,
+                                                       double* __restrict__ dst) {
+    const int nblk = gridDim.x;
+    const int lb = xcd_order(blockIdx.x, nblk);
+    const double gc = *gcoef;
+    const double sc = scale ? *scale : 1.0;
+    SGKS_LANES_SWITCH(At.lanes, {
+        constexpr int rpg = kBlock / V;
+        const int64_t ng = (n + rpg - 1) / rpg;
+        const int64_t g0 = ng * lb / nblk, g1 = ng * (lb + 1) / nblk;
+        const int g = threadIdx.x % V;
+        for (int64_t grp = g0; grp < g1; ++grp) {
+            const int64_t row = grp * rpg + threadIdx.x / V;
+            if (row < n) {
+                double v = row_dot<V, T>(At, u, row, g);
+                v += mu * row_dot<V, T>(Lt, t, row, g);
+                if (g == 0) dst[row] = sc * (v + gc * gx[row]);
+            }
+        }
+    })
+}
+
+__global__ __launch_bounds__(kBlock) void k_lincomb(LinComb lc, int64_t n, double* __restrict__ out,
+                                                   int accumulate) {
+    double cf[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        double f = 0.0;
+        if (q < lc.nt) {
+            const LinTerm& tm = lc.t[q];
+            f = tm.h;
+            if (tm.d1) f *= tm.inv1 ? 1.0 / *tm.d1 : *tm.d1;
+            if (tm.d2) f *= *tm.d2;
+        }
+        cf[q] = f;
+    }
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        double a = accumulate ? out[i] : 0.0;
+        for (int q = 0; q < lc.nt; ++q) a += cf[q] * lc.t[q].v[i];
+        out[i] = a;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_f64(double* p, int64_t n, double v) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        p[i] = v;
+}
+
+// out[i] = sum_q sign_q(i) v[bin_q(i)] / sqrt(zeta)  (S^T v of the stream's
+// embedding: 0 S_A, 1 S_L), i < m
 template <int Z>
 __global__ __launch_bounds__(kBlock) void k_sketch_transpose(const double* __restrict__ v, int s,
-                                                            int64_t m, uint64_t seed,
+                                                            int64_t m, uint64_t seed, int stream,
                                                             int identity, double scale,
                                                             double* __restrict__ out,
                                                             int staged) {
@@ -2354,7 +2647,7 @@ __global__ __launch_bounds__(kBlock) void k_sketch_transpose(const double* __res
         } else {
             int bin[Z];
             double sg[Z];
-            sketch_column<Z>(seed, 0, i, s, bin, sg);
+            sketch_column<Z>(seed, stream, i, s, bin, sg);
             a = 0.0;
 #pragma unroll
             for (int q = 0; q < Z; ++q) a += sg[q] * vs[bin[q]];
@@ -2759,19 +3052,25 @@ void launch_backward_small(const State& S, double* v_out, double* gmu_out, hipSt
 }
 
 void launch_sketch_transpose(const State& S, const double* v, double* out, hipStream_t st) {
+    launch_sketch_transpose_side(S, 0, v, out, st);
+}
+
+void launch_sketch_transpose_side(const State& S, int side, const double* v, double* out,
+                                  hipStream_t st) {
+    const int64_t h = side ? S.p : S.m;
     if (S.sketch_mode == kSketchSrtt) {
-        hipLaunchKernelGGL(k_srtt_transpose, dim3(grid_for(S.m, kBlock, 2048)), dim3(kBlock), 0,
-                           st, v, S.s, S.m, S.rowsA, S.seed, out);
+        hipLaunchKernelGGL(k_srtt_transpose, dim3(grid_for(h, kBlock, 2048)), dim3(kBlock), 0,
+                           st, v, S.s, h, side ? S.rowsL : S.rowsA, S.seed, side, out);
         return;
     }
-    const int nb = grid_for(S.m, kBlock, 4096);
+    const int nb = grid_for(h, kBlock, 4096);
     const int staged = (size_t)S.s * sizeof(double) <= (size_t)kScatterLdsBytes ? 1 : 0;
     const size_t shm = staged ? (size_t)S.s * sizeof(double) : 0;
     const double scale = 1.0 / sqrt((double)S.zeta);
     const int ident = S.sketch_mode == 1 ? 1 : 0;
 #define SGKS_ST(Zv)                                                                        \
     hipLaunchKernelGGL((k_sketch_transpose<Zv>), dim3(nb), dim3(kBlock), shm, st, v, S.s, \
-                       S.m, S.seed, ident, scale, out, staged)
+                       h, S.seed, side, ident, scale, out, staged)
     switch (S.zeta) {
         case 2: SGKS_ST(2); break;
         case 4: SGKS_ST(4); break;
@@ -2779,6 +3078,93 @@ void launch_sketch_transpose(const State& S, const double* v, double* out, hipSt
         default: SGKS_ST(8); break;
     }
 #undef SGKS_ST
+}
+
+void launch_record_y(const State* Sdev, hipStream_t st) {
+    SGKS_LAUNCH(k_record_y, dim3(1), dim3(kBlock), 0, st, Sdev);
+}
+
+void launch_rev_small(const State& S, const Rev& R, int ell, int k, int j, int c, int c_done,
+                      int fin, hipStream_t st) {
+    hipLaunchKernelGGL(k_rev_small, dim3(1), dim3(kRevThreads), 0, st, S, R, ell, k, j, c,
+                       c_done, fin);
+}
+
+void launch_rev_svec(const State& S, const Rev& R, int dk, hipStream_t st) {
+    const int nbs = (S.s + 63) / 64;
+    hipLaunchKernelGGL(k_rev_svec, dim3(2 * nbs), dim3(kBlock), 0, st, S, R, dk, nbs);
+}
+
+void launch_rev_tgemv(const State& S, const Rev& R, int i0, int ncols, hipStream_t st) {
+    launch_gemv_plain(S, R.E + (int64_t)i0 * S.n, R.kap + i0, ncols, nullptr, R.tv, st);
+}
+
+void launch_rev_forward(const State& S, const Rev& R, const double* wc, hipStream_t st) {
+    int nbA = 0;
+    const int nb = forward_blocks(S, true, &nbA);
+    const bool pat = S.sketch_mode == kSketchSparseSign && S.patA && S.patL;
+    if (!pat) {   // the transposes of the other sketches in launches of their own
+        launch_sketch_transpose_side(S, 0, R.zA, R.bA, st);
+        launch_sketch_transpose_side(S, 1, R.zL, R.bL, st);
+    }
+    const double zs = 1.0 / sqrt((double)S.zeta);
+#define SGKS_RF(Tv, Zv)                                                                      \
+    hipLaunchKernelGGL((k_rev_forward<Tv, Zv>), dim3(nb), dim3(kBlock), 0, st, S.A, S.L, nbA, \
+                       (const double*)R.tv, (const double*)R.bA, (const double*)R.bL,         \
+                       (const double*)R.zA, (const double*)R.zL, S.patA, S.patL, zs, wc, S.u, \
+                       S.t, R.ldot)
+#define SGKS_RF_Z(Tv)                                  \
+    if (!pat) {                                        \
+        SGKS_RF(Tv, 0);                                \
+    } else {                                           \
+        switch (S.zeta) {                              \
+            case 2: SGKS_RF(Tv, 2); break;             \
+            case 4: SGKS_RF(Tv, 4); break;             \
+            case 16: SGKS_RF(Tv, 16); break;           \
+            default: SGKS_RF(Tv, 8); break;            \
+        }                                              \
+    }
+    if (S.vdt == 0) {
+        SGKS_RF_Z(float)
+    } else {
+        SGKS_RF_Z(double)
+    }
+#undef SGKS_RF_Z
+#undef SGKS_RF
+}
+
+void launch_rev_adjoint(const State& S, const Rev& R, const double* gx, const double* scale,
+                        double* dst, hipStream_t st) {
+    const int nb = adjoint_blocks(S);
+    if (S.vdt == 0)
+        hipLaunchKernelGGL(k_rev_adjoint<float>, dim3(nb), dim3(kBlock), 0, st, S.At, S.Lt, S.mu,
+                           (const double*)S.u, (const double*)S.t, S.n, gx,
+                           (const double*)(R.rs + 1), scale, dst);
+    else
+        hipLaunchKernelGGL(k_rev_adjoint<double>, dim3(nb), dim3(kBlock), 0, st, S.At, S.Lt, S.mu,
+                           (const double*)S.u, (const double*)S.t, S.n, gx,
+                           (const double*)(R.rs + 1), scale, dst);
+}
+
+void launch_gemvt_mat(const State& S, const double* M, const double* v, int ncols, hipStream_t st) {
+    const size_t shm = (size_t)S.gt_rows * sizeof(double);
+    hipLaunchKernelGGL(k_gemvt, dim3(S.ngt), dim3(kBlock), shm, st, M, (const double*)S.cs, v,
+                       (const int*)S.d, ncols, S.n, S.gt_rows, S.gpart, S.dmax);
+}
+
+void launch_lincomb(const LinComb& lc, int64_t n, double* out, bool accumulate, hipStream_t st) {
+    hipLaunchKernelGGL(k_lincomb, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, st, lc, n, out,
+                       accumulate ? 1 : 0);
+}
+
+void launch_gemv_plain(const State& S, const double* M, const double* coef, int ncols,
+                       const double* base, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_gemv, dim3(gemv_blocks(S)), dim3(kBlock), 0, st, M, (const double*)nullptr,
+                       coef, (const int*)S.d, ncols, S.n, base, out, (const int32_t*)nullptr);
+}
+
+void launch_fill(double* p, int64_t n, double v, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, st, p, n, v);
 }
 
 void launch_scaled_W_cols(const State& S, int col0, int ncols, double* dst, hipStream_t st) {

@@ -54,6 +54,7 @@ class Options(ctypes.Structure):
                 ("lanes_At", ctypes.c_int32), ("append_groups", ctypes.c_int32),
                 ("graph", ctypes.c_int32), ("gradient_form", ctypes.c_int32),
                 ("autotune", ctypes.c_int32), ("method", ctypes.c_int32),
+                ("keep_history", ctypes.c_int32),
                 ("order", ctypes.c_void_p),
                 ("stream", ctypes.c_void_p),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
@@ -101,6 +102,9 @@ def load_library(path=LIB_PATH):
     L.sgks_backward.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                 P(ctypes.c_double)]
     L.sgks_backward.restype = ctypes.c_int
+    L.sgks_backward_total.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      P(ctypes.c_double), P(ctypes.c_double)]
+    L.sgks_backward_total.restype = ctypes.c_int
     L.sgks_copy_state.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                   ctypes.c_int64]
     L.sgks_copy_state.restype = ctypes.c_int64
@@ -188,7 +192,7 @@ def _check(code, where):
 
 def make_options(lib, vdt, stream, *, ell=3, max_iters=200, zeta=8, refine_steps=0, qr_passes=2,
                  sketch="sparse_sign", lanes_A=0, lanes_At=0, append_groups=0, graph=False,
-                 autotune=False, gradient="maintained", method="sgks"):
+                 autotune=False, gradient="maintained", method="sgks", keep_history=False):
     o = Options()
     lib.sgks_default_options(ctypes.byref(o))
     o.ell, o.max_iters, o.zeta, o.value_dtype = ell, max_iters, zeta, vdt
@@ -201,6 +205,7 @@ def make_options(lib, vdt, stream, *, ell=3, max_iters=200, zeta=8, refine_steps
     if method not in ("sgks", "gks"):
         raise ValueError(method)
     o.method = METHOD_GKS if method == "gks" else METHOD_SGKS
+    o.keep_history = int(bool(keep_history))
     o.stream = ctypes.c_void_p(stream.cuda_stream)
     return o
 
@@ -273,6 +278,25 @@ class SGKS:
                                        ctypes.c_void_p(gb.data_ptr()), ctypes.byref(gm)),
                "sgks_backward")
         return gb, gm.value
+
+    def backward_total(self, grad_x, with_error=False):
+        """(d loss/d b, d loss/d mu) through every expansion (sgks_backward_total);
+        the solver must be created with keep_history=True.  with_error: also the
+        rounding-error estimate d eps kappa(G)^2.  Warns when it exceeds 1e-3."""
+        import torch
+        grad_x = grad_x.to(torch.float64).contiguous()
+        gb = torch.empty(self.m, dtype=torch.float64, device=self.b.device)
+        gm, est = ctypes.c_double(), ctypes.c_double()
+        _check(self._lib.sgks_backward_total(self._h, ctypes.c_void_p(grad_x.data_ptr()),
+                                             ctypes.c_void_p(gb.data_ptr()), ctypes.byref(gm),
+                                             ctypes.byref(est)),
+               "sgks_backward_total")
+        if not est.value <= 1e-3:
+            import warnings
+            warnings.warn(f"sgks_backward_total: estimated relative error {est.value:.1e} "
+                          "(d eps kappa(G)^2); the gradient is dominated by rounding",
+                          RuntimeWarning, stacklevel=2)
+        return (gb, gm.value, est.value) if with_error else (gb, gm.value)
 
     def profile(self, on=True):
         _check(self._lib.sgks_profile_enable(self._h, 1 if on else 0), "sgks_profile_enable")
@@ -516,7 +540,9 @@ _FUNCTION = None
 
 
 def _function_class():
-    """torch.autograd.Function whose backward is the library's frozen-basis adjoint."""
+    """torch.autograd.Function whose backward is the library's frozen-basis adjoint
+    (sgks_backward) or, with adjoint="total", the total derivative through every
+    expansion (sgks_backward_total)."""
     global _FUNCTION
     if _FUNCTION is not None:
         return _FUNCTION
@@ -526,6 +552,7 @@ def _function_class():
         """x_k = sGKS(b, mu).  backward: d loss/d b = S_A^T Q_A R_A z and
         d loss/d mu = -(R_L z).(R_L y), z = H^{-1} W^T grad_x, with the basis W and
         the factors Q_A, R_A, R_L of the forward solve held fixed (sgks_backward);
+        with adjoint="total" the derivative of the whole map (sgks_backward_total).
         W stays on the device between the two calls."""
 
         @staticmethod
@@ -533,16 +560,24 @@ def _function_class():
             if opts.get("refine_steps", 0) and (ctx.needs_input_grad[0] or ctx.needs_input_grad[1]):
                 raise ValueError("sgks_solve: no backward with refine_steps > 0 (the adjoint "
                                  "is that of the unrefined projected solve)")
+            opts = dict(opts)
+            adjoint = opts.pop("adjoint", "frozen")
+            if adjoint not in ("frozen", "total"):
+                raise ValueError(adjoint)
+            if adjoint == "total":
+                opts["keep_history"] = True
             S = SGKS(A, L, b.detach().contiguous(), float(mu), s, seed, **opts)
             S.iterate(k)
             ctx.solver = S
+            ctx.total = adjoint == "total"
             ctx.b_dtype = b.dtype
             ctx.mu_meta = (mu.dtype, mu.device, mu.shape) if torch.is_tensor(mu) else None
             return S.solution()
 
         @staticmethod
         def backward(ctx, grad_x):
-            gb, gmu = ctx.solver.backward(grad_x)
+            gb, gmu = (ctx.solver.backward_total(grad_x) if ctx.total
+                       else ctx.solver.backward(grad_x))
             gmu_t = None
             if ctx.mu_meta is not None:
                 dt, dev, shp = ctx.mu_meta
@@ -554,6 +589,7 @@ def _function_class():
 
 
 def sgks_solve(A: DeviceCsr, L: DeviceCsr, b, mu, s, k, seed=0, **opts):
-    """Differentiable x_k (float64 tensor) of k sGKS expansions; b and mu may require grad."""
+    """Differentiable x_k (float64 tensor) of k sGKS expansions; b and mu may require grad.
+    adjoint="frozen" (default) or "total" selects the backward (see _function_class)."""
     opts.setdefault("max_iters", max(int(k), 1))
     return _function_class().apply(b, mu, A, L, int(s), int(seed), int(k), opts)

@@ -256,6 +256,47 @@ def host_cores():
 # GPU measurement of one workload
 # ----------------------------------------------------------------------------
 
+def total_adjoint_cost(G, torch, np, P, order, reps=3):
+    """The total-derivative adjoint (sgks_backward_total) at the workload's k, outside
+    the timed steps: the forward solve with its y history recorded, then the reverse
+    sweep, each timed with the stream synchronised (median of reps), and the sweep's
+    rounding-error estimate d eps kappa(G)^2 (large once the basis is numerically
+    rank-deficient: the gradient is then dominated by rounding)."""
+    import warnings
+    from workloads.generators import image_order
+    dev = torch.device("cuda:0")
+    A, L, b = G.upload_problem(P)
+    opts = dict(ell=P.ell, max_iters=P.k, zeta=P.zeta, refine_steps=0, keep_history=True)
+    io = image_order(P) if order else None
+    if io is not None:
+        opts["order"] = torch.as_tensor(io, dtype=torch.int32, device=dev)
+    g = torch.as_tensor(2.0 * (np.zeros(P.n) - P.x_true), device=dev)
+    fwd, bwd, est = [], [], None
+    for r in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S = G.SGKS(A, L, b, P.mu, P.s, P.seed, **opts)
+        S.iterate(P.k)
+        x = S.solution()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        gx = 2.0 * x + g
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore", RuntimeWarning)
+            _, _, est = S.backward_total(gx, with_error=True)
+        t3 = time.perf_counter()
+        S.close()
+        if r:   # the first round warms up
+            fwd.append(t1 - t0)
+            bwd.append(t3 - t2)
+    f, bk = 1e3 * float(np.median(fwd)), 1e3 * float(np.median(bwd))
+    return {"k": P.k, "forward_with_history_ms": f, "backward_ms": bk,
+            "backward_over_forward": bk / f, "err_est": est,
+            "loss": "||x_k - x_true||^2", "timed": "outside the headline steps"}
+
+
 def measure(G, torch, P, steps, warmup, *, backward, profile, graph=False, autotune=False,
             gradient="maintained", order=True):
     """Time `steps` complete solves of P (create + k expansions + x_k [+ backward]).
@@ -615,6 +656,8 @@ def main():
                          "the Morton order of each image frame")
     ap.add_argument("--no-plain", action="store_true",
                     help="with --workload batch: time the batched solve only (no plain solves)")
+    ap.add_argument("--no-total-adjoint", action="store_true",
+                    help="skip the total-derivative adjoint measured beside the headline")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -707,6 +750,11 @@ def main():
             out["adjoint_vs_plain"].update(adjoint_rel_err(G, np, P, res))
         except Exception as e:      # reported, never fatal to the measurement
             out["adjoint_vs_plain"]["rel_err_error"] = repr(e)
+        if not args.no_total_adjoint:
+            try:
+                out["total_adjoint"] = total_adjoint_cost(G, torch, np, P, order)
+            except Exception as e:      # reported, never fatal to the measurement
+                out["total_adjoint"] = {"error": repr(e)}
     if not args.no_extras:
         sec = {}
         for name in ("deblur2d", "ct2d"):

@@ -2384,10 +2384,21 @@ __global__ __launch_bounds__(kRevThreads) void k_rev_small(State S, Rev R, int e
     }
     if (j >= 0) {
         const int dj = ell + j;
-        for (int i = threadIdx.x; i < dj; i += kRevThreads) {
-            gv[i] = strided_sum(S.gpart + i, dmax, S.ngt);
-            yv[i] = S.yh[(int64_t)dj * dmax + i];
+        // W_j^T x^_j from the ngt partials: tpc lanes of a wave per column (the largest
+        // power of two with tpc dj <= kRevThreads), each summing every tpc-th partial in
+        // order, then a shuffle tree (fixed order)
+        int tpc = 64;
+        while (tpc > 1 && tpc * dj > kRevThreads) tpc >>= 1;
+        for (int base = 0; base < dj; base += kRevThreads / tpc) {
+            const int i = base + (int)threadIdx.x / tpc, l = threadIdx.x % tpc;
+            const int cnt = l < S.ngt ? (S.ngt - l + tpc - 1) / tpc : 0;
+            double a = (i < dj) ? strided_sum(S.gpart + (int64_t)l * dmax + min(i, dj - 1),
+                                              (int64_t)tpc * dmax, cnt)
+                                : 0.0;
+            for (int off = tpc / 2; off > 0; off >>= 1) a += __shfl_xor(a, off);
+            if (i < dj && l == 0) gv[i] = a;
         }
+        for (int i = threadIdx.x; i < dj; i += kRevThreads) yv[i] = S.yh[(int64_t)dj * dmax + i];
         __syncthreads();
         tri_mv(Gi, dmax, 1, dj, 1, gv, tvv);   // G_j^{-T} W_j^T x^_j
         __syncthreads();

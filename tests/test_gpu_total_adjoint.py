@@ -248,3 +248,55 @@ def test_total_adjoint_error_estimate_bounds_the_rounding_spread():
         assert abs(gm1 - gm2) <= est * abs(gm1)
         if k == 30:
             assert est <= 1e-6
+
+
+def test_total_adjoint_graph_replay_workspace_and_profiling():
+    """The y history is recorded inside captured graphs of 1 and 8 expansions and in a
+    caller's workspace (no device allocation), and profiling does not change it: every
+    variant gives the kernel-by-kernel gradient bit for bit."""
+    P = problem("dynamic_ct", "small")
+    k = 12
+    say("case total adjoint graph/workspace/profiling")
+    g_x = seed_grad(P.n)
+    gt = torch.as_tensor(g_x, device="cuda")
+    S0, gb0, gm0, rc, it = gpu_total(P, k, g_x)
+    S0.close()
+    A, L, b = G.upload_problem(P)
+    opts = dict(ell=P.ell, zeta=P.zeta, max_iters=k, refine_steps=0, keep_history=True)
+    nb = G.workspace_bytes(A, L, P.s, value_dtype=P.dtype, **opts)
+    nb0 = G.workspace_bytes(A, L, P.s, value_dtype=P.dtype,
+                            **{**opts, "keep_history": False})
+    assert nb > nb0 + 8 * P.n * k    # E alone is n max_iters doubles
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    for kw in ({"graph": True}, {"workspace": ws}, {"profile": True}):
+        prof = kw.pop("profile", False)
+        S = G.SGKS(A, L, b, P.mu, P.s, P.seed, **opts, **kw)
+        if prof:
+            S.profile(True)
+        S.iterate(k)
+        gb, gm = S.backward_total(gt)
+        assert np.array_equal(gb.cpu().numpy(), gb0) and gm == gm0, kw
+        S.close()
+
+
+def test_total_adjoint_after_breakdown_is_the_closed_form():
+    """A = L = I with identity sketches: span{b} holds the solution, the first expansion
+    breaks down, and x = b / (1 + mu) for every b.  The reverse sweep over the expansions
+    done (none) gives d(g.x)/db = g / (1 + mu) and d(g.x)/dmu = -(g.b) / (1 + mu)^2."""
+    I = sp.identity(64, format="csr")
+    I.indices = I.indices.astype(np.int32)
+    I.indptr = I.indptr.astype(np.int32)
+    bh = np.linspace(1.0, 2.0, 64)
+    A = G.DeviceCsr.from_scipy(I)
+    b = torch.as_tensor(bh, device="cuda")
+    mu = 0.5
+    g = seed_grad(64, 3)
+    say("case total adjoint after breakdown")
+    S = G.SGKS(A, A, b, mu, 64, 0, ell=1, max_iters=4, sketch="identity", keep_history=True)
+    S.iterate(4)
+    rc, it = S.status()
+    assert rc == G.BREAKDOWN and it == 0
+    gb, gm = S.backward_total(torch.as_tensor(g, device="cuda"))
+    S.close()
+    assert rel(gb.cpu().numpy(), g / (1 + mu)) <= 1e-13
+    assert abs(gm + (g @ bh) / (1 + mu) ** 2) <= 1e-13 * abs(g @ bh)

@@ -144,8 +144,8 @@ typedef struct {
                                 of sgks_backward_total (about 2 dmax^2 + n (max_iters + ell + 4)
                                 + m + p + 2 s doubles more); needs method SGKS, the
                                 maintained gradient form and refine_steps = 0, else
-                                SGKS_ERR_INVALID_ARG at create; not for batches.  0 = off
-                                (default)                                                      */
+                                SGKS_ERR_INVALID_ARG at create; in a batch every problem
+                                keeps its history.  0 = off (default)                          */
     const int32_t *order;    /* NULL (default) or device array of n int32: a permutation of the
                                 unknowns the context works in internally, order[i] = the
                                 caller's unknown at internal position i (e.g. pixels along a

@@ -245,8 +245,8 @@ int enqueue_iteration(const sgks::Plan& P, int refine_steps, Profiler* pr, hipSt
     }
     if (fork && hipStreamWaitEvent(st, ss->join, 0) != hipSuccess) return SGKS_ERR_HIP;
     if (refine_steps > 0) enqueue_refinement(P, refine_steps, pr, st);
-    // y of this solve, for the total-derivative adjoint (one problem)
-    if (P.np == 1 && P.host[0].yh) sgks::launch_record_y(P.SS, st);
+    // y of this solve, for the total-derivative adjoint
+    if (P.record_y) sgks::launch_record_y(P.SS, P.np, st);
     return SGKS_OK;
 }
 
@@ -1057,7 +1057,7 @@ int sgks_create(const sgks_csr* A, const sgks_csr* L, const void* b, double mu, 
     if (!S.Mnt && c->opt.refine_steps > 0)
         enqueue_refinement(c->plan, c->opt.refine_steps, nullptr, st);
     if (S.yh) {
-        sgks::launch_record_y(c->Sdev, st);
+        sgks::launch_record_y(c->Sdev, 1, st);
         if (c->opt.max_iters > 0) sgks::launch_fill(c->rv.ones, c->opt.max_iters, 1.0, st);
     }
     c->d_host = c->opt.ell;
@@ -1200,7 +1200,7 @@ int sgks_backward_total(sgks_ctx* c, const double* grad_x, double* grad_b, doubl
     do { if ((expr) != hipSuccess) return SGKS_ERR_HIP; } while (0)
     if (!c || !grad_x || !grad_b) return SGKS_ERR_INVALID_ARG;
     State& S = c->S;
-    if (!S.yh || c->borrowed) return SGKS_ERR_INVALID_ARG;
+    if (!S.yh) return SGKS_ERR_INVALID_ARG;
     const int stw = sync_status(c);
     if (stw < 0) return stw;
     sgks::Rev R = c->rv;
@@ -1487,7 +1487,6 @@ size_t sgks_batch_workspace_bytes(int32_t count, const sgks_problem* probs,
         o = *opt;
     else
         sgks_default_options(&o);
-    if (o.keep_history) return 0;
     std::vector<size_t> sizes;
     if (!batch_sizes(count, probs, o, sizes)) return 0;
     size_t total = 0;
@@ -1505,8 +1504,7 @@ int sgks_batch_create(int32_t count, const sgks_problem* probs, const sgks_optio
         o = *opt;
     else
         sgks_default_options(&o);
-    if (o.lanes_A || o.lanes_At || o.append_groups || o.method != SGKS_METHOD_SGKS ||
-        o.keep_history)
+    if (o.lanes_A || o.lanes_At || o.append_groups || o.method != SGKS_METHOD_SGKS)
         return SGKS_ERR_INVALID_ARG;
     for (int i = 0; i < count; ++i) {
         const int rc = sgks_validate(&probs[i].A, &probs[i].L, probs[i].b, probs[i].mu,

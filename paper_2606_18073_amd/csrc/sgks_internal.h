@@ -241,6 +241,7 @@ struct Plan {
     BTab ap1_side_hw;   // compact append with the H W column: 2 + hw_blocks per problem
     BTab adj_hw_sep;    // H W column in a launch of its own (adjoint workgroups)
     int fuse_hw;        // H W column inside the compact side launch (small total nnz)
+    int record_y;       // the problems keep the y history (keep_history, common to the set)
     BTab one;           // one workgroup per problem
 };
 
@@ -274,8 +275,8 @@ void launch_sketch_transpose(const State& S, const double* v, double* out, hipSt
 void launch_sketch_transpose_side(const State& S, int side, const double* v, double* out,
                                   hipStream_t st);
 // ----- total-derivative adjoint (reverse sweep) ----------------------------
-// row d of yh = y (one problem, device State)
-void launch_record_y(const State* Sdev, hipStream_t st);
+// row d of yh = y for each of the np problems of a device State array
+void launch_record_y(const State* Sdev, int np, hipStream_t st);
 // one-workgroup step: j >= 0 the adjoint solve of the projected problem with
 // ell + j columns (from the W^T partials in gpart); c >= 0 the small data of
 // column c; c_done >= 0 adds the L partials of column c_done to d loss / d mu;

@@ -2350,8 +2350,9 @@ __global__ __launch_bounds__(kBlock) void k_backward_small(State S, double* v_ou
 // along the column vanishes: x_k depends on the span of W only).
 // ---------------------------------------------------------------------------
 
+// one workgroup per problem
 __global__ __launch_bounds__(kBlock) void k_record_y(const State* __restrict__ SS) {
-    const State S = load_state(SS, 0);
+    const State S = load_state(SS, blockIdx.x);
     const int d = *S.d;
     double* row = S.yh + (int64_t)d * S.dmax;
     for (int i = threadIdx.x; i < d; i += kBlock) row[i] = S.y[i];
@@ -3091,8 +3092,8 @@ void launch_sketch_transpose_side(const State& S, int side, const double* v, dou
 #undef SGKS_ST
 }
 
-void launch_record_y(const State* Sdev, hipStream_t st) {
-    SGKS_LAUNCH(k_record_y, dim3(1), dim3(kBlock), 0, st, Sdev);
+void launch_record_y(const State* Sdev, int np, hipStream_t st) {
+    SGKS_LAUNCH(k_record_y, dim3(np), dim3(kBlock), 0, st, Sdev);
 }
 
 void launch_rev_small(const State& S, const Rev& R, int ell, int k, int j, int c, int c_done,
@@ -3222,6 +3223,7 @@ int plan_build(Plan& P, const State* host, const State* dev, int np, const int* 
     P.max_s = 0;
     P.max_gt_rows = 0;
     P.gradient_form = host[0].gradient_form;
+    P.record_y = host[0].yh != nullptr ? 1 : 0;
     int fwd[kMaxBatch], adj[kMaxBatch], sc[kMaxBatch], gv[kMaxBatch], gt[kMaxBatch],
         ap[kMaxBatch], apf[kMaxBatch], ap1s[kMaxBatch], one[kMaxBatch],
         gr[kMaxBatch], ap1h[kMaxBatch], ahs[kMaxBatch];

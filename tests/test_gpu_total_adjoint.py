@@ -186,7 +186,7 @@ def test_total_adjoint_autograd_order_and_resume():
 
 def test_total_adjoint_refusals():
     """Without keep_history the entry point refuses (no device work); keep_history is
-    refused with refinement, the direct gradient form, GKS and batches."""
+    refused with refinement, the direct gradient form and GKS."""
     P = problem("deblur1d", "small")
     say("case total adjoint refusals")
     S, x = G.solve_problem(P, k=2)
@@ -198,8 +198,6 @@ def test_total_adjoint_refusals():
         with pytest.raises(G.SgksError) as e:
             G.solve_problem(P, k=1, keep_history=True, **kw)
         assert e.value.code == -1
-    with pytest.raises(G.SgksError):
-        G.solve_batch([P, P], k=1, keep_history=True)
 
 
 def test_total_adjoint_dynamic_ct_full_size():
@@ -300,3 +298,21 @@ def test_total_adjoint_after_breakdown_is_the_closed_form():
     S.close()
     assert rel(gb.cpu().numpy(), g / (1 + mu)) <= 1e-13
     assert abs(gm + (g @ bh) / (1 + mu) ** 2) <= 1e-13 * abs(g @ bh)
+
+
+def test_total_adjoint_in_a_batch():
+    """Every problem of a batch (uneven sizes, one launch per step for all) keeps its y
+    history; each problem's total adjoint equals that of its plain solve bit for bit.
+    Also a batch of one problem."""
+    Ps = problem("batch", "small")
+    k = 8
+    say("case total adjoint batch", [(P.name, P.n) for P in Ps])
+    for sel in (Ps, Ps[:1]):
+        B, _ = G.solve_batch(sel, k=k, keep_history=True, refine_steps=0)
+        for i, P in enumerate(sel):
+            g = seed_grad(P.n, 30 + i)
+            gbB, gmB = B.problem(i).backward_total(torch.as_tensor(g, device="cuda"))
+            S, gbP, gmP, rc, it = gpu_total(P, k, g, ell=sel[0].ell, zeta=sel[0].zeta)
+            S.close()
+            assert np.array_equal(gbB.cpu().numpy(), gbP) and gmB == gmP, i
+        B.close()

@@ -1446,6 +1446,7 @@ void sgks_destroy(sgks_ctx* c) {
 
 struct sgks_batch {
     std::vector<sgks_ctx*> ctx;
+    std::vector<State> host;    // host copies of the States (the plan points at them)
     State* Sdev = nullptr;      // device array of the problems' States
     bool own_sdev = false;      // allocated here (not in a caller's workspace)
     sgks::Plan plan;
@@ -1535,7 +1536,8 @@ int sgks_batch_create(int32_t count, const sgks_problem* probs, const sgks_optio
         sgks_batch_destroy(B);
         return rc;
     };
-    std::vector<State> host(count);
+    std::vector<State>& host = B->host;
+    host.resize(count);
     std::vector<int> groups(count);
     for (int i = 0; i < count; ++i) {
         sgks_ctx* c = nullptr;

@@ -316,3 +316,24 @@ def test_total_adjoint_in_a_batch():
             S.close()
             assert np.array_equal(gbB.cpu().numpy(), gbP) and gmB == gmP, i
         B.close()
+
+
+def test_total_adjoint_then_iterate_further():
+    """The reverse sweep leaves the forward state intact: backward after 5 expansions,
+    5 more expansions, backward again -- equal, bit for bit, to 10 expansions then one
+    backward (and x_10 equal too)."""
+    P = problem("deblur2d", "small")
+    say("case total adjoint then iterate")
+    g_x = seed_grad(P.n)
+    gt = torch.as_tensor(g_x, device="cuda")
+    S1, _ = G.solve_problem(P, k=5, keep_history=True, refine_steps=0, max_iters=10)
+    S1.backward_total(gt)
+    S1.iterate(5)
+    gb1, gm1 = S1.backward_total(gt)
+    x1 = S1.solution().cpu().numpy()
+    S1.close()
+    S2, gb2, gm2, rc, it = gpu_total(P, 10, g_x)
+    x2 = S2.solution().cpu().numpy()
+    S2.close()
+    assert np.array_equal(x1, x2)
+    assert np.array_equal(gb1.cpu().numpy(), gb2) and gm1 == gm2

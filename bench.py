@@ -811,5 +811,21 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def _stop_helper_processes():
+    """The spawn pools start multiprocessing's resource-tracker process, which otherwise
+    exits only after it notices that this process has ended; stop it and wait for it so
+    that no process of the benchmark outlives the command."""
+    import gc
+    gc.collect()   # the pools' semaphores are unlinked and unregistered first
+    try:
+        from multiprocessing import resource_tracker
+        resource_tracker._resource_tracker._stop()
+    except Exception:
+        pass
+
+
 if __name__ == "__main__":
-    main()
+    try:
+        main()
+    finally:
+        _stop_helper_processes()

@@ -52,9 +52,13 @@ def oracle_total(P, k, g_x, sketch="sparse_sign", permute=None, ell=None):
 
 
 def gpu_total(P, k, g_x, **kw):
+    import warnings
     kw.setdefault("refine_steps", 0)
     S, x = G.solve_problem(P, k=k, keep_history=True, **kw)
-    gb, gmu = S.backward_total(torch.as_tensor(g_x, device="cuda"))
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore", RuntimeWarning)   # the estimate is logged instead
+        gb, gmu, est = S.backward_total(torch.as_tensor(g_x, device="cuda"), with_error=True)
+    say(f"  error estimate d eps kappa(G)^2 = {est:.2e}")
     rc, it = S.status()
     return S, gb.cpu().numpy(), gmu, rc, it
 
@@ -337,3 +341,13 @@ def test_total_adjoint_then_iterate_further():
     S2.close()
     assert np.array_equal(x1, x2)
     assert np.array_equal(gb1.cpu().numpy(), gb2) and gm1 == gm2
+
+
+@pytest.mark.parametrize("name", ["ct_exp2", "traveltime_exp3", "dynamic_ct_exp4"])
+def test_total_adjoint_paper_shapes_small(name):
+    """The paper's Exp. 2-4 shapes at small size; travel time has s = 1,500, beyond the
+    one-workgroup append (the multi-workgroup append chain)."""
+    P = problem(name, "small")
+    say("case total adjoint paper shape", name, P.n, P.m, P.s, P.k)
+    S = check_against_oracle(P, P.k)
+    S.close()

@@ -949,40 +949,91 @@ __global__ __launch_bounds__(kBlock) void kb_srtt(const State* __restrict__ SS, 
     srtt_pair(S, S.u, S.t, S.nbL, sl.blk, sh);
 }
 
-constexpr int kSrttStage = 2048;   // frequencies staged in LDS at a time (transpose)
+// S^T v on the matrix cores.  With i = 256 Q + r the angle of entry (k_j, i) splits
+// as phi_{Q,j} + psi_{r,j}, phi = pi k_j (512 Q + 1) / (2 h), psi = pi k_j r / h, so
+//   (S^T v)_i = sqrt(h/s) E_i sum_j [cos psi_{r,j} alpha_{Q,j} - sin psi_{r,j} beta_{Q,j}],
+//   alpha = c_j v_j cos phi_{Q,j}, beta = c_j v_j sin phi_{Q,j}:
+// a (256 x 2s) by (2s x h/256) product whose left factor is the side's cosine and
+// sine tables (built at create).  A wave takes 64 rows r (four 16-row tiles) and
+// 32 blocks Q (two 16-wide tiles); the right operand is formed on the fly, one
+// sincospi per lane and tile for each step of 4 frequencies; the sine part goes
+// into the same accumulator with its sign folded into the operand.
+constexpr int kSrttTQ = 2;   // 16-wide Q tiles per wave of the transpose
 
-// out_i = sqrt(m/s) E_i sum_j c_{k_j} cos(pi k_j (2 i + 1) / (2 m)) v_j  (S_A^T v)
-__global__ __launch_bounds__(kBlock) void k_srtt_transpose(const double* __restrict__ v, int s,
-                                                          int64_t m, const int32_t* __restrict__ rows,
-                                                          uint64_t seed, int stream,
-                                                          double* __restrict__ out) {
-    __shared__ double vs[kSrttStage];
-    __shared__ int32_t ks_[kSrttStage];
-    const uint64_t gam = 0x9E3779B97F4A7C15ull;
-    const uint64_t ksg = mix64(seed + gam * (uint64_t)(stream + 3));
-    const double sc = sqrt((double)m / (double)s);
-    for (int64_t i0 = (int64_t)blockIdx.x * kBlock; i0 < m; i0 += (int64_t)gridDim.x * kBlock) {
-        const int64_t i = i0 + threadIdx.x;
-        double acc = 0.0;
-        for (int j0 = 0; j0 < s; j0 += kSrttStage) {
-            const int nj = min(kSrttStage, s - j0);
-            __syncthreads();
-            for (int q = threadIdx.x; q < nj; q += kBlock) {
-                const int k = rows[j0 + q];
-                ks_[q] = k;
-                vs[q] = v[j0 + q] * (k == 0 ? sqrt(1.0 / (double)m) : sqrt(2.0 / (double)m));
+__global__ __launch_bounds__(kBlock) void k_srtt_transpose_mfma(
+    const double* __restrict__ vA, const double* __restrict__ vL, int s, int spad, int64_t m,
+    int64_t p, const int32_t* __restrict__ rowsA, const int32_t* __restrict__ rowsL,
+    const double* __restrict__ TA, const double* __restrict__ TL, uint64_t seed, int nbA,
+    double* __restrict__ outA, double* __restrict__ outL) {
+    const bool isA = (int)blockIdx.x < nbA;
+    const int b = isA ? blockIdx.x : blockIdx.x - nbA;
+    const int64_t h = isA ? m : p;
+    const double* __restrict__ v = isA ? vA : vL;
+    const int32_t* __restrict__ rows = isA ? rowsA : rowsL;
+    const double* __restrict__ T = isA ? TA : TL;
+    double* __restrict__ out = isA ? outA : outL;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t nQ = (h + kSrttB - 1) / kSrttB;
+    const int64_t Q0 = (int64_t)b * 16 * kSrttTQ;
+    // A operand: lane l holds A[r = l % 16][kk = l / 16] = T[j0 + l / 16][r0 + l % 16]
+    const double* Tc = T + (int64_t)(lane >> 4) * kSrttB + 64 * w + (lane & 15);
+    const double* Tsn = Tc + (int64_t)spad * kSrttB;
+    const double c0 = sqrt(1.0 / (double)h), c1 = sqrt(2.0 / (double)h);
+    sgks_double4 acc[kSrttTQ][4];
+#pragma unroll
+    for (int qt = 0; qt < kSrttTQ; ++qt)
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) acc[qt][rt] = sgks_double4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+    for (int j0 = 0; j0 < spad; j0 += 4) {
+        // B operand: lane l holds B[kk = l / 16][Q = l % 16]
+        const int j = j0 + (lane >> 4);
+        const bool on = j < s;
+        const double vj = on ? v[j] : 0.0;
+        const int64_t kj = on ? rows[j] : 0;
+        const double cj = (kj == 0 ? c0 : c1) * vj;
+        double bc[kSrttTQ], bs[kSrttTQ];
+#pragma unroll
+        for (int qt = 0; qt < kSrttTQ; ++qt) {
+            const int64_t Q = Q0 + 16 * qt + (lane & 15);
+            const int64_t a = (kj * (2 * kSrttB * Q + 1)) % (4 * h);   // phi mod 2 pi
+            double sn, cs;
+            sincospi((double)a / (double)(2 * h), &sn, &cs);
+            bc[qt] = cj * cs;
+            bs[qt] = -cj * sn;
+        }
+        double tc[4], ts[4];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+            tc[rt] = Tc[(int64_t)j0 * kSrttB + 16 * rt];
+            ts[rt] = Tsn[(int64_t)j0 * kSrttB + 16 * rt];
+        }
+#pragma unroll
+        for (int qt = 0; qt < kSrttTQ; ++qt)
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) {
+                acc[qt][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(tc[rt], bc[qt], acc[qt][rt], 0, 0, 0);
+                acc[qt][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ts[rt], bs[qt], acc[qt][rt], 0, 0, 0);
             }
-            __syncthreads();
-            if (i < m)
-                for (int q = 0; q < nj; ++q) {
-                    const int64_t r = ((int64_t)ks_[q] * (2 * i + 1)) % (4 * m);
-                    acc += cospi((double)r / (double)(2 * m)) * vs[q];
+    }
+    // element t of lane l holds D[r = 4 t + l / 16][Q = l % 16]
+    const uint64_t gam = 0x9E3779B97F4A7C15ull;
+    const uint64_t ks = mix64(seed + gam * (uint64_t)((isA ? 0 : 1) + 3));
+    const double sc = sqrt((double)h / (double)s);
+#pragma unroll
+    for (int qt = 0; qt < kSrttTQ; ++qt) {
+        const int64_t Q = Q0 + 16 * qt + (lane & 15);
+        if (Q >= nQ) continue;
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int64_t i = Q * kSrttB + 64 * w + 16 * rt + 4 * t + (lane >> 4);
+                if (i < h) {
+                    const double sg = (mix64(ks + gam * (uint64_t)(i + 1)) & 1ull) ? -1.0 : 1.0;
+                    out[i] = sc * sg * acc[qt][rt][t];
                 }
-        }
-        if (i < m) {
-            const double sg = (mix64(ksg + gam * (uint64_t)(i + 1)) & 1ull) ? -1.0 : 1.0;
-            out[i] = sc * sg * acc;
-        }
+            }
     }
 }
 
@@ -3071,8 +3122,12 @@ void launch_sketch_transpose_side(const State& S, int side, const double* v, dou
                                   hipStream_t st) {
     const int64_t h = side ? S.p : S.m;
     if (S.sketch_mode == kSketchSrtt) {
-        hipLaunchKernelGGL(k_srtt_transpose, dim3(grid_for(h, kBlock, 2048)), dim3(kBlock), 0,
-                           st, v, S.s, h, side ? S.rowsL : S.rowsA, S.seed, side, out);
+        // one side's Q tiles (the kernel's first nbA workgroups take S_A, the rest S_L)
+        const int per = 16 * kSrttTQ;
+        const int nb = (int)(((h + kSrttB - 1) / kSrttB + per - 1) / per);
+        hipLaunchKernelGGL(k_srtt_transpose_mfma, dim3(nb), dim3(kBlock), 0, st, v, v, S.s,
+                           srtt_pad(S.s), S.m, S.p, S.rowsA, S.rowsL, S.srtTA, S.srtTL, S.seed,
+                           side ? 0 : nb, out, out);
         return;
     }
     const int nb = grid_for(h, kBlock, 4096);
@@ -3115,7 +3170,15 @@ void launch_rev_forward(const State& S, const Rev& R, const double* wc, hipStrea
     int nbA = 0;
     const int nb = forward_blocks(S, true, &nbA);
     const bool pat = S.sketch_mode == kSketchSparseSign && S.patA && S.patL;
-    if (!pat) {   // the transposes of the other sketches in launches of their own
+    if (S.sketch_mode == kSketchSrtt) {
+        // both sides' transposes in one grid (the S_A side alone fills few compute units)
+        const int per = 16 * kSrttTQ;
+        const int nbA2 = (int)(((S.m + kSrttB - 1) / kSrttB + per - 1) / per);
+        const int nbL2 = (int)(((S.p + kSrttB - 1) / kSrttB + per - 1) / per);
+        hipLaunchKernelGGL(k_srtt_transpose_mfma, dim3(nbA2 + nbL2), dim3(kBlock), 0, st,
+                           (const double*)R.zA, (const double*)R.zL, S.s, srtt_pad(S.s), S.m,
+                           S.p, S.rowsA, S.rowsL, S.srtTA, S.srtTL, S.seed, nbA2, R.bA, R.bL);
+    } else if (!pat) {   // identity: the transposes in launches of their own
         launch_sketch_transpose_side(S, 0, R.zA, R.bA, st);
         launch_sketch_transpose_side(S, 1, R.zL, R.bL, st);
     }

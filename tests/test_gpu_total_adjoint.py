@@ -96,9 +96,10 @@ def test_total_adjoint_few_expansions_and_initial_dims(k, ell):
     S.close()
 
 
-@pytest.mark.parametrize("sketch", ["srtt", "identity"])
-def test_total_adjoint_other_sketches(sketch):
-    P = problem("deblur1d", "small")
+@pytest.mark.parametrize("sketch,name", [("srtt", "deblur1d"), ("srtt", "dynamic_ct"),
+                                         ("identity", "deblur1d")])
+def test_total_adjoint_other_sketches(sketch, name):
+    P = problem(name, "small")
     if sketch == "identity":
         P = _with_s(P, max(P.m, P.p))
     say("case total adjoint sketch", sketch)
@@ -351,3 +352,29 @@ def test_total_adjoint_paper_shapes_small(name):
     say("case total adjoint paper shape", name, P.n, P.m, P.s, P.k)
     S = check_against_oracle(P, P.k)
     S.close()
+
+
+def test_srtt_transposes_full_size():
+    """The SRTT transposes on the matrix cores at full size (S_A^T: m = 327,600, 1,280
+    blocks of 256 rows, the last one partial; S_L^T: p = 1,474,560): the frozen adjoint
+    (S_A^T alone) and the total adjoint (both sides at every column) against the oracle's
+    fast-DCT transposes, dynamic CT, k = 5."""
+    P = problem("dynamic_ct", "full")
+    k = 5
+    say("case srtt transposes full size", P.m, P.p, P.s)
+    g_x = seed_grad(P.n)
+    S, gb, gmu, rc, it = gpu_total(P, k, g_x, sketch="srtt")
+    assert rc == 0 and it == k
+    fb, fmu = S.backward(torch.as_tensor(g_x, device="cuda"))
+    res = O.Result(S.solution().cpu().numpy(), S.state("y"), S.state("W"), S.state("Q_A"),
+                   S.state("R_A"), S.state("Q_L"), S.state("R_L"), S.state("d_A"),
+                   S.state("G"), S.state("c_b"), k, 0, [], [])
+    S.close()
+    fb_o, fmu_o = O.frozen_adjoint_b(res, P.mu, g_x, P.A, P.L, P.s, P.seed, P.zeta,
+                                     sketch="srtt")
+    ef = rel(fb.cpu().numpy(), fb_o)
+    gb_o, gmu_o = oracle_total(P, k, g_x, sketch="srtt")
+    eb, em = rel(gb, gb_o), abs(gmu - gmu_o) / abs(gmu_o)
+    say(f"  frozen grad_b rel err {ef:.2e}; total grad_b {eb:.2e}, grad_mu {em:.2e}")
+    assert ef <= 1e-10
+    assert eb <= 1e-9 and em <= 1e-9

@@ -247,10 +247,12 @@ int sgks_backward(sgks_ctx *ctx, const double *grad_x, double *grad_b, double *g
  * Accuracy: every solve is inverted through N = G^T G, so rounding errors grow
  * like eps kappa(G)^2 (G the final stacked factor [R_A; sqrt(mu) R_L] = U G,
  * whose leading blocks are the G_j); *err_est (host, may be NULL) receives
- * d eps kappa(G)^2, kappa from power iterations on G and G^{-1}.  Where it is
- * near 1 or above (the basis of Alg. 2 is never reorthogonalised, so kappa
- * grows with k) the result is not to be trusted; the frozen adjoint
- * (sgks_backward) loses accuracy far later.
+ * d eps kappa(G)^2, kappa from power iterations on G and G^{-1}, a pessimistic
+ * bound on the relative rounding error.  The basis of Alg. 2 is never
+ * reorthogonalised, so kappa grows with k; where the estimate is large (the
+ * Python binding warns above 1e-3) the gradient is dominated by rounding; the
+ * frozen adjoint (sgks_backward) loses accuracy far later.  Returns the
+ * context's negative device status if it has one.
  * Synchronising; the context can iterate further afterwards. */
 int sgks_backward_total(sgks_ctx *ctx, const double *grad_x, double *grad_b, double *grad_mu,
                         double *err_est);

@@ -75,6 +75,12 @@ def test_validation_codes(lib):
     # identity sketch needs s >= max(m, p)
     assert _v(lib, A, L, s=150, sketch_mode=G.SKETCH_IDENTITY) == -4
     assert _v(lib, A, L, s=160, sketch_mode=G.SKETCH_IDENTITY) == 0
+    # the total-derivative adjoint's history: sGKS, maintained form, no refinement
+    assert _v(lib, A, L, keep_history=1) == 0
+    assert _v(lib, A, L, keep_history=2) == -1
+    assert _v(lib, A, L, keep_history=1, refine_steps=1) == -1
+    assert _v(lib, A, L, keep_history=1, gradient_form=G.GRADIENT_DIRECT) == -1
+    assert _v(lib, A, L, keep_history=1, method=G.METHOD_GKS) == -1
 
 
 def test_strerror(lib):
@@ -135,6 +141,7 @@ int main(void) {
     printf("%zu %zu\n", offsetof(sgks_options, workspace), offsetof(sgks_options, workspace_bytes));
     printf("%zu %zu\n", offsetof(sgks_options, method), offsetof(sgks_options, order));
     printf("%zu\n", offsetof(sgks_problem, order));
+    printf("%zu\n", offsetof(sgks_options, keep_history));
     return 0;
 }
 """
@@ -153,7 +160,7 @@ def test_struct_layouts_match_the_header(tmp_path):
     assert got == [ctypes.sizeof(O), O.graph.offset, O.stream.offset, ctypes.sizeof(P),
                    P.b.offset, P.seed.offset, ctypes.sizeof(G.CsrStruct), P.sketch_rows.offset,
                    O.workspace.offset, O.workspace_bytes.offset, O.method.offset,
-                   O.order.offset, P.order.offset]
+                   O.order.offset, P.order.offset, O.keep_history.offset]
 
 
 def test_workspace_bytes_host_only(lib):
@@ -174,6 +181,8 @@ def test_workspace_bytes_host_only(lib):
     assert ws(gradient_form=G.GRADIENT_DIRECT) < base       # no HW
     assert ws(s=50) == 0                                     # invalid: s < ell + max_iters
     assert ws(zeta=3) == 0
+    # keep_history: at least E (n x max_iters) and the y and u histories
+    assert ws(keep_history=1) - base >= 8 * 80 * 100 + 2 * 8 * 103 * 104
 
 
 def test_batch_workspace_bytes_and_checks_before_device_work(lib):

@@ -711,7 +711,8 @@ void layout_context(sgks_ctx* c, Arena& ar) {
         ar.add(&R.vL, dmax * 8);
         ar.add(&R.dz, dmax * 8);
         ar.add(&R.dp, dmax * 8);
-        ar.add(&R.kap, (size_t)(K + 1) * 8);
+        R.kld = K + 1;
+        ar.add(&R.kap, (size_t)dmax * (K + 1) * 8);
         ar.add(&R.ones, (size_t)(K > 0 ? K : 1) * 8);
         ar.add(&R.rs, 16 * 8);
     }
@@ -1222,28 +1223,59 @@ int sgks_backward_total(sgks_ctx* c, const double* grad_x, double* grad_b, doubl
     SGKS_HIP_OK(hipMemsetAsync(R.ubar, 0, (size_t)dmax * 8, st));
     SGKS_HIP_OK(hipMemsetAsync(R.rs, 0, 16 * 8, st));
 
-    // one column c: its adjoint, scaled by `scale`, into dst
-    auto column = [&](int c_, const double* scale, double* dst) {
-        sgks::launch_rev_svec(S, R, d, st);                    // Q R C[:, c] (- S_A b ubar_c)
+    // The coefficients of every column's sum over the stored e_i come from the y
+    // history alone, so the next column's sum (bandwidth bound) runs on the second
+    // stream beside this column's adjoint solve (one workgroup, latency bound).
+    sgks::launch_rev_kap(S, R, ell, k, st);
+    SideStream* ss = c->side.ready() ? &c->side : nullptr;
+    bool pending = false;
+    auto tgemv = [&](int c_) -> int {   // tv for column c_ (after the e_i it reads)
         const int i0 = c_ - ell + 1 > 0 ? c_ - ell + 1 : 0;
-        sgks::launch_rev_tgemv(S, R, i0, k - i0, st);          // sum_i (y_i)_c e_i
+        if (!ss) {
+            sgks::launch_rev_tgemv(S, R, c_, i0, k - i0, st);
+            return SGKS_OK;
+        }
+        if (hipEventRecord(ss->fork, st) != hipSuccess ||
+            hipStreamWaitEvent(ss->side, ss->fork, 0) != hipSuccess)
+            return SGKS_ERR_HIP;
+        sgks::launch_rev_tgemv(S, R, c_, i0, k - i0, ss->side);
+        if (hipEventRecord(ss->join, ss->side) != hipSuccess) return SGKS_ERR_HIP;
+        pending = true;
+        return SGKS_OK;
+    };
+    auto join = [&]() -> int {
+        if (pending) {
+            if (hipStreamWaitEvent(st, ss->join, 0) != hipSuccess) return SGKS_ERR_HIP;
+            pending = false;
+        }
+        return SGKS_OK;
+    };
+    // one column c: its adjoint, scaled by `scale`, into dst (its tv already formed)
+    auto column = [&](int c_, const double* scale, double* dst) -> int {
+        sgks::launch_rev_svec(S, R, d, st);                    // Q R C[:, c] (- S_A b ubar_c)
+        if (join()) return SGKS_ERR_HIP;
         sgks::launch_rev_forward(S, R, S.W + (size_t)c_ * n, st);   // with S_A^T zA, S_L^T zL
         sgks::launch_rev_adjoint(S, R, grad_x, scale, dst, st);
+        return SGKS_OK;
     };
     // the last solve: W_k^T grad_x, then the columns from the newest down
     sgks::launch_gemvt(S, grad_x, d, st);
+    if (tgemv(d - 1)) return SGKS_ERR_HIP;
     sgks::launch_rev_small(S, R, ell, k, k, d - 1, -1, 0, st);
     for (int j = k - 1; j >= 0; --j) {
         const int cc = ell + j;   // made from the gradient r_j
         double* e = R.E + (size_t)j * n;
-        column(cc, S.cs + cc, e);   // e_j = adjoint / ||r_j||
+        if (column(cc, S.cs + cc, e)) return SGKS_ERR_HIP;   // e_j = adjoint / ||r_j||
         sgks::launch_gemvt_mat(S, S.HW, e, cc, st);   // W_j^T H e_j
+        if (tgemv(cc - 1)) return SGKS_ERR_HIP;
         sgks::launch_rev_small(S, R, ell, k, j, cc - 1, cc, 0, st);
     }
     for (int cc = ell - 1; cc >= 0; --cc) {
-        column(cc, nullptr, R.vbar + (size_t)cc * n);
+        if (column(cc, nullptr, R.vbar + (size_t)cc * n)) return SGKS_ERR_HIP;
+        if (cc > 0 && tgemv(cc - 1)) return SGKS_ERR_HIP;
         sgks::launch_rev_small(S, R, ell, k, -1, cc - 1, cc, cc == 0 ? 1 : 0, st);
     }
+    if (join()) return SGKS_ERR_HIP;
     // the initial basis: v_i = p_i / ||p_i||, p_i = (I - V_i V_i^T) A^T A v_{i-1}
     // (raw columns: W[:, i] = p_i / cs[i - 1], cs[i] = 1 / ||W[:, i]||)
     for (int i = ell - 1; i >= 1; --i) {

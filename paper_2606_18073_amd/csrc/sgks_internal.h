@@ -205,7 +205,8 @@ struct Rev {
     double* vL;     // dmax: R_L C[:, c]
     double* dz;     // dmax: coefficient vectors of the initial-basis reverse
     double* dp;     // dmax
-    double* kap;    // max_iters + 1: (y_i)_c, the coefficients of tv
+    double* kap;    // d_max x kld: row c = (y_i)_c, i <= k (the coefficients of tv for column c)
+    int kld;        // max_iters + 1
     double* ones;   // max_iters
     double* rs;     // 16 scalars: [0] d loss / d mu, [1] (y_k)_c, [2] ubar_c
     int nldot;
@@ -284,8 +285,10 @@ void launch_record_y(const State* Sdev, int np, hipStream_t st);
 void launch_rev_small(const State& S, const Rev& R, int ell, int k, int j, int c, int c_done,
                       int fin, hipStream_t st);
 void launch_rev_svec(const State& S, const Rev& R, int dk, hipStream_t st);
-// tv = E[:, i0 : i0 + ncols] kap[i0 : i0 + ncols]
-void launch_rev_tgemv(const State& S, const Rev& R, int i0, int ncols, hipStream_t st);
+// kap row c = (y_i)_c from the y history, c < ell + k, i <= k
+void launch_rev_kap(const State& S, const Rev& R, int ell, int k, hipStream_t st);
+// tv = E[:, i0 : i0 + ncols] (row c of kap)[i0 : i0 + ncols]
+void launch_rev_tgemv(const State& S, const Rev& R, int c, int i0, int ncols, hipStream_t st);
 // u = A tv - S_A^T zA, t = L tv - S_L^T zL, partials of (L wc) . (L tv)
 void launch_rev_forward(const State& S, const Rev& R, const double* wc, hipStream_t st);
 // dst = scale (A^T u + mu L^T t + rs[1] gx)   (scale null: 1)

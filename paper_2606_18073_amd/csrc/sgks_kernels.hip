@@ -2475,7 +2475,6 @@ __global__ __launch_bounds__(kRevThreads) void k_rev_small(State S, Rev R, int e
             sU[i] = R.uh[(int64_t)(ell + i) * dmax + c];
         }
         __syncthreads();
-        for (int i = i0 + (int)threadIdx.x; i < k; i += kRevThreads) R.kap[i] = sY[i];
         if (threadIdx.x == 0) {
             R.rs[1] = sY[k];
             R.rs[2] = R.ubar[c];
@@ -2523,6 +2522,17 @@ __global__ __launch_bounds__(kRevThreads) void k_rev_small(State S, Rev R, int e
             R.vL[r] = 0.0;
         }
         if (threadIdx.x == 0) R.rs[2] = 0.0;
+    }
+}
+
+// kap[c kld + i] = (y_i)_c = yh[(ell + i) dmax + c]
+__global__ __launch_bounds__(kBlock) void k_rev_kap(State S, Rev R, int ell, int k) {
+    const int dk = ell + k;
+    const int64_t tot = (int64_t)dk * (k + 1);
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < tot;
+         e += (int64_t)gridDim.x * kBlock) {
+        const int c = (int)(e / (k + 1)), i = (int)(e % (k + 1));
+        R.kap[(int64_t)c * R.kld + i] = S.yh[(int64_t)(ell + i) * S.dmax + c];
     }
 }
 
@@ -3162,8 +3172,15 @@ void launch_rev_svec(const State& S, const Rev& R, int dk, hipStream_t st) {
     hipLaunchKernelGGL(k_rev_svec, dim3(2 * nbs), dim3(kBlock), 0, st, S, R, dk, nbs);
 }
 
-void launch_rev_tgemv(const State& S, const Rev& R, int i0, int ncols, hipStream_t st) {
-    launch_gemv_plain(S, R.E + (int64_t)i0 * S.n, R.kap + i0, ncols, nullptr, R.tv, st);
+void launch_rev_kap(const State& S, const Rev& R, int ell, int k, hipStream_t st) {
+    const int64_t tot = (int64_t)(ell + k) * (k + 1);
+    hipLaunchKernelGGL(k_rev_kap, dim3(grid_for(tot, kBlock, 1024)), dim3(kBlock), 0, st, S, R,
+                       ell, k);
+}
+
+void launch_rev_tgemv(const State& S, const Rev& R, int c, int i0, int ncols, hipStream_t st) {
+    launch_gemv_plain(S, R.E + (int64_t)i0 * S.n, R.kap + (int64_t)c * R.kld + i0, ncols,
+                      nullptr, R.tv, st);
 }
 
 void launch_rev_forward(const State& S, const Rev& R, const double* wc, hipStream_t st) {

@@ -984,7 +984,6 @@ __global__ __launch_bounds__(kBlock) void k_srtt_transpose_mfma(
     for (int qt = 0; qt < kSrttTQ; ++qt)
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt) acc[qt][rt] = sgks_double4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 2
     for (int j0 = 0; j0 < spad; j0 += 4) {
         // B operand: lane l holds B[kk = l / 16][Q = l % 16]
         const int j = j0 + (lane >> 4);

@@ -141,8 +141,8 @@ typedef struct {
                                 nnz/row and a fixed tile count (default)                        */
     int32_t method;          /* SGKS_METHOD_SGKS (default) or SGKS_METHOD_GKS (see above)      */
     int32_t keep_history;    /* 1 = record y after every projected solve, and hold the buffers
-                                of sgks_backward_total (about 2 dmax^2 + n (max_iters + ell + 4)
-                                + m + p + 2 s doubles more); needs method SGKS, the
+                                of sgks_backward_total (about 3 dmax^2 + n (max_iters + ell + 4)
+                                + m + p + 2 s doubles more, dmax = ell + max_iters); needs method SGKS, the
                                 maintained gradient form and refine_steps = 0, else
                                 SGKS_ERR_INVALID_ARG at create; in a batch every problem
                                 keeps its history.  0 = off (default)                          */

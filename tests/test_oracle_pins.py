@@ -470,6 +470,27 @@ def test_total_adjoint_at_full_space_is_dense_adjoint():
     assert abs(gmu - gmu_dense) <= tol * abs(gmu_dense)
 
 
+def test_total_adjoint_of_identity_sketch_is_the_derivative_of_gks():
+    """Prop. 1: with identity sketches sGKS_0 has the iterates of GKS (Alg. 1, whose basis
+    is reorthogonalised).  The total adjoint of sGKS_0 therefore differentiates the GKS map:
+    compare with central differences of the oracle's GKS solution."""
+    A, L, b, mu = tiny2d(N=6)
+    k = 5
+    s = max(A.shape[0], L.shape[0])
+    rng = np.random.default_rng(9)
+    g_x = rng.standard_normal(A.shape[1])
+    gb, gmu = O.total_adjoint(A, L, b, mu, k, s, 0, g_x, sketch="identity")
+    f = lambda bb, mm: float(g_x @ O.gks(A, L, bb, mm, k).x)
+    for _ in range(3):
+        db = rng.standard_normal(b.size)
+        h = 1e-5 * np.linalg.norm(b) / np.linalg.norm(db)
+        fd = (f(b + h * db, mu) - f(b - h * db, mu)) / (2 * h)
+        assert abs(fd - gb @ db) <= 1e-6 * max(abs(fd), 1e-3)
+    hm = 1e-5 * mu
+    fdm = (f(b, mu + hm) - f(b, mu - hm)) / (2 * hm)
+    assert abs(fdm - gmu) <= 1e-6 * max(abs(fdm), 1e-3)
+
+
 def test_total_adjoint_pins_reject_a_wrong_solve_and_the_frozen_adjoint(monkeypatch):
     """The difference pin separates the total derivative from plausible slips: the
     frozen-basis adjoint (no path through W) and a projected solve applied with one

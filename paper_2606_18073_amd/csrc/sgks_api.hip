@@ -715,6 +715,7 @@ void layout_context(sgks_ctx* c, Arena& ar) {
         ar.add(&R.kap, (size_t)dmax * (K + 1) * 8);
         ar.add(&R.ones, (size_t)(K > 0 ? K : 1) * 8);
         ar.add(&R.rs, 16 * 8);
+        ar.add(&R.mupart, (size_t)(K + 1) * 8);
     }
     if (S.method == SGKS_METHOD_GKS) {
         ar.add(&S.QAt, (size_t)S.m * dmax * 8);
@@ -1276,6 +1277,7 @@ int sgks_backward_total(sgks_ctx* c, const double* grad_x, double* grad_b, doubl
         sgks::launch_rev_small(S, R, ell, k, -1, cc - 1, cc, cc == 0 ? 1 : 0, st);
     }
     if (join()) return SGKS_ERR_HIP;
+    sgks::launch_rev_mu(S, R, ell, k, st);   // the solves' mu terms, off the column chain
     // the initial basis: v_i = p_i / ||p_i||, p_i = (I - V_i V_i^T) A^T A v_{i-1}
     // (raw columns: W[:, i] = p_i / cs[i - 1], cs[i] = 1 / ||W[:, i]||)
     for (int i = ell - 1; i >= 1; --i) {

@@ -209,6 +209,7 @@ struct Rev {
     int kld;        // max_iters + 1
     double* ones;   // max_iters
     double* rs;     // 16 scalars: [0] d loss / d mu, [1] (y_k)_c, [2] ubar_c
+    double* mupart; // max_iters + 1: (B_L u_j) . (B_L y_j) of each solve
     int nldot;
 };
 
@@ -285,6 +286,8 @@ void launch_record_y(const State* Sdev, int np, hipStream_t st);
 void launch_rev_small(const State& S, const Rev& R, int ell, int k, int j, int c, int c_done,
                       int fin, hipStream_t st);
 void launch_rev_svec(const State& S, const Rev& R, int dk, hipStream_t st);
+// d loss / d mu -= sum_j (B_L u_j) . (B_L y_j) over the k + 1 solves (after the sweep)
+void launch_rev_mu(const State& S, const Rev& R, int ell, int k, hipStream_t st);
 // kap row c = (y_i)_c from the y history, c < ell + k, i <= k
 void launch_rev_kap(const State& S, const Rev& R, int ell, int k, hipStream_t st);
 // tv = E[:, i0 : i0 + ncols] (row c of kap)[i0 : i0 + ncols]

@@ -2417,7 +2417,6 @@ __global__ __launch_bounds__(kRevThreads) void k_rev_small(State S, Rev R, int e
     __shared__ double gv[kMaxD];
     __shared__ double tvv[kMaxD];
     __shared__ double uv[kMaxD];
-    __shared__ double yv[kMaxD];
     __shared__ double l1[kMaxD];
     __shared__ double l2[kMaxD];
     __shared__ double sY[kMaxD + 1];
@@ -2449,7 +2448,6 @@ __global__ __launch_bounds__(kRevThreads) void k_rev_small(State S, Rev R, int e
             for (int off = tpc / 2; off > 0; off >>= 1) a += __shfl_xor(a, off);
             if (i < dj && l == 0) gv[i] = a;
         }
-        for (int i = threadIdx.x; i < dj; i += kRevThreads) yv[i] = S.yh[(int64_t)dj * dmax + i];
         __syncthreads();
         tri_mv(Gi, dmax, 1, dj, 1, gv, tvv);   // G_j^{-T} W_j^T x^_j
         __syncthreads();
@@ -2459,12 +2457,6 @@ __global__ __launch_bounds__(kRevThreads) void k_rev_small(State S, Rev R, int e
             R.uh[(int64_t)dj * dmax + i] = uv[i];
             R.ubar[i] += uv[i];
         }
-        tri_mv2(S.RL, 1, dmax, dj, uv, yv, l1, l2);   // B_L u_j, B_L y_j (as R_L products)
-        __syncthreads();
-        double pr = 0.0;
-        for (int i = threadIdx.x; i < dj; i += kRevThreads) pr += l1[i] * l2[i];
-        pr = block_sum(pr, red);
-        if (threadIdx.x == 0) R.rs[0] -= pr;   // -(B_L u_j) . (B_L y_j)
         __syncthreads();
     }
     if (c >= 0) {
@@ -2522,6 +2514,35 @@ __global__ __launch_bounds__(kRevThreads) void k_rev_small(State S, Rev R, int e
         }
         if (threadIdx.x == 0) R.rs[2] = 0.0;
     }
+}
+
+// mupart[j] = (R_L u_j) . (R_L y_j) (= (B_L u_j) . (B_L y_j)), one workgroup per solve j
+// with d_j = ell + j columns; then the last launch subtracts them in order from
+// d loss / d mu
+__global__ __launch_bounds__(kBlock) void k_rev_mu(State S, Rev R, int ell) {
+    __shared__ double uv[kMaxD];
+    __shared__ double yv[kMaxD];
+    __shared__ double l1[kMaxD];
+    __shared__ double l2[kMaxD];
+    __shared__ double red[kWaves];
+    const int j = blockIdx.x, dj = ell + j, dmax = S.dmax;
+    for (int i = threadIdx.x; i < dj; i += kBlock) {
+        uv[i] = R.uh[(int64_t)dj * dmax + i];
+        yv[i] = S.yh[(int64_t)dj * dmax + i];
+    }
+    __syncthreads();
+    tri_mv2(S.RL, 1, dmax, dj, uv, yv, l1, l2);
+    __syncthreads();
+    double pr = 0.0;
+    for (int i = threadIdx.x; i < dj; i += kBlock) pr += l1[i] * l2[i];
+    pr = block_sum(pr, red);
+    if (threadIdx.x == 0) R.mupart[j] = pr;
+}
+
+__global__ __launch_bounds__(kBlock) void k_rev_mu_sum(Rev R, int k) {
+    __shared__ double red[kWaves];
+    const double a = block_sum(thread_strided_sum(R.mupart, k + 1, kBlock), red);
+    if (threadIdx.x == 0) R.rs[0] -= a;
 }
 
 // kap[c kld + i] = (y_i)_c = yh[(ell + i) dmax + c]
@@ -3164,6 +3185,11 @@ void launch_rev_small(const State& S, const Rev& R, int ell, int k, int j, int c
                       int fin, hipStream_t st) {
     hipLaunchKernelGGL(k_rev_small, dim3(1), dim3(kRevThreads), 0, st, S, R, ell, k, j, c,
                        c_done, fin);
+}
+
+void launch_rev_mu(const State& S, const Rev& R, int ell, int k, hipStream_t st) {
+    hipLaunchKernelGGL(k_rev_mu, dim3(k + 1), dim3(kBlock), 0, st, S, R, ell);
+    hipLaunchKernelGGL(k_rev_mu_sum, dim3(1), dim3(kBlock), 0, st, R, k);
 }
 
 void launch_rev_svec(const State& S, const Rev& R, int dk, hipStream_t st) {

@@ -378,3 +378,23 @@ def test_srtt_transposes_full_size():
     say(f"  frozen grad_b rel err {ef:.2e}; total grad_b {eb:.2e}, grad_mu {em:.2e}")
     assert ef <= 1e-10
     assert eb <= 1e-9 and em <= 1e-9
+
+
+@pytest.mark.parametrize("zeta,passes", [(2, 2), (4, 2), (16, 2), (8, 1)])
+def test_total_adjoint_zeta_and_single_projection(zeta, passes):
+    """Every instantiation of the reverse forward product's sparse-sign transposes (zeta
+    entries per column gathered from the cached pattern) and the single-projection QR
+    append (eq:updqr as written), against the oracle."""
+    import copy
+    P = copy.copy(problem("dynamic_ct", "small"))
+    P.zeta = zeta
+    k = 10
+    say("case total adjoint zeta/passes", zeta, passes)
+    g_x = seed_grad(P.n)
+    S, gb, gmu, rc, it = gpu_total(P, k, g_x, qr_passes=passes)
+    assert rc == 0 and it == k
+    S.close()
+    gb_o, gmu_o = O.total_adjoint(P.A, P.L, P.b, P.mu, k, P.s, P.seed, g_x, zeta=zeta, ell=P.ell)
+    eb, em = rel(gb, gb_o), abs(gmu - gmu_o) / abs(gmu_o)
+    say(f"  grad_b rel err {eb:.2e}, grad_mu {em:.2e}")
+    assert eb <= 1e-9 and em <= 1e-9
